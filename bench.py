@@ -1,0 +1,184 @@
+"""Benchmark of the CROSS hot path on one MI355X.
+
+Workload (one "step"): forward + inverse NTT of a CKKS-shaped batch,
+N = 2^16 split 256 x 256, L = 24 limbs of 28-bit primes, 8 ciphertexts x 2
+polynomials = 384 limb-NTTs each way, through the BAT int8-MFMA path.  Inputs
+are resident in HBM before timing starts.  Reported beside it: the same step
+through the plain radix-2 butterfly kernels (bit-identical results, checked),
+the roofline of the dominant kernel from live HIP-event timings, and the CPU
+oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "N=2^16 NTTs/sec and HE-Mult/s, int8-MFMA vs butterfly, bit-exact"
+INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s
+HBM_PEAK_GBS = 8000.0
+
+LOG_N, LOG_R, L, POLYS = 16, 8, 24, 16
+
+
+def gemm_ops_per_launch(log_n, log_r, nlimb_polys, kind):
+    # algorithmic int8 ops of one BAT GEMM step: 2 * (4U) * (4U) * V per limb-polynomial
+    R, C = 1 << log_r, 1 << (log_n - log_r)
+    U, V = (R, C) if kind == "left" else (C, R)
+    return 2.0 * (4 * U) * (4 * U) * V * nlimb_polys
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2501_07047_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, kernel_hash):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if still current."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != kernel_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle's textbook NTT (numpy, one process) on a bounded sample of the workload."""
+    import numpy as np
+    import synthetic
+    from oracle.ntt import ntt_ct, intt_gs
+    from oracle.primes import psi
+    primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
+    n = 1 << LOG_N
+    done = 0
+    t0 = time.perf_counter()
+    for limb in range(len(primes)):
+        q = primes[limb]
+        p = psi(q, n)
+        y = ntt_ct(x[:, limb].astype(np.uint64), q, p)
+        intt_gs(y, q, p)
+        done += 2 * POLYS
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "limb-NTT/s", "cores": 1, "kind": "oracle",
+            "sample": "%d limb-NTTs (forward+inverse, N=2^16, %d polys x %d limbs) in %.1f s, "
+                      "oracle.ntt.ntt_ct/intt_gs, single process" % (done, POLYS, done // (2 * POLYS), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the hot path shards by ciphertext with no "
+              "exchange, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synthetic
+    from paper_2501_07047_amd import binding as B
+
+    torch.cuda.set_device(0)
+    B.set_ntt_split(LOG_N, LOG_R)
+    primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
+    host = torch.from_numpy(x.view(np.int32))
+    data = host.cuda()
+    ref = host.cuda()
+    stream = torch.cuda.current_stream()
+
+    def step_mfma():
+        B.ntt_forward(data, primes)
+        B.ntt_inverse(data, primes)
+
+    def step_bf():
+        B.ntt_forward_butterfly(ref, primes)
+        B.ntt_inverse_butterfly(ref, primes)
+
+    # bit-exactness of the timed configuration: MFMA forward == butterfly forward, round trip == input
+    B.ntt_forward(data, primes)
+    B.ntt_forward_butterfly(ref, primes)
+    torch.cuda.synchronize()
+    exact = bool(torch.equal(data, ref))
+    B.ntt_inverse(data, primes)
+    B.ntt_inverse_butterfly(ref, primes)
+    torch.cuda.synchronize()
+    exact = exact and bool(torch.equal(data, host.cuda())) and bool(torch.equal(ref, data))
+
+    for _ in range(args.warmup):
+        step_mfma()
+    torch.cuda.synchronize()
+    B.profile_report()
+    B.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_mfma()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = B.profile_report()
+    B.profile_enable(False)
+
+    for _ in range(max(1, args.warmup // 2)):
+        step_bf()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bf_steps = max(2, args.steps // 4)
+    for _ in range(bf_steps):
+        step_bf()
+    torch.cuda.synchronize()
+    dt_bf = time.perf_counter() - t1
+
+    limb_ntts = 2 * L * POLYS
+    value = limb_ntts * args.steps / dt
+    bf_value = limb_ntts * bf_steps / dt_bf
+
+    # dominant kernel: the GEMM family with the larger total event time
+    fam = max(("bat_gemm_left", "bat_gemm_right"), key=lambda k: prof.get(k, (0, 0.0))[1])
+    launches, total_ms = prof.get(fam, (1, float("nan")))
+    avg_s = total_ms / 1e3 / max(1, launches)
+    ops = gemm_ops_per_launch(LOG_N, LOG_R, L * POLYS, "left" if fam.endswith("left") else "right")
+    achieved = ops / avg_s / 1e12
+    khash = source_hash("ntt_mfma.hip")
+    roof = {"bound": "mfma", "kernel": fam, "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
+            "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
+            "traffic": traffic_for(fam, khash), "avg_launch_us": round(avg_s * 1e6, 2),
+            "ops_per_launch": ops, "launches_timed": launches,
+            "event_ms_by_kernel": {k: [v[0], round(v[1], 3)] for k, v in prof.items()}}
+
+    line = {"metric": METRIC, "value": round(value, 1), "unit": "limb-NTT/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8",
+            "data": "synthetic",
+            "config": {"workload": "NTT+INTT, N=2^16 as 256x256, L=24 28-bit primes, "
+                                   "8 ciphertexts x 2 polys (384 limb-NTTs each way)",
+                       "log_n": LOG_N, "R": 1 << LOG_R, "C": 1 << (LOG_N - LOG_R), "L": L,
+                       "polys": POLYS},
+            "poly_ntt_per_s": round(value / L, 1),
+            "butterfly_limb_ntt_per_s": round(bf_value, 1),
+            "speedup_vs_butterfly": round(value / bf_value, 3),
+            "bit_exact": exact,
+            "roofline": roof}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

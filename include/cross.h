@@ -1,0 +1,126 @@
+/*
+ * cross.h -- C ABI of libcross: the CROSS hot path (arXiv 2501.07047) on AMD
+ * MI355X (gfx950): RNS negacyclic NTT/INTT and the CKKS modular matrix
+ * products rewritten as exact int8 MFMA matrix multiplies (BAT + MAT).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Residues are uint32 values in [0, q).  Inputs outside that range give
+ *    unspecified (but memory-safe) results.
+ *  - Polynomial data is device memory laid out [batch][L][N] (limb-major per
+ *    polynomial, N contiguous coefficients per limb).  Pointers must be
+ *    16-byte aligned.  The caller owns every data buffer.
+ *  - NTT form ("evaluation form") stores slot p = a(psi^(2*brv_N(p)+1)) in
+ *    position p (bit-reversed order; Sec. MAT: the layout-invariant 3-step
+ *    NTT delivers its output directly in bit-reversed order).  psi is the
+ *    canonical primitive 2N-th root g^((q-1)/2N), g the smallest generator of
+ *    Z_q^* (see cross_root).
+ *  - Primes: 2 < q < 2^28, prime, q = 1 (mod 2N).  Arrays of primes are host
+ *    memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls return
+ *    after enqueueing; argument errors are reported synchronously and nothing
+ *    is enqueued; device faults surface at the caller's next synchronisation.
+ *  - A context is bound to one HIP device and is not thread-safe: use one per
+ *    host thread.  It owns the precomputed tables and an internal workspace
+ *    (device memory, grown on demand and freed by cross_ctx_destroy).
+ *  - Every function returns a cross_status; cross_last_error() describes the
+ *    most recent failure on that context.
+ */
+#ifndef CROSS_H
+#define CROSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cross_status {
+  CROSS_OK = 0,
+  CROSS_EINVAL = -1,       /* bad argument (null pointer, size, alignment, layout) */
+  CROSS_ENOTPRIME = -2,    /* a modulus is not prime */
+  CROSS_ENOROOT = -3,      /* q != 1 (mod 2N): no primitive 2N-th root of unity */
+  CROSS_ERANGE = -4,       /* q >= 2^28 (residues must split into four 7-bit chunks) */
+  CROSS_ENOMEM = -5,       /* device allocation failed */
+  CROSS_EDEVICE = -6,      /* HIP runtime error while enqueueing */
+  CROSS_EUNSUPPORTED = -7  /* valid but unsupported shape */
+} cross_status;
+
+#define CROSS_MAX_LIMBS 64   /* L + K limit per call */
+#define CROSS_MIN_LOG_N 4
+#define CROSS_MAX_LOG_N 16
+
+typedef struct cross_ctx_s* cross_ctx;
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+cross_status cross_ctx_create(int hip_device, cross_ctx* out);
+/* Free tables, workspace and the context.  Waits for the device to go idle. */
+void cross_ctx_destroy(cross_ctx ctx);
+/* Text of the last error on ctx (valid until the next call on ctx). */
+const char* cross_last_error(cross_ctx ctx);
+
+/* Canonical psi for (q, N = 2^log_n): *psi_out = g^((q-1)/2N).  Validates q. */
+cross_status cross_root(uint32_t q, uint32_t log_n, uint32_t* psi_out);
+
+/* Force the 3-step split N = R x C with R = 2^log_r for transforms of size
+ * 2^log_n on this context (the autotuner's choice otherwise; default
+ * R = 2^floor(log_n/2)).  4 <= log_r and 4 <= log_n - log_r. */
+cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r);
+
+/*
+ * Forward negacyclic NTT, in place, of `batch` polynomials of L limbs each
+ * (Sec. MAT, layout-invariant 3-step NTT; Sec. BAT for the int8 products):
+ * for every b < batch and limb i < L, data[b][i][:] (coefficients, natural
+ * order) is replaced by its NTT form modulo primes[i] (bit-reversed order).
+ * Steps 1 and 3 run as BAT-expanded int8 MFMA GEMMs; step 2 is fused into the
+ * epilogue of step 1.  Uses batch*L*N*4 bytes of context workspace.
+ *   log_n  : 4..16 (log_n >= 8 runs on MFMA; smaller sizes use the butterfly kernels)
+ *   primes : host array of L primes (see conventions)
+ *   L      : 1..CROSS_MAX_LIMBS;  batch >= 1
+ *   data   : device, uint32 [batch][L][2^log_n]
+ */
+cross_status cross_ntt_forward(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                               uint32_t batch, uint32_t* data, void* stream);
+/* Inverse of cross_ntt_forward (NTT form in bit-reversed order -> coefficients),
+ * N^-1 included.  Same arguments. */
+cross_status cross_ntt_inverse(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                               uint32_t batch, uint32_t* data, void* stream);
+
+/* Baseline: the same transforms as plain radix-2 butterflies on the vector
+ * ALUs, one launch per stage (App. "Radix-2 Cooley-Tukey NTT").  Bit-identical
+ * results to cross_ntt_forward / cross_ntt_inverse.  Same arguments. */
+cross_status cross_ntt_forward_butterfly(cross_ctx ctx, uint32_t log_n, const uint32_t* primes,
+                                         uint32_t L, uint32_t batch, uint32_t* data, void* stream);
+cross_status cross_ntt_inverse_butterfly(cross_ctx ctx, uint32_t log_n, const uint32_t* primes,
+                                         uint32_t L, uint32_t batch, uint32_t* data, void* stream);
+
+/*
+ * Kernel timing with HIP events (tracing aid).  While enabled, every kernel
+ * launch the library makes is bracketed by a pair of events recorded on the
+ * launch stream.  cross_profile_report synchronises on the recorded events
+ * and writes one line per kernel family, "name launches total_ms\n", into
+ * `buf` (NUL-terminated, truncated to `len`), then clears the record.
+ */
+cross_status cross_profile_enable(cross_ctx ctx, int enable);
+cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len);
+
+/*
+ * Host-only introspection of the offline-compiled tables (no device work):
+ * copies one table of the (q, N = 2^log_n, R = 2^log_r) plan into host memory
+ * `out` of `*bytes` bytes.  If out is NULL, *bytes receives the size needed.
+ *   which 0/1/2/3: BAT-expanded int8 matrices, forward step 1 / forward step 3 /
+ *                  inverse step 3 (applied last) / inverse step 1 (applied first),
+ *                  stored tile-major: byte (m, k) at (k/64)*(M*64) + m*64 + k%64,
+ *                  entry chunk_i((T[x][u] * 2^32 * 2^(7j)) mod q), m = 4u+i, k = 4x+j
+ *                  (Alg. bat_deployment, DirectScalarBAT with the Montgomery factor folded in)
+ *   which 4/5    : uint32 step-2 twiddles in Montgomery form, forward [R][C] and
+ *                  inverse transposed [C][R] (Sec. MAT, layout-invariant 3-step NTT)
+ * Returns CROSS_EINVAL for a bad `which`, split or buffer size.
+ */
+cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,
+                               void* out, uint64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CROSS_H */

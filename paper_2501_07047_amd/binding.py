@@ -1,0 +1,183 @@
+"""Thin Python binding of libcross (argument marshalling only).
+
+Every function takes torch tensors that live on a HIP device (any 4-byte
+dtype; bit patterns are treated as uint32 residues), checks shapes, and calls
+the C entry point of the same name in ``libcross.so`` with raw device
+pointers and the current torch stream.  No arithmetic happens here: if the
+shared library is missing, every call raises.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcross.so")
+
+STATUS = {0: "CROSS_OK", -1: "CROSS_EINVAL", -2: "CROSS_ENOTPRIME", -3: "CROSS_ENOROOT",
+          -4: "CROSS_ERANGE", -5: "CROSS_ENOMEM", -6: "CROSS_EDEVICE", -7: "CROSS_EUNSUPPORTED"}
+
+
+class CrossError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+_ctx = {}
+
+c_u32 = ctypes.c_uint32
+c_i32 = ctypes.c_int32
+c_vp = ctypes.c_void_p
+c_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+# name -> argtypes (restype is always int = cross_status unless noted)
+SIGNATURES = {
+    "cross_ctx_create": [ctypes.c_int, ctypes.POINTER(c_vp)],
+    "cross_ctx_destroy": [c_vp],
+    "cross_last_error": [c_vp],
+    "cross_root": [c_u32, c_u32, c_u32p],
+    "cross_set_ntt_split": [c_vp, c_u32, c_u32],
+    "cross_ntt_forward": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
+    "cross_ntt_inverse": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
+    "cross_ntt_forward_butterfly": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
+    "cross_ntt_inverse_butterfly": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
+    "cross_profile_enable": [c_vp, ctypes.c_int],
+    "cross_profile_report": [c_vp, ctypes.c_char_p, ctypes.c_uint64],
+    "cross_host_tables": [c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
+}
+
+
+def lib():
+    """Load libcross.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcross.so is not built (run __graft_entry__.build())")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        l.cross_ctx_destroy.restype = None
+        l.cross_last_error.restype = ctypes.c_char_p
+        _lib = l
+    return _lib
+
+
+def exported_symbols():
+    return list(SIGNATURES)
+
+
+def context(device=None):
+    """Per-device library context, created on first use."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else int(device)
+    if dev not in _ctx:
+        h = c_vp()
+        st = lib().cross_ctx_create(dev, ctypes.byref(h))
+        if st != 0:
+            raise CrossError(st, "cross_ctx_create(%d)" % dev)
+        _ctx[dev] = h
+    return _ctx[dev]
+
+
+def _check(st, ctx):
+    if st != 0:
+        raise CrossError(st, lib().cross_last_error(ctx).decode())
+
+
+def _u32_array(values):
+    vals = [int(v) for v in values]
+    return (ctypes.c_uint32 * len(vals))(*vals)
+
+
+def _dev_ptr(t, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.element_size() != 4 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous 4-byte tensor" % name)
+    return c_vp(t.data_ptr())
+
+
+def _stream(t):
+    import torch
+    return c_vp(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _log2(n):
+    if n <= 0 or n & (n - 1):
+        raise ValueError("N must be a power of two")
+    return n.bit_length() - 1
+
+
+def root(q, log_n):
+    out = ctypes.c_uint32()
+    st = lib().cross_root(q, log_n, ctypes.byref(out))
+    if st != 0:
+        raise CrossError(st, "cross_root(%d, %d)" % (q, log_n))
+    return out.value
+
+
+def set_ntt_split(log_n, log_r, device=None):
+    ctx = context(device)
+    _check(lib().cross_set_ntt_split(ctx, log_n, log_r), ctx)
+
+
+def _ntt(fn, data, primes):
+    if data.dim() != 3:
+        raise ValueError("data must be [batch][L][N]")
+    batch, L, n = data.shape
+    if L != len(primes):
+        raise ValueError("len(primes) != L")
+    ctx = context(data.device.index)
+    _check(getattr(lib(), fn)(ctx, _log2(n), _u32_array(primes), L, batch,
+                              _dev_ptr(data, "data"), _stream(data)), ctx)
+    return data
+
+
+def ntt_forward(data, primes):
+    """In-place forward NTT of data[batch][L][N] (see cross_ntt_forward)."""
+    return _ntt("cross_ntt_forward", data, primes)
+
+
+def ntt_inverse(data, primes):
+    return _ntt("cross_ntt_inverse", data, primes)
+
+
+def ntt_forward_butterfly(data, primes):
+    return _ntt("cross_ntt_forward_butterfly", data, primes)
+
+
+def ntt_inverse_butterfly(data, primes):
+    return _ntt("cross_ntt_inverse_butterfly", data, primes)
+
+
+def host_tables(q, log_n, log_r, which):
+    """Copy one offline-compiled table into a numpy array (host only, no GPU)."""
+    import numpy as np
+    nbytes = ctypes.c_uint64(0)
+    st = lib().cross_host_tables(q, log_n, log_r, which, None, ctypes.byref(nbytes))
+    if st != 0:
+        raise CrossError(st, "cross_host_tables")
+    buf = np.empty(nbytes.value, dtype=np.uint8)
+    st = lib().cross_host_tables(q, log_n, log_r, which, c_vp(buf.ctypes.data), ctypes.byref(nbytes))
+    if st != 0:
+        raise CrossError(st, "cross_host_tables")
+    return buf.view(np.int8) if which < 4 else buf.view(np.uint32)
+
+
+def profile_enable(enable=True, device=None):
+    ctx = context(device)
+    _check(lib().cross_profile_enable(ctx, 1 if enable else 0), ctx)
+
+
+def profile_report(device=None):
+    """{kernel family: (launches, total_ms)} since the last report (synchronises)."""
+    ctx = context(device)
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(lib().cross_profile_report(ctx, buf, len(buf)), ctx)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

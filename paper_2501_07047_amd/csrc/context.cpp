@@ -1,0 +1,374 @@
+// Context, plan cache and the NTT entry points of the C ABI.
+#include "context.h"
+
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+
+#include "params.h"
+
+namespace cross {
+
+cross_status fail(cross_ctx ctx, cross_status code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n) {
+  if (q >= (1u << 28)) return fail(ctx, CROSS_ERANGE, "modulus " + std::to_string(q) + " >= 2^28");
+  if (q < 3 || !is_prime_u32(q)) return fail(ctx, CROSS_ENOTPRIME, "modulus " + std::to_string(q) + " is not prime");
+  if ((q - 1) % (2ull << log_n)) return fail(ctx, CROSS_ENOROOT, "modulus " + std::to_string(q) + " != 1 mod 2N");
+  return CROSS_OK;
+}
+
+ProfScope::ProfScope(cross_ctx c, const char* name, hipStream_t st) : ctx(c), s(st) {
+  if (!ctx || !ctx->prof) return;
+  cross_ctx_s::ProfRec r{name, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+  (void)hipEventRecord(r.a, s);
+  idx = (int)ctx->prof_recs.size();
+  ctx->prof_recs.push_back(r);
+}
+
+ProfScope::~ProfScope() {
+  if (idx >= 0) (void)hipEventRecord(ctx->prof_recs[idx].b, s);
+}
+
+int split_of(cross_ctx ctx, int log_n) {
+  auto it = ctx->split.find(log_n);
+  if (it != ctx->split.end()) return it->second;
+  return log_n / 2;
+}
+
+static cross_status dev_alloc(cross_ctx ctx, size_t bytes, void** out) {
+  if (hipMalloc(out, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, CROSS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return CROSS_OK;
+}
+
+cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out) {
+  const int log_r = (log_n >= 8) ? split_of(ctx, log_n) : 0;
+  auto key = std::make_tuple(q, log_n, log_r);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = it->second;
+    return CROSS_OK;
+  }
+  NttTables t;
+  try {
+    // below N = 2^8 a 3-step split cannot fill one 64-deep MFMA step: butterfly twiddles only
+    build_ntt_tables(q, log_n, log_r, t, log_n >= 8);
+  } catch (const std::exception& e) {
+    return fail(ctx, CROSS_EINVAL, e.what());
+  }
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t sz = al(t.fwd_left.size()) + al(t.fwd_right.size()) + al(t.inv_left.size()) +
+              al(t.inv_right.size()) + al(t.fwd_tw.size() * 4) + al(t.inv_tw.size() * 4) +
+              al(t.bf_fwd.size() * 4) + al(t.bf_inv.size() * 4);
+  Plan* p = new Plan();
+  cross_status st = dev_alloc(ctx, sz, &p->block);
+  if (st != CROSS_OK) {
+    delete p;
+    return st;
+  }
+  char* base = static_cast<char*>(p->block);
+  size_t off = 0;
+  auto put = [&](const void* src, size_t bytes) -> void* {
+    void* dst = base + off;
+    if (bytes) (void)hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    off += al(bytes);
+    return bytes ? dst : nullptr;
+  };
+  p->fwd_left = (int8_t*)put(t.fwd_left.data(), t.fwd_left.size());
+  p->fwd_right = (int8_t*)put(t.fwd_right.data(), t.fwd_right.size());
+  p->inv_left = (int8_t*)put(t.inv_left.data(), t.inv_left.size());
+  p->inv_right = (int8_t*)put(t.inv_right.data(), t.inv_right.size());
+  p->fwd_tw = (uint32_t*)put(t.fwd_tw.data(), t.fwd_tw.size() * 4);
+  p->inv_tw = (uint32_t*)put(t.inv_tw.data(), t.inv_tw.size() * 4);
+  p->bf_fwd = (uint32_t*)put(t.bf_fwd.data(), t.bf_fwd.size() * 4);
+  p->bf_inv = (uint32_t*)put(t.bf_inv.data(), t.bf_inv.size() * 4);
+  if (hipGetLastError() != hipSuccess) {
+    (void)hipFree(p->block);
+    delete p;
+    return fail(ctx, CROSS_EDEVICE, "table upload failed");
+  }
+  p->q = q;
+  p->qinv = inv_mod_2_32(q);
+  p->psi = root_2n(q, log_n);
+  p->log_n = log_n;
+  p->log_r = log_r;
+  p->bf_ninv = t.bf_ninv;
+  ctx->plans[key] = p;
+  *out = p;
+  return CROSS_OK;
+}
+
+cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, void** out) {
+  std::string key(static_cast<const char*>(host), bytes);
+  auto it = ctx->job_cache.find(key);
+  if (it != ctx->job_cache.end()) {
+    *out = it->second;
+    return CROSS_OK;
+  }
+  void* d = nullptr;
+  cross_status st = dev_alloc(ctx, bytes ? bytes : 16, &d);
+  if (st != CROSS_OK) return st;
+  if (hipMemcpy(d, host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return fail(ctx, CROSS_EDEVICE, "job list upload failed");
+  }
+  ctx->job_cache[key] = d;
+  *out = d;
+  return CROSS_OK;
+}
+
+cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out) {
+  DevBuf& b = ctx->workspace[s];
+  if (b.size < bytes) {
+    if (b.ptr) {
+      // the old buffer may still be in use by work queued on this stream
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(b.ptr);
+      b.ptr = nullptr;
+      b.size = 0;
+    }
+    cross_status st = dev_alloc(ctx, bytes, &b.ptr);
+    if (st != CROSS_OK) return st;
+    b.size = bytes;
+  }
+  *out = b.ptr;
+  return CROSS_OK;
+}
+
+cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
+                       const std::vector<uint64_t>& offs, uint32_t* data, uint64_t stride,
+                       int npoly, bool inverse, uint32_t* tmp, hipStream_t s) {
+  if (plans.empty()) return CROSS_OK;
+  const int log_n = plans[0]->log_n;
+  const int log_r = plans[0]->log_r;
+  std::vector<GemmJob> j1(plans.size()), j2(plans.size());
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    j1[i] = GemmJob{inverse ? p->inv_right : p->fwd_left, inverse ? p->inv_tw : p->fwd_tw,
+                    offs[i], offs[i], p->q, p->qinv};
+    j2[i] = GemmJob{inverse ? p->inv_left : p->fwd_right, nullptr, offs[i], offs[i], p->q, p->qinv};
+  }
+  void *d1 = nullptr, *d2 = nullptr;
+  cross_status st = cached_device_copy(ctx, j1.data(), j1.size() * sizeof(GemmJob), &d1);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, j2.data(), j2.size() * sizeof(GemmJob), &d2);
+  if (st != CROSS_OK) return st;
+  GemmLaunch g{};
+  g.njobs = (int)plans.size();
+  g.src_stride = g.dst_stride = stride;
+  g.npoly = npoly;
+  g.log_r = log_r;
+  g.log_c = log_n - log_r;
+  // step 1 (data -> tmp, packed chunks, twiddle fused) then step 3 (tmp -> data)
+  g.jobs = (const GemmJob*)d1;
+  g.src = data;
+  g.dst = tmp;
+  g.kind = inverse ? kRight : kLeft;
+  g.in_packed = false;
+  g.out_packed = true;
+  g.twiddle = true;
+  hipError_t e;
+  {
+    ProfScope ps(ctx, inverse ? "bat_gemm_right" : "bat_gemm_left", s);
+    e = launch_bat_gemm(g, s);
+  }
+  if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("step-1 launch: ") + hipGetErrorString(e));
+  g.jobs = (const GemmJob*)d2;
+  g.src = tmp;
+  g.dst = data;
+  g.kind = inverse ? kLeft : kRight;
+  g.in_packed = true;
+  g.out_packed = false;
+  g.twiddle = false;
+  {
+    ProfScope ps(ctx, inverse ? "bat_gemm_left" : "bat_gemm_right", s);
+    e = launch_bat_gemm(g, s);
+  }
+  if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("step-3 launch: ") + hipGetErrorString(e));
+  return CROSS_OK;
+}
+
+static cross_status ntt_common(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                               uint32_t batch, uint32_t* data, void* stream, bool inverse,
+                               bool butterfly) {
+  if (!ctx) return CROSS_EINVAL;
+  if (log_n < CROSS_MIN_LOG_N || log_n > CROSS_MAX_LOG_N)
+    return fail(ctx, CROSS_EINVAL, "log_n out of range [4, 16]");
+  if (!primes || !data) return fail(ctx, CROSS_EINVAL, "null pointer");
+  if (L < 1 || L > CROSS_MAX_LIMBS) return fail(ctx, CROSS_EINVAL, "L out of range");
+  if (batch < 1) return fail(ctx, CROSS_EINVAL, "batch must be >= 1");
+  if (reinterpret_cast<uintptr_t>(data) & 15) return fail(ctx, CROSS_EINVAL, "data not 16-byte aligned");
+  for (uint32_t i = 0; i < L; ++i) {
+    cross_status st = check_prime(ctx, primes[i], log_n);
+    if (st != CROSS_OK) return st;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t N = 1ull << log_n;
+  std::vector<Plan*> plans(L);
+  std::vector<uint64_t> offs(L);
+  for (uint32_t i = 0; i < L; ++i) {
+    cross_status st = get_plan(ctx, primes[i], (int)log_n, &plans[i]);
+    if (st != CROSS_OK) return st;
+    offs[i] = i * N;
+  }
+  if (butterfly || log_n < 8) {
+    std::vector<ButterflyJob> jobs(L);
+    for (uint32_t i = 0; i < L; ++i)
+      jobs[i] = ButterflyJob{inverse ? plans[i]->bf_inv : plans[i]->bf_fwd, offs[i], plans[i]->q,
+                             plans[i]->qinv, plans[i]->bf_ninv};
+    void* dj = nullptr;
+    cross_status st = cached_device_copy(ctx, jobs.data(), jobs.size() * sizeof(ButterflyJob), &dj);
+    if (st != CROSS_OK) return st;
+    hipError_t e;
+    {
+      ProfScope ps(ctx, "butterfly_ntt", s);
+      e = launch_butterfly((const ButterflyJob*)dj, (int)L, data, (uint64_t)L * N, (int)batch,
+                           (int)log_n, inverse, s);
+    }
+    if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("butterfly launch: ") + hipGetErrorString(e));
+    return CROSS_OK;
+  }
+  void* tmp = nullptr;
+  cross_status st = workspace(ctx, s, (size_t)batch * L * N * 4, &tmp);
+  if (st != CROSS_OK) return st;
+  return ntt_limbs(ctx, plans, offs, data, (uint64_t)L * N, (int)batch, inverse, (uint32_t*)tmp, s);
+}
+
+}  // namespace cross
+
+using namespace cross;
+
+extern "C" {
+
+cross_status cross_ctx_create(int hip_device, cross_ctx* out) {
+  if (!out) return CROSS_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+    (void)hipGetLastError();
+    return CROSS_EDEVICE;
+  }
+  cross_ctx c = new cross_ctx_s();
+  c->device = hip_device;
+  *out = c;
+  return CROSS_OK;
+}
+
+void cross_ctx_destroy(cross_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->plans) {
+    (void)hipFree(kv.second->block);
+    delete kv.second;
+  }
+  for (auto& kv : ctx->job_cache) (void)hipFree(kv.second);
+  for (auto& kv : ctx->const_cache) (void)hipFree(kv.second);
+  for (auto& kv : ctx->workspace) (void)hipFree(kv.second.ptr);
+  delete ctx;
+}
+
+const char* cross_last_error(cross_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+cross_status cross_root(uint32_t q, uint32_t log_n, uint32_t* psi_out) {
+  if (!psi_out || log_n < 1 || log_n > 26) return CROSS_EINVAL;
+  cross_status st = check_prime(nullptr, q, log_n);
+  if (st != CROSS_OK) return st;
+  *psi_out = root_2n(q, log_n);
+  return CROSS_OK;
+}
+
+cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r) {
+  if (!ctx) return CROSS_EINVAL;
+  if (log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4 || log_r > log_n)
+    return fail(ctx, CROSS_EINVAL, "split needs 4 <= log_r <= log_n - 4");
+  ctx->split[(int)log_n] = (int)log_r;
+  return CROSS_OK;
+}
+
+cross_status cross_ntt_forward(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                               uint32_t batch, uint32_t* data, void* stream) {
+  return ntt_common(ctx, log_n, primes, L, batch, data, stream, false, false);
+}
+cross_status cross_ntt_inverse(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                               uint32_t batch, uint32_t* data, void* stream) {
+  return ntt_common(ctx, log_n, primes, L, batch, data, stream, true, false);
+}
+cross_status cross_ntt_forward_butterfly(cross_ctx ctx, uint32_t log_n, const uint32_t* primes,
+                                         uint32_t L, uint32_t batch, uint32_t* data, void* stream) {
+  return ntt_common(ctx, log_n, primes, L, batch, data, stream, false, true);
+}
+cross_status cross_ntt_inverse_butterfly(cross_ctx ctx, uint32_t log_n, const uint32_t* primes,
+                                         uint32_t L, uint32_t batch, uint32_t* data, void* stream) {
+  return ntt_common(ctx, log_n, primes, L, batch, data, stream, true, true);
+}
+
+cross_status cross_profile_enable(cross_ctx ctx, int enable) {
+  if (!ctx) return CROSS_EINVAL;
+  ctx->prof = enable != 0;
+  return CROSS_OK;
+}
+
+cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len) {
+  if (!ctx || !buf || len == 0) return CROSS_EINVAL;
+  std::map<std::string, std::pair<long, double>> agg;
+  for (auto& r : ctx->prof_recs) {
+    float ms = 0.f;
+    (void)hipEventSynchronize(r.b);
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& x = agg[r.name];
+      x.first += 1;
+      x.second += ms;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  ctx->prof_recs.clear();
+  std::string out;
+  for (auto& kv : agg) {
+    char line[256];
+    snprintf(line, sizeof line, "%s %ld %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+    out += line;
+  }
+  size_t n = out.size() < len - 1 ? out.size() : (size_t)(len - 1);
+  std::memcpy(buf, out.data(), n);
+  buf[n] = 0;
+  return CROSS_OK;
+}
+
+cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,
+                               void* out, uint64_t* bytes) {
+  if (!bytes || which > 5 || log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4)
+    return CROSS_EINVAL;
+  cross_status st = check_prime(nullptr, q, log_n);
+  if (st != CROSS_OK) return st;
+  NttTables t;
+  build_ntt_tables(q, log_n, log_r, t);
+  const void* src = nullptr;
+  uint64_t n = 0;
+  switch (which) {
+    case 0: src = t.fwd_left.data(); n = t.fwd_left.size(); break;
+    case 1: src = t.fwd_right.data(); n = t.fwd_right.size(); break;
+    case 2: src = t.inv_left.data(); n = t.inv_left.size(); break;
+    case 3: src = t.inv_right.data(); n = t.inv_right.size(); break;
+    case 4: src = t.fwd_tw.data(); n = t.fwd_tw.size() * 4; break;
+    default: src = t.inv_tw.data(); n = t.inv_tw.size() * 4; break;
+  }
+  if (!out) {
+    *bytes = n;
+    return CROSS_OK;
+  }
+  if (*bytes < n) return CROSS_EINVAL;
+  std::memcpy(out, src, n);
+  *bytes = n;
+  return CROSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+// Library context: device tables, job-list cache and per-stream workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cross.h"
+#include "kernels.h"
+
+namespace cross {
+
+// Device-resident tables of one (q, N, R) NTT plan.
+struct Plan {
+  uint32_t q = 0, qinv = 0, psi = 0;
+  int log_n = 0, log_r = 0;
+  int8_t *fwd_left = nullptr, *fwd_right = nullptr, *inv_left = nullptr, *inv_right = nullptr;
+  uint32_t *fwd_tw = nullptr, *inv_tw = nullptr, *bf_fwd = nullptr, *bf_inv = nullptr;
+  uint32_t bf_ninv = 0;
+  void* block = nullptr;
+};
+
+// A device buffer that only grows; freed when the context goes away.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t size = 0;
+};
+
+struct Status {
+  cross_status code;
+  std::string msg;
+};
+
+// Event bracket around one kernel launch (no-op unless profiling is enabled).
+struct ProfScope {
+  cross_ctx ctx;
+  hipStream_t s;
+  int idx = -1;
+  ProfScope(cross_ctx c, const char* name, hipStream_t st);
+  ~ProfScope();
+};
+
+}  // namespace cross
+
+struct cross_ctx_s {
+  int device = 0;
+  std::string err;
+  std::map<std::tuple<uint32_t, int, int>, cross::Plan*> plans;
+  std::map<std::string, void*> job_cache;     // serialised job list -> device copy
+  std::map<hipStream_t, cross::DevBuf> workspace;
+  std::map<int, int> split;                   // log_n -> log_r override
+  std::map<std::string, void*> const_cache;   // other device-resident constants
+  bool prof = false;
+  struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_recs;
+};
+
+namespace cross {
+
+cross_status fail(cross_ctx ctx, cross_status code, const std::string& msg);
+cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n);
+cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out);
+int split_of(cross_ctx ctx, int log_n);
+// Device copy of a POD array, cached by content.
+cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, void** out);
+// Per-stream scratch of at least `bytes`.
+cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out);
+
+// Run forward / inverse NTTs for a list of limbs, each given by (plan, element
+// offset) inside `data` with `npoly` polynomials at `stride` elements apart.
+// `tmp` must hold (max offset + npoly*stride) elements laid out like data.
+cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
+                       const std::vector<uint64_t>& offs, uint32_t* data, uint64_t stride,
+                       int npoly, bool inverse, uint32_t* tmp, hipStream_t s);
+
+}  // namespace cross

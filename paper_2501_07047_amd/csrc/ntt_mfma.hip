@@ -1,0 +1,265 @@
+// BAT int8-MFMA steps of the layout-invariant 3-step negacyclic NTT
+// (arXiv 2501.07047, Sec. BAT "Accelerating core HE kernels", Alg. bat_deployment;
+// Sec. MAT "Applying MAT to 4-step NTT").
+//
+// One launch runs one step for many limbs.  Each step is a modular matrix
+// product with a pre-known twiddle matrix, carried out as an exact int8 GEMM:
+// residues (< 2^28) are split into four 7-bit chunks (RuntimeCompileRight), the
+// pre-known matrix was expanded on the host into 4x4 chunk blocks
+// (OfflineCompileLeft / DirectScalarBAT, with the Montgomery factor 2^32 folded
+// in), so every int32 partial sum is exact.  The epilogue merges the four
+// chunk partial sums of one output (ChunkMerge), reduces with Montgomery REDC
+// (Alg. montgomery_reduction, result in [0, 2q)), optionally multiplies by the
+// step-2 twiddle, and finishes with one conditional subtraction (the final
+// reduction the paper assigns to Barrett; one subtraction suffices here).
+//
+// GEMM view (M x K times K x Ncols):
+//   A[m][k]: pre-known, m = 4*u + i (output u, output chunk i), k = 4*x + j (input x, chunk j)
+//   B[k][n]: chunk j of data element x of column n;  n = poly * V + v
+// MFMA v_mfma_i32_16x16x64_i8: lane l holds rows 4*(l/16) .. +3 of column l%16 of
+// its 16x16 output block, i.e. all four chunk rows of one output: the merge is
+// entirely in-register.
+//
+// Rows of the output block order chunks fastest (m = 4u + i) for exactly that reason.
+#include "kernels.h"
+
+namespace cross {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BK = 64;            // K per MFMA step
+constexpr int LDS_ROW = BK + 16;  // padded LDS row (bytes): 16 lanes x 16 B hit 64 distinct banks
+
+__device__ __forceinline__ uint32_t pack_chunks(uint32_t x) {
+  // four 7-bit chunks of x (< 2^28) in the four bytes of one word
+  return (x & 0x7fu) | ((x << 1) & 0x7f00u) | ((x << 2) & 0x7f0000u) | ((x << 3) & 0x7f000000u);
+}
+
+__device__ __forceinline__ uint32_t redc(uint64_t z, uint32_t q, uint32_t qinv) {
+  // z < q * 2^32  ->  z * 2^-32 mod q in (0, 2q)
+  uint32_t t = (uint32_t)z * qinv;
+  uint32_t u = __umulhi(t, q);
+  return (uint32_t)(z >> 32) + q - u;
+}
+
+template <int WM, int WN, int MB, int NB, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__global__ void __launch_bounds__(WM * WN * 64)
+bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
+  constexpr int NT = WM * WN * 64;
+  constexpr int BM = WM * MB * 16;
+  constexpr int BN = WN * NB * 16;
+  __shared__ __attribute__((aligned(16))) int8_t lds_a[BM * LDS_ROW];
+  __shared__ __attribute__((aligned(16))) int8_t lds_b[BN * LDS_ROW];
+
+  const int R = 1 << g.log_r, C = 1 << g.log_c;
+  const int U = RIGHT ? C : R;          // outputs per column (and inputs per column)
+  const int V = RIGHT ? R : C;          // columns per polynomial
+  const int M = 4 * U, K = 4 * U;
+  const int ncols = g.npoly * V;
+
+  // XCD-aware tile order: consecutive logical tiles land on the same XCD so a
+  // job's table and columns stay in one L2.
+  const int total = g.njobs * tiles_m * tiles_n;
+  int bid = blockIdx.x;
+  int logical = bid;
+  if ((total & 7) == 0) logical = (bid & 7) * (total >> 3) + (bid >> 3);
+  const int per_job = tiles_m * tiles_n;
+  const int job_id = logical / per_job;
+  const int rem = logical - job_id * per_job;
+  const int tn = rem / tiles_m;          // m fastest: tiles sharing columns run together
+  const int tm = rem - tn * tiles_m;
+  const GemmJob job = g.jobs[job_id];
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+
+  const uint32_t* src = g.src + job.src_off;
+  const int8_t* tab = job.table;
+
+  v4i acc[MB][NB];
+#pragma unroll
+  for (int a = 0; a < MB; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+
+  // ---- global -> register staging --------------------------------------
+  constexpr int A_VEC = BM * BK / 16 / NT;     // 16-byte table pieces per thread
+  static_assert(A_VEC >= 1, "tile too small");
+  v4i ra[A_VEC];
+  // B staging: each thread owns BN*16 words / NT words (16 = inputs per K step)
+  constexpr int B_WORDS = BN * 16 / NT;
+  static_assert(B_WORDS >= 1 && (B_WORDS % 4) == 0, "B staging");
+  uint32_t rb[B_WORDS];
+
+  auto load_a = [&](int ks) {
+    const int8_t* base = tab + (size_t)ks * ((size_t)M * BK) + (size_t)m0 * BK;
+#pragma unroll
+    for (int i = 0; i < A_VEC; ++i) {
+      int piece = tid + i * NT;                 // contiguous 16 B pieces of the tile
+      ra[i] = *reinterpret_cast<const v4i*>(base + piece * 16);
+    }
+  };
+
+  // B element (input x, column n) lives at src + poly * stride + x * sx + v * sv
+  auto load_b = [&](int ks) {
+    const int x0 = ks * 16;
+    if (!RIGHT) {
+      // inputs run down rows (stride C); columns are contiguous: thread = column
+      constexpr int TPC = NT / BN;              // threads per column
+      const int n = n0 + (tid % BN);
+      const int xs = (tid / BN) * B_WORDS;      // first input row of this thread
+      const bool ok = n < ncols;
+      const int poly = ok ? n / V : 0, v = ok ? n - poly * V : 0;
+      const uint32_t* p = src + (size_t)poly * g.src_stride + (size_t)(x0 + xs) * C + v;
+#pragma unroll
+      for (int w = 0; w < B_WORDS; ++w) rb[w] = ok ? p[(size_t)w * C] : 0u;
+      (void)TPC;
+    } else {
+      // inputs run along a row (contiguous); thread = (column, run of B_WORDS inputs)
+      constexpr int TPC = 16 / B_WORDS;
+      const int n = n0 + tid / TPC;
+      const int xs = (tid % TPC) * B_WORDS;
+      const bool ok = n < ncols;
+      const int poly = ok ? n / V : 0, v = ok ? n - poly * V : 0;
+      const uint32_t* p = src + (size_t)poly * g.src_stride + (size_t)v * C + x0 + xs;
+#pragma unroll
+      for (int w = 0; w < B_WORDS; w += 4) {
+        if (ok) {
+          v4i t = *reinterpret_cast<const v4i*>(p + w);
+          rb[w] = t.x; rb[w + 1] = t.y; rb[w + 2] = t.z; rb[w + 3] = t.w;
+        } else {
+          rb[w] = rb[w + 1] = rb[w + 2] = rb[w + 3] = 0u;
+        }
+      }
+    }
+  };
+
+  auto store_lds = [&]() {
+#pragma unroll
+    for (int i = 0; i < A_VEC; ++i) {
+      int piece = tid + i * NT;
+      int row = piece >> 2, kq = piece & 3;
+      *reinterpret_cast<v4i*>(lds_a + row * LDS_ROW + kq * 16) = ra[i];
+    }
+    int n, xs;
+    if (!RIGHT) {
+      n = tid % BN;
+      xs = (tid / BN) * B_WORDS;
+    } else {
+      constexpr int TPC = 16 / B_WORDS;
+      n = tid / TPC;
+      xs = (tid % TPC) * B_WORDS;
+    }
+#pragma unroll
+    for (int w = 0; w < B_WORDS; w += 4) {
+      v4i t;
+      t.x = IN_PACKED ? rb[w] : pack_chunks(rb[w]);
+      t.y = IN_PACKED ? rb[w + 1] : pack_chunks(rb[w + 1]);
+      t.z = IN_PACKED ? rb[w + 2] : pack_chunks(rb[w + 2]);
+      t.w = IN_PACKED ? rb[w + 3] : pack_chunks(rb[w + 3]);
+      *reinterpret_cast<v4i*>(lds_b + n * LDS_ROW + (xs + w) * 4) = t;
+    }
+  };
+
+  const int nk = K / BK;
+  load_a(0);
+  load_b(0);
+  for (int ks = 0; ks < nk; ++ks) {
+    __syncthreads();
+    store_lds();
+    __syncthreads();
+    if (ks + 1 < nk) {
+      load_a(ks + 1);
+      load_b(ks + 1);
+    }
+    const int koff = (lane >> 4) * 16;
+    v4i fa[MB], fb[NB];
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+      fa[a] = *reinterpret_cast<const v4i*>(lds_a + (wm * MB * 16 + a * 16 + (lane & 15)) * LDS_ROW + koff);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      fb[b] = *reinterpret_cast<const v4i*>(lds_b + (wn * NB * 16 + b * 16 + (lane & 15)) * LDS_ROW + koff);
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+  }
+
+  // ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ----------
+  const uint32_t q = job.q, qinv = job.qinv;
+  uint32_t* dst = g.dst + job.dst_off;
+#pragma unroll
+  for (int a = 0; a < MB; ++a) {
+    const int u = (m0 + wm * MB * 16 + a * 16) / 4 + (lane >> 4);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int n = n0 + wn * NB * 16 + b * 16 + (lane & 15);
+      if (n >= ncols) continue;
+      const int poly = n / V, v = n - poly * V;
+      v4i s = acc[a][b];
+      uint64_t z = (uint64_t)(uint32_t)s.x + ((uint64_t)(uint32_t)s.y << 7) +
+                   ((uint64_t)(uint32_t)s.z << 14) + ((uint64_t)(uint32_t)s.w << 21);
+      uint32_t r = redc(z, q, qinv);
+      if (TW) {
+        uint32_t w = job.tw[(size_t)u * V + v];
+        r = redc((uint64_t)r * w, q, qinv);
+      }
+      if (r >= q) r -= q;
+      if (OUT_PACKED) r = pack_chunks(r);
+      size_t off = RIGHT ? (size_t)v * C + u : (size_t)u * C + v;
+      dst[(size_t)poly * g.dst_stride + off] = r;
+    }
+  }
+  (void)M;
+}
+
+template <int WM, int WN, int MB, int NB, bool RIGHT, bool INP, bool OUTP, bool TW>
+hipError_t launch_cfg(const GemmLaunch& g, hipStream_t s) {
+  constexpr int BM = WM * MB * 16, BN = WN * NB * 16;
+  const int U = RIGHT ? (1 << g.log_c) : (1 << g.log_r);
+  const int V = RIGHT ? (1 << g.log_r) : (1 << g.log_c);
+  const int M = 4 * U;
+  if (M % BM) return hipErrorInvalidValue;
+  const int tiles_m = M / BM;
+  const int ncols = g.npoly * V;
+  const int tiles_n = (ncols + BN - 1) / BN;
+  const int grid = g.njobs * tiles_m * tiles_n;
+  hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, RIGHT, INP, OUTP, TW>), dim3(grid),
+                     dim3(WM * WN * 64), 0, s, g, tiles_m, tiles_n);
+  return hipGetLastError();
+}
+
+template <int WM, int WN, int MB, int NB>
+hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
+  // forward: LEFT(plain in, packed out, twiddle) then RIGHT(packed in, plain out)
+  // inverse: RIGHT(plain in, packed out, twiddle) then LEFT(packed in, plain out)
+  const bool right = g.kind == kRight;
+  if (!right && !g.in_packed && g.out_packed && g.twiddle)
+    return launch_cfg<WM, WN, MB, NB, false, false, true, true>(g, s);
+  if (right && g.in_packed && !g.out_packed && !g.twiddle)
+    return launch_cfg<WM, WN, MB, NB, true, true, false, false>(g, s);
+  if (right && !g.in_packed && g.out_packed && g.twiddle)
+    return launch_cfg<WM, WN, MB, NB, true, false, true, true>(g, s);
+  if (!right && g.in_packed && !g.out_packed && !g.twiddle)
+    return launch_cfg<WM, WN, MB, NB, false, true, false, false>(g, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s) {
+  const int U = (g.kind == kRight) ? (1 << g.log_c) : (1 << g.log_r);
+  const int M = 4 * U;
+  if (M >= 256) return dispatch_flags<2, 2, 8, 4>(g, s);     // 256 x 128 tile
+  if (M >= 128) return dispatch_flags<2, 2, 4, 2>(g, s);     // 128 x 64 tile
+  if (M >= 64) return dispatch_flags<2, 2, 2, 2>(g, s);      // 64 x 64 tile
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cross

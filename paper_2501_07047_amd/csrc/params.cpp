@@ -1,0 +1,182 @@
+// Host precompute: primality, roots and the MAT-permuted, BAT-expanded twiddle
+// tables of the layout-invariant 3-step negacyclic NTT (arXiv 2501.07047,
+// Sec. MAT "Bit-reverse shuffling elimination" and Alg. bat_deployment,
+// procedures DirectScalarBAT / OfflineCompileLeft).
+#include "params.h"
+
+#include <stdexcept>
+
+namespace cross {
+
+uint32_t powmod(uint64_t b, uint64_t e, uint32_t q) {
+  uint64_t r = 1 % q;
+  b %= q;
+  while (e) {
+    if (e & 1) r = r * b % q;
+    b = b * b % q;
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+
+// Deterministic Miller-Rabin for 32-bit n (bases 2, 7, 61).
+bool is_prime_u32(uint32_t n) {
+  if (n < 2) return false;
+  static const uint32_t small[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 61};
+  for (uint32_t p : small) {
+    if (n % p == 0) return n == p;
+  }
+  uint32_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  for (uint32_t a : {2u, 7u, 61u}) {
+    uint64_t x = powmod(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s; ++r) {
+      x = x * x % n;
+      if (x == n - 1) {
+        comp = false;
+        break;
+      }
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+uint32_t smallest_generator(uint32_t q) {
+  std::vector<uint32_t> fs;
+  uint32_t m = q - 1;
+  for (uint32_t p = 2; (uint64_t)p * p <= m; ++p) {
+    if (m % p == 0) {
+      fs.push_back(p);
+      while (m % p == 0) m /= p;
+    }
+  }
+  if (m > 1) fs.push_back(m);
+  for (uint32_t g = 2;; ++g) {
+    bool ok = true;
+    for (uint32_t f : fs) {
+      if (powmod(g, (q - 1) / f, q) == 1) {
+        ok = false;
+        break;
+      }
+    }
+    if (ok) return g;
+  }
+}
+
+uint32_t root_2n(uint32_t q, uint32_t log_n) {
+  uint64_t two_n = 2ull << log_n;
+  if ((q - 1) % two_n) throw std::invalid_argument("q != 1 mod 2N");
+  return powmod(smallest_generator(q), (q - 1) / two_n, q);
+}
+
+uint32_t inv_mod_2_32(uint32_t q) {
+  uint32_t x = q;  // Newton iteration: correct to 3 bits, doubles each step
+  for (int i = 0; i < 5; ++i) x *= 2u - q * x;
+  return x;
+}
+
+uint32_t bitrev(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) {
+    r = (r << 1) | (x & 1);
+    x >>= 1;
+  }
+  return r;
+}
+
+void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
+                std::vector<int8_t>& out) {
+  const int M = kChunks * n_out, K = kChunks * n_in;
+  if (n_in <= 0 || n_out <= 0 || K % kTileK != 0 || (size_t)T.size() != (size_t)n_in * n_out)
+    throw std::invalid_argument("bat_expand: table shape does not tile");
+  out.assign((size_t)M * K, 0);
+  const uint64_t r32 = ((uint64_t)1 << 32) % q;
+  for (int in = 0; in < n_in; ++in) {
+    for (int o = 0; o < n_out; ++o) {
+      uint64_t t = (uint64_t)T[(size_t)in * n_out + o] * r32 % q;  // Montgomery form
+      for (int j = 0; j < kChunks; ++j) {
+        uint64_t v = (t << (kChunkBits * j)) % q;                 // a * 2^(bp j) mod q
+        for (int i = 0; i < kChunks; ++i) {
+          int m = o * kChunks + i, k = in * kChunks + j;
+          int8_t c = (int8_t)((v >> (kChunkBits * i)) & ((1u << kChunkBits) - 1));
+          out[(size_t)(k / kTileK) * ((size_t)M * kTileK) + (size_t)m * kTileK + (k % kTileK)] = c;
+        }
+      }
+    }
+  }
+}
+
+void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, bool with_bat) {
+  const uint32_t N = 1u << log_n, R = 1u << log_r, C = N / R, N2 = 2 * N;
+  const int log_c = (int)(log_n - log_r);
+  const uint32_t psi = root_2n(q, log_n);
+  std::vector<uint32_t> pw(N2);
+  uint64_t x = 1;
+  for (uint32_t e = 0; e < N2; ++e) {
+    pw[e] = (uint32_t)x;
+    x = x * psi % q;
+  }
+  auto P = [&](int64_t e) { return pw[(uint32_t)(((e % (int64_t)N2) + N2) % N2)]; };
+  const uint64_t r32 = ((uint64_t)1 << 32) % q;
+  const uint64_t ninv = powmod(N, q - 2, q);
+
+  // Radix-2 butterfly baseline: psi^brv_N(i) and psi^-brv_N(i), Montgomery form.
+  t.bf_fwd.resize(N);
+  t.bf_inv.resize(N);
+  for (uint32_t i = 0; i < N; ++i) {
+    uint32_t b = bitrev(i, (int)log_n);
+    t.bf_fwd[i] = (uint32_t)(P(b) * r32 % q);
+    t.bf_inv[i] = (uint32_t)(P(-(int64_t)b) * r32 % q);
+  }
+  t.bf_ninv = (uint32_t)(ninv * r32 % q);
+  if (!with_bat) return;
+
+  // Step-1 matrix TF1[k][r] = psi^(C r (2 brv_R(k)+1)); as a left-known product
+  // Y[k][c] = sum_r TF1[k][r] A[r][c], i.e. "in" = r, "out" = k.
+  std::vector<uint32_t> m1((size_t)R * R), im1((size_t)R * R);
+  for (uint32_t k = 0; k < R; ++k) {
+    int64_t odd = 2 * (int64_t)bitrev(k, (int)log_r) + 1;
+    for (uint32_t r = 0; r < R; ++r) {
+      m1[(size_t)r * R + k] = P((int64_t)C * r * odd);
+      // inverse step 2 (left-known): a[r][c] = sum_k ITF1[r][k] Y[k][c], "in" = k, "out" = r
+      im1[(size_t)k * R + r] = (uint32_t)((uint64_t)P(-(int64_t)C * r * odd) * ninv % q);
+    }
+  }
+  bat_expand(m1, R, R, q, t.fwd_left);
+  bat_expand(im1, R, R, q, t.inv_left);
+
+  // Step-3 matrix TF3[c][c'] = psi^(2R c brv_C(c')): out[k][c'] = sum_c Y[k][c] TF3[c][c'],
+  // "in" = c, "out" = c'.  Inverse step 1: Y[k][c] = sum_c' Ahat[k][c'] ITF3[c'][c].
+  std::vector<uint32_t> m3((size_t)C * C), im3((size_t)C * C);
+  for (uint32_t c = 0; c < C; ++c) {
+    for (uint32_t cp = 0; cp < C; ++cp) {
+      int64_t e = 2 * (int64_t)R * c * bitrev(cp, log_c);
+      m3[(size_t)c * C + cp] = P(e);
+      im3[(size_t)cp * C + c] = P(-e);
+    }
+  }
+  bat_expand(m3, C, C, q, t.fwd_right);
+  bat_expand(im3, C, C, q, t.inv_right);
+
+  // Step-2 twiddles T2[k][c] = psi^(c (2 brv_R(k)+1)), stored [k][c] (left kernel epilogue);
+  // inverse twiddles IT2[k][c] = psi^(-c (2 brv_R(k)+1)), stored transposed [c][k]
+  // (right kernel epilogue, whose lanes run along k).
+  t.fwd_tw.resize((size_t)R * C);
+  t.inv_tw.resize((size_t)R * C);
+  for (uint32_t k = 0; k < R; ++k) {
+    int64_t odd = 2 * (int64_t)bitrev(k, (int)log_r) + 1;
+    for (uint32_t c = 0; c < C; ++c) {
+      t.fwd_tw[(size_t)k * C + c] = (uint32_t)(P((int64_t)c * odd) * r32 % q);
+      t.inv_tw[(size_t)c * R + k] = (uint32_t)(P(-(int64_t)c * odd) * r32 % q);
+    }
+  }
+}
+
+}  // namespace cross

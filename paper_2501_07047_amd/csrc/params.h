@@ -1,0 +1,42 @@
+// Host-side number theory and table construction for the BAT/MAT NTT.
+//
+// Everything here runs once per (prime, N, R) on the host ("offline compile"
+// of the pre-known operands, Sec. BAT and Sec. MAT of arXiv 2501.07047) and is
+// uploaded to the device once.  Pure C++; no device code.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace cross {
+
+constexpr int kChunkBits = 7;   // bp: 7-bit chunks fit non-negative int8 MFMA operands
+constexpr int kChunks = 4;      // Kc: four 7-bit chunks hold a residue below 2^28
+constexpr int kTileK = 64;      // K extent of one table tile (one 16x16x64 MFMA step)
+
+uint32_t powmod(uint64_t b, uint64_t e, uint32_t q);
+bool is_prime_u32(uint32_t n);
+uint32_t smallest_generator(uint32_t q);
+// Canonical primitive 2N-th root: g^((q-1)/2N) for the smallest generator g.
+uint32_t root_2n(uint32_t q, uint32_t log_n);
+uint32_t inv_mod_2_32(uint32_t q);       // q^-1 mod 2^32 (q odd)
+uint32_t bitrev(uint32_t x, int bits);
+
+// BAT-expanded table of a pre-known residue matrix T (rows = "in", cols = "out"):
+// dense int8 matrix D[m = out*4 + i][k = in*4 + j] = chunk_i((T[in][out] * 2^32 * 2^(7j)) mod q),
+// stored tile-major: offset(m, k) = (k / 64) * (M * 64) + m * 64 + (k % 64), M = 4 * n_out.
+// The 2^32 is the Montgomery factor removed by the epilogue's REDC.
+// Throws std::invalid_argument unless 4 * n_in is a multiple of 64.
+void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
+                std::vector<int8_t>& out);
+
+struct NttTables {
+  // forward: step 1 (left-known, rows), step 2 twiddle, step 3 (right-known, cols)
+  std::vector<int8_t> fwd_left, fwd_right, inv_left, inv_right;
+  std::vector<uint32_t> fwd_tw, inv_tw;      // Montgomery form (x * 2^32 mod q)
+  std::vector<uint32_t> bf_fwd, bf_inv;      // butterfly twiddles, Montgomery form
+  uint32_t bf_ninv;                          // N^-1 * 2^32 mod q (butterfly inverse scale)
+};
+// with_bat = false builds only the butterfly twiddles (sizes below the MFMA minimum).
+void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, bool with_bat = true);
+
+}  // namespace cross

@@ -1,0 +1,122 @@
+"""GPU parity of the NTT entry points against the oracle (bit-exact)."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle.ntt import ntt_def, intt_def, ntt_ct, intt_gs, horner_eval, bitrev
+from oracle.primes import psi as psi_of
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_ntt(x, primes, inverse=False):
+    n = x.shape[-1]
+    out = np.empty(x.shape, dtype=np.uint64)
+    f = intt_gs if inverse else ntt_ct
+    for i, q in enumerate(primes):
+        out[:, i] = f(x[:, i].astype(np.uint64), q, psi_of(q, n))
+    return out
+
+
+def test_config1_n4096_against_definition():
+    from paper_2501_07047_amd import binding as B
+    primes, x = synthetic.ntt_batch(0, 12, 1, 1)
+    q = primes[0]
+    psi = psi_of(q, 4096)
+    d = to_dev(x)
+    B.ntt_forward(d, primes)
+    got = to_host(d)[0, 0]
+    ref = ntt_def(x[0, 0], q, psi)
+    assert np.array_equal(got, ref)
+    B.ntt_inverse(d, primes)
+    assert np.array_equal(to_host(d), x)
+    dd = to_dev(ref[None, None])
+    B.ntt_inverse(dd, primes)
+    assert np.array_equal(to_host(dd)[0, 0], intt_def(ref, q, psi))
+
+
+@pytest.mark.parametrize("log_n,L,batch", [(8, 1, 1), (9, 2, 3), (10, 3, 5), (11, 2, 2),
+                                           (12, 4, 3), (13, 2, 2), (14, 3, 1), (15, 2, 3),
+                                           (16, 2, 1)])
+def test_sizes_and_ragged_batches(log_n, L, batch):
+    from paper_2501_07047_amd import binding as B
+    primes, x = synthetic.ntt_batch(log_n * 100 + L, log_n, L, batch)
+    x[0, 0, :4] = [0, primes[0] - 1, 1, primes[0] - 2]
+    ref = _oracle_ntt(x, primes)
+    d = to_dev(x)
+    B.ntt_forward(d, primes)
+    assert np.array_equal(to_host(d), ref)
+    B.ntt_inverse(d, primes)
+    assert np.array_equal(to_host(d), x)
+
+
+@pytest.mark.parametrize("log_n", [4, 5, 6, 7, 8, 12])
+def test_butterfly_matches_oracle(log_n):
+    from paper_2501_07047_amd import binding as B
+    primes, x = synthetic.ntt_batch(log_n, log_n, 3, 2)
+    ref = _oracle_ntt(x, primes)
+    d = to_dev(x)
+    B.ntt_forward_butterfly(d, primes)
+    assert np.array_equal(to_host(d), ref)
+    B.ntt_inverse_butterfly(d, primes)
+    assert np.array_equal(to_host(d), x)
+    # small sizes route cross_ntt_forward to the butterfly kernels as well
+    d = to_dev(x)
+    B.ntt_forward(d, primes)
+    assert np.array_equal(to_host(d), ref)
+
+
+@pytest.mark.parametrize("log_n,log_r", [(12, 4), (12, 8), (14, 5), (16, 7), (16, 9)])
+def test_other_splits(log_n, log_r):
+    from paper_2501_07047_amd import binding as B
+    B.set_ntt_split(log_n, log_r)
+    try:
+        primes, x = synthetic.ntt_batch(log_r, log_n, 2, 2)
+        ref = _oracle_ntt(x, primes)
+        d = to_dev(x)
+        B.ntt_forward(d, primes)
+        assert np.array_equal(to_host(d), ref)
+        B.ntt_inverse(d, primes)
+        assert np.array_equal(to_host(d), x)
+    finally:
+        B.set_ntt_split(log_n, log_n // 2)
+
+
+def test_config2_full_size_spot_checks():
+    # N = 2^16 as 256 x 256, L = 24, 8 ciphertexts x 2 polys, in the launch shape the bench times
+    from paper_2501_07047_amd import binding as B
+    primes, x = synthetic.ntt_batch(2, 16, 24, 16)
+    d = to_dev(x)
+    B.ntt_forward(d, primes)
+    got = to_host(d)
+    bf = to_dev(x)
+    B.ntt_forward_butterfly(bf, primes)
+    assert np.array_equal(to_host(bf), got)            # two independent GPU paths agree
+    g = np.random.Generator(np.random.PCG64(123))
+    n = 1 << 16
+    for limb in (0, 7, 23):
+        q = primes[limb]
+        psi = psi_of(q, n)
+        for b in (0, 15):
+            pos = g.integers(0, n, 16)
+            xs = [pow(psi, 2 * bitrev(int(p), 16) + 1, q) for p in pos]
+            assert np.array_equal(got[b, limb, pos], horner_eval(x[b, limb], q, xs))
+    full = ntt_ct(x[:, 11].astype(np.uint64), primes[11], psi_of(primes[11], n))
+    assert np.array_equal(got[:, 11], full)
+    B.ntt_inverse(d, primes)
+    assert np.array_equal(to_host(d), x)
+
+
+def test_argument_errors():
+    import torch
+    from paper_2501_07047_amd import binding as B
+    d = torch.zeros((1, 1, 4096), dtype=torch.int32, device="cuda")
+    with pytest.raises(B.CrossError) as e:
+        B.ntt_forward(d, [268042241 + 2])
+    assert e.value.code in (-2, -3)
+    with pytest.raises(B.CrossError) as e:
+        B.ntt_forward(d, [7681])
+    assert e.value.code == -3
+    with pytest.raises(ValueError):
+        B.ntt_forward(torch.zeros((1, 1, 1000), dtype=torch.int32, device="cuda"), [268042241])

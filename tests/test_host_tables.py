@@ -1,0 +1,83 @@
+"""CPU emulation of the BAT int8 GEMM steps with the library's own offline tables.
+
+The tables come from libcross (host-only entry point cross_host_tables); the
+GEMM, ChunkMerge and Montgomery steps are emulated here in numpy int64 exactly
+as the kernels define them, and the result is compared with the oracle's NTT.
+This checks the table layout, the BAT expansion and the 3-step reading
+before any kernel runs.
+"""
+import numpy as np
+import pytest
+
+from oracle.ntt import ntt_ct, intt_gs
+from oracle.primes import prime_chain, psi as psi_of
+
+
+def _dense(tab, M, K):
+    t = tab.astype(np.int64).reshape(K // 64, M, 64)
+    return t.transpose(1, 0, 2).reshape(M, K)
+
+
+def _chunks_rows(X):
+    # X: [inputs][cols] -> [(input, j)][cols]
+    X = X.astype(np.int64)
+    out = np.empty((X.shape[0] * 4, X.shape[1]), dtype=np.int64)
+    for j in range(4):
+        out[j::4] = (X >> (7 * j)) & 0x7F
+    return out
+
+
+def _merge_reduce(P, q):
+    U = P.shape[0] // 4
+    Z = sum(P[i::4].astype(object) << (7 * i) for i in range(4))
+    assert int(np.max(P)) < (1 << 31) and int(np.min(P)) >= 0
+    rinv = pow(1 << 32, -1, q)
+    return np.array((Z * rinv) % q, dtype=np.uint64).reshape(U, -1)
+
+
+def _emulate(X, q, log_n, log_r, inverse):
+    from paper_2501_07047_amd import binding
+    R, C = 1 << log_r, 1 << (log_n - log_r)
+    rinv = pow(1 << 32, -1, q)
+    if not inverse:
+        t1 = _dense(binding.host_tables(q, log_n, log_r, 0), 4 * R, 4 * R)
+        t3 = _dense(binding.host_tables(q, log_n, log_r, 1), 4 * C, 4 * C)
+        tw = binding.host_tables(q, log_n, log_r, 4).reshape(R, C).astype(object)
+        A = X.reshape(R, C)
+        Y = _merge_reduce(t1 @ _chunks_rows(A), q)                 # [k][c]
+        Y = np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
+        out = _merge_reduce(t3 @ _chunks_rows(Y.T), q)            # [c'][k]
+        return out.T.reshape(-1)
+    t3 = _dense(binding.host_tables(q, log_n, log_r, 3), 4 * C, 4 * C)
+    t1 = _dense(binding.host_tables(q, log_n, log_r, 2), 4 * R, 4 * R)
+    tw = binding.host_tables(q, log_n, log_r, 5).reshape(C, R).astype(object)
+    A = X.reshape(R, C)
+    Y = _merge_reduce(t3 @ _chunks_rows(A.T), q)                   # [c][k]
+    Y = np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
+    out = _merge_reduce(t1 @ _chunks_rows(Y.T), q)                # [r][c]
+    return out.reshape(-1)
+
+
+@pytest.mark.parametrize("log_n,log_r", [(8, 4), (10, 5), (10, 4), (10, 6), (12, 6)])
+def test_emulated_bat_ntt_matches_oracle(log_n, log_r):
+    n = 1 << log_n
+    for q in prime_chain(2):
+        psi = psi_of(q, n)
+        g = np.random.Generator(np.random.PCG64(log_n * 7 + log_r))
+        a = g.integers(0, q, n).astype(np.uint64)
+        a[0] = q - 1
+        ref = ntt_ct(a, q, psi)
+        assert np.array_equal(_emulate(a, q, log_n, log_r, False), ref)
+        assert np.array_equal(_emulate(ref, q, log_n, log_r, True), a)
+        assert np.array_equal(intt_gs(ref, q, psi), a)
+
+
+def test_table_entries_are_7bit_chunks():
+    from paper_2501_07047_amd import binding
+    q = prime_chain(1)[0]
+    for which in range(4):
+        t = binding.host_tables(q, 12, 6, which)
+        assert t.min() >= 0 and t.max() <= 127
+    for which in (4, 5):
+        t = binding.host_tables(q, 12, 6, which)
+        assert int(t.max()) < q
