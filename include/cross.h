@@ -95,6 +95,82 @@ cross_status cross_ntt_inverse_butterfly(cross_ctx ctx, uint32_t log_n, const ui
                                          uint32_t L, uint32_t batch, uint32_t* data, void* stream);
 
 /*
+ * Negacyclic polynomial product (config-1 check of the convolution theorem):
+ * out = INTT(NTT(a) * NTT(b)) limb-wise, i.e. a*b in Z_q[x]/(x^N + 1).
+ * a, b, out: device [batch][L][N] coefficient form (a and b are read before out is
+ * written, so out may alias either).  Uses 2*batch*L*N*4 bytes of workspace.
+ */
+cross_status cross_poly_mul(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                            uint32_t batch, const uint32_t* a, const uint32_t* b, uint32_t* out,
+                            void* stream);
+
+/*
+ * Fast basis conversion (App. "Basis Conversion (BConv)"): for every
+ * coefficient n, out_j = sum_i [in_i * qhat_i^-1]_{q_i} * [qhat_i]_{p_j} mod p_j with
+ * qhat_i = prod_{i' != i} q_{i'} over src_primes.  Step 1 is fused into the
+ * prologue of step 2, which runs as a BAT-expanded int8 MFMA GEMM.  This is
+ * the approximate ("fast") conversion: the result may differ from the exact
+ * CRT value by a multiple u*Q, 0 <= u < l.
+ *   in : device [batch][l][N] coefficient form mod src_primes (1 <= l <= 32, distinct)
+ *   out: device [batch][lp][N] mod dst_primes (1 <= lp <= 64); must not alias in
+ *   log_n: 5..16
+ */
+cross_status cross_bconv(cross_ctx ctx, uint32_t log_n, const uint32_t* src_primes, uint32_t l,
+                         const uint32_t* dst_primes, uint32_t lp, const uint32_t* in, uint32_t* out,
+                         uint32_t batch, void* stream);
+
+/*
+ * CKKS parameters for hybrid key switching (Tab. perf_cmp "L, log2 q, Dnum").
+ * Digit j holds limbs [j*alpha, min((j+1)*alpha, L)), alpha = ceil(L/dnum);
+ * a digit with no limb is inactive (its ModUp output is zero).  Limits:
+ * 5 <= log_n <= 16, L + K <= 64, alpha <= 32, K <= 32; primes pairwise distinct.
+ */
+typedef struct cross_ckks_params {
+  uint32_t log_n;           /* N = 2^log_n */
+  uint32_t L;               /* ciphertext limbs (the Q primes) */
+  uint32_t K;               /* special primes (P = product of the last K primes) */
+  uint32_t dnum;            /* key-switch digits */
+  const uint32_t* primes;   /* host array of L + K primes: Q first, then P */
+} cross_ckks_params;
+
+/*
+ * ModUp (hybrid key switching): in = d, NTT form [batch][L][N] (not modified);
+ * out = [batch][dnum][L+K][N] NTT form with, for digit j, out[j][t] = d[t] for
+ * limbs t of the digit and out[j][t] = NTT_t(BConv_{digit j -> t}(INTT(d))) for
+ * every other limb t < L+K.  out must not alias in.
+ */
+cross_status cross_keyswitch_modup(cross_ctx ctx, const cross_ckks_params* params, const uint32_t* in,
+                                   uint32_t* out, uint32_t batch, void* stream);
+/*
+ * ModDown: in = x, NTT form [batch][L+K][N] (not modified); out = [batch][L][N]
+ * with out_i = (x_i - NTT_{q_i}(BConv_{P -> q_i}(INTT_P(x_P)))) * P^-1 mod q_i.
+ */
+cross_status cross_keyswitch_moddown(cross_ctx ctx, const cross_ckks_params* params,
+                                     const uint32_t* in, uint32_t* out, uint32_t batch, void* stream);
+
+/*
+ * HE-Mult with relinearisation, no rescale (Tab. perf_cmp "HE-Mult"):
+ * d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (NTT form, limb-wise), then
+ * out = (d0 + ModDown(sum_j ModUp(d2)_j * key_j.b), d1 + ModDown(sum_j ModUp(d2)_j * key_j.a)).
+ *   ct_a, ct_b, out: device [batch][2][L][N] NTT form; out aliases neither input
+ *   relin_key      : device [dnum][2][L+K][N] NTT form, index 0 = b, 1 = a
+ */
+cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* params, const uint32_t* ct_a,
+                           const uint32_t* ct_b, const uint32_t* relin_key, uint32_t* out,
+                           uint32_t batch, void* stream);
+
+/*
+ * Rotate by `steps` slots (Tab. perf_cmp "Rotate"): Galois element
+ * g = 5^steps mod 2N (steps taken mod N/2); automorphism first, in NTT form
+ * (slot p <- slot brv(((2 brv(p)+1) g mod 2N - 1)/2)), then the key switch of
+ * the second component with rot_key (the key for g, layout as relin_key):
+ * out = (sigma(c0) + ModDown(acc_b), ModDown(acc_a)).  ct, out: [batch][2][L][N].
+ */
+cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* params, int32_t steps,
+                          const uint32_t* ct, const uint32_t* rot_key, uint32_t* out, uint32_t batch,
+                          void* stream);
+
+/*
  * Kernel timing with HIP events (tracing aid).  While enabled, every kernel
  * launch the library makes is bracketed by a pair of events recorded on the
  * launch stream.  cross_profile_report synchronises on the recorded events

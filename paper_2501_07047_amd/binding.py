@@ -41,6 +41,12 @@ SIGNATURES = {
     "cross_ntt_inverse": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
     "cross_ntt_forward_butterfly": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
     "cross_ntt_inverse_butterfly": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
+    "cross_poly_mul": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp],
+    "cross_bconv": [c_vp, c_u32, c_u32p, c_u32, c_u32p, c_u32, c_vp, c_vp, c_u32, c_vp],
+    "cross_keyswitch_modup": [c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
+    "cross_keyswitch_moddown": [c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
+    "cross_he_mult": [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
+    "cross_rotate": [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_profile_enable": [c_vp, ctypes.c_int],
     "cross_profile_report": [c_vp, ctypes.c_char_p, ctypes.c_uint64],
     "cross_host_tables": [c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
@@ -180,4 +186,92 @@ def profile_report(device=None):
     for line in buf.value.decode().splitlines():
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
+    return out
+
+
+class CkksParams(ctypes.Structure):
+    """Mirror of cross_ckks_params."""
+    _fields_ = [("log_n", c_u32), ("L", c_u32), ("K", c_u32), ("dnum", c_u32), ("primes", c_u32p)]
+
+
+def _params(qs, ps, dnum, n):
+    arr = _u32_array(list(qs) + list(ps))
+    prm = CkksParams(_log2(n), len(qs), len(ps), dnum, ctypes.cast(arr, c_u32p))
+    prm._keep = arr
+    return prm
+
+
+def _shape(t, shape, name):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+
+
+def poly_mul(a, b, out, primes):
+    """out = a * b in Z_q[x]/(x^N+1) limb-wise; all [batch][L][N] coefficient form."""
+    batch, L, n = a.shape
+    _shape(b, a.shape, "b")
+    _shape(out, a.shape, "out")
+    ctx = context(a.device.index)
+    _check(lib().cross_poly_mul(ctx, _log2(n), _u32_array(primes), L, batch, _dev_ptr(a, "a"),
+                                _dev_ptr(b, "b"), _dev_ptr(out, "out"), _stream(a)), ctx)
+    return out
+
+
+def bconv(inp, src_primes, dst_primes, out):
+    """Fast basis conversion of inp [batch][l][N] into out [batch][lp][N] (coefficient form)."""
+    batch, l, n = inp.shape
+    _shape(out, (batch, len(dst_primes), n), "out")
+    if l != len(src_primes):
+        raise ValueError("inp limbs != len(src_primes)")
+    ctx = context(inp.device.index)
+    _check(lib().cross_bconv(ctx, _log2(n), _u32_array(src_primes), l, _u32_array(dst_primes),
+                             len(dst_primes), _dev_ptr(inp, "inp"), _dev_ptr(out, "out"), batch,
+                             _stream(inp)), ctx)
+    return out
+
+
+def keyswitch_modup(inp, out, qs, ps, dnum):
+    """inp [batch][L][N] -> out [batch][dnum][L+K][N], NTT form."""
+    batch, L, n = inp.shape
+    _shape(out, (batch, dnum, L + len(ps), n), "out")
+    prm = _params(qs, ps, dnum, n)
+    ctx = context(inp.device.index)
+    _check(lib().cross_keyswitch_modup(ctx, ctypes.byref(prm), _dev_ptr(inp, "inp"), _dev_ptr(out, "out"),
+                                       batch, _stream(inp)), ctx)
+    return out
+
+
+def keyswitch_moddown(inp, out, qs, ps, dnum):
+    """inp [batch][L+K][N] -> out [batch][L][N], NTT form."""
+    batch, lk, n = inp.shape
+    _shape(out, (batch, len(qs), n), "out")
+    prm = _params(qs, ps, dnum, n)
+    ctx = context(inp.device.index)
+    _check(lib().cross_keyswitch_moddown(ctx, ctypes.byref(prm), _dev_ptr(inp, "inp"), _dev_ptr(out, "out"),
+                                         batch, _stream(inp)), ctx)
+    return out
+
+
+def he_mult(a, b, key, out, qs, ps, dnum):
+    """HE-Mult + relinearisation: a, b, out [batch][2][L][N]; key [dnum][2][L+K][N]."""
+    batch, two, L, n = a.shape
+    _shape(b, a.shape, "b")
+    _shape(out, a.shape, "out")
+    _shape(key, (dnum, 2, L + len(ps), n), "key")
+    prm = _params(qs, ps, dnum, n)
+    ctx = context(a.device.index)
+    _check(lib().cross_he_mult(ctx, ctypes.byref(prm), _dev_ptr(a, "a"), _dev_ptr(b, "b"), _dev_ptr(key, "key"),
+                               _dev_ptr(out, "out"), batch, _stream(a)), ctx)
+    return out
+
+
+def rotate(ct, steps, key, out, qs, ps, dnum):
+    """Rotation by `steps` (Galois element 5^steps mod 2N): ct, out [batch][2][L][N]."""
+    batch, two, L, n = ct.shape
+    _shape(out, ct.shape, "out")
+    _shape(key, (dnum, 2, L + len(ps), n), "key")
+    prm = _params(qs, ps, dnum, n)
+    ctx = context(ct.device.index)
+    _check(lib().cross_rotate(ctx, ctypes.byref(prm), int(steps), _dev_ptr(ct, "ct"), _dev_ptr(key, "key"),
+                              _dev_ptr(out, "out"), batch, _stream(ct)), ctx)
     return out

@@ -1,0 +1,552 @@
+// CKKS operations of the C ABI: polynomial product, basis conversion, hybrid
+// key switching (ModUp / inner product / ModDown), HE-Mult and Rotate.
+//
+// The paper (arXiv 2501.07047) evaluates HE-Mult and Rotate with dnum-digit
+// hybrid key switching (Tab. perf_cmp, Sec. Evaluation latency breakdown) and
+// maps its BConv onto the matrix engine with BAT (App. "Basis Conversion");
+// it cites rather than defines the key switch, so the steps follow the usual
+// hybrid form: digits of alpha = ceil(L/dnum) consecutive limbs; ModUp = INTT,
+// BConv of each digit to all other limbs, NTT; inner product with the
+// evaluation key; ModDown = INTT of the special limbs, BConv to Q, NTT,
+// (x - y) * P^-1.  All buffers are in NTT form; limbs are ordered Q then P.
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "context.h"
+#include "params.h"
+
+namespace cross {
+
+namespace {
+
+LimbMod limb_mod(uint32_t q) {
+  LimbMod m{};
+  int k = 0;
+  while ((1ull << k) <= q) ++k;           // bit length
+  m.q = q;
+  m.bar_k = (uint32_t)k;
+  m.bar_m = (uint32_t)(((unsigned __int128)1 << (2 * k)) / q);
+  return m;
+}
+
+uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+
+// Fragment-ordered BAT table of the BConv matrix [qhat_i]_t (see bconv_kernel).
+std::vector<int8_t> bconv_table(const std::vector<uint32_t>& src, const std::vector<uint32_t>& dst) {
+  const int ns = (int)src.size(), nd = (int)dst.size();
+  const int kb = (ns + 7) / 8, mb = (nd + 7) / 8;
+  std::vector<int8_t> out((size_t)mb * kb * 1024, 0);
+  // Montgomery-form [qhat_i]_t * 2^(7j) mod t, chunked
+  std::vector<uint32_t> qh((size_t)nd * ns);
+  for (int t = 0; t < nd; ++t) {
+    const uint32_t p = dst[t];
+    for (int i = 0; i < ns; ++i) {
+      uint64_t h = 1;
+      for (int i2 = 0; i2 < ns; ++i2)
+        if (i2 != i) h = h * (src[i2] % p) % p;
+      qh[(size_t)t * ns + i] = (uint32_t)(h * (((uint64_t)1 << 32) % p) % p);
+    }
+  }
+  for (int m = 0; m < mb; ++m)
+    for (int k = 0; k < kb; ++k)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e = 0; e < 16; ++e) {
+          const int row = m * 32 + (lane & 31);
+          const int t = row / 4, ii = row % 4;
+          const int i = k * 8 + (lane >> 5) * 4 + e / 4, j = e % 4;
+          int8_t v = 0;
+          if (t < nd && i < ns) {
+            const uint32_t p = dst[t];
+            uint64_t x = ((uint64_t)qh[(size_t)t * ns + i] << (kChunkBits * j)) % p;
+            v = (int8_t)((x >> (kChunkBits * ii)) & 0x7f);
+          }
+          out[((size_t)(m * kb + k) * 1024) + lane * 16 + e] = v;
+        }
+  return out;
+}
+
+// Device-resident constants of one BConv (source set -> target set).
+struct BconvStatic {
+  const BconvSrc* src = nullptr;
+  const BconvDst* dst = nullptr;
+  const int8_t* table = nullptr;
+  int nsrc = 0, ndst = 0;
+};
+
+cross_status make_bconv(cross_ctx ctx, const std::vector<uint32_t>& sp, const std::vector<uint64_t>& soff,
+                        const std::vector<uint32_t>& dp, const std::vector<uint64_t>& doff,
+                        BconvStatic* out) {
+  std::vector<BconvSrc> s(sp.size());
+  for (size_t i = 0; i < sp.size(); ++i) {
+    uint64_t h = 1;
+    for (size_t i2 = 0; i2 < sp.size(); ++i2)
+      if (i2 != i) h = h * (sp[i2] % sp[i]) % sp[i];
+    uint32_t w = powmod(h, sp[i] - 2, sp[i]);
+    s[i] = BconvSrc{soff[i], sp[i], w, shoup(w, sp[i]), 0};
+  }
+  std::vector<BconvDst> d(dp.size());
+  for (size_t t = 0; t < dp.size(); ++t) d[t] = BconvDst{doff[t], dp[t], inv_mod_2_32(dp[t])};
+  std::vector<int8_t> tab = bconv_table(sp, dp);
+  void *a = nullptr, *b = nullptr, *c = nullptr;
+  cross_status st = cached_device_copy(ctx, s.data(), s.size() * sizeof(BconvSrc), &a);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, d.data(), d.size() * sizeof(BconvDst), &b);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, tab.data(), tab.size(), &c);
+  if (st != CROSS_OK) return st;
+  out->src = (const BconvSrc*)a;
+  out->dst = (const BconvDst*)b;
+  out->table = (const int8_t*)c;
+  out->nsrc = (int)sp.size();
+  out->ndst = (int)dp.size();
+  return CROSS_OK;
+}
+
+hipError_t run_bconv(cross_ctx ctx, const BconvStatic& bs, const uint32_t* in, uint64_t in_stride,
+                     uint32_t* out, uint64_t out_stride, int npoly, int log_n, hipStream_t s) {
+  BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, in, out, in_stride, out_stride, npoly, log_n};
+  ProfScope ps(ctx, "bconv", s);
+  return launch_bconv(g, s);
+}
+
+struct CkksPlan {
+  int log_n = 0, L = 0, K = 0, dnum = 0, alpha = 0, ndig = 0;
+  std::vector<uint32_t> primes;
+  std::vector<Plan*> plans;               // L + K
+  const LimbMod* mods = nullptr;          // L + K, device
+  const TailConst* tail = nullptr;        // L, device
+  std::vector<BconvStatic> modup;         // per active digit: digit limbs -> all other limbs
+  std::vector<std::vector<int>> targets;  // per active digit
+  BconvStatic moddown;                    // P -> Q
+  const uint64_t* copy_src = nullptr;     // per active digit limb list (ModUp copies)
+  const uint64_t* copy_dst = nullptr;
+};
+
+
+
+cross_status validate_primes(cross_ctx ctx, const uint32_t* p, uint32_t n, uint32_t log_n) {
+  for (uint32_t i = 0; i < n; ++i) {
+    cross_status st = check_prime(ctx, p[i], log_n);
+    if (st != CROSS_OK) return st;
+    for (uint32_t j = 0; j < i; ++j)
+      if (p[j] == p[i]) return fail(ctx, CROSS_EINVAL, "primes must be pairwise distinct");
+  }
+  return CROSS_OK;
+}
+
+cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan** out) {
+  if (!prm || !prm->primes) return fail(ctx, CROSS_EINVAL, "null params");
+  if (prm->log_n < 5 || prm->log_n > CROSS_MAX_LOG_N) return fail(ctx, CROSS_EINVAL, "log_n out of range [5, 16]");
+  if (prm->L < 1 || prm->K < 1 || prm->dnum < 1 || prm->L + prm->K > CROSS_MAX_LIMBS)
+    return fail(ctx, CROSS_EINVAL, "need L >= 1, K >= 1, dnum >= 1, L + K <= 64");
+  const int L = (int)prm->L, K = (int)prm->K, dnum = (int)prm->dnum;
+  const int alpha = (L + dnum - 1) / dnum;
+  if (alpha > 32 || K > 32) return fail(ctx, CROSS_EUNSUPPORTED, "digit or special basis above 32 limbs");
+  std::string key((const char*)prm->primes, (L + K) * 4);
+  key += std::to_string(prm->log_n) + "/" + std::to_string(L) + "/" + std::to_string(K) + "/" +
+         std::to_string(dnum) + "/" + std::to_string(split_of(ctx, (int)prm->log_n));
+  auto it = ctx->ext_plans.find(key);
+  if (it != ctx->ext_plans.end()) {
+    *out = static_cast<CkksPlan*>(it->second.get());
+    return CROSS_OK;
+  }
+  cross_status st = validate_primes(ctx, prm->primes, L + K, prm->log_n);
+  if (st != CROSS_OK) return st;
+  std::shared_ptr<CkksPlan> holder = std::make_shared<CkksPlan>();
+  CkksPlan* c = holder.get();
+  c->log_n = (int)prm->log_n;
+  c->L = L;
+  c->K = K;
+  c->dnum = dnum;
+  c->alpha = alpha;
+  c->ndig = (L + alpha - 1) / alpha;
+  c->primes.assign(prm->primes, prm->primes + L + K);
+  const uint64_t N = 1ull << prm->log_n;
+  for (int i = 0; i < L + K; ++i) {
+    Plan* p = nullptr;
+    st = get_plan(ctx, c->primes[i], c->log_n, &p);
+    if (st != CROSS_OK) return st;
+    c->plans.push_back(p);
+  }
+  std::vector<LimbMod> mods(L + K);
+  for (int i = 0; i < L + K; ++i) mods[i] = limb_mod(c->primes[i]);
+  uint64_t P = 1;
+  std::vector<TailConst> tail(L);
+  for (int i = 0; i < L; ++i) {
+    const uint32_t q = c->primes[i];
+    uint64_t pm = 1;
+    for (int k = 0; k < K; ++k) pm = pm * (c->primes[L + k] % q) % q;
+    uint32_t pinv = powmod(pm, q - 2, q);
+    tail[i] = TailConst{q, pinv, shoup(pinv, q), 0};
+  }
+  (void)P;
+  void *dm = nullptr, *dt = nullptr;
+  st = cached_device_copy(ctx, mods.data(), mods.size() * sizeof(LimbMod), &dm);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, tail.data(), tail.size() * sizeof(TailConst), &dt);
+  if (st != CROSS_OK) return st;
+  c->mods = (const LimbMod*)dm;
+  c->tail = (const TailConst*)dt;
+  // ModUp BConvs: digit j (limbs [lo, hi) of x [L][N]) -> ext[j][t] for t outside the digit
+  std::vector<uint64_t> csrc, cdst;
+  for (int j = 0; j < c->ndig; ++j) {
+    const int lo = j * alpha, hi = std::min(L, (j + 1) * alpha);
+    std::vector<uint32_t> sp, dp;
+    std::vector<uint64_t> so, dof;
+    std::vector<int> tg;
+    for (int i = lo; i < hi; ++i) {
+      sp.push_back(c->primes[i]);
+      so.push_back((uint64_t)i * N);
+      csrc.push_back((uint64_t)i * N);
+      cdst.push_back(((uint64_t)j * (L + K) + i) * N);
+    }
+    for (int t = 0; t < L + K; ++t) {
+      if (t >= lo && t < hi) continue;
+      dp.push_back(c->primes[t]);
+      dof.push_back(((uint64_t)j * (L + K) + t) * N);
+      tg.push_back(t);
+    }
+    BconvStatic bs;
+    st = make_bconv(ctx, sp, so, dp, dof, &bs);
+    if (st != CROSS_OK) return st;
+    c->modup.push_back(bs);
+    c->targets.push_back(tg);
+  }
+  void *a = nullptr, *b = nullptr;
+  st = cached_device_copy(ctx, csrc.data(), csrc.size() * 8, &a);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, cdst.data(), cdst.size() * 8, &b);
+  if (st != CROSS_OK) return st;
+  c->copy_src = (const uint64_t*)a;
+  c->copy_dst = (const uint64_t*)b;
+  // ModDown BConv: P limbs (coefficient form, [K][N] per poly) -> Q limbs ([L][N] per poly)
+  {
+    std::vector<uint32_t> sp(c->primes.begin() + L, c->primes.end()), dp(c->primes.begin(), c->primes.begin() + L);
+    std::vector<uint64_t> so(K), dof(L);
+    for (int k = 0; k < K; ++k) so[k] = (uint64_t)(L + k) * N;
+    for (int i = 0; i < L; ++i) dof[i] = (uint64_t)i * N;
+    st = make_bconv(ctx, sp, so, dp, dof, &c->moddown);
+    if (st != CROSS_OK) return st;
+  }
+  ctx->ext_plans[key] = holder;
+  *out = c;
+  return CROSS_OK;
+}
+
+#define HIPCHK(expr, what)                                                              \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string(what) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// NTT/INTT of a list of limbs (by index into c->plans) at given offsets.
+cross_status ntt_list(cross_ctx ctx, const CkksPlan* c, const std::vector<int>& limb,
+                      const std::vector<uint64_t>& offs, uint32_t* data, uint64_t stride, int npoly,
+                      bool inverse, uint32_t* tmp, hipStream_t s) {
+  std::vector<Plan*> pl(limb.size());
+  for (size_t i = 0; i < limb.size(); ++i) pl[i] = c->plans[limb[i]];
+  return ntt_limbs(ctx, pl, offs, data, stride, npoly, inverse, tmp, s);
+}
+
+// ModUp of d (NTT form, [B][L][N], may be overwritten: used as the INTT scratch)
+// into ext [B][dnum][L+K][N].  `tmp` holds B*dnum*(L+K)*N words.
+cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t* ext, int B,
+                        uint32_t* tmp, hipStream_t s) {
+  const int L = c->L, K = c->K, LK = L + K;
+  const uint64_t N = 1ull << c->log_n;
+  const uint64_t ext_stride = (uint64_t)c->dnum * LK * N;
+  // 1. digit limbs are copied unchanged (NTT form)
+  {
+    ProfScope ps(ctx, "limb_copy", s);
+    HIPCHK(launch_limb_copy(d, (uint64_t)L * N, c->copy_src, ext, ext_stride, c->copy_dst, L, c->log_n, B, s),
+           "modup copy");
+  }
+  // inactive digits are zero
+  if (c->ndig < c->dnum) {
+    std::vector<uint64_t> zo;
+    for (int j = c->ndig; j < c->dnum; ++j)
+      for (int t = 0; t < LK; ++t) zo.push_back(((uint64_t)j * LK + t) * N);
+    void* dz = nullptr;
+    cross_status st = cached_device_copy(ctx, zo.data(), zo.size() * 8, &dz);
+    if (st != CROSS_OK) return st;
+    HIPCHK(launch_limb_copy(nullptr, 0, (const uint64_t*)dz, ext, ext_stride, (const uint64_t*)dz,
+                            (int)zo.size(), c->log_n, B, s), "modup zero");
+  }
+  // 2. coefficient form of d
+  std::vector<int> li(L);
+  std::vector<uint64_t> lo(L);
+  for (int i = 0; i < L; ++i) {
+    li[i] = i;
+    lo[i] = (uint64_t)i * N;
+  }
+  cross_status st = ntt_list(ctx, c, li, lo, d, (uint64_t)L * N, B, true, tmp, s);
+  if (st != CROSS_OK) return st;
+  // 3. BConv of each digit to the other limbs, then 4. NTT of all converted limbs in one launch
+  std::vector<int> nl;
+  std::vector<uint64_t> no;
+  for (int j = 0; j < c->ndig; ++j) {
+    HIPCHK(run_bconv(ctx, c->modup[j], d, (uint64_t)L * N, ext, ext_stride, B, c->log_n, s), "modup bconv");
+    for (int t : c->targets[j]) {
+      nl.push_back(t);
+      no.push_back(((uint64_t)j * LK + t) * N);
+    }
+  }
+  return ntt_list(ctx, c, nl, no, ext, ext_stride, B, false, tmp, s);
+}
+
+// ModDown of acc ([npoly][L+K][N], NTT form; its P limbs are overwritten) into out
+// ([npoly][L][N]): out = base + (acc_Q - NTT(BConv(INTT(acc_P)))) * P^-1.
+cross_status moddown_core(cross_ctx ctx, const CkksPlan* c, uint32_t* acc, int npoly, uint32_t* z,
+                          const uint32_t* base, bool base_only_even, uint32_t* out, uint32_t* tmp,
+                          hipStream_t s) {
+  const int L = c->L, K = c->K, LK = L + K;
+  const uint64_t N = 1ull << c->log_n;
+  std::vector<int> pl(K);
+  std::vector<uint64_t> po(K);
+  for (int k = 0; k < K; ++k) {
+    pl[k] = L + k;
+    po[k] = (uint64_t)(L + k) * N;
+  }
+  cross_status st = ntt_list(ctx, c, pl, po, acc, (uint64_t)LK * N, npoly, true, tmp, s);
+  if (st != CROSS_OK) return st;
+  HIPCHK(run_bconv(ctx, c->moddown, acc, (uint64_t)LK * N, z, (uint64_t)L * N, npoly, c->log_n, s), "moddown bconv");
+  std::vector<int> ql(L);
+  std::vector<uint64_t> qo(L);
+  for (int i = 0; i < L; ++i) {
+    ql[i] = i;
+    qo[i] = (uint64_t)i * N;
+  }
+  st = ntt_list(ctx, c, ql, qo, z, (uint64_t)L * N, npoly, false, tmp, s);
+  if (st != CROSS_OK) return st;
+  ProfScope ps(ctx, "moddown_tail", s);
+  HIPCHK(launch_moddown_tail(acc, (uint64_t)LK * N, z, base, out, (uint64_t)L * N, c->tail, L, c->log_n,
+                             npoly, base_only_even, s), "moddown tail");
+  return CROSS_OK;
+}
+
+struct KsWork {
+  uint32_t *d, *ext, *tmp, *acc, *z;
+};
+
+cross_status ks_workspace(cross_ctx ctx, const CkksPlan* c, int B, hipStream_t s, KsWork* w) {
+  const uint64_t N = 1ull << c->log_n;
+  const uint64_t LK = c->L + c->K;
+  const uint64_t nd = (uint64_t)B * c->L * N, next = (uint64_t)B * c->dnum * LK * N;
+  const uint64_t nacc = (uint64_t)B * 2 * LK * N, nz = (uint64_t)B * 2 * c->L * N;
+  const uint64_t ntmp = std::max(std::max(next, nacc), std::max(nz, nd));
+  void* base = nullptr;
+  cross_status st = workspace(ctx, s, (nd + next + ntmp + nacc + nz) * 4, &base);
+  if (st != CROSS_OK) return st;
+  uint32_t* p = (uint32_t*)base;
+  w->d = p;
+  w->ext = p + nd;
+  w->tmp = w->ext + next;
+  w->acc = w->tmp + ntmp;
+  w->z = w->acc + nacc;
+  return CROSS_OK;
+}
+
+cross_status begin(cross_ctx ctx) {
+  if (!ctx) return CROSS_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
+  return CROSS_OK;
+}
+
+bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Key switch of d (NTT form, [B][L][N], in workspace w.d): ModUp, inner product with key, ModDown
+// of both accumulators into out0/out1 of out [B][2][L][N] with optional base.
+cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* key, int B, KsWork& w,
+                            uint32_t* out, const uint32_t* base, bool base_only_even, hipStream_t s) {
+  cross_status st = modup_core(ctx, c, w.d, w.ext, B, w.tmp, s);
+  if (st != CROSS_OK) return st;
+  {
+    ProfScope ps(ctx, "inner_product", s);
+    HIPCHK(launch_inner_product(w.ext, key, w.acc, c->mods, c->L + c->K, c->dnum, c->ndig, c->log_n, B, s),
+           "inner product");
+  }
+  return moddown_core(ctx, c, w.acc, 2 * B, w.z, base, base_only_even, out, w.tmp, s);
+}
+
+cross_status perm_table(cross_ctx ctx, int log_n, uint32_t g, const uint32_t** out) {
+  const uint32_t N = 1u << log_n;
+  std::vector<uint32_t> perm(N);
+  for (uint32_t p = 0; p < N; ++p) {
+    uint64_t e = (2ull * bitrev(p, log_n) + 1) * g % (2ull * N);
+    perm[p] = bitrev((uint32_t)((e - 1) / 2), log_n);
+  }
+  void* d = nullptr;
+  cross_status st = cached_device_copy(ctx, perm.data(), perm.size() * 4, &d);
+  *out = (const uint32_t*)d;
+  return st;
+}
+
+}  // namespace
+
+}  // namespace cross
+
+using namespace cross;
+
+extern "C" {
+
+cross_status cross_poly_mul(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                            uint32_t batch, const uint32_t* a, const uint32_t* b, uint32_t* out,
+                            void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  if (!primes || !a || !b || !out || !aligned(a) || !aligned(b) || !aligned(out))
+    return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
+  if (log_n < CROSS_MIN_LOG_N || log_n > CROSS_MAX_LOG_N || L < 1 || L > CROSS_MAX_LIMBS || batch < 1)
+    return fail(ctx, CROSS_EINVAL, "bad shape");
+  for (uint32_t i = 0; i < L; ++i) {
+    st = check_prime(ctx, primes[i], log_n);
+    if (st != CROSS_OK) return st;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t N = 1ull << log_n, tot = (uint64_t)batch * L * N;
+  std::vector<Plan*> plans(L);
+  std::vector<uint64_t> offs(L);
+  std::vector<LimbMod> mods(L);
+  for (uint32_t i = 0; i < L; ++i) {
+    st = get_plan(ctx, primes[i], (int)log_n, &plans[i]);
+    if (st != CROSS_OK) return st;
+    offs[i] = i * N;
+    mods[i] = limb_mod(primes[i]);
+  }
+  void *ws = nullptr, *dm = nullptr;
+  st = workspace(ctx, s, tot * 2 * 4, &ws);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, mods.data(), mods.size() * sizeof(LimbMod), &dm);
+  if (st != CROSS_OK) return st;
+  uint32_t* wb = (uint32_t*)ws;
+  uint32_t* tmp = wb + tot;
+  HIPCHK(hipMemcpyAsync(wb, b, tot * 4, hipMemcpyDeviceToDevice, s), "copy b");   // b first: out may alias b
+  HIPCHK(hipMemcpyAsync(out, a, tot * 4, hipMemcpyDeviceToDevice, s), "copy a");
+  const uint64_t stride = (uint64_t)L * N;
+  auto ntt = [&](uint32_t* d, bool inv) -> cross_status {
+    if (log_n < 8) {
+      std::vector<ButterflyJob> jobs(L);
+      for (uint32_t i = 0; i < L; ++i)
+        jobs[i] = ButterflyJob{inv ? plans[i]->bf_inv : plans[i]->bf_fwd, offs[i], plans[i]->q,
+                               plans[i]->qinv, plans[i]->bf_ninv};
+      void* dj = nullptr;
+      cross_status s2 = cached_device_copy(ctx, jobs.data(), jobs.size() * sizeof(ButterflyJob), &dj);
+      if (s2 != CROSS_OK) return s2;
+      HIPCHK(launch_butterfly((const ButterflyJob*)dj, (int)L, d, stride, (int)batch, (int)log_n, inv, s), "butterfly");
+      return CROSS_OK;
+    }
+    return ntt_limbs(ctx, plans, offs, d, stride, (int)batch, inv, tmp, s);
+  };
+  if ((st = ntt(out, false)) != CROSS_OK) return st;
+  if ((st = ntt(wb, false)) != CROSS_OK) return st;
+  {
+    ProfScope ps(ctx, "pointwise_mul", s);
+    HIPCHK(launch_pointwise_mul(out, wb, out, (const LimbMod*)dm, (int)L, (int)log_n, (int)batch, s), "pointwise");
+  }
+  return ntt(out, true);
+}
+
+cross_status cross_bconv(cross_ctx ctx, uint32_t log_n, const uint32_t* src_primes, uint32_t l,
+                         const uint32_t* dst_primes, uint32_t lp, const uint32_t* in, uint32_t* out,
+                         uint32_t batch, void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  if (!src_primes || !dst_primes || !in || !out || !aligned(in) || !aligned(out))
+    return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
+  if (log_n < 5 || log_n > CROSS_MAX_LOG_N || l < 1 || l > 32 || lp < 1 || lp > CROSS_MAX_LIMBS || batch < 1)
+    return fail(ctx, CROSS_EINVAL, "bad shape (1 <= l <= 32, 1 <= lp <= 64, 5 <= log_n <= 16)");
+  st = validate_primes(ctx, src_primes, l, 0);
+  if (st != CROSS_OK) return st;
+  for (uint32_t j = 0; j < lp; ++j) {
+    st = check_prime(ctx, dst_primes[j], 0);
+    if (st != CROSS_OK) return st;
+  }
+  const uint64_t N = 1ull << log_n;
+  std::vector<uint32_t> sp(src_primes, src_primes + l), dp(dst_primes, dst_primes + lp);
+  std::vector<uint64_t> so(l), dof(lp);
+  for (uint32_t i = 0; i < l; ++i) so[i] = i * N;
+  for (uint32_t j = 0; j < lp; ++j) dof[j] = j * N;
+  BconvStatic bs;
+  st = make_bconv(ctx, sp, so, dp, dof, &bs);
+  if (st != CROSS_OK) return st;
+  HIPCHK(run_bconv(ctx, bs, in, (uint64_t)l * N, out, (uint64_t)lp * N, (int)batch, (int)log_n, (hipStream_t)stream),
+         "bconv");
+  return CROSS_OK;
+}
+
+cross_status cross_keyswitch_modup(cross_ctx ctx, const cross_ckks_params* prm, const uint32_t* in,
+                                   uint32_t* out, uint32_t batch, void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  CkksPlan* c = nullptr;
+  if ((st = get_ckks_plan(ctx, prm, &c)) != CROSS_OK) return st;
+  if (!in || !out || !aligned(in) || !aligned(out) || batch < 1) return fail(ctx, CROSS_EINVAL, "bad buffer or batch");
+  hipStream_t s = (hipStream_t)stream;
+  KsWork w;
+  if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
+  const uint64_t N = 1ull << c->log_n;
+  HIPCHK(hipMemcpyAsync(w.d, in, (uint64_t)batch * c->L * N * 4, hipMemcpyDeviceToDevice, s), "copy in");
+  return modup_core(ctx, c, w.d, out, (int)batch, w.tmp, s);
+}
+
+cross_status cross_keyswitch_moddown(cross_ctx ctx, const cross_ckks_params* prm, const uint32_t* in,
+                                     uint32_t* out, uint32_t batch, void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  CkksPlan* c = nullptr;
+  if ((st = get_ckks_plan(ctx, prm, &c)) != CROSS_OK) return st;
+  if (!in || !out || !aligned(in) || !aligned(out) || batch < 1) return fail(ctx, CROSS_EINVAL, "bad buffer or batch");
+  hipStream_t s = (hipStream_t)stream;
+  KsWork w;
+  if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
+  const uint64_t N = 1ull << c->log_n, LK = c->L + c->K;
+  HIPCHK(hipMemcpyAsync(w.acc, in, (uint64_t)batch * LK * N * 4, hipMemcpyDeviceToDevice, s), "copy in");
+  return moddown_core(ctx, c, w.acc, (int)batch, w.z, nullptr, false, out, w.tmp, s);
+}
+
+cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* prm, const uint32_t* ct_a,
+                           const uint32_t* ct_b, const uint32_t* relin_key, uint32_t* out,
+                           uint32_t batch, void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  CkksPlan* c = nullptr;
+  if ((st = get_ckks_plan(ctx, prm, &c)) != CROSS_OK) return st;
+  if (!ct_a || !ct_b || !relin_key || !out || !aligned(ct_a) || !aligned(ct_b) || !aligned(relin_key) ||
+      !aligned(out) || batch < 1)
+    return fail(ctx, CROSS_EINVAL, "bad buffer or batch");
+  if (out == ct_a || out == ct_b) return fail(ctx, CROSS_EINVAL, "out must not alias the inputs");
+  hipStream_t s = (hipStream_t)stream;
+  KsWork w;
+  if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
+  {
+    ProfScope ps(ctx, "tensor", s);
+    HIPCHK(launch_tensor(ct_a, ct_b, out, w.d, c->mods, c->L, c->log_n, (int)batch, s), "tensor");
+  }
+  return keyswitch_into(ctx, c, relin_key, (int)batch, w, out, out, false, s);
+}
+
+cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* prm, int32_t steps, const uint32_t* ct,
+                          const uint32_t* rot_key, uint32_t* out, uint32_t batch, void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  CkksPlan* c = nullptr;
+  if ((st = get_ckks_plan(ctx, prm, &c)) != CROSS_OK) return st;
+  if (!ct || !rot_key || !out || !aligned(ct) || !aligned(rot_key) || !aligned(out) || batch < 1)
+    return fail(ctx, CROSS_EINVAL, "bad buffer or batch");
+  if (out == ct) return fail(ctx, CROSS_EINVAL, "out must not alias ct");
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t N = 1ull << c->log_n;
+  const int64_t half = (int64_t)N / 2;
+  const uint64_t r = (uint64_t)((((int64_t)steps % half) + half) % half);
+  const uint32_t g = powmod(5, r, (uint32_t)(2 * N));
+  const uint32_t* perm = nullptr;
+  if ((st = perm_table(ctx, c->log_n, g, &perm)) != CROSS_OK) return st;
+  KsWork w;
+  if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
+  const uint64_t L = c->L;
+  {
+    ProfScope ps(ctx, "automorphism", s);
+    // sigma(c0) -> out[b][0] (the ModDown base of the first component); sigma(c1) -> workspace
+    HIPCHK(launch_automorphism(ct, 2 * L * N, out, 2 * L * N, perm, c->log_n, (int)L, (int)batch, s), "sigma c0");
+    HIPCHK(launch_automorphism(ct + L * N, 2 * L * N, w.d, L * N, perm, c->log_n, (int)L, (int)batch, s), "sigma c1");
+  }
+  return keyswitch_into(ctx, c, rot_key, (int)batch, w, out, out, true, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,297 @@
+// Vector-ALU streams and the BConv MFMA GEMM of CKKS key switching
+// (arXiv 2501.07047: Tab. HE_operator_AI_operator -- VecModMul / VecModAdd;
+// App. "Basis Conversion (BConv)" -- step 1 L x N VecModMul, step 2 (N, L, L')
+// MatModMul, the latter on int8 MFMA through BAT; Sec. Evaluation -- HE-Mult and
+// Rotate built from NTT, BConv, VecModMul and automorphism).
+//
+// The streams are HBM-bound: every kernel reads and writes each residue once,
+// with 128-bit (4 x uint32) coalesced accesses per lane.
+#include "kernels.h"
+
+namespace cross {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// Barrett multiplication for two runtime residues (Alg. barrett): with
+// k = bitlen(q) and m = floor(2^(2k)/q), t = ((z >> (k-1)) * m) >> (k+1)
+// underestimates floor(z/q) by at most 2, so two conditional subtractions finish.
+__device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const LimbMod& md) {
+  uint64_t z = (uint64_t)a * b;
+  uint32_t zh = (uint32_t)(z >> (md.bar_k - 1));
+  uint32_t t = (uint32_t)(((uint64_t)zh * md.bar_m) >> (md.bar_k + 1));
+  uint32_t r = (uint32_t)z - t * md.q;
+  if (r >= md.q) r -= md.q;
+  if (r >= md.q) r -= md.q;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t q) {
+  uint32_t r = a + b;
+  return r >= q ? r - q : r;
+}
+
+// Shoup multiplication by a pre-known w (w_shoup = floor(w 2^32 / q)): result in [0, q).
+__device__ __forceinline__ uint32_t mulmod_shoup(uint32_t x, uint32_t w, uint32_t ws, uint32_t q) {
+  uint32_t t = __umulhi(x, ws);
+  uint32_t r = x * w - t * q;
+  return r >= q ? r - q : r;
+}
+
+__device__ __forceinline__ uint32_t pack_chunks(uint32_t x) {
+  return (x & 0x7fu) | ((x << 1) & 0x7f00u) | ((x << 2) & 0x7f0000u) | ((x << 3) & 0x7f000000u);
+}
+
+__global__ void __launch_bounds__(256)
+tensor_kernel(const v4u* a, const v4u* b, v4u* out, v4u* d2, const LimbMod* mods, int L,
+              int log_n4, uint64_t total4) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total4) return;
+  const uint64_t per_limb = 1ull << log_n4;            // vectors per limb
+  const uint64_t limb_all = i >> log_n4;                // (b, limb)
+  const int limb = (int)(limb_all % L);
+  const uint64_t bb = limb_all / L;
+  const uint64_t w = i & (per_limb - 1);
+  const uint64_t o0 = ((bb * 2 + 0) * L + limb) * per_limb + w;
+  const uint64_t o1 = ((bb * 2 + 1) * L + limb) * per_limb + w;
+  const LimbMod md = mods[limb];
+  v4u a0 = a[o0], a1 = a[o1], b0 = b[o0], b1 = b[o1];
+  v4u r0, r1, r2;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r0[k] = mulmod(a0[k], b0[k], md);
+    r1[k] = addmod(mulmod(a0[k], b1[k], md), mulmod(a1[k], b0[k], md), md.q);
+    r2[k] = mulmod(a1[k], b1[k], md);
+  }
+  out[o0] = r0;
+  out[o1] = r1;
+  d2[(bb * L + limb) * per_limb + w] = r2;
+}
+
+__global__ void __launch_bounds__(256)
+inner_product_kernel(const v4u* ext, const v4u* key, v4u* acc, const LimbMod* mods, int LK,
+                     int dnum, int ndig, int log_n4, uint64_t total4) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total4) return;
+  const uint64_t per_limb = 1ull << log_n4;
+  const uint64_t limb_all = i >> log_n4;
+  const int t = (int)(limb_all % LK);
+  const uint64_t bb = limb_all / LK;
+  const uint64_t w = i & (per_limb - 1);
+  const LimbMod md = mods[t];
+  v4u s0 = {0, 0, 0, 0}, s1 = {0, 0, 0, 0};
+  for (int j = 0; j < ndig; ++j) {
+    v4u e = ext[((bb * dnum + j) * LK + t) * per_limb + w];
+    v4u k0 = key[((uint64_t)(j * 2 + 0) * LK + t) * per_limb + w];
+    v4u k1 = key[((uint64_t)(j * 2 + 1) * LK + t) * per_limb + w];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s0[k] = addmod(s0[k], mulmod(e[k], k0[k], md), md.q);
+      s1[k] = addmod(s1[k], mulmod(e[k], k1[k], md), md.q);
+    }
+  }
+  acc[((bb * 2 + 0) * LK + t) * per_limb + w] = s0;
+  acc[((bb * 2 + 1) * LK + t) * per_limb + w] = s1;
+}
+
+__global__ void __launch_bounds__(256)
+moddown_tail_kernel(const v4u* acc, uint64_t acc_stride4, const v4u* z, const v4u* base, v4u* out,
+                    uint64_t out_stride4, const TailConst* tc, int L, int log_n4, uint64_t total4,
+                    bool base_only_even) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total4) return;
+  const uint64_t per_limb = 1ull << log_n4;
+  const uint64_t limb_all = i >> log_n4;
+  const int limb = (int)(limb_all % L);
+  const uint64_t p = limb_all / L;
+  const uint64_t w = i & (per_limb - 1);
+  const TailConst c = tc[limb];
+  v4u x = acc[p * acc_stride4 + limb * per_limb + w];
+  v4u y = z[(p * L + limb) * per_limb + w];
+  const uint64_t oo = p * out_stride4 + limb * per_limb + w;
+  const bool use_base = base && (!base_only_even || (p & 1) == 0);
+  v4u bs = use_base ? base[oo] : v4u{0, 0, 0, 0};
+  v4u r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t d = x[k] + c.q - y[k];                       // in (0, 2q)
+    r[k] = addmod(bs[k], mulmod_shoup(d, c.pinv, c.pinv_shoup, c.q), c.q);
+  }
+  out[oo] = r;
+}
+
+__global__ void __launch_bounds__(256)
+automorphism_kernel(const uint32_t* in, uint64_t in_stride, uint32_t* out, uint64_t out_stride,
+                    const uint32_t* perm, int log_n, int L, uint64_t total) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const uint64_t n = 1ull << log_n;
+  const uint64_t limb_all = i >> log_n;
+  const uint64_t p = limb_all / L;
+  const uint64_t l = limb_all - p * L;
+  const uint64_t x = i & (n - 1);
+  out[p * out_stride + l * n + x] = in[p * in_stride + l * n + perm[x]];
+}
+
+__global__ void __launch_bounds__(256)
+pointwise_kernel(const v4u* a, const v4u* b, v4u* out, const LimbMod* mods, int L, int log_n4,
+                 uint64_t total4) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total4) return;
+  const int limb = (int)((i >> log_n4) % L);
+  const LimbMod md = mods[limb];
+  v4u x = a[i], y = b[i], r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = mulmod(x[k], y[k], md);
+  out[i] = r;
+}
+
+__global__ void __launch_bounds__(256)
+limb_copy_kernel(const v4u* src, uint64_t src_stride4, const uint64_t* src_off, v4u* dst,
+                 uint64_t dst_stride4, const uint64_t* dst_off, int nl, int log_n4, uint64_t total4) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total4) return;
+  const uint64_t per_limb = 1ull << log_n4;
+  const uint64_t limb_all = i >> log_n4;
+  const int l = (int)(limb_all % nl);
+  const uint64_t p = limb_all / nl;
+  const uint64_t w = i & (per_limb - 1);
+  v4u v = src ? src[p * src_stride4 + src_off[l] / 4 + w] : v4u{0, 0, 0, 0};
+  dst[p * dst_stride4 + dst_off[l] / 4 + w] = v;
+}
+
+// ---- BConv on MFMA -----------------------------------------------------------
+// GEMM: out[(t, ii)][n] = sum_{(i, j)} A[(t, ii)][(i, j)] * chunk_j(b_i[n]), with
+// A[(t, ii)][(i, j)] = chunk_ii(([qhat_i]_t * 2^32 * 2^(7j)) mod t) (BAT, Montgomery form).
+// v_mfma_i32_32x32x32_i8: 8 targets x 8 sources x 32 coefficients per instruction.
+// Lane l of a 32x32 output block holds rows 8(v/4) + 4(l/32) + v%4 (v < 16) of
+// column l%32, so the four chunk rows of each target sit in four consecutive
+// registers and the merge stays in-register.  Each wave owns 32 coefficients.
+constexpr int BCONV_MAX_KB = 4;   // up to 32 source limbs
+
+__global__ void __launch_bounds__(256)
+bconv_kernel(BconvLaunch g) {
+  const int lane = threadIdx.x & 63;
+  const int wave_global = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t n_per_poly = 1ull << g.log_n;
+  const uint64_t col0 = (uint64_t)wave_global * 32;
+  const uint64_t poly = col0 >> g.log_n;
+  if (poly >= (uint64_t)g.npoly) return;
+  const uint64_t n = (col0 & (n_per_poly - 1)) + (lane & 31);
+  const int kblocks = (g.nsrc + 7) >> 3;
+  const int mblocks = (g.ndst + 7) >> 3;
+  const uint32_t* in = g.in + poly * g.in_stride;
+  uint32_t* out = g.out + poly * g.out_stride;
+
+  // B fragments: step 1 (x * qhat^-1 mod q) and chunking, one v4i per K block
+  v4i bf[BCONV_MAX_KB];
+#pragma unroll
+  for (int kb = 0; kb < BCONV_MAX_KB; ++kb) {
+    v4i f = {0, 0, 0, 0};
+    if (kb < kblocks) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = kb * 8 + (lane >> 5) * 4 + e;
+        uint32_t v = 0;
+        if (i < g.nsrc) {
+          const BconvSrc sd = g.src[i];
+          v = pack_chunks(mulmod_shoup(in[sd.off + n], sd.w, sd.w_shoup, sd.q));
+        }
+        f[e] = (int)v;
+      }
+    }
+    bf[kb] = f;
+  }
+
+  for (int mb = 0; mb < mblocks; ++mb) {
+    v16i acc = {};
+    for (int kb = 0; kb < kblocks; ++kb) {
+      const v4i a = *reinterpret_cast<const v4i*>(g.table + ((size_t)(mb * kblocks + kb) * 1024) + lane * 16);
+      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bf[kb], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+      const int t = mb * 8 + 2 * g4 + (lane >> 5);
+      if (t >= g.ndst) continue;
+      const BconvDst d = g.dst[t];
+      uint64_t z = (uint64_t)(uint32_t)acc[4 * g4] + ((uint64_t)(uint32_t)acc[4 * g4 + 1] << 7) +
+                   ((uint64_t)(uint32_t)acc[4 * g4 + 2] << 14) + ((uint64_t)(uint32_t)acc[4 * g4 + 3] << 21);
+      uint32_t tq = (uint32_t)z * d.qinv;
+      uint32_t r = (uint32_t)(z >> 32) + d.q - __umulhi(tq, d.q);
+      if (r >= d.q) r -= d.q;
+      out[d.off + n] = r;
+    }
+  }
+}
+
+inline unsigned blocks_for(uint64_t total, int per = 256) { return (unsigned)((total + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
+                         const LimbMod* mods, int L, int log_n, int B, hipStream_t s) {
+  const uint64_t total4 = ((uint64_t)B * L) << (log_n - 2);
+  hipLaunchKernelGGL(tensor_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
+                     (const v4u*)b, (v4u*)out, (v4u*)d2, mods, L, log_n - 2, total4);
+  return hipGetLastError();
+}
+
+hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32_t* acc,
+                                const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
+                                hipStream_t s) {
+  const uint64_t total4 = ((uint64_t)B * LK) << (log_n - 2);
+  hipLaunchKernelGGL(inner_product_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
+                     (const v4u*)ext, (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2,
+                     total4);
+  return hipGetLastError();
+}
+
+hipError_t launch_moddown_tail(const uint32_t* acc, uint64_t acc_stride, const uint32_t* z,
+                               const uint32_t* base, uint32_t* out, uint64_t out_stride,
+                               const TailConst* tc, int L, int log_n, int npoly,
+                               bool base_only_even, hipStream_t s) {
+  const uint64_t total4 = ((uint64_t)npoly * L) << (log_n - 2);
+  hipLaunchKernelGGL(moddown_tail_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
+                     (const v4u*)acc, acc_stride / 4, (const v4u*)z, (const v4u*)base, (v4u*)out,
+                     out_stride / 4, tc, L, log_n - 2, total4, base_only_even);
+  return hipGetLastError();
+}
+
+hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t* out,
+                               uint64_t out_stride, const uint32_t* perm, int log_n, int L,
+                               int npoly, hipStream_t s) {
+  const uint64_t total = ((uint64_t)npoly * L) << log_n;
+  hipLaunchKernelGGL(automorphism_kernel, dim3(blocks_for(total)), dim3(256), 0, s, in, in_stride,
+                     out, out_stride, perm, log_n, L, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_pointwise_mul(const uint32_t* a, const uint32_t* b, uint32_t* out,
+                                const LimbMod* mods, int L, int log_n, int B, hipStream_t s) {
+  const uint64_t total4 = ((uint64_t)B * L) << (log_n - 2);
+  hipLaunchKernelGGL(pointwise_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
+                     (const v4u*)b, (v4u*)out, mods, L, log_n - 2, total4);
+  return hipGetLastError();
+}
+
+hipError_t launch_limb_copy(const uint32_t* src, uint64_t src_stride, const uint64_t* src_off,
+                            uint32_t* dst, uint64_t dst_stride, const uint64_t* dst_off, int nl,
+                            int log_n, int npoly, hipStream_t s) {
+  const uint64_t total4 = ((uint64_t)npoly * nl) << (log_n - 2);
+  hipLaunchKernelGGL(limb_copy_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)src,
+                     src_stride / 4, src_off, (v4u*)dst, dst_stride / 4, dst_off, nl, log_n - 2,
+                     total4);
+  return hipGetLastError();
+}
+
+hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s) {
+  if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5) return hipErrorInvalidValue;
+  const uint64_t waves = ((uint64_t)b.npoly << b.log_n) / 32;
+  hipLaunchKernelGGL(bconv_kernel, dim3(blocks_for(waves * 64)), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+
+}  // namespace cross

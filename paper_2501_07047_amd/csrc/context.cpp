@@ -148,6 +148,23 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   if (plans.empty()) return CROSS_OK;
   const int log_n = plans[0]->log_n;
   const int log_r = plans[0]->log_r;
+  if (log_n < 8) {
+    // below the MFMA minimum (4R >= 64): radix-2 kernels, in place
+    std::vector<ButterflyJob> jobs(plans.size());
+    for (size_t i = 0; i < plans.size(); ++i)
+      jobs[i] = ButterflyJob{inverse ? plans[i]->bf_inv : plans[i]->bf_fwd, offs[i], plans[i]->q,
+                             plans[i]->qinv, plans[i]->bf_ninv};
+    void* dj = nullptr;
+    cross_status st = cached_device_copy(ctx, jobs.data(), jobs.size() * sizeof(ButterflyJob), &dj);
+    if (st != CROSS_OK) return st;
+    hipError_t e;
+    {
+      ProfScope ps(ctx, "butterfly_ntt", s);
+      e = launch_butterfly((const ButterflyJob*)dj, (int)jobs.size(), data, stride, npoly, log_n, inverse, s);
+    }
+    if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("butterfly launch: ") + hipGetErrorString(e));
+    return CROSS_OK;
+  }
   std::vector<GemmJob> j1(plans.size()), j2(plans.size());
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -53,6 +54,7 @@ struct cross_ctx_s {
   std::map<hipStream_t, cross::DevBuf> workspace;
   std::map<int, int> split;                   // log_n -> log_r override
   std::map<std::string, void*> const_cache;   // other device-resident constants
+  std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)
   bool prof = false;
   struct ProfRec {
     std::string name;

@@ -45,3 +45,77 @@ hipError_t launch_butterfly(const ButterflyJob* jobs, int njobs, uint32_t* data,
                             int npoly, int log_n, bool inverse, hipStream_t s);
 
 }  // namespace cross
+
+namespace cross {
+
+// Per-limb modulus constants for the vector-ALU streams.
+struct LimbMod {
+  uint32_t q;
+  uint32_t bar_m;     // floor(2^(2k) / q), k = bit length of q (Barrett, Alg. barrett)
+  uint32_t bar_k;     // k
+  uint32_t pad;
+};
+
+// Tensor product of two ciphertext batches in NTT form (HE-Mult step 1):
+// out0 = a0 b0, out1 = a0 b1 + a1 b0, d2 = a1 b1, limb-wise mod q_i.
+// a, b, out: [B][2][L][N]; d2: [B][L][N].
+hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
+                         const LimbMod* mods, int L, int log_n, int B, hipStream_t s);
+
+// Key-switch inner product: acc[b][s][t] = sum_j ext[b][j][t] * key[j][s][t] mod p_t,
+// j < ndig (active digits), s in {0, 1}.  ext: [B][dnum][LK][N], key: [dnum][2][LK][N],
+// acc: [B][2][LK][N].
+hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32_t* acc,
+                                const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
+                                hipStream_t s);
+
+// ModDown tail: out[p][i] = (base[p][i] + (acc[p][i] - z[p][i]) * Pinv_i) mod q_i for the
+// first L limbs of every polynomial p < npoly.  base may be null (treated as 0) or alias out.
+// acc stride: acc_stride elements per poly; z and out/base: L*N per poly.
+struct TailConst {
+  uint32_t q, pinv, pinv_shoup, pad;
+};
+hipError_t launch_moddown_tail(const uint32_t* acc, uint64_t acc_stride, const uint32_t* z,
+                               const uint32_t* base, uint32_t* out, uint64_t out_stride,
+                               const TailConst* tc, int L, int log_n, int npoly,
+                               bool base_only_even, hipStream_t s);
+
+// NTT-domain automorphism: out[p][l][x] = in[p][l][perm[x]] for L limbs of npoly polynomials.
+hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t* out,
+                               uint64_t out_stride, const uint32_t* perm, int log_n, int L,
+                               int npoly, hipStream_t s);
+
+// Pointwise product (VecModMul): out = a * b mod q_limb, all [B][L][N].
+hipError_t launch_pointwise_mul(const uint32_t* a, const uint32_t* b, uint32_t* out,
+                                const LimbMod* mods, int L, int log_n, int B, hipStream_t s);
+
+// Strided limb copy / zero: for each poly p < npoly and limb l < nl:
+// dst[p*dst_stride + dst_off[l] ..+N] = src ? src[p*src_stride + src_off[l] ..] : 0.
+hipError_t launch_limb_copy(const uint32_t* src, uint64_t src_stride, const uint64_t* src_off,
+                            uint32_t* dst, uint64_t dst_stride, const uint64_t* dst_off, int nl,
+                            int log_n, int npoly, hipStream_t s);
+
+// Fast basis conversion (App. BConv) as an int8 MFMA GEMM.
+// Step 1 (fused prologue): b_i = x_i * qhat_i^-1 mod q_i (Shoup constants per source).
+// Step 2: out_t = sum_i b_i [qhat_i]_t mod t via the BAT-expanded table (32x32x32 MFMA).
+struct BconvSrc {
+  uint64_t off;        // element offset of source limb i within a polynomial
+  uint32_t q, w, w_shoup, pad;   // w = qhat_i^-1 mod q_i
+};
+struct BconvDst {
+  uint64_t off;        // element offset of target limb t within a polynomial
+  uint32_t q, qinv;    // target prime, q^-1 mod 2^32
+};
+struct BconvLaunch {
+  const BconvSrc* src;    // nsrc entries (device)
+  const BconvDst* dst;    // ndst entries (device)
+  const int8_t* table;    // fragment-ordered BAT table, mblocks x kblocks x 1 KB
+  int nsrc, ndst;
+  const uint32_t* in;
+  uint32_t* out;
+  uint64_t in_stride, out_stride;   // elements per polynomial
+  int npoly, log_n;
+};
+hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s);
+
+}  // namespace cross
