@@ -79,12 +79,46 @@ def cpu_baseline(budget_s=12.0):
                       "oracle.ntt.ntt_ct/intt_gs, single process" % (done, POLYS, done // (2 * POLYS), dt)}
 
 
+def he_mult_bench(B, steps, warmup, batch):
+    """HE-Mult + relinearisation at N=2^16, L=24, dnum=3, K=8 (and Rotate at the same shape)."""
+    import numpy as np
+    import torch
+    import synthetic
+    qs, ps, a, b, key = synthetic.ckks_pair(0, 16, 24, 3, 8, batch)
+    da = torch.from_numpy(a.view(np.int32)).cuda()
+    db = torch.from_numpy(b.view(np.int32)).cuda()
+    dk = torch.from_numpy(key.view(np.int32)).cuda()
+    out = torch.empty_like(da)
+    res = {}
+    for name, fn in (("he_mult", lambda: B.he_mult(da, db, dk, out, qs, ps, 3)),
+                     ("rotate", lambda: B.rotate(da, 1, dk, out, qs, ps, 3))):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        B.profile_report()
+        B.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = B.profile_report()
+        B.profile_enable(False)
+        res[name] = {"per_s": round(batch * steps / dt, 1), "us_per_op": round(dt / steps / batch * 1e6, 1),
+                     "batch": batch,
+                     "event_us_per_op_by_kernel": {k: round(v[1] * 1e3 / steps / batch, 1) for k, v in prof.items()}}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=["all", "ntt", "copy"], default="all",
+                    help="ntt: time only the NTT step; copy: a plain 256 MiB device copy "
+                         "(calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path shards by ciphertext with no "
@@ -97,6 +131,15 @@ def main():
     from paper_2501_07047_amd import binding as B
 
     torch.cuda.set_device(0)
+    if args.only == "copy":
+        src = torch.ones(1 << 26, dtype=torch.int32, device="cuda")     # 256 MiB
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": args.steps}))
+        return
     B.set_ntt_split(LOG_N, LOG_R)
     primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
     host = torch.from_numpy(x.view(np.int32))
@@ -122,8 +165,14 @@ def main():
     torch.cuda.synchronize()
     exact = exact and bool(torch.equal(data, host.cuda())) and bool(torch.equal(ref, data))
 
-    for _ in range(args.warmup):
+    # warm up for at least ~0.5 s so clocks have ramped before the timed region
+    t_w = time.perf_counter()
+    n_w = 0
+    while n_w < args.warmup or (time.perf_counter() - t_w < 0.5 and n_w < 200):
         step_mfma()
+        n_w += 1
+        if n_w % 10 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     B.profile_report()
     B.profile_enable(True)
@@ -175,6 +224,15 @@ def main():
             "speedup_vs_butterfly": round(value / bf_value, 3),
             "bit_exact": exact,
             "roofline": roof}
+    if args.only == "ntt":
+        print(json.dumps(line))
+        return
+    he1 = he_mult_bench(B, max(4, args.steps // 2), 2, 1)
+    he8 = he_mult_bench(B, max(2, args.steps // 8), 1, 8)
+    line["he_mult_per_s"] = he8["he_mult"]["per_s"]
+    line["he_mult"] = {"config": "N=2^16, L=24, dnum=3 (alpha=8), K=8 special primes, tensor + relinearisation",
+                       "batch1": he1["he_mult"], "batch8": he8["he_mult"]}
+    line["rotate"] = {"config": "same parameters, 1 slot", "batch1": he1["rotate"], "batch8": he8["rotate"]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))

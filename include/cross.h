@@ -67,6 +67,12 @@ cross_status cross_root(uint32_t q, uint32_t log_n, uint32_t* psi_out);
  * R = 2^floor(log_n/2)).  4 <= log_r and 4 <= log_n - log_r. */
 cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r);
 
+/* Workgroup tile of the BAT int8 GEMM steps on this context (autotuner knob):
+ * 0 = automatic (by shape and grid size), 1 = 256x256 (8 waves), 2 = 256x128,
+ * 3 = 128x64, 4 = 64x64.  A tile larger than a step's matrix falls back to auto.
+ * Results are identical for every tile; only speed changes. */
+cross_status cross_set_gemm_tile(cross_ctx ctx, int tile);
+
 /*
  * Forward negacyclic NTT, in place, of `batch` polynomials of L limbs each
  * (Sec. MAT, layout-invariant 3-step NTT; Sec. BAT for the int8 products):

@@ -37,6 +37,7 @@ SIGNATURES = {
     "cross_last_error": [c_vp],
     "cross_root": [c_u32, c_u32, c_u32p],
     "cross_set_ntt_split": [c_vp, c_u32, c_u32],
+    "cross_set_gemm_tile": [c_vp, ctypes.c_int],
     "cross_ntt_forward": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
     "cross_ntt_inverse": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
     "cross_ntt_forward_butterfly": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
@@ -127,6 +128,12 @@ def root(q, log_n):
 def set_ntt_split(log_n, log_r, device=None):
     ctx = context(device)
     _check(lib().cross_set_ntt_split(ctx, log_n, log_r), ctx)
+
+
+def set_gemm_tile(tile, device=None):
+    """0 = auto, 1 = 256x256, 2 = 256x128, 3 = 128x64, 4 = 64x64 (see cross_set_gemm_tile)."""
+    ctx = context(device)
+    _check(lib().cross_set_gemm_tile(ctx, int(tile)), ctx)
 
 
 def _ntt(fn, data, primes):

@@ -182,6 +182,7 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   g.npoly = npoly;
   g.log_r = log_r;
   g.log_c = log_n - log_r;
+  g.tile = ctx->gemm_tile;
   // step 1 (data -> tmp, packed chunks, twiddle fused) then step 3 (tmp -> data)
   g.jobs = (const GemmJob*)d1;
   g.src = data;
@@ -307,6 +308,13 @@ cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r) 
   if (log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4 || log_r > log_n)
     return fail(ctx, CROSS_EINVAL, "split needs 4 <= log_r <= log_n - 4");
   ctx->split[(int)log_n] = (int)log_r;
+  return CROSS_OK;
+}
+
+cross_status cross_set_gemm_tile(cross_ctx ctx, int tile) {
+  if (!ctx) return CROSS_EINVAL;
+  if (tile < 0 || tile > 4) return fail(ctx, CROSS_EINVAL, "tile must be 0 (auto) .. 4");
+  ctx->gemm_tile = tile;
   return CROSS_OK;
 }
 

@@ -32,7 +32,13 @@ struct GemmLaunch {
   int log_r, log_c;
   int kind;                // StepKind
   bool in_packed, out_packed, twiddle;
+  int tile;                // GemmTile; kTileAuto picks by shape and grid size
 };
+
+// Workgroup tile shapes of the BAT GEMM (rows x columns of the int8 product).
+enum GemmTile { kTileAuto = 0, kTile256x256 = 1, kTile256x128 = 2, kTile128x64 = 3, kTile64x64 = 4 };
+// Tile that launch_bat_gemm would use for g (resolves kTileAuto).
+int resolve_gemm_tile(const GemmLaunch& g);
 
 hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s);
 

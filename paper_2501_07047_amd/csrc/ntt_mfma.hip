@@ -44,14 +44,15 @@ __device__ __forceinline__ uint32_t redc(uint64_t z, uint32_t q, uint32_t qinv) 
   return (uint32_t)(z >> 32) + q - u;
 }
 
-template <int WM, int WN, int MB, int NB, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
-__global__ void __launch_bounds__(WM * WN * 64)
+template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   constexpr int NT = WM * WN * 64;
   constexpr int BM = WM * MB * 16;
   constexpr int BN = WN * NB * 16;
-  __shared__ __attribute__((aligned(16))) int8_t lds_a[BM * LDS_ROW];
-  __shared__ __attribute__((aligned(16))) int8_t lds_b[BN * LDS_ROW];
+  // two LDS stages: the next K step is written while the current one is multiplied
+  __shared__ __attribute__((aligned(16))) int8_t lds_a[2][BM * LDS_ROW];
+  __shared__ __attribute__((aligned(16))) int8_t lds_b[2][BN * LDS_ROW];
 
   const int R = 1 << g.log_r, C = 1 << g.log_c;
   const int U = RIGHT ? C : R;          // outputs per column (and inputs per column)
@@ -86,73 +87,52 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = v4i{0, 0, 0, 0};
 
-  // ---- global -> register staging --------------------------------------
+  // ---- global -> register staging ------------------------------------------
   constexpr int A_VEC = BM * BK / 16 / NT;     // 16-byte table pieces per thread
   static_assert(A_VEC >= 1, "tile too small");
-  v4i ra[A_VEC];
   // B staging: each thread owns BN*16 words / NT words (16 = inputs per K step)
   constexpr int B_WORDS = BN * 16 / NT;
-  static_assert(B_WORDS >= 1 && (B_WORDS % 4) == 0, "B staging");
+  static_assert(B_WORDS >= 4 && (B_WORDS % 4) == 0, "B staging");
+  constexpr int TPC_R = 16 / B_WORDS;           // RIGHT: threads per column
+  v4i ra[A_VEC];
   uint32_t rb[B_WORDS];
 
-  auto load_a = [&](int ks) {
+  // this thread's B column and first input of a K step
+  const int b_n = RIGHT ? tid / TPC_R : tid % BN;
+  const int b_xs = RIGHT ? (tid % TPC_R) * B_WORDS : (tid / BN) * B_WORDS;
+  const bool b_ok = (n0 + b_n) < ncols;
+  const uint32_t* b_base;
+  {
+    const int n = b_ok ? n0 + b_n : 0;
+    const int poly = n / V, v = n - poly * V;
+    b_base = src + (size_t)poly * g.src_stride + (RIGHT ? (size_t)v * C + b_xs : (size_t)b_xs * C + v);
+  }
+
+  auto load = [&](int ks) {
     const int8_t* base = tab + (size_t)ks * ((size_t)M * BK) + (size_t)m0 * BK;
 #pragma unroll
-    for (int i = 0; i < A_VEC; ++i) {
-      int piece = tid + i * NT;                 // contiguous 16 B pieces of the tile
-      ra[i] = *reinterpret_cast<const v4i*>(base + piece * 16);
-    }
-  };
-
-  // B element (input x, column n) lives at src + poly * stride + x * sx + v * sv
-  auto load_b = [&](int ks) {
+    for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const v4i*>(base + (tid + i * NT) * 16);
+    // B element (input x, column n) lives at src + poly * stride + x * sx + v * sv
     const int x0 = ks * 16;
     if (!RIGHT) {
-      // inputs run down rows (stride C); columns are contiguous: thread = column
-      constexpr int TPC = NT / BN;              // threads per column
-      const int n = n0 + (tid % BN);
-      const int xs = (tid / BN) * B_WORDS;      // first input row of this thread
-      const bool ok = n < ncols;
-      const int poly = ok ? n / V : 0, v = ok ? n - poly * V : 0;
-      const uint32_t* p = src + (size_t)poly * g.src_stride + (size_t)(x0 + xs) * C + v;
+      const uint32_t* p = b_base + (size_t)x0 * C;
 #pragma unroll
-      for (int w = 0; w < B_WORDS; ++w) rb[w] = ok ? p[(size_t)w * C] : 0u;
-      (void)TPC;
+      for (int w = 0; w < B_WORDS; ++w) rb[w] = b_ok ? p[(size_t)w * C] : 0u;
     } else {
-      // inputs run along a row (contiguous); thread = (column, run of B_WORDS inputs)
-      constexpr int TPC = 16 / B_WORDS;
-      const int n = n0 + tid / TPC;
-      const int xs = (tid % TPC) * B_WORDS;
-      const bool ok = n < ncols;
-      const int poly = ok ? n / V : 0, v = ok ? n - poly * V : 0;
-      const uint32_t* p = src + (size_t)poly * g.src_stride + (size_t)v * C + x0 + xs;
+      const uint32_t* p = b_base + x0;
 #pragma unroll
       for (int w = 0; w < B_WORDS; w += 4) {
-        if (ok) {
-          v4i t = *reinterpret_cast<const v4i*>(p + w);
-          rb[w] = t.x; rb[w + 1] = t.y; rb[w + 2] = t.z; rb[w + 3] = t.w;
-        } else {
-          rb[w] = rb[w + 1] = rb[w + 2] = rb[w + 3] = 0u;
-        }
+        v4i t = b_ok ? *reinterpret_cast<const v4i*>(p + w) : v4i{0, 0, 0, 0};
+        rb[w] = t.x; rb[w + 1] = t.y; rb[w + 2] = t.z; rb[w + 3] = t.w;
       }
     }
   };
 
-  auto store_lds = [&]() {
+  auto store_lds = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_VEC; ++i) {
       int piece = tid + i * NT;
-      int row = piece >> 2, kq = piece & 3;
-      *reinterpret_cast<v4i*>(lds_a + row * LDS_ROW + kq * 16) = ra[i];
-    }
-    int n, xs;
-    if (!RIGHT) {
-      n = tid % BN;
-      xs = (tid / BN) * B_WORDS;
-    } else {
-      constexpr int TPC = 16 / B_WORDS;
-      n = tid / TPC;
-      xs = (tid % TPC) * B_WORDS;
+      *reinterpret_cast<v4i*>(&lds_a[buf][(piece >> 2) * LDS_ROW + (piece & 3) * 16]) = ra[i];
     }
 #pragma unroll
     for (int w = 0; w < B_WORDS; w += 4) {
@@ -161,34 +141,41 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
       t.y = IN_PACKED ? rb[w + 1] : pack_chunks(rb[w + 1]);
       t.z = IN_PACKED ? rb[w + 2] : pack_chunks(rb[w + 2]);
       t.w = IN_PACKED ? rb[w + 3] : pack_chunks(rb[w + 3]);
-      *reinterpret_cast<v4i*>(lds_b + n * LDS_ROW + (xs + w) * 4) = t;
+      *reinterpret_cast<v4i*>(&lds_b[buf][b_n * LDS_ROW + (b_xs + w) * 4]) = t;
     }
   };
 
-  const int nk = K / BK;
-  load_a(0);
-  load_b(0);
-  for (int ks = 0; ks < nk; ++ks) {
-    __syncthreads();
-    store_lds();
-    __syncthreads();
-    if (ks + 1 < nk) {
-      load_a(ks + 1);
-      load_b(ks + 1);
-    }
+  auto compute = [&](int buf) {
     const int koff = (lane >> 4) * 16;
     v4i fa[MB], fb[NB];
 #pragma unroll
     for (int a = 0; a < MB; ++a)
-      fa[a] = *reinterpret_cast<const v4i*>(lds_a + (wm * MB * 16 + a * 16 + (lane & 15)) * LDS_ROW + koff);
+      fa[a] = *reinterpret_cast<const v4i*>(&lds_a[buf][(wm * MB * 16 + a * 16 + (lane & 15)) * LDS_ROW + koff]);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      fb[b] = *reinterpret_cast<const v4i*>(lds_b + (wn * NB * 16 + b * 16 + (lane & 15)) * LDS_ROW + koff);
+      fb[b] = *reinterpret_cast<const v4i*>(&lds_b[buf][(wn * NB * 16 + b * 16 + (lane & 15)) * LDS_ROW + koff]);
+    __builtin_amdgcn_s_setprio(1);   // keep the matrix pipe fed ahead of the staging waves
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    __builtin_amdgcn_s_setprio(0);
+  };
+
+  // Software pipeline over K steps: LDS stage ks&1 is multiplied while stage
+  // (ks+1)&1 is written from registers and step ks+2 is in flight from global
+  // memory.  One barrier per step.
+  const int nk = K / BK;
+  load(0);
+  store_lds(0);
+  if (nk > 1) load(1);
+  __syncthreads();
+  for (int ks = 0; ks < nk; ++ks) {
+    if (ks + 1 < nk) store_lds((ks + 1) & 1);
+    if (ks + 2 < nk) load(ks + 2);
+    compute(ks & 1);
+    __syncthreads();
   }
 
   // ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ----------
@@ -219,7 +206,7 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   (void)M;
 }
 
-template <int WM, int WN, int MB, int NB, bool RIGHT, bool INP, bool OUTP, bool TW>
+template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool INP, bool OUTP, bool TW>
 hipError_t launch_cfg(const GemmLaunch& g, hipStream_t s) {
   constexpr int BM = WM * MB * 16, BN = WN * NB * 16;
   const int U = RIGHT ? (1 << g.log_c) : (1 << g.log_r);
@@ -230,36 +217,58 @@ hipError_t launch_cfg(const GemmLaunch& g, hipStream_t s) {
   const int ncols = g.npoly * V;
   const int tiles_n = (ncols + BN - 1) / BN;
   const int grid = g.njobs * tiles_m * tiles_n;
-  hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, RIGHT, INP, OUTP, TW>), dim3(grid),
+  hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, RIGHT, INP, OUTP, TW>), dim3(grid),
                      dim3(WM * WN * 64), 0, s, g, tiles_m, tiles_n);
   return hipGetLastError();
 }
 
-template <int WM, int WN, int MB, int NB>
+template <int WM, int WN, int MB, int NB, int OCC>
 hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
   // forward: LEFT(plain in, packed out, twiddle) then RIGHT(packed in, plain out)
   // inverse: RIGHT(plain in, packed out, twiddle) then LEFT(packed in, plain out)
   const bool right = g.kind == kRight;
   if (!right && !g.in_packed && g.out_packed && g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, false, false, true, true>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, false, false, true, true>(g, s);
   if (right && g.in_packed && !g.out_packed && !g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, true, true, false, false>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, true, true, false, false>(g, s);
   if (right && !g.in_packed && g.out_packed && g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, true, false, true, true>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, true, false, true, true>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, false, true, false, false>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, false, true, false, false>(g, s);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+int resolve_gemm_tile(const GemmLaunch& g) {
+  const int U = (g.kind == kRight) ? (1 << g.log_c) : (1 << g.log_r);
+  const int V = (g.kind == kRight) ? (1 << g.log_r) : (1 << g.log_c);
+  const int M = 4 * U;
+  const long ncols = (long)g.npoly * V;
+  int t = g.tile;
+  if (t == kTile256x256 && M < 256) t = kTileAuto;
+  if (t == kTile256x128 && M < 256) t = kTileAuto;
+  if (t == kTile128x64 && M < 128) t = kTileAuto;
+  if (t != kTileAuto) return t;
+  if (M >= 256) {
+    // prefer the large tile when it still gives every CU two workgroups
+    long grid = (long)g.njobs * (M / 256) * ((ncols + 127) / 128);
+    if (grid >= 512) return kTile256x128;
+    return kTile128x64;
+  }
+  if (M >= 128) return kTile128x64;
+  return kTile64x64;
+}
+
 hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s) {
   const int U = (g.kind == kRight) ? (1 << g.log_c) : (1 << g.log_r);
-  const int M = 4 * U;
-  if (M >= 256) return dispatch_flags<2, 2, 8, 4>(g, s);     // 256 x 128 tile
-  if (M >= 128) return dispatch_flags<2, 2, 4, 2>(g, s);     // 128 x 64 tile
-  if (M >= 64) return dispatch_flags<2, 2, 2, 2>(g, s);      // 64 x 64 tile
-  return hipErrorInvalidValue;
+  if (4 * U < 64) return hipErrorInvalidValue;
+  switch (resolve_gemm_tile(g)) {
+    case kTile256x256: return dispatch_flags<2, 4, 8, 4, 2>(g, s);   // 8 waves, one workgroup per CU
+    case kTile256x128: return dispatch_flags<2, 2, 8, 4, 2>(g, s);   // 4 waves, two workgroups per CU
+    case kTile128x64: return dispatch_flags<2, 2, 4, 2, 2>(g, s);
+    default: return dispatch_flags<2, 2, 2, 2, 2>(g, s);
+  }
 }
 
 }  // namespace cross

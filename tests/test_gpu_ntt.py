@@ -120,3 +120,20 @@ def test_argument_errors():
     assert e.value.code == -3
     with pytest.raises(ValueError):
         B.ntt_forward(torch.zeros((1, 1, 1000), dtype=torch.int32, device="cuda"), [268042241])
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+def test_every_tile_shape_is_bit_exact(tile):
+    from paper_2501_07047_amd import binding as B
+    B.set_gemm_tile(tile)
+    try:
+        for log_n, L, batch in ((16, 2, 3), (12, 3, 2), (10, 2, 1)):
+            primes, x = synthetic.ntt_batch(tile * 10 + log_n, log_n, L, batch)
+            ref = _oracle_ntt(x, primes)
+            d = to_dev(x)
+            B.ntt_forward(d, primes)
+            assert np.array_equal(to_host(d), ref)
+            B.ntt_inverse(d, primes)
+            assert np.array_equal(to_host(d), x)
+    finally:
+        B.set_gemm_tile(0)
