@@ -177,6 +177,45 @@ cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* params, int32_
                           void* stream);
 
 /*
+ * Batch runtime (many jobs of uneven N and limb count in one pass).
+ * Jobs are lowered onto a fixed sequence of 15 work-list launches (one per
+ * step of the hot path, each covering that step for every job; the BAT GEMM
+ * steps run as persistent grids over (task, tile) lists), optionally captured
+ * once into a hipGraph so that a run is a single graph launch.  Results are
+ * bit-identical to the per-call entry points.
+ *   op CROSS_OP_NTT_FORWARD / _INVERSE: params.log_n, params.L, params.primes (L
+ *        primes); data = device [batch][L][N], transformed in place.
+ *   op CROSS_OP_HE_MULT: params as cross_he_mult; ct_a, ct_b, key, out as there.
+ *   op CROSS_OP_ROTATE : params, steps, ct_a (the ciphertext), key (rotation key), out.
+ * Limits: 12 <= log_n <= 16 and both R, C >= 64 for every job.  All buffers
+ * must stay allocated while the batch exists; their contents may change
+ * between runs.  A batch owns its workspace; concurrent runs of one batch race.
+ */
+enum { CROSS_OP_NTT_FORWARD = 1, CROSS_OP_NTT_INVERSE = 2, CROSS_OP_HE_MULT = 3, CROSS_OP_ROTATE = 4 };
+typedef struct cross_job {
+  uint32_t op;
+  cross_ckks_params params;
+  uint32_t batch;           /* polynomials (NTT) or ciphertexts */
+  int32_t steps;            /* rotation steps (CROSS_OP_ROTATE) */
+  uint32_t* data;           /* NTT jobs */
+  const uint32_t* ct_a;
+  const uint32_t* ct_b;
+  const uint32_t* key;
+  uint32_t* out;
+} cross_job;
+typedef struct cross_batch_s* cross_batch;
+/* Plan the jobs (tables, task lists, workspace) and, if use_graph, capture the
+ * launch sequence into a hipGraph.  No device work runs until cross_batch_run. */
+cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
+                                cross_batch* out);
+/* Enqueue one pass over every job on `stream` (graph launch or eager launches). */
+cross_status cross_batch_run(cross_batch batch, void* stream);
+/* Launch count per run (eager), workspace bytes and total GEMM tiles per run. */
+cross_status cross_batch_info(cross_batch batch, uint32_t* launches, uint64_t* workspace_bytes,
+                              uint64_t* gemm_tiles);
+void cross_batch_destroy(cross_batch batch);
+
+/*
  * Kernel timing with HIP events (tracing aid).  While enabled, every kernel
  * launch the library makes is bracketed by a pair of events recorded on the
  * launch stream.  cross_profile_report synchronises on the recorded events

@@ -48,6 +48,10 @@ SIGNATURES = {
     "cross_keyswitch_moddown": [c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_he_mult": [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_rotate": [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_u32, c_vp],
+    "cross_batch_create": [c_vp, c_vp, c_u32, ctypes.c_int, ctypes.POINTER(c_vp)],
+    "cross_batch_run": [c_vp, c_vp],
+    "cross_batch_info": [c_vp, ctypes.POINTER(c_u32), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+    "cross_batch_destroy": [c_vp],
     "cross_profile_enable": [c_vp, ctypes.c_int],
     "cross_profile_report": [c_vp, ctypes.c_char_p, ctypes.c_uint64],
     "cross_host_tables": [c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
@@ -66,6 +70,7 @@ def lib():
             f.argtypes = args
             f.restype = ctypes.c_int
         l.cross_ctx_destroy.restype = None
+        l.cross_batch_destroy.restype = None
         l.cross_last_error.restype = ctypes.c_char_p
         _lib = l
     return _lib
@@ -282,3 +287,77 @@ def rotate(ct, steps, key, out, qs, ps, dnum):
     _check(lib().cross_rotate(ctx, ctypes.byref(prm), int(steps), _dev_ptr(ct, "ct"), _dev_ptr(key, "key"),
                               _dev_ptr(out, "out"), batch, _stream(ct)), ctx)
     return out
+
+
+OP_NTT_FORWARD, OP_NTT_INVERSE, OP_HE_MULT, OP_ROTATE = 1, 2, 3, 4
+
+
+class Job(ctypes.Structure):
+    """Mirror of cross_job."""
+    _fields_ = [("op", c_u32), ("params", CkksParams), ("batch", c_u32), ("steps", c_i32),
+                ("data", c_vp), ("ct_a", c_vp), ("ct_b", c_vp), ("key", c_vp), ("out", c_vp)]
+
+
+def _ptr(t):
+    return None if t is None else _dev_ptr(t, "buffer").value
+
+
+class Batch:
+    """A planned batch of jobs (cross_batch).  Each job is a dict:
+    {"op": "ntt_forward"|"ntt_inverse", "data": t[batch][L][N], "primes": [...]}
+    {"op": "he_mult", "a", "b", "key", "out", "qs", "ps", "dnum"}
+    {"op": "rotate", "ct", "key", "out", "qs", "ps", "dnum", "steps"}
+    Tensors must stay alive while the batch exists."""
+
+    def __init__(self, jobs, use_graph=True, device=None):
+        self.ctx = context(device)
+        arr = (Job * len(jobs))()
+        self._keep = []
+        for i, j in enumerate(jobs):
+            op = j["op"]
+            if op in ("ntt_forward", "ntt_inverse"):
+                d = j["data"]
+                bt, L, n = d.shape
+                prm = _params(j["primes"], [], 1, n)
+                prm.K = 0
+                arr[i] = Job(OP_NTT_FORWARD if op == "ntt_forward" else OP_NTT_INVERSE, prm, bt, 0,
+                             _ptr(d), None, None, None, None)
+            elif op == "he_mult":
+                a = j["a"]
+                prm = _params(j["qs"], j["ps"], j["dnum"], a.shape[-1])
+                arr[i] = Job(OP_HE_MULT, prm, a.shape[0], 0, None, _ptr(a), _ptr(j["b"]), _ptr(j["key"]),
+                             _ptr(j["out"]))
+            elif op == "rotate":
+                a = j["ct"]
+                prm = _params(j["qs"], j["ps"], j["dnum"], a.shape[-1])
+                arr[i] = Job(OP_ROTATE, prm, a.shape[0], int(j["steps"]), None, _ptr(a), None, _ptr(j["key"]),
+                             _ptr(j["out"]))
+            else:
+                raise ValueError("unknown op %r" % op)
+            self._keep.append(prm)
+        self._keep.append(arr)
+        h = c_vp()
+        _check(lib().cross_batch_create(self.ctx, ctypes.cast(arr, c_vp), len(jobs), 1 if use_graph else 0,
+                                        ctypes.byref(h)), self.ctx)
+        self.handle = h
+
+    def run(self, stream=None):
+        import torch
+        s = c_vp(torch.cuda.current_stream().cuda_stream) if stream is None else c_vp(stream)
+        _check(lib().cross_batch_run(self.handle, s), self.ctx)
+
+    def info(self):
+        n, ws, tiles = c_u32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().cross_batch_info(self.handle, ctypes.byref(n), ctypes.byref(ws), ctypes.byref(tiles)), self.ctx)
+        return {"launches": n.value, "workspace_bytes": ws.value, "gemm_tiles": tiles.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cross_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

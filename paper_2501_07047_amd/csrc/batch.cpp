@@ -1,0 +1,419 @@
+// Batch runtime: many jobs of uneven N, limb count and kind in a fixed
+// sequence of work-list launches, optionally captured once as a hipGraph.
+//
+// Every job is lowered onto the same 15 phases (automorphism, tensor product,
+// ModUp copies, INTT, BConv, NTT, inner product, ModDown INTT / BConv / NTT,
+// tail).  A phase is one launch whose task list holds the work of every job
+// that takes part in it: GEMM phases list (task, tile) pairs of the BAT NTT
+// steps, each task carrying its own N, R x C split, prime, tables and buffers,
+// and run as one persistent grid; vector phases list one task per polynomial.
+// Launch boundaries order the phases, so a batch of any size costs 15
+// launches, and replaying the captured graph costs one.
+#include <algorithm>
+#include <memory>
+#include <string>
+
+#include "ckks_plan.h"
+#include "context.h"
+#include "params.h"
+
+namespace cross {
+
+namespace {
+
+enum PhaseId {
+  kAuto, kTensor, kCopy, kInv1, kInv2, kBconvUp, kFwd1, kFwd3, kInner, kInv1P, kInv2P, kBconvDown,
+  kFwd1Z, kFwd3Z, kTail, kNumPhases
+};
+
+struct GemmPhase {
+  std::vector<GemmTask> tasks;
+  std::vector<GemmTileRef> tiles;
+  const GemmTask* d_tasks = nullptr;
+  const GemmTileRef* d_tiles = nullptr;
+};
+
+}  // namespace
+
+}  // namespace cross
+
+struct cross_batch_s {
+  cross_ctx ctx = nullptr;
+  int grid = 512;
+  cross::GemmPhase gemm[cross::kNumPhases];
+  std::vector<cross::AutoTask> autos;
+  std::vector<cross::TensorTask> tensors;
+  std::vector<cross::CopyTask> copies;
+  std::vector<cross::BconvLaunch> bconv_up, bconv_down;
+  std::vector<cross::InnerTask> inners;
+  std::vector<cross::TailTask> tails;
+  const cross::AutoTask* d_autos = nullptr;
+  const cross::TensorTask* d_tensors = nullptr;
+  const cross::CopyTask* d_copies = nullptr;
+  const cross::BconvLaunch *d_bconv_up = nullptr, *d_bconv_down = nullptr;
+  const cross::InnerTask* d_inners = nullptr;
+  const cross::TailTask* d_tails = nullptr;
+  uint64_t max_auto = 0, max_tensor = 0, max_copy = 0, max_inner = 0, max_tail = 0;
+  uint64_t max_waves_up = 0, max_waves_down = 0;
+  std::vector<void*> allocs;
+  uint64_t ws_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace cross {
+
+namespace {
+
+template <typename T>
+cross_status upload(cross_batch b, const std::vector<T>& v, const T** out) {
+  *out = nullptr;
+  if (v.empty()) return CROSS_OK;
+  void* d = nullptr;
+  if (hipMalloc(&d, v.size() * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(b->ctx, CROSS_ENOMEM, "batch task list allocation failed");
+  }
+  b->allocs.push_back(d);
+  if (hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
+  *out = static_cast<const T*>(d);
+  return CROSS_OK;
+}
+
+// Add the tiles of one limb list of one NTT step to a GEMM phase.
+// Limb i of polynomial p lives at base + p * stride + offs[i]; `tmp` has the same layout.
+void add_ntt_step(GemmPhase& ph, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+                  const uint32_t* src_base, uint32_t* dst_base, uint64_t stride, int npoly, bool inverse,
+                  bool first) {
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    const int log_r = p->log_r, log_c = p->log_n - p->log_r;
+    // first step: forward = left-known TF1 (+T2), inverse = right-known ITF3 (+IT2)
+    const bool right = inverse ? first : !first;
+    GemmTask t{};
+    if (inverse)
+      t.table = first ? p->inv_right : p->inv_left;
+    else
+      t.table = first ? p->fwd_left : p->fwd_right;
+    t.tw = first ? (inverse ? p->inv_tw : p->fwd_tw) : nullptr;
+    t.src = src_base + offs[i];
+    t.dst = dst_base + offs[i];
+    t.src_stride = t.dst_stride = stride;
+    t.q = p->q;
+    t.qinv = p->qinv;
+    t.npoly = npoly;
+    t.log_r = (int16_t)log_r;
+    t.log_c = (int16_t)log_c;
+    const int U = right ? (1 << log_c) : (1 << log_r);
+    const int V = right ? (1 << log_r) : (1 << log_c);
+    const int tm_n = 4 * U / gemm_list_tile_rows();
+    const long ncols = (long)npoly * V;
+    const int tn_n = (int)((ncols + gemm_list_tile_cols() - 1) / gemm_list_tile_cols());
+    const uint32_t id = (uint32_t)ph.tasks.size();
+    ph.tasks.push_back(t);
+    for (int tn = 0; tn < tn_n; ++tn)
+      for (int tm = 0; tm < tm_n; ++tm) ph.tiles.push_back(GemmTileRef{id, (uint16_t)tm, (uint16_t)tn});
+  }
+}
+
+// A full NTT (both steps) of a limb list through `tmp`.
+void add_ntt(cross_batch b, int first_phase, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+             uint32_t* data, uint32_t* tmp, uint64_t stride, int npoly, bool inverse) {
+  add_ntt_step(b->gemm[first_phase], plans, offs, data, tmp, stride, npoly, inverse, true);
+  add_ntt_step(b->gemm[first_phase + 1], plans, offs, tmp, data, stride, npoly, inverse, false);
+}
+
+bool split_ok(const Plan* p) {
+  // the work-list GEMM uses 256-row tiles: both 4R and 4C must be multiples of 256
+  return p->log_r >= 6 && p->log_n - p->log_r >= 6;
+}
+
+hipError_t run_phases(cross_batch b, hipStream_t s, bool prof) {
+  cross_ctx ctx = b->ctx;
+  hipError_t e = hipSuccess;
+  auto gemm = [&](int ph, int kind, bool inp, bool outp, bool tw, const char* name) {
+    if (e != hipSuccess || b->gemm[ph].tiles.empty()) return;
+    const int nt = (int)b->gemm[ph].tiles.size();
+    const int grid = std::min(b->grid, ((nt + 7) / 8) * 8);
+    ProfScope ps(prof ? ctx : nullptr, name, s);
+    e = launch_bat_gemm_list(b->gemm[ph].d_tasks, b->gemm[ph].d_tiles, nt, grid, kind, inp, outp, tw, s);
+  };
+  auto vec = [&](const char* name, auto fn) {
+    if (e != hipSuccess) return;
+    ProfScope ps(prof ? ctx : nullptr, name, s);
+    e = fn();
+  };
+  vec("automorphism", [&] { return launch_auto_list(b->d_autos, (int)b->autos.size(), b->max_auto, s); });
+  vec("tensor", [&] { return launch_tensor_list(b->d_tensors, (int)b->tensors.size(), b->max_tensor, s); });
+  vec("limb_copy", [&] { return launch_copy_list(b->d_copies, (int)b->copies.size(), b->max_copy, s); });
+  gemm(kInv1, kRight, false, true, true, "bat_gemm_right");
+  gemm(kInv2, kLeft, true, false, false, "bat_gemm_left");
+  vec("bconv", [&] { return launch_bconv_list(b->d_bconv_up, (int)b->bconv_up.size(), b->max_waves_up, s); });
+  gemm(kFwd1, kLeft, false, true, true, "bat_gemm_left");
+  gemm(kFwd3, kRight, true, false, false, "bat_gemm_right");
+  vec("inner_product", [&] { return launch_inner_list(b->d_inners, (int)b->inners.size(), b->max_inner, s); });
+  gemm(kInv1P, kRight, false, true, true, "bat_gemm_right");
+  gemm(kInv2P, kLeft, true, false, false, "bat_gemm_left");
+  vec("bconv", [&] { return launch_bconv_list(b->d_bconv_down, (int)b->bconv_down.size(), b->max_waves_down, s); });
+  gemm(kFwd1Z, kLeft, false, true, true, "bat_gemm_left");
+  gemm(kFwd3Z, kRight, true, false, false, "bat_gemm_right");
+  vec("moddown_tail", [&] { return launch_tail_list(b->d_tails, (int)b->tails.size(), b->max_tail, s); });
+  return e;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+}  // namespace cross
+
+using namespace cross;
+
+extern "C" {
+
+void cross_batch_destroy(cross_batch b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (void* p : b->allocs) (void)hipFree(p);
+  delete b;
+}
+
+cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
+                                cross_batch* out) {
+  if (!ctx || !out) return CROSS_EINVAL;
+  *out = nullptr;
+  if (!jobs || njobs == 0) return fail(ctx, CROSS_EINVAL, "empty job list");
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
+  std::unique_ptr<cross_batch_s, void (*)(cross_batch)> b(new cross_batch_s(), cross_batch_destroy);
+  b->ctx = ctx;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
+    b->grid = ((2 * ncu + 7) / 8) * 8;   // two resident GEMM workgroups per CU
+
+  // ---- pass 1: validate, plan, size the workspace --------------------------------
+  struct JobPlan {
+    CkksPlan* c = nullptr;
+    std::vector<Plan*> plans;   // NTT jobs
+    uint64_t ws = 0;            // words
+  };
+  std::vector<JobPlan> jp(njobs);
+  uint64_t ws_words = 0;
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const cross_job& J = jobs[j];
+    const cross_ckks_params& P = J.params;
+    if (J.batch < 1) return fail(ctx, CROSS_EINVAL, "job " + std::to_string(j) + ": batch must be >= 1");
+    if (P.log_n < 12 || P.log_n > CROSS_MAX_LOG_N)
+      return fail(ctx, CROSS_EUNSUPPORTED, "job " + std::to_string(j) + ": batch runtime needs 12 <= log_n <= 16");
+    const uint64_t N = 1ull << P.log_n;
+    if (J.op == CROSS_OP_NTT_FORWARD || J.op == CROSS_OP_NTT_INVERSE) {
+      if (!J.data || !aligned16(J.data) || !P.primes || P.L < 1 || P.L > CROSS_MAX_LIMBS)
+        return fail(ctx, CROSS_EINVAL, "job " + std::to_string(j) + ": bad NTT job");
+      for (uint32_t i = 0; i < P.L; ++i) {
+        cross_status st = check_prime(ctx, P.primes[i], P.log_n);
+        if (st != CROSS_OK) return st;
+        Plan* p = nullptr;
+        if ((st = get_plan(ctx, P.primes[i], (int)P.log_n, &p)) != CROSS_OK) return st;
+        if (!split_ok(p)) return fail(ctx, CROSS_EUNSUPPORTED, "batch runtime needs R, C >= 64");
+        jp[j].plans.push_back(p);
+      }
+      jp[j].ws = (uint64_t)J.batch * P.L * N;
+    } else if (J.op == CROSS_OP_HE_MULT || J.op == CROSS_OP_ROTATE) {
+      cross_status st = get_ckks_plan(ctx, &P, &jp[j].c);
+      if (st != CROSS_OK) return st;
+      for (Plan* p : jp[j].c->plans)
+        if (!split_ok(p)) return fail(ctx, CROSS_EUNSUPPORTED, "batch runtime needs R, C >= 64");
+      const bool he = J.op == CROSS_OP_HE_MULT;
+      if (!J.ct_a || !J.key || !J.out || (he && !J.ct_b) || !aligned16(J.ct_a) || !aligned16(J.key) ||
+          !aligned16(J.out) || (he && !aligned16(J.ct_b)))
+        return fail(ctx, CROSS_EINVAL, "job " + std::to_string(j) + ": bad ciphertext job");
+      const CkksPlan* c = jp[j].c;
+      const uint64_t LK = c->L + c->K;
+      const uint64_t nd = (uint64_t)c->L * N, next = (uint64_t)c->dnum * LK * N;
+      const uint64_t nacc = 2 * LK * N, nz = 2ull * c->L * N;
+      // NTT scratch is used with the layouts of d, ext, acc and z in turn
+      const uint64_t ntmp = std::max(next, nacc);
+      jp[j].ws = (uint64_t)J.batch * (nd + next + ntmp + nacc + nz);
+    } else {
+      return fail(ctx, CROSS_EINVAL, "job " + std::to_string(j) + ": unknown op");
+    }
+    ws_words += (jp[j].ws + 63) & ~(uint64_t)63;
+  }
+  void* wsp = nullptr;
+  if (hipMalloc(&wsp, ws_words * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, CROSS_ENOMEM, "batch workspace allocation failed");
+  }
+  b->allocs.push_back(wsp);
+  b->ws_bytes = ws_words * 4;
+
+  // ---- pass 2: lower every job onto the phases ------------------------------------
+  uint32_t* ws = static_cast<uint32_t*>(wsp);
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const cross_job& J = jobs[j];
+    const uint64_t N = 1ull << J.params.log_n;
+    uint32_t* mine = ws;
+    ws += (jp[j].ws + 63) & ~(uint64_t)63;
+    if (J.op == CROSS_OP_NTT_FORWARD || J.op == CROSS_OP_NTT_INVERSE) {
+      const bool inv = J.op == CROSS_OP_NTT_INVERSE;
+      std::vector<uint64_t> offs(J.params.L);
+      for (uint32_t i = 0; i < J.params.L; ++i) offs[i] = i * N;
+      add_ntt(b.get(), inv ? kInv1 : kFwd1, jp[j].plans, offs, J.data, mine, (uint64_t)J.params.L * N,
+              (int)J.batch, inv);
+      continue;
+    }
+    const CkksPlan* c = jp[j].c;
+    const bool he = J.op == CROSS_OP_HE_MULT;
+    const int L = c->L, K = c->K, LK = L + K, B = (int)J.batch;
+    const uint64_t nd = (uint64_t)L * N, next = (uint64_t)c->dnum * LK * N, nacc = 2ull * LK * N;
+    const uint64_t ntmp = std::max(next, nacc);
+    uint32_t* d = mine;
+    uint32_t* ext = d + B * nd;
+    uint32_t* tmp = ext + B * next;
+    uint32_t* acc = tmp + B * ntmp;
+    uint32_t* z = acc + B * nacc;
+    const uint64_t ct = 2 * nd;   // words per ciphertext
+    const uint32_t* perm = nullptr;
+    if (!he) {
+      const int64_t half = (int64_t)N / 2;
+      const uint64_t r = (uint64_t)((((int64_t)J.steps % half) + half) % half);
+      cross_status st = perm_table(ctx, c->log_n, powmod(5, r, (uint32_t)(2 * N)), &perm);
+      if (st != CROSS_OK) return st;
+    }
+    for (int bb = 0; bb < B; ++bb) {
+      const uint32_t* a = J.ct_a + bb * ct;
+      uint32_t* o = J.out + bb * ct;
+      uint32_t* db = d + bb * nd;
+      if (he) {
+        b->tensors.push_back(TensorTask{a, J.ct_b + bb * ct, o, db, c->mods, L, c->log_n, nd / 4});
+        b->max_tensor = std::max(b->max_tensor, nd / 4);
+      } else {
+        b->autos.push_back(AutoTask{a, o, perm, c->log_n, nd});            // sigma(c0) -> out[0]
+        b->autos.push_back(AutoTask{a + nd, db, perm, c->log_n, nd});      // sigma(c1) -> d
+        b->max_auto = std::max(b->max_auto, nd);
+      }
+      // ModUp: digit limbs copied unchanged, inactive digits zeroed
+      uint32_t* eb = ext + bb * next;
+      for (int dj = 0; dj < c->dnum; ++dj) {
+        if (dj < c->ndig) {
+          const int lo = dj * c->alpha, hi = std::min(L, (dj + 1) * c->alpha);
+          const uint64_t cnt = (uint64_t)(hi - lo) * N / 4;
+          b->copies.push_back(CopyTask{db + lo * N, eb + ((uint64_t)dj * LK + lo) * N, cnt});
+          b->max_copy = std::max(b->max_copy, cnt);
+        } else {
+          b->copies.push_back(CopyTask{nullptr, eb + (uint64_t)dj * LK * N, (uint64_t)LK * N / 4});
+          b->max_copy = std::max(b->max_copy, (uint64_t)LK * N / 4);
+        }
+      }
+      b->inners.push_back(InnerTask{eb, J.key, acc + bb * nacc, c->mods, LK, c->dnum, c->ndig, c->log_n,
+                                    (uint64_t)LK * N / 4});
+      b->max_inner = std::max(b->max_inner, (uint64_t)LK * N / 4);
+      for (int sidx = 0; sidx < 2; ++sidx) {
+        const uint32_t* base = (he || sidx == 0) ? o + sidx * nd : nullptr;
+        b->tails.push_back(TailTask{acc + bb * nacc + sidx * (uint64_t)LK * N, z + (bb * 2 + sidx) * nd, base,
+                                    o + sidx * nd, c->tail, L, c->log_n, nd / 4});
+        b->max_tail = std::max(b->max_tail, nd / 4);
+      }
+    }
+    // INTT of d (all L limbs)
+    std::vector<Plan*> qp(c->plans.begin(), c->plans.begin() + L);
+    std::vector<uint64_t> qo(L);
+    for (int i = 0; i < L; ++i) qo[i] = i * N;
+    add_ntt(b.get(), kInv1, qp, qo, d, tmp, nd, B, true);
+    // BConv of each digit, NTT of every converted limb
+    std::vector<Plan*> ep;
+    std::vector<uint64_t> eo;
+    for (int dj = 0; dj < c->ndig; ++dj) {
+      const BconvStatic& bs = c->modup[dj];
+      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, d, ext, nd, next, B, c->log_n};
+      b->bconv_up.push_back(g);
+      b->max_waves_up = std::max(b->max_waves_up, ((uint64_t)B << c->log_n) / 32);
+      for (int t : c->targets[dj]) {
+        ep.push_back(c->plans[t]);
+        eo.push_back(((uint64_t)dj * LK + t) * N);
+      }
+    }
+    add_ntt(b.get(), kFwd1, ep, eo, ext, tmp, next, B, false);
+    // ModDown of both accumulators: INTT of P limbs, BConv P -> Q, NTT of Q limbs
+    std::vector<Plan*> pp(c->plans.begin() + L, c->plans.end());
+    std::vector<uint64_t> po(K);
+    for (int k = 0; k < K; ++k) po[k] = (uint64_t)(L + k) * N;
+    add_ntt(b.get(), kInv1P, pp, po, acc, tmp, (uint64_t)LK * N, 2 * B, true);
+    {
+      const BconvStatic& bs = c->moddown;
+      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, acc, z, (uint64_t)LK * N, nd, 2 * B, c->log_n};
+      b->bconv_down.push_back(g);
+      b->max_waves_down = std::max(b->max_waves_down, ((uint64_t)(2 * B) << c->log_n) / 32);
+    }
+    add_ntt(b.get(), kFwd1Z, qp, qo, z, tmp, nd, 2 * B, false);
+  }
+
+  // ---- pass 3: device task lists ---------------------------------------------------
+  cross_status st = CROSS_OK;
+  for (int ph = 0; ph < kNumPhases && st == CROSS_OK; ++ph) {
+    st = upload(b.get(), b->gemm[ph].tasks, &b->gemm[ph].d_tasks);
+    if (st == CROSS_OK) st = upload(b.get(), b->gemm[ph].tiles, &b->gemm[ph].d_tiles);
+  }
+  if (st == CROSS_OK) st = upload(b.get(), b->autos, &b->d_autos);
+  if (st == CROSS_OK) st = upload(b.get(), b->tensors, &b->d_tensors);
+  if (st == CROSS_OK) st = upload(b.get(), b->copies, &b->d_copies);
+  if (st == CROSS_OK) st = upload(b.get(), b->bconv_up, &b->d_bconv_up);
+  if (st == CROSS_OK) st = upload(b.get(), b->bconv_down, &b->d_bconv_down);
+  if (st == CROSS_OK) st = upload(b.get(), b->inners, &b->d_inners);
+  if (st == CROSS_OK) st = upload(b.get(), b->tails, &b->d_tails);
+  if (st != CROSS_OK) return st;
+
+  if (use_graph) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+      return fail(ctx, CROSS_EDEVICE, "capture stream creation failed");
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = run_phases(b.get(), cs, false);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    b->graph = g;
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  }
+  *out = b.release();
+  return CROSS_OK;
+}
+
+cross_status cross_batch_run(cross_batch b, void* stream) {
+  if (!b) return CROSS_EINVAL;
+  cross_ctx ctx = b->ctx;
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (b->exec) {
+    ProfScope ps(ctx, "batch_graph", s);
+    e = hipGraphLaunch(b->exec, s);
+  } else {
+    e = run_phases(b, s, true);
+  }
+  if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("batch run: ") + hipGetErrorString(e));
+  return CROSS_OK;
+}
+
+cross_status cross_batch_info(cross_batch b, uint32_t* launches, uint64_t* workspace_bytes, uint64_t* gemm_tiles) {
+  if (!b) return CROSS_EINVAL;
+  uint32_t n = 0;
+  uint64_t tiles = 0;
+  for (int ph = 0; ph < kNumPhases; ++ph) {
+    n += b->gemm[ph].tiles.empty() ? 0 : 1;
+    tiles += b->gemm[ph].tiles.size();
+  }
+  n += !b->autos.empty() + !b->tensors.empty() + !b->copies.empty() + !b->bconv_up.empty() +
+       !b->bconv_down.empty() + !b->inners.empty() + !b->tails.empty();
+  if (launches) *launches = n;
+  if (workspace_bytes) *workspace_bytes = b->ws_bytes;
+  if (gemm_tiles) *gemm_tiles = tiles;
+  return CROSS_OK;
+}
+
+}  // extern "C"

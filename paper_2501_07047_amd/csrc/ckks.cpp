@@ -15,6 +15,7 @@
 
 #include "context.h"
 #include "params.h"
+#include "ckks_plan.h"
 
 namespace cross {
 
@@ -66,14 +67,6 @@ std::vector<int8_t> bconv_table(const std::vector<uint32_t>& src, const std::vec
   return out;
 }
 
-// Device-resident constants of one BConv (source set -> target set).
-struct BconvStatic {
-  const BconvSrc* src = nullptr;
-  const BconvDst* dst = nullptr;
-  const int8_t* table = nullptr;
-  int nsrc = 0, ndst = 0;
-};
-
 cross_status make_bconv(cross_ctx ctx, const std::vector<uint32_t>& sp, const std::vector<uint64_t>& soff,
                         const std::vector<uint32_t>& dp, const std::vector<uint64_t>& doff,
                         BconvStatic* out) {
@@ -108,18 +101,6 @@ hipError_t run_bconv(cross_ctx ctx, const BconvStatic& bs, const uint32_t* in, u
   return launch_bconv(g, s);
 }
 
-struct CkksPlan {
-  int log_n = 0, L = 0, K = 0, dnum = 0, alpha = 0, ndig = 0;
-  std::vector<uint32_t> primes;
-  std::vector<Plan*> plans;               // L + K
-  const LimbMod* mods = nullptr;          // L + K, device
-  const TailConst* tail = nullptr;        // L, device
-  std::vector<BconvStatic> modup;         // per active digit: digit limbs -> all other limbs
-  std::vector<std::vector<int>> targets;  // per active digit
-  BconvStatic moddown;                    // P -> Q
-  const uint64_t* copy_src = nullptr;     // per active digit limb list (ModUp copies)
-  const uint64_t* copy_dst = nullptr;
-};
 
 
 
@@ -132,6 +113,8 @@ cross_status validate_primes(cross_ctx ctx, const uint32_t* p, uint32_t n, uint3
   }
   return CROSS_OK;
 }
+
+}  // namespace
 
 cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan** out) {
   if (!prm || !prm->primes) return fail(ctx, CROSS_EINVAL, "null params");
@@ -229,6 +212,21 @@ cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan
   *out = c;
   return CROSS_OK;
 }
+
+cross_status perm_table(cross_ctx ctx, int log_n, uint32_t g, const uint32_t** out) {
+  const uint32_t N = 1u << log_n;
+  std::vector<uint32_t> perm(N);
+  for (uint32_t p = 0; p < N; ++p) {
+    uint64_t e = (2ull * bitrev(p, log_n) + 1) * g % (2ull * N);
+    perm[p] = bitrev((uint32_t)((e - 1) / 2), log_n);
+  }
+  void* d = nullptr;
+  cross_status st = cached_device_copy(ctx, perm.data(), perm.size() * 4, &d);
+  *out = (const uint32_t*)d;
+  return st;
+}
+
+namespace {
 
 #define HIPCHK(expr, what)                                                              \
   do {                                                                                  \
@@ -365,18 +363,6 @@ cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* ke
   return moddown_core(ctx, c, w.acc, 2 * B, w.z, base, base_only_even, out, w.tmp, s);
 }
 
-cross_status perm_table(cross_ctx ctx, int log_n, uint32_t g, const uint32_t** out) {
-  const uint32_t N = 1u << log_n;
-  std::vector<uint32_t> perm(N);
-  for (uint32_t p = 0; p < N; ++p) {
-    uint64_t e = (2ull * bitrev(p, log_n) + 1) * g % (2ull * N);
-    perm[p] = bitrev((uint32_t)((e - 1) / 2), log_n);
-  }
-  void* d = nullptr;
-  cross_status st = cached_device_copy(ctx, perm.data(), perm.size() * 4, &d);
-  *out = (const uint32_t*)d;
-  return st;
-}
 
 }  // namespace
 

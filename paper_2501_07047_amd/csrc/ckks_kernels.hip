@@ -172,11 +172,10 @@ limb_copy_kernel(const v4u* src, uint64_t src_stride4, const uint64_t* src_off, 
 // registers and the merge stays in-register.  Each wave owns 32 coefficients.
 constexpr int BCONV_MAX_KB = 4;   // up to 32 source limbs
 
-__global__ void __launch_bounds__(256)
-bconv_kernel(BconvLaunch g) {
+__device__ __forceinline__ void bconv_wave(const BconvLaunch& g, uint64_t wave_global) {
   const int lane = threadIdx.x & 63;
-  const int wave_global = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint64_t n_per_poly = 1ull << g.log_n;
+  if (wave_global * 32 >= ((uint64_t)g.npoly << g.log_n)) return;
   const uint64_t col0 = (uint64_t)wave_global * 32;
   const uint64_t poly = col0 >> g.log_n;
   if (poly >= (uint64_t)g.npoly) return;
@@ -225,6 +224,108 @@ bconv_kernel(BconvLaunch g) {
       out[d.off + n] = r;
     }
   }
+}
+
+__global__ void __launch_bounds__(256)
+bconv_kernel(BconvLaunch g) {
+  bconv_wave(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+}
+
+__global__ void __launch_bounds__(256)
+bconv_list_kernel(const BconvLaunch* tasks) {
+  const BconvLaunch g = tasks[blockIdx.y];
+  bconv_wave(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+}
+
+__global__ void __launch_bounds__(256)
+tensor_list_kernel(const TensorTask* tasks) {
+  const TensorTask t = tasks[blockIdx.y];
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.count4) return;
+  const int log_n4 = t.log_n - 2;
+  const uint64_t per_limb = 1ull << log_n4;
+  const int limb = (int)(i >> log_n4);
+  const uint64_t w = i & (per_limb - 1);
+  const LimbMod md = t.mods[limb];
+  const v4u* a = (const v4u*)t.a;
+  const v4u* b = (const v4u*)t.b;
+  const uint64_t o0 = (uint64_t)limb * per_limb + w, o1 = ((uint64_t)t.L + limb) * per_limb + w;
+  v4u a0 = a[o0], a1 = a[o1], b0 = b[o0], b1 = b[o1];
+  v4u r0, r1, r2;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r0[k] = mulmod(a0[k], b0[k], md);
+    r1[k] = addmod(mulmod(a0[k], b1[k], md), mulmod(a1[k], b0[k], md), md.q);
+    r2[k] = mulmod(a1[k], b1[k], md);
+  }
+  ((v4u*)t.out)[o0] = r0;
+  ((v4u*)t.out)[o1] = r1;
+  ((v4u*)t.d2)[o0] = r2;
+}
+
+__global__ void __launch_bounds__(256)
+auto_list_kernel(const AutoTask* tasks) {
+  const AutoTask t = tasks[blockIdx.y];
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.count) return;
+  const uint64_t n = 1ull << t.log_n;
+  const uint64_t limb = i >> t.log_n;
+  t.out[i] = t.in[limb * n + t.perm[i & (n - 1)]];
+}
+
+__global__ void __launch_bounds__(256)
+copy_list_kernel(const CopyTask* tasks) {
+  const CopyTask t = tasks[blockIdx.y];
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.count4) return;
+  ((v4u*)t.dst)[i] = t.src ? ((const v4u*)t.src)[i] : v4u{0, 0, 0, 0};
+}
+
+__global__ void __launch_bounds__(256)
+inner_list_kernel(const InnerTask* tasks) {
+  const InnerTask t = tasks[blockIdx.y];
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.count4) return;
+  const int log_n4 = t.log_n - 2;
+  const uint64_t per_limb = 1ull << log_n4;
+  const int limb = (int)(i >> log_n4);
+  const uint64_t w = i & (per_limb - 1);
+  const LimbMod md = t.mods[limb];
+  const v4u* ext = (const v4u*)t.ext;
+  const v4u* key = (const v4u*)t.key;
+  v4u s0 = {0, 0, 0, 0}, s1 = {0, 0, 0, 0};
+  for (int j = 0; j < t.ndig; ++j) {
+    v4u e = ext[((uint64_t)j * t.LK + limb) * per_limb + w];
+    v4u k0 = key[((uint64_t)(j * 2 + 0) * t.LK + limb) * per_limb + w];
+    v4u k1 = key[((uint64_t)(j * 2 + 1) * t.LK + limb) * per_limb + w];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s0[k] = addmod(s0[k], mulmod(e[k], k0[k], md), md.q);
+      s1[k] = addmod(s1[k], mulmod(e[k], k1[k], md), md.q);
+    }
+  }
+  ((v4u*)t.acc)[(uint64_t)limb * per_limb + w] = s0;
+  ((v4u*)t.acc)[((uint64_t)t.LK + limb) * per_limb + w] = s1;
+}
+
+__global__ void __launch_bounds__(256)
+tail_list_kernel(const TailTask* tasks) {
+  const TailTask t = tasks[blockIdx.y];
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= t.count4) return;
+  const int log_n4 = t.log_n - 2;
+  const int limb = (int)(i >> log_n4);
+  const TailConst c = t.tc[limb];
+  v4u x = ((const v4u*)t.acc)[i];
+  v4u y = ((const v4u*)t.z)[i];
+  v4u bs = t.base ? ((const v4u*)t.base)[i] : v4u{0, 0, 0, 0};
+  v4u r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t d = x[k] + c.q - y[k];
+    r[k] = addmod(bs[k], mulmod_shoup(d, c.pinv, c.pinv_shoup, c.q), c.q);
+  }
+  ((v4u*)t.out)[i] = r;
 }
 
 inline unsigned blocks_for(uint64_t total, int per = 256) { return (unsigned)((total + per - 1) / per); }
@@ -284,6 +385,37 @@ hipError_t launch_limb_copy(const uint32_t* src, uint64_t src_stride, const uint
   hipLaunchKernelGGL(limb_copy_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)src,
                      src_stride / 4, src_off, (v4u*)dst, dst_stride / 4, dst_off, nl, log_n - 2,
                      total4);
+  return hipGetLastError();
+}
+
+hipError_t launch_tensor_list(const TensorTask* t, int n, uint64_t max4, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tensor_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+hipError_t launch_auto_list(const AutoTask* t, int n, uint64_t max_count, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(auto_list_kernel, dim3(blocks_for(max_count), n), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+hipError_t launch_copy_list(const CopyTask* t, int n, uint64_t max4, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+hipError_t launch_inner_list(const InnerTask* t, int n, uint64_t max4, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(inner_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+hipError_t launch_tail_list(const TailTask* t, int n, uint64_t max4, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tail_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  return hipGetLastError();
+}
+hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_waves, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bconv_list_kernel, dim3(blocks_for(max_waves * 64), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 

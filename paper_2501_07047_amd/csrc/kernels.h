@@ -42,6 +42,29 @@ int resolve_gemm_tile(const GemmLaunch& g);
 
 hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s);
 
+// Work-list GEMM step (batch runtime): each task is one limb list of one
+// transform with its own shape and buffers; each tile ref names (task, tm, tn)
+// of a 256 x 128 tile (gemm_list_tile_rows/cols).  All tasks of one launch share
+// the step kind and the packed/twiddle flags.  `grid` must be a multiple of 8.
+struct GemmTask {
+  const int8_t* table;
+  const uint32_t* tw;
+  const uint32_t* src;
+  uint32_t* dst;
+  uint64_t src_stride, dst_stride;
+  uint32_t q, qinv;
+  int32_t npoly;
+  int16_t log_r, log_c;
+};
+struct GemmTileRef {
+  uint32_t task;
+  uint16_t tm, tn;
+};
+int gemm_list_tile_rows();
+int gemm_list_tile_cols();
+hipError_t launch_bat_gemm_list(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
+                                int kind, bool in_packed, bool out_packed, bool twiddle, hipStream_t s);
+
 struct ButterflyJob {
   const uint32_t* tw;      // psi^brv(i) (or its inverse), Montgomery form, N entries
   uint64_t off;            // element offset of the limb in the launch's buffer
@@ -124,4 +147,59 @@ struct BconvLaunch {
 };
 hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s);
 
+}  // namespace cross
+
+namespace cross {
+
+// ---- work-list forms of the vector streams (batch runtime) ------------------
+// One task per blockIdx.y; each task covers `count4` 16-byte vectors.
+struct TensorTask {            // one ciphertext pair: a, b, out [2][L][N], d2 [L][N]
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t* out;
+  uint32_t* d2;
+  const LimbMod* mods;
+  int L, log_n;
+  uint64_t count4;
+};
+struct CopyTask {              // dst[0 .. 4*count4) = src ? src[...] : 0
+  const uint32_t* src;
+  uint32_t* dst;
+  uint64_t count4;
+};
+struct InnerTask {             // one ciphertext: ext [dnum][LK][N], key [dnum][2][LK][N], acc [2][LK][N]
+  const uint32_t* ext;
+  const uint32_t* key;
+  uint32_t* acc;
+  const LimbMod* mods;
+  int LK, dnum, ndig, log_n;
+  uint64_t count4;
+};
+struct TailTask {              // one polynomial: out[i] = base[i] + (acc[i] - z[i]) * Pinv_i, i < L
+  const uint32_t* acc;
+  const uint32_t* z;
+  const uint32_t* base;
+  uint32_t* out;
+  const TailConst* tc;
+  int L, log_n;
+  uint64_t count4;
+};
+hipError_t launch_tensor_list(const TensorTask* t, int n, uint64_t max4, hipStream_t s);
+hipError_t launch_copy_list(const CopyTask* t, int n, uint64_t max4, hipStream_t s);
+hipError_t launch_inner_list(const InnerTask* t, int n, uint64_t max4, hipStream_t s);
+hipError_t launch_tail_list(const TailTask* t, int n, uint64_t max4, hipStream_t s);
+// BConv over many independent conversions (one BconvLaunch per task, pointers absolute).
+hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_waves, hipStream_t s);
+
+}  // namespace cross
+
+namespace cross {
+struct AutoTask {              // out[l][x] = in[l][perm[x]] for L limbs of one polynomial
+  const uint32_t* in;
+  uint32_t* out;
+  const uint32_t* perm;
+  int log_n;
+  uint64_t count;              // L * N
+};
+hipError_t launch_auto_list(const AutoTask* t, int n, uint64_t max_count, hipStream_t s);
 }  // namespace cross

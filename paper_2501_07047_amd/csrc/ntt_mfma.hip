@@ -44,42 +44,36 @@ __device__ __forceinline__ uint32_t redc(uint64_t z, uint32_t q, uint32_t qinv) 
   return (uint32_t)(z >> 32) + q - u;
 }
 
-template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
-__global__ void __launch_bounds__(WM * WN * 64, OCC)
-bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
+// One BM x BN output tile of one step (all of K).  Shared by the uniform
+// launch (one limb list of one shape) and the work-list launch (mixed shapes).
+struct TileArgs {
+  const int8_t* table;
+  const uint32_t* tw;
+  const uint32_t* src;
+  uint32_t* dst;
+  uint64_t src_stride, dst_stride;
+  uint32_t q, qinv;
+  int npoly, log_r, log_c;
+  int m0, n0;
+};
+
+template <int WM, int WN, int MB, int NB, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8_t* lds_b) {
   constexpr int NT = WM * WN * 64;
   constexpr int BM = WM * MB * 16;
   constexpr int BN = WN * NB * 16;
-  // two LDS stages: the next K step is written while the current one is multiplied
-  __shared__ __attribute__((aligned(16))) int8_t lds_a[2][BM * LDS_ROW];
-  __shared__ __attribute__((aligned(16))) int8_t lds_b[2][BN * LDS_ROW];
-
-  const int R = 1 << g.log_r, C = 1 << g.log_c;
+  const int R = 1 << t.log_r, C = 1 << t.log_c;
   const int U = RIGHT ? C : R;          // outputs per column (and inputs per column)
   const int V = RIGHT ? R : C;          // columns per polynomial
   const int M = 4 * U, K = 4 * U;
-  const int ncols = g.npoly * V;
-
-  // XCD-aware tile order: consecutive logical tiles land on the same XCD so a
-  // job's table and columns stay in one L2.
-  const int total = g.njobs * tiles_m * tiles_n;
-  int bid = blockIdx.x;
-  int logical = bid;
-  if ((total & 7) == 0) logical = (bid & 7) * (total >> 3) + (bid >> 3);
-  const int per_job = tiles_m * tiles_n;
-  const int job_id = logical / per_job;
-  const int rem = logical - job_id * per_job;
-  const int tn = rem / tiles_m;          // m fastest: tiles sharing columns run together
-  const int tm = rem - tn * tiles_m;
-  const GemmJob job = g.jobs[job_id];
-  const int m0 = tm * BM, n0 = tn * BN;
-
+  const int ncols = t.npoly * V;
+  const int m0 = t.m0, n0 = t.n0;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
 
-  const uint32_t* src = g.src + job.src_off;
-  const int8_t* tab = job.table;
+  const uint32_t* src = t.src;
+  const int8_t* tab = t.table;
 
   v4i acc[MB][NB];
 #pragma unroll
@@ -105,7 +99,7 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   {
     const int n = b_ok ? n0 + b_n : 0;
     const int poly = n / V, v = n - poly * V;
-    b_base = src + (size_t)poly * g.src_stride + (RIGHT ? (size_t)v * C + b_xs : (size_t)b_xs * C + v);
+    b_base = src + (size_t)poly * t.src_stride + (RIGHT ? (size_t)v * C + b_xs : (size_t)b_xs * C + v);
   }
 
   auto load = [&](int ks) {
@@ -132,7 +126,7 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
 #pragma unroll
     for (int i = 0; i < A_VEC; ++i) {
       int piece = tid + i * NT;
-      *reinterpret_cast<v4i*>(&lds_a[buf][(piece >> 2) * LDS_ROW + (piece & 3) * 16]) = ra[i];
+      *reinterpret_cast<v4i*>(&lds_a[buf * (BM * LDS_ROW) + (piece >> 2) * LDS_ROW + (piece & 3) * 16]) = ra[i];
     }
 #pragma unroll
     for (int w = 0; w < B_WORDS; w += 4) {
@@ -141,7 +135,7 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
       t.y = IN_PACKED ? rb[w + 1] : pack_chunks(rb[w + 1]);
       t.z = IN_PACKED ? rb[w + 2] : pack_chunks(rb[w + 2]);
       t.w = IN_PACKED ? rb[w + 3] : pack_chunks(rb[w + 3]);
-      *reinterpret_cast<v4i*>(&lds_b[buf][b_n * LDS_ROW + (b_xs + w) * 4]) = t;
+      *reinterpret_cast<v4i*>(&lds_b[buf * (BN * LDS_ROW) + b_n * LDS_ROW + (b_xs + w) * 4]) = t;
     }
   };
 
@@ -150,10 +144,10 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
     v4i fa[MB], fb[NB];
 #pragma unroll
     for (int a = 0; a < MB; ++a)
-      fa[a] = *reinterpret_cast<const v4i*>(&lds_a[buf][(wm * MB * 16 + a * 16 + (lane & 15)) * LDS_ROW + koff]);
+      fa[a] = *reinterpret_cast<const v4i*>(&lds_a[buf * (BM * LDS_ROW) + (wm * MB * 16 + a * 16 + (lane & 15)) * LDS_ROW + koff]);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      fb[b] = *reinterpret_cast<const v4i*>(&lds_b[buf][(wn * NB * 16 + b * 16 + (lane & 15)) * LDS_ROW + koff]);
+      fb[b] = *reinterpret_cast<const v4i*>(&lds_b[buf * (BN * LDS_ROW) + (wn * NB * 16 + b * 16 + (lane & 15)) * LDS_ROW + koff]);
     __builtin_amdgcn_s_setprio(1);   // keep the matrix pipe fed ahead of the staging waves
 #pragma unroll
     for (int a = 0; a < MB; ++a)
@@ -179,8 +173,8 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   }
 
   // ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ----------
-  const uint32_t q = job.q, qinv = job.qinv;
-  uint32_t* dst = g.dst + job.dst_off;
+  const uint32_t q = t.q, qinv = t.qinv;
+  uint32_t* dst = t.dst;
 #pragma unroll
   for (int a = 0; a < MB; ++a) {
     const int u = (m0 + wm * MB * 16 + a * 16) / 4 + (lane >> 4);
@@ -194,16 +188,62 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
                    ((uint64_t)(uint32_t)s.z << 14) + ((uint64_t)(uint32_t)s.w << 21);
       uint32_t r = redc(z, q, qinv);
       if (TW) {
-        uint32_t w = job.tw[(size_t)u * V + v];
+        uint32_t w = t.tw[(size_t)u * V + v];
         r = redc((uint64_t)r * w, q, qinv);
       }
       if (r >= q) r -= q;
       if (OUT_PACKED) r = pack_chunks(r);
       size_t off = RIGHT ? (size_t)v * C + u : (size_t)u * C + v;
-      dst[(size_t)poly * g.dst_stride + off] = r;
+      dst[(size_t)poly * t.dst_stride + off] = r;
     }
   }
   (void)M;
+}
+
+template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__global__ void __launch_bounds__(WM * WN * 64, OCC)
+bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
+  constexpr int BM = WM * MB * 16;
+  constexpr int BN = WN * NB * 16;
+  // two LDS stages: the next K step is written while the current one is multiplied
+  __shared__ __attribute__((aligned(16))) int8_t lds_a[2 * BM * LDS_ROW];
+  __shared__ __attribute__((aligned(16))) int8_t lds_b[2 * BN * LDS_ROW];
+  // XCD-aware tile order: consecutive logical tiles land on the same XCD so a
+  // job's table and columns stay in one L2.
+  const int total = g.njobs * tiles_m * tiles_n;
+  const int bid = blockIdx.x;
+  int logical = bid;
+  if ((total & 7) == 0) logical = (bid & 7) * (total >> 3) + (bid >> 3);
+  const int per_job = tiles_m * tiles_n;
+  const int job_id = logical / per_job;
+  const int rem = logical - job_id * per_job;
+  const int tn = rem / tiles_m;          // m fastest: tiles sharing columns run together
+  const int tm = rem - tn * tiles_m;
+  const GemmJob job = g.jobs[job_id];
+  TileArgs t{job.table, job.tw, g.src + job.src_off, g.dst + job.dst_off, g.src_stride, g.dst_stride,
+             job.q, job.qinv, g.npoly, g.log_r, g.log_c, tm * BM, tn * BN};
+  gemm_tile<WM, WN, MB, NB, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
+}
+
+// Work-list form: tiles of many tasks (mixed N, R x C, primes, buffers) in one
+// persistent launch.  The grid is a multiple of 8; XCD x (= blockIdx % 8) walks
+// the x-th eighth of the tile list so each task's tiles share one L2.
+template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__global__ void __launch_bounds__(WM * WN * 64, OCC)
+bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles) {
+  constexpr int BM = WM * MB * 16;
+  constexpr int BN = WN * NB * 16;
+  __shared__ __attribute__((aligned(16))) int8_t lds_a[2 * BM * LDS_ROW];
+  __shared__ __attribute__((aligned(16))) int8_t lds_b[2 * BN * LDS_ROW];
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
+  const int lo = (int)((long)ntiles * xcd / 8), hi = (int)((long)ntiles * (xcd + 1) / 8);
+  for (int i = lo + local; i < hi; i += per_xcd) {
+    const GemmTileRef r = tiles[i];
+    const GemmTask k = tasks[r.task];
+    TileArgs t{k.table, k.tw, k.src, k.dst, k.src_stride, k.dst_stride, k.q, k.qinv, k.npoly,
+               k.log_r, k.log_c, (int)r.tm * BM, (int)r.tn * BN};
+    gemm_tile<WM, WN, MB, NB, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
+  }
 }
 
 template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool INP, bool OUTP, bool TW>
@@ -239,6 +279,29 @@ hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
 }
 
 }  // namespace
+
+template <bool RIGHT, bool INP, bool OUTP, bool TW>
+hipError_t launch_list_cfg(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
+                           hipStream_t s) {
+  hipLaunchKernelGGL((bat_gemm_list_kernel<2, 2, 8, 4, 2, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(256), 0, s,
+                     tasks, tiles, ntiles);
+  return hipGetLastError();
+}
+
+int gemm_list_tile_rows() { return 256; }
+int gemm_list_tile_cols() { return 128; }
+
+hipError_t launch_bat_gemm_list(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
+                                int kind, bool in_packed, bool out_packed, bool twiddle, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  if (grid <= 0 || (grid & 7)) return hipErrorInvalidValue;
+  const bool right = kind == kRight;
+  if (!right && !in_packed && out_packed && twiddle) return launch_list_cfg<false, false, true, true>(tasks, tiles, ntiles, grid, s);
+  if (right && in_packed && !out_packed && !twiddle) return launch_list_cfg<true, true, false, false>(tasks, tiles, ntiles, grid, s);
+  if (right && !in_packed && out_packed && twiddle) return launch_list_cfg<true, false, true, true>(tasks, tiles, ntiles, grid, s);
+  if (!right && in_packed && !out_packed && !twiddle) return launch_list_cfg<false, true, false, false>(tasks, tiles, ntiles, grid, s);
+  return hipErrorInvalidValue;
+}
 
 int resolve_gemm_tile(const GemmLaunch& g) {
   const int U = (g.kind == kRight) ? (1 << g.log_c) : (1 << g.log_r);
