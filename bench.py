@@ -110,6 +110,87 @@ def he_mult_bench(B, steps, warmup, batch):
     return res
 
 
+def uneven_batch_bench(B, replays):
+    """Config C4: 64 ciphertexts, N in {2^13..2^16}, L in [4, 36], HE-Mult (p = 0.5) else
+    NTT of both polynomials; one captured graph per pass vs. the per-job calls."""
+    import torch
+    import synthetic
+    pool = synthetic.DevicePool(4)
+    jobs, calls = [], []
+    for k, (op, log_n, L) in enumerate(synthetic.uneven_jobs(4, 64)):
+        qs, ps, _ = pool.params(L)
+        a, b = pool.ciphertexts(log_n, L, k)
+        if op == "he_mult":
+            key = pool.key(log_n, L, "relin")
+            out = torch.empty((1,) + tuple(a.shape), dtype=torch.int32, device="cuda")
+            j = {"op": "he_mult", "a": a.unsqueeze(0), "b": b.unsqueeze(0), "key": key, "out": out,
+                 "qs": qs, "ps": ps, "dnum": 3}
+            calls.append(lambda j=j: B.he_mult(j["a"], j["b"], j["key"], torch.empty_like(j["out"]),
+                                               j["qs"], j["ps"], 3))
+        else:
+            data = a.clone()
+            j = {"op": "ntt_forward", "data": data, "primes": qs}
+            scratch = a.clone()
+            calls.append(lambda s=scratch, q=qs: B.ntt_forward(s, q))
+        jobs.append(j)
+    torch.cuda.synchronize()
+    bt = B.Batch(jobs, use_graph=True)
+    info = bt.info()
+    for _ in range(3):
+        bt.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        bt.run()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / replays
+    for c in calls:
+        c()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, replays // 4)):
+        for c in calls:
+            c()
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / max(1, replays // 4)
+    bt.close()
+    n_he = sum(1 for j in jobs if j["op"] == "he_mult")
+    return {"config": "64 ciphertexts, N in {2^13..2^16}, L in [4,36], dnum=3, K=alpha; "
+                      "%d HE-Mult + %d NTT(2 polys)" % (n_he, 64 - n_he),
+            "graph_ms_per_pass": round(t_graph * 1e3, 3), "per_job_calls_ms_per_pass": round(t_eager * 1e3, 3),
+            "speedup_vs_per_job_calls": round(t_eager / t_graph, 3),
+            "ciphertexts_per_s": round(64 / t_graph, 1), "launches_per_pass_eager": info["launches"],
+            "gemm_tiles_per_pass": info["gemm_tiles"], "replays": replays}
+
+
+def serving_bench(n_req, budget_gb=4.0):
+    """Config C5: Poisson arrivals of HE-Mult / Rotate requests, N in {2^14..2^16}, L in [8, 36]."""
+    import torch
+    import synthetic
+    from paper_2501_07047_amd import serving as S
+    pool = synthetic.DevicePool(5)
+    budget = int(budget_gb * (1 << 30))
+
+    def run(rate, seed):
+        specs = synthetic.poisson_requests(seed, n_req, rate)
+        reqs = S.build_requests(specs, pool)
+        torch.cuda.synchronize()
+        return S.Server(S.GpuExecutor(slots=4), hbm_budget=budget, slots=4, max_group=8).run(reqs)
+
+    run(1e9, 99)                                   # warm plans and keys
+    sat = run(1e9, 7)                              # closed loop: every request waiting at t = 0
+    out = {"config": "%d requests per point, HE-Mult p=0.5 else Rotate r in {1..64}, N in {2^14,2^15,2^16}, "
+                     "L in [8,36], dnum=3, K=alpha, HBM budget %.1f GiB, 4 stream slots" % (n_req, budget_gb),
+           "saturation_per_s": round(sat["throughput_per_s"], 1), "points": []}
+    for f in (0.5, 0.8, 0.95):
+        r = run(f * sat["throughput_per_s"], 8)
+        out["points"].append({"load": f, "rate_per_s": round(f * sat["throughput_per_s"], 1),
+                              "throughput_per_s": round(r["throughput_per_s"], 1),
+                              "p50_ms": round(r["p50_ms"], 3), "p99_ms": round(r["p99_ms"], 3),
+                              "peak_hbm_gib": round(r["peak_hbm_bytes"] / (1 << 30), 2)})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +314,8 @@ def main():
     line["he_mult"] = {"config": "N=2^16, L=24, dnum=3 (alpha=8), K=8 special primes, tensor + relinearisation",
                        "batch1": he1["he_mult"], "batch8": he8["he_mult"]}
     line["rotate"] = {"config": "same parameters, 1 slot", "batch1": he1["rotate"], "batch8": he8["rotate"]}
+    line["uneven_batch"] = uneven_batch_bench(B, max(4, args.steps // 2))
+    line["serving"] = serving_bench(200)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))

@@ -208,6 +208,18 @@ typedef struct cross_batch_s* cross_batch;
  * launch sequence into a hipGraph.  No device work runs until cross_batch_run. */
 cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
                                 cross_batch* out);
+/* Bytes of device workspace a batch of these jobs needs when the caller provides it. */
+cross_status cross_batch_workspace_bytes(cross_ctx ctx, const cross_job* jobs, uint32_t njobs,
+                                         uint64_t* bytes);
+/* As cross_batch_create, but all of the batch's device memory (scratch and task
+ * lists) is carved from the caller's `workspace` (256-byte aligned, at least
+ * cross_batch_workspace_bytes): the batch allocates and frees no device memory
+ * and destroying it does not synchronise the device, so the caller must know
+ * that its last run has finished.  Task lists are copied on `stream`; run the
+ * batch on the same stream (or order it after that copy). */
+cross_status cross_batch_create_in(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
+                                   void* workspace, uint64_t workspace_bytes, void* stream,
+                                   cross_batch* out);
 /* Enqueue one pass over every job on `stream` (graph launch or eager launches). */
 cross_status cross_batch_run(cross_batch batch, void* stream);
 /* Launch count per run (eager), workspace bytes and total GEMM tiles per run. */

@@ -49,6 +49,8 @@ SIGNATURES = {
     "cross_he_mult": [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_rotate": [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_batch_create": [c_vp, c_vp, c_u32, ctypes.c_int, ctypes.POINTER(c_vp)],
+    "cross_batch_workspace_bytes": [c_vp, c_vp, c_u32, ctypes.POINTER(ctypes.c_uint64)],
+    "cross_batch_create_in": [c_vp, c_vp, c_u32, ctypes.c_int, c_vp, ctypes.c_uint64, c_vp, ctypes.POINTER(c_vp)],
     "cross_batch_run": [c_vp, c_vp],
     "cross_batch_info": [c_vp, ctypes.POINTER(c_u32), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
     "cross_batch_destroy": [c_vp],
@@ -302,43 +304,69 @@ def _ptr(t):
     return None if t is None else _dev_ptr(t, "buffer").value
 
 
+def _marshal_jobs(jobs):
+    """Job dicts -> (cross_job array, objects that must outlive it)."""
+    arr = (Job * len(jobs))()
+    keep = [arr]
+    for i, j in enumerate(jobs):
+        op = j["op"]
+        if op in ("ntt_forward", "ntt_inverse"):
+            d = j["data"]
+            bt, L, n = d.shape
+            prm = _params(j["primes"], [], 1, n)
+            prm.K = 0
+            arr[i] = Job(OP_NTT_FORWARD if op == "ntt_forward" else OP_NTT_INVERSE, prm, bt, 0,
+                         _ptr(d), None, None, None, None)
+        elif op == "he_mult":
+            a = j["a"]
+            prm = _params(j["qs"], j["ps"], j["dnum"], a.shape[-1])
+            arr[i] = Job(OP_HE_MULT, prm, a.shape[0], 0, None, _ptr(a), _ptr(j["b"]), _ptr(j["key"]),
+                         _ptr(j["out"]))
+        elif op == "rotate":
+            a = j["ct"]
+            prm = _params(j["qs"], j["ps"], j["dnum"], a.shape[-1])
+            arr[i] = Job(OP_ROTATE, prm, a.shape[0], int(j["steps"]), None, _ptr(a), None, _ptr(j["key"]),
+                         _ptr(j["out"]))
+        else:
+            raise ValueError("unknown op %r" % op)
+        keep.append(prm)
+    return arr, keep
+
+
+def batch_workspace_bytes(jobs, device=None):
+    """Device bytes Batch(jobs, workspace=...) needs."""
+    ctx = context(device)
+    arr, keep = _marshal_jobs(jobs)
+    n = ctypes.c_uint64(0)
+    _check(lib().cross_batch_workspace_bytes(ctx, ctypes.cast(arr, c_vp), len(jobs), ctypes.byref(n)), ctx)
+    return n.value
+
+
 class Batch:
     """A planned batch of jobs (cross_batch).  Each job is a dict:
     {"op": "ntt_forward"|"ntt_inverse", "data": t[batch][L][N], "primes": [...]}
     {"op": "he_mult", "a", "b", "key", "out", "qs", "ps", "dnum"}
     {"op": "rotate", "ct", "key", "out", "qs", "ps", "dnum", "steps"}
-    Tensors must stay alive while the batch exists."""
+    Tensors must stay alive while the batch exists.  With `workspace` (a device
+    tensor of at least batch_workspace_bytes(jobs) bytes, 256-byte aligned) the
+    batch allocates no device memory and closing it does not synchronise."""
 
-    def __init__(self, jobs, use_graph=True, device=None):
+    def __init__(self, jobs, use_graph=True, device=None, workspace=None, stream=None):
+        self.handle = None
         self.ctx = context(device)
-        arr = (Job * len(jobs))()
-        self._keep = []
-        for i, j in enumerate(jobs):
-            op = j["op"]
-            if op in ("ntt_forward", "ntt_inverse"):
-                d = j["data"]
-                bt, L, n = d.shape
-                prm = _params(j["primes"], [], 1, n)
-                prm.K = 0
-                arr[i] = Job(OP_NTT_FORWARD if op == "ntt_forward" else OP_NTT_INVERSE, prm, bt, 0,
-                             _ptr(d), None, None, None, None)
-            elif op == "he_mult":
-                a = j["a"]
-                prm = _params(j["qs"], j["ps"], j["dnum"], a.shape[-1])
-                arr[i] = Job(OP_HE_MULT, prm, a.shape[0], 0, None, _ptr(a), _ptr(j["b"]), _ptr(j["key"]),
-                             _ptr(j["out"]))
-            elif op == "rotate":
-                a = j["ct"]
-                prm = _params(j["qs"], j["ps"], j["dnum"], a.shape[-1])
-                arr[i] = Job(OP_ROTATE, prm, a.shape[0], int(j["steps"]), None, _ptr(a), None, _ptr(j["key"]),
-                             _ptr(j["out"]))
-            else:
-                raise ValueError("unknown op %r" % op)
-            self._keep.append(prm)
-        self._keep.append(arr)
+        arr, self._keep = _marshal_jobs(jobs)
         h = c_vp()
-        _check(lib().cross_batch_create(self.ctx, ctypes.cast(arr, c_vp), len(jobs), 1 if use_graph else 0,
-                                        ctypes.byref(h)), self.ctx)
+        if workspace is None:
+            _check(lib().cross_batch_create(self.ctx, ctypes.cast(arr, c_vp), len(jobs), 1 if use_graph else 0,
+                                            ctypes.byref(h)), self.ctx)
+        else:
+            import torch
+            st = c_vp(torch.cuda.current_stream().cuda_stream) if stream is None else c_vp(stream)
+            _check(lib().cross_batch_create_in(self.ctx, ctypes.cast(arr, c_vp), len(jobs), 1 if use_graph else 0,
+                                               c_vp(workspace.data_ptr()),
+                                               workspace.numel() * workspace.element_size(), st, ctypes.byref(h)),
+                   self.ctx)
+            self._keep.append(workspace)
         self.handle = h
 
     def run(self, stream=None):

@@ -57,6 +57,10 @@ struct cross_batch_s {
   uint64_t max_waves_up = 0, max_waves_down = 0;
   std::vector<void*> allocs;
   uint64_t ws_bytes = 0;
+  bool external = false;        // scratch and task lists live in the caller's workspace
+  char* ext_cursor = nullptr;   // next free byte of the caller's workspace (task lists)
+  char* ext_end = nullptr;
+  hipStream_t upload_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -65,20 +69,43 @@ namespace cross {
 
 namespace {
 
+uint64_t align256(uint64_t x) { return (x + 255) & ~(uint64_t)255; }
+
+template <typename T>
+uint64_t list_bytes(const std::vector<T>& v) { return align256(v.size() * sizeof(T)); }
+
 template <typename T>
 cross_status upload(cross_batch b, const std::vector<T>& v, const T** out) {
   *out = nullptr;
   if (v.empty()) return CROSS_OK;
   void* d = nullptr;
-  if (hipMalloc(&d, v.size() * sizeof(T)) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(b->ctx, CROSS_ENOMEM, "batch task list allocation failed");
+  if (b->external) {
+    const uint64_t n = list_bytes(v);
+    if (b->ext_cursor + n > b->ext_end) return fail(b->ctx, CROSS_EINVAL, "workspace too small for the task lists");
+    d = b->ext_cursor;
+    b->ext_cursor += n;
+    // stream-ordered before any run enqueued on the same stream; the host vector lives in the batch
+    if (hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, b->upload_stream) != hipSuccess)
+      return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
+  } else {
+    if (hipMalloc(&d, v.size() * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(b->ctx, CROSS_ENOMEM, "batch task list allocation failed");
+    }
+    b->allocs.push_back(d);
+    if (hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
   }
-  b->allocs.push_back(d);
-  if (hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
-    return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
   *out = static_cast<const T*>(d);
   return CROSS_OK;
+}
+
+uint64_t task_list_bytes(cross_batch b) {
+  uint64_t n = 0;
+  for (int ph = 0; ph < kNumPhases; ++ph) n += list_bytes(b->gemm[ph].tasks) + list_bytes(b->gemm[ph].tiles);
+  n += list_bytes(b->autos) + list_bytes(b->tensors) + list_bytes(b->copies) + list_bytes(b->bconv_up) +
+       list_bytes(b->bconv_down) + list_bytes(b->inners) + list_bytes(b->tails);
+  return n;
 }
 
 // Add the tiles of one limb list of one NTT step to a GEMM phase.
@@ -175,17 +202,24 @@ extern "C" {
 void cross_batch_destroy(cross_batch b) {
   if (!b) return;
   (void)hipSetDevice(b->ctx->device);
-  (void)hipDeviceSynchronize();
+  if (!b->external) (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (void* p : b->allocs) (void)hipFree(p);
   delete b;
 }
 
-cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
-                                cross_batch* out) {
-  if (!ctx || !out) return CROSS_EINVAL;
-  *out = nullptr;
+}  // extern "C"
+
+namespace cross {
+namespace {
+
+// size_only: plan and lower, then report the bytes a caller-provided workspace needs.
+cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph, void* ext_ws,
+                         uint64_t ext_bytes, hipStream_t upload_stream, bool size_only, uint64_t* need,
+                         cross_batch* out) {
+  if (!ctx || (!out && !size_only)) return CROSS_EINVAL;
+  if (out) *out = nullptr;
   if (!jobs || njobs == 0) return fail(ctx, CROSS_EINVAL, "empty job list");
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
   std::unique_ptr<cross_batch_s, void (*)(cross_batch)> b(new cross_batch_s(), cross_batch_destroy);
@@ -243,11 +277,18 @@ cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t n
     ws_words += (jp[j].ws + 63) & ~(uint64_t)63;
   }
   void* wsp = nullptr;
-  if (hipMalloc(&wsp, ws_words * 4) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, CROSS_ENOMEM, "batch workspace allocation failed");
+  const uint64_t scratch = align256(ws_words * 4);
+  if (size_only || ext_ws) {
+    // lower against the caller's base (or a stand-in aligned base when only sizing)
+    wsp = ext_ws ? ext_ws : reinterpret_cast<void*>((uintptr_t)1 << 20);
+    b->external = true;
+  } else {
+    if (hipMalloc(&wsp, ws_words * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, CROSS_ENOMEM, "batch workspace allocation failed");
+    }
+    b->allocs.push_back(wsp);
   }
-  b->allocs.push_back(wsp);
   b->ws_bytes = ws_words * 4;
 
   // ---- pass 2: lower every job onto the phases ------------------------------------
@@ -352,6 +393,18 @@ cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t n
   }
 
   // ---- pass 3: device task lists ---------------------------------------------------
+  if (size_only) {
+    *need = scratch + task_list_bytes(b.get());
+    b->external = true;   // nothing was allocated: destroy must not synchronise
+    return CROSS_OK;
+  }
+  if (ext_ws) {
+    if ((reinterpret_cast<uintptr_t>(ext_ws) & 255) != 0 || ext_bytes < scratch + task_list_bytes(b.get()))
+      return fail(ctx, CROSS_EINVAL, "workspace must be 256-byte aligned and at least cross_batch_workspace_bytes");
+    b->ext_cursor = static_cast<char*>(ext_ws) + scratch;
+    b->ext_end = static_cast<char*>(ext_ws) + ext_bytes;
+    b->upload_stream = upload_stream;
+  }
   cross_status st = CROSS_OK;
   for (int ph = 0; ph < kNumPhases && st == CROSS_OK; ++ph) {
     st = upload(b.get(), b->gemm[ph].tasks, &b->gemm[ph].d_tasks);
@@ -382,6 +435,28 @@ cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t n
   }
   *out = b.release();
   return CROSS_OK;
+}
+
+}  // namespace
+}  // namespace cross
+
+extern "C" {
+
+cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
+                                cross_batch* out) {
+  return build_batch(ctx, jobs, njobs, use_graph, nullptr, 0, nullptr, false, nullptr, out);
+}
+
+cross_status cross_batch_workspace_bytes(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, uint64_t* bytes) {
+  if (!bytes) return CROSS_EINVAL;
+  return build_batch(ctx, jobs, njobs, 0, nullptr, 0, nullptr, true, bytes, nullptr);
+}
+
+cross_status cross_batch_create_in(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
+                                   void* workspace, uint64_t workspace_bytes, void* stream, cross_batch* out) {
+  if (!workspace) return ctx ? fail(ctx, CROSS_EINVAL, "null workspace") : CROSS_EINVAL;
+  return build_batch(ctx, jobs, njobs, use_graph, workspace, workspace_bytes, static_cast<hipStream_t>(stream),
+                     false, nullptr, out);
 }
 
 cross_status cross_batch_run(cross_batch b, void* stream) {

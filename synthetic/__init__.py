@@ -103,3 +103,65 @@ def uneven_jobs(seed: int, count: int = 64):
         op = "he_mult" if g.random() < 0.5 else "ntt"
         jobs.append((op, log_n, L))
     return jobs
+
+
+def poisson_requests(seed: int, count: int, rate: float, log_ns=(14, 15, 16), L_range=(8, 36),
+                     p_mult: float = 0.5, rot_steps=(1, 2, 4, 8, 16, 32, 64)):
+    """Request-loop workload (C5): arrival times of a Poisson process with `rate`
+    requests/s, op HE-Mult with probability p_mult else Rotate by a step from
+    rot_steps, N drawn from log_ns, L uniform in L_range (inclusive)."""
+    g = rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += float(g.exponential(1.0 / rate)) if rate > 0 else 0.0
+        log_n = int(g.choice(log_ns))
+        L = int(g.integers(L_range[0], L_range[1] + 1))
+        op = "he_mult" if g.random() < p_mult else "rotate"
+        steps = int(g.choice(rot_steps))
+        out.append({"rid": i, "arrival": t, "op": op, "log_n": log_n, "L": L, "steps": steps})
+    return out
+
+
+class DevicePool:
+    """Seeded synthetic ciphertexts and keys generated on the GPU, per parameter set.
+
+    For each (log_n, L) a few ciphertext pairs and one key per kind ('relin' or a
+    rotation step) are drawn uniformly per limb in [0, q_i) with a seeded torch
+    generator; requests reference them, so a long request stream does not hold
+    one fresh key per request.
+    """
+
+    def __init__(self, seed: int, dnum: int = 3, variants: int = 2):
+        self.seed, self.dnum, self.variants = seed, dnum, variants
+        self.cts, self.keys = {}, {}
+
+    def _uniform(self, shape, plist, n, salt):
+        import torch
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed((self.seed * 1000003 + salt) & 0x7FFFFFFF)
+        rows = []
+        for idx in np.ndindex(*shape):
+            for q in plist:
+                rows.append(torch.randint(0, q, (n,), generator=gen, device="cuda", dtype=torch.int64))
+        return torch.stack(rows).to(torch.int32).reshape(tuple(shape) + (len(plist), n))
+
+    def params(self, L):
+        return ckks_params(L, self.dnum)
+
+    def ciphertexts(self, log_n, L, variant):
+        key = (log_n, L, variant % self.variants)
+        if key not in self.cts:
+            qs, _, _ = self.params(L)
+            salt = (log_n * 64 + L) * 16 + key[2] * 2
+            self.cts[key] = (self._uniform((2,), qs, 1 << log_n, salt),
+                             self._uniform((2,), qs, 1 << log_n, salt + 1))
+        return self.cts[key]
+
+    def key(self, log_n, L, kind):
+        k = (log_n, L, kind)
+        if k not in self.keys:
+            qs, ps, _ = self.params(L)
+            kid = 0 if kind == "relin" else 1 + int(kind[1])
+            self.keys[k] = self._uniform((self.dnum, 2), qs + ps, 1 << log_n, 100000 + (log_n * 64 + L) * 128 + kid)
+        return self.keys[k]
