@@ -116,6 +116,7 @@ def uneven_batch_bench(B, replays):
     import torch
     import synthetic
     pool = synthetic.DevicePool(4)
+    tuned = {log_n: B.autotune(log_n, L=8, batch=4) for log_n in (13, 14, 15, 16)}
     jobs, calls = [], []
     for k, (op, log_n, L) in enumerate(synthetic.uneven_jobs(4, 64)):
         qs, ps, _ = pool.params(L)
@@ -160,7 +161,9 @@ def uneven_batch_bench(B, replays):
             "graph_ms_per_pass": round(t_graph * 1e3, 3), "per_job_calls_ms_per_pass": round(t_eager * 1e3, 3),
             "speedup_vs_per_job_calls": round(t_eager / t_graph, 3),
             "ciphertexts_per_s": round(64 / t_graph, 1), "launches_per_pass_eager": info["launches"],
-            "gemm_tiles_per_pass": info["gemm_tiles"], "replays": replays}
+            "gemm_tiles_per_pass": info["gemm_tiles"], "replays": replays,
+            "autotuned": {str(k): {"R": 1 << v["log_r"], "C": 1 << (k - v["log_r"]), "tile": v["tile"],
+                                   "ntt_fwd_inv_us_L8_b4": round(v["us"], 1)} for k, v in tuned.items()}}
 
 
 def serving_bench(n_req, budget_gb=4.0):
@@ -315,6 +318,7 @@ def main():
                        "batch1": he1["he_mult"], "batch8": he8["he_mult"]}
     line["rotate"] = {"config": "same parameters, 1 slot", "batch1": he1["rotate"], "batch8": he8["rotate"]}
     line["uneven_batch"] = uneven_batch_bench(B, max(4, args.steps // 2))
+    B.set_ntt_split(LOG_N, LOG_R)
     line["serving"] = serving_bench(200)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

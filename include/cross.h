@@ -67,6 +67,18 @@ cross_status cross_root(uint32_t q, uint32_t log_n, uint32_t* psi_out);
  * R = 2^floor(log_n/2)).  4 <= log_r and 4 <= log_n - log_r. */
 cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r);
 
+/* Autotuner: time forward + inverse NTTs of `batch` x L limbs of size 2^log_n
+ * (8 <= log_n <= 16) for every split R = 2^log_r with 4 <= log_r <= log_n - 4
+ * within a factor of four of square, and R, C >= 64 from log_n = 12 up so the
+ * batch runtime can use the result (the paper sweeps (R, C) and keeps the
+ * best), and every GEMM tile; keep the fastest on this context for that size
+ * (as cross_set_ntt_split plus a per-size tile).  If cache_path is non-NULL a
+ * matching line "<device> <log_n> <L> <batch> <log_r> <tile> <us>" is reused
+ * without timing, else the new choice is appended.  Any out pointer may be NULL.
+ * Allocates batch*L*N*4 bytes of scratch while timing; synchronises the device. */
+cross_status cross_autotune(cross_ctx ctx, uint32_t log_n, uint32_t L, uint32_t batch, const char* cache_path,
+                            uint32_t* log_r_out, int* tile_out, double* us_out);
+
 /* Workgroup tile of the BAT int8 GEMM steps on this context (autotuner knob):
  * 0 = automatic (by shape and grid size), 1 = 256x256 (8 waves), 2 = 256x128,
  * 3 = 128x64, 4 = 64x64.  A tile larger than a step's matrix falls back to auto.

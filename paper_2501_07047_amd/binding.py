@@ -38,6 +38,8 @@ SIGNATURES = {
     "cross_root": [c_u32, c_u32, c_u32p],
     "cross_set_ntt_split": [c_vp, c_u32, c_u32],
     "cross_set_gemm_tile": [c_vp, ctypes.c_int],
+    "cross_autotune": [c_vp, c_u32, c_u32, c_u32, ctypes.c_char_p, ctypes.POINTER(c_u32),
+                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
     "cross_ntt_forward": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
     "cross_ntt_inverse": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
     "cross_ntt_forward_butterfly": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
@@ -141,6 +143,16 @@ def set_gemm_tile(tile, device=None):
     """0 = auto, 1 = 256x256, 2 = 256x128, 3 = 128x64, 4 = 64x64 (see cross_set_gemm_tile)."""
     ctx = context(device)
     _check(lib().cross_set_gemm_tile(ctx, int(tile)), ctx)
+
+
+def autotune(log_n, L=8, batch=8, cache_path=None, device=None):
+    """Time the candidate splits and tiles for 2^log_n transforms and keep the best
+    on the context; returns {"log_r", "tile", "us"} (see cross_autotune)."""
+    ctx = context(device)
+    r, t, us = c_u32(), ctypes.c_int(), ctypes.c_double()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib().cross_autotune(ctx, log_n, L, batch, path, ctypes.byref(r), ctypes.byref(t), ctypes.byref(us)), ctx)
+    return {"log_r": r.value, "tile": t.value, "us": us.value}
 
 
 def _ntt(fn, data, primes):

@@ -183,6 +183,10 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   g.log_r = log_r;
   g.log_c = log_n - log_r;
   g.tile = ctx->gemm_tile;
+  if (g.tile == 0) {
+    auto it = ctx->tile_by_logn.find(log_n);
+    if (it != ctx->tile_by_logn.end()) g.tile = it->second;
+  }
   // step 1 (data -> tmp, packed chunks, twiddle fused) then step 3 (tmp -> data)
   g.jobs = (const GemmJob*)d1;
   g.src = data;

@@ -54,6 +54,7 @@ struct cross_ctx_s {
   std::map<hipStream_t, cross::DevBuf> workspace;
   std::map<int, int> split;                   // log_n -> log_r override
   int gemm_tile = 0;                          // GemmTile override (0 = auto)
+  std::map<int, int> tile_by_logn;            // autotuned GemmTile per transform size
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)
   bool prof = false;

@@ -137,3 +137,26 @@ def test_every_tile_shape_is_bit_exact(tile):
             assert np.array_equal(to_host(d), x)
     finally:
         B.set_gemm_tile(0)
+
+
+def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
+    from paper_2501_07047_amd import binding as B
+    cache = tmp_path / "tune.txt"
+    try:
+        for log_n in (12, 13):
+            res = B.autotune(log_n, L=2, batch=2, cache_path=cache)
+            assert 4 <= res["log_r"] <= log_n - 4 and 1 <= res["tile"] <= 4 and res["us"] > 0
+            again = B.autotune(log_n, L=2, batch=2, cache_path=cache)
+            # served from the cache file (microseconds are stored to 3 decimals)
+            assert (again["log_r"], again["tile"]) == (res["log_r"], res["tile"])
+            assert abs(again["us"] - res["us"]) < 1e-2
+            primes, x = synthetic.ntt_batch(log_n, log_n, 3, 2)
+            ref = _oracle_ntt(x, primes)
+            d = to_dev(x)
+            B.ntt_forward(d, primes)
+            assert np.array_equal(to_host(d), ref)
+        lines = cache.read_text().strip().splitlines()
+        assert len(lines) == 2 and all(len(l.split()) == 7 for l in lines)
+    finally:
+        for log_n in (12, 13):
+            B.set_ntt_split(log_n, log_n // 2)
