@@ -80,8 +80,10 @@ cross_status cross_autotune(cross_ctx ctx, uint32_t log_n, uint32_t L, uint32_t 
                             uint32_t* log_r_out, int* tile_out, double* us_out);
 
 /* Workgroup tile of the BAT int8 GEMM steps on this context (autotuner knob):
- * 0 = automatic (by shape and grid size), 1 = 256x256 (8 waves), 2 = 256x128,
- * 3 = 128x64, 4 = 64x64.  A tile larger than a step's matrix falls back to auto.
+ * 0 = automatic (by shape and grid size), 1 = 256x256 (8 waves of 128x64),
+ * 2 = 256x128 (4 waves of 128x64), 3 = 128x64, 4 = 64x64, 5 = 256x128 (8 waves
+ * of 64x64), 6 = 256x256 (16 waves of 64x64).  A tile larger than a step's
+ * matrix falls back to auto.
  * Results are identical for every tile; only speed changes. */
 cross_status cross_set_gemm_tile(cross_ctx ctx, int tile);
 
@@ -255,8 +257,9 @@ cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len);
  * `out` of `*bytes` bytes.  If out is NULL, *bytes receives the size needed.
  *   which 0/1/2/3: BAT-expanded int8 matrices, forward step 1 / forward step 3 /
  *                  inverse step 3 (applied last) / inverse step 1 (applied first),
- *                  stored tile-major: byte (m, k) at (k/64)*(M*64) + m*64 + k%64,
- *                  entry chunk_i((T[x][u] * 2^32 * 2^(7j)) mod q), m = 4u+i, k = 4x+j
+ *                  entry chunk_i((T[x][u] * 2^32 * 2^(7j)) mod q), m = 4u+i, k = 4x+j,
+ *                  stored in MFMA fragment order: byte (m, k) at
+ *                  ((k/64)*(M/16) + m/16)*1024 + 16*(m%16 + 16*((k%64)/16)) + k%16
  *                  (Alg. bat_deployment, DirectScalarBAT with the Montgomery factor folded in)
  *   which 4/5    : uint32 step-2 twiddles in Montgomery form, forward [R][C] and
  *                  inverse transposed [C][R] (Sec. MAT, layout-invariant 3-step NTT)

@@ -30,7 +30,6 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int BK = 64;            // K per MFMA step
-constexpr int LDS_ROW = BK + 16;  // padded LDS row (bytes): 16 lanes x 16 B hit 64 distinct banks
 
 __device__ __forceinline__ uint32_t pack_chunks(uint32_t x) {
   // four 7-bit chunks of x (< 2^28) in the four bytes of one word
@@ -57,14 +56,33 @@ struct TileArgs {
   int m0, n0;
 };
 
+// LDS holds two stages of the A tile (BM/16 fragments) and the B tile (BN/16
+// fragments).  A fragment is the 1 KB operand of one 16x16x64 MFMA in lane
+// order (lane l: row l%16, K bytes 16*(l/16) .. +15).  The tables are stored in
+// the same order in global memory, so staging is contiguous 16-byte copies and
+// every LDS access -- staging writes and MFMA operand reads -- is a lane-linear
+// 16-byte access, free of bank conflicts.
+//
+// Pipeline over 64-deep K steps with one barrier per step: step k+1 is written
+// to the idle LDS stage from registers while step k is multiplied and step
+// k+2 is loaded from global memory.  Plain residues are cut into 7-bit chunks
+// on the way into LDS; packed data (the intermediate) is copied as is.
 template <int WM, int WN, int MB, int NB, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
 __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8_t* lds_b) {
-  constexpr int NT = WM * WN * 64;
+  constexpr int NW = WM * WN;
+  constexpr int NT = NW * 64;
   constexpr int BM = WM * MB * 16;
   constexpr int BN = WN * NB * 16;
+  constexpr int FA = BM / 16, FB = BN / 16;          // fragments per stage
+  constexpr int STAGE_A = FA * 1024, STAGE_B = FB * 1024;
+  constexpr int A_PIECES = FA * 64 / NT;             // 16-byte table pieces per thread
+  constexpr int B_PIECES = FB * 64 / NT;             // 16-byte data pieces per thread (4 inputs x 1 column)
+  static_assert(A_PIECES >= 1 && FA * 64 % NT == 0 && B_PIECES >= 1 && FB * 64 % NT == 0, "tile split");
+
   const int R = 1 << t.log_r, C = 1 << t.log_c;
   const int U = RIGHT ? C : R;          // outputs per column (and inputs per column)
   const int V = RIGHT ? R : C;          // columns per polynomial
+  const int log_v = RIGHT ? t.log_r : t.log_c;   // V is a power of two: shifts, not divisions
   const int M = 4 * U, K = 4 * U;
   const int ncols = t.npoly * V;
   const int m0 = t.m0, n0 = t.n0;
@@ -72,94 +90,80 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
 
-  const uint32_t* src = t.src;
-  const int8_t* tab = t.table;
-
   v4i acc[MB][NB];
 #pragma unroll
   for (int a = 0; a < MB; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = v4i{0, 0, 0, 0};
 
-  // ---- global -> register staging ------------------------------------------
-  constexpr int A_VEC = BM * BK / 16 / NT;     // 16-byte table pieces per thread
-  static_assert(A_VEC >= 1, "tile too small");
-  // B staging: each thread owns BN*16 words / NT words (16 = inputs per K step)
-  constexpr int B_WORDS = BN * 16 / NT;
-  static_assert(B_WORDS >= 4 && (B_WORDS % 4) == 0, "B staging");
-  constexpr int TPC_R = 16 / B_WORDS;           // RIGHT: threads per column
-  v4i ra[A_VEC];
-  uint32_t rb[B_WORDS];
-
-  // this thread's B column and first input of a K step
-  const int b_n = RIGHT ? tid / TPC_R : tid % BN;
-  const int b_xs = RIGHT ? (tid % TPC_R) * B_WORDS : (tid / BN) * B_WORDS;
-  const bool b_ok = (n0 + b_n) < ncols;
-  const uint32_t* b_base;
-  {
-    const int n = b_ok ? n0 + b_n : 0;
-    const int poly = n / V, v = n - poly * V;
-    b_base = src + (size_t)poly * t.src_stride + (RIGHT ? (size_t)v * C + b_xs : (size_t)b_xs * C + v);
+  // Element (input x, column v) of one polynomial:
+  //   plain, row side   : x*C + v        plain, column side  : v*C + x
+  //   packed, row side  : v*R + x (the inverse intermediate is stored transposed)
+  //   packed, col side  : v*C + x
+  // Piece p of a stage is lane p%64 of fragment p/64: column n0 + 16*(p/64) + p%16,
+  // inputs 4*((p%64)/16) .. +3 of the K step.  Columns past the end read column 0;
+  // their outputs are never stored.
+  const uint32_t* colbase[B_PIECES];
+#pragma unroll
+  for (int i = 0; i < B_PIECES; ++i) {
+    const int piece = tid + i * NT;
+    int n = n0 + (piece >> 6) * 16 + (piece & 15);
+    if (n >= ncols) n = 0;
+    const int gp = ((piece & 63) >> 4) * 4;
+    const int poly = n >> log_v, v = n & (V - 1);
+    size_t off;
+    if (IN_PACKED) off = (size_t)v * (RIGHT ? C : R) + gp;
+    else off = RIGHT ? (size_t)v * C + gp : (size_t)gp * C + v;
+    colbase[i] = t.src + (size_t)poly * t.src_stride + off;
   }
+  const int8_t* tab = t.table + (size_t)(m0 / 16) * 1024;
 
+  v4i ra[A_PIECES], rb[B_PIECES];
   auto load = [&](int ks) {
-    const int8_t* base = tab + (size_t)ks * ((size_t)M * BK) + (size_t)m0 * BK;
+    const int8_t* g = tab + (size_t)ks * ((size_t)(M / 16) * 1024);
 #pragma unroll
-    for (int i = 0; i < A_VEC; ++i) ra[i] = *reinterpret_cast<const v4i*>(base + (tid + i * NT) * 16);
-    // B element (input x, column n) lives at src + poly * stride + x * sx + v * sv
-    const int x0 = ks * 16;
-    if (!RIGHT) {
-      const uint32_t* p = b_base + (size_t)x0 * C;
+    for (int i = 0; i < A_PIECES; ++i) ra[i] = *reinterpret_cast<const v4i*>(g + (tid + i * NT) * 16);
 #pragma unroll
-      for (int w = 0; w < B_WORDS; ++w) rb[w] = b_ok ? p[(size_t)w * C] : 0u;
-    } else {
-      const uint32_t* p = b_base + x0;
-#pragma unroll
-      for (int w = 0; w < B_WORDS; w += 4) {
-        v4i t = b_ok ? *reinterpret_cast<const v4i*>(p + w) : v4i{0, 0, 0, 0};
-        rb[w] = t.x; rb[w + 1] = t.y; rb[w + 2] = t.z; rb[w + 3] = t.w;
+    for (int i = 0; i < B_PIECES; ++i) {
+      if (IN_PACKED || RIGHT) {
+        rb[i] = *reinterpret_cast<const v4i*>(colbase[i] + ks * 16);
+      } else {
+        const uint32_t* p = colbase[i] + (size_t)(ks * 16) * C;
+        rb[i] = v4i{(int)p[0], (int)p[C], (int)p[2 * C], (int)p[3 * C]};
       }
     }
   };
-
-  auto store_lds = [&](int buf) {
+  auto store_lds = [&](int st) {
 #pragma unroll
-    for (int i = 0; i < A_VEC; ++i) {
-      int piece = tid + i * NT;
-      *reinterpret_cast<v4i*>(&lds_a[buf * (BM * LDS_ROW) + (piece >> 2) * LDS_ROW + (piece & 3) * 16]) = ra[i];
-    }
+    for (int i = 0; i < A_PIECES; ++i)
+      *reinterpret_cast<v4i*>(lds_a + st * STAGE_A + (tid + i * NT) * 16) = ra[i];
 #pragma unroll
-    for (int w = 0; w < B_WORDS; w += 4) {
-      v4i t;
-      t.x = IN_PACKED ? rb[w] : pack_chunks(rb[w]);
-      t.y = IN_PACKED ? rb[w + 1] : pack_chunks(rb[w + 1]);
-      t.z = IN_PACKED ? rb[w + 2] : pack_chunks(rb[w + 2]);
-      t.w = IN_PACKED ? rb[w + 3] : pack_chunks(rb[w + 3]);
-      *reinterpret_cast<v4i*>(&lds_b[buf * (BN * LDS_ROW) + b_n * LDS_ROW + (b_xs + w) * 4]) = t;
+    for (int i = 0; i < B_PIECES; ++i) {
+      v4i w = rb[i];
+      if (!IN_PACKED) {
+        w.x = pack_chunks(w.x);
+        w.y = pack_chunks(w.y);
+        w.z = pack_chunks(w.z);
+        w.w = pack_chunks(w.w);
+      }
+      *reinterpret_cast<v4i*>(lds_b + st * STAGE_B + (tid + i * NT) * 16) = w;
     }
   };
-
-  auto compute = [&](int buf) {
-    const int koff = (lane >> 4) * 16;
+  auto compute = [&](int st) {
     v4i fa[MB], fb[NB];
 #pragma unroll
     for (int a = 0; a < MB; ++a)
-      fa[a] = *reinterpret_cast<const v4i*>(&lds_a[buf * (BM * LDS_ROW) + (wm * MB * 16 + a * 16 + (lane & 15)) * LDS_ROW + koff]);
+      fa[a] = *reinterpret_cast<const v4i*>(lds_a + st * STAGE_A + (wm * MB + a) * 1024 + lane * 16);
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      fb[b] = *reinterpret_cast<const v4i*>(&lds_b[buf * (BN * LDS_ROW) + (wn * NB * 16 + b * 16 + (lane & 15)) * LDS_ROW + koff]);
-    __builtin_amdgcn_s_setprio(1);   // keep the matrix pipe fed ahead of the staging waves
+      fb[b] = *reinterpret_cast<const v4i*>(lds_b + st * STAGE_B + (wn * NB + b) * 1024 + lane * 16);
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
       for (int b = 0; b < NB; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
-    __builtin_amdgcn_s_setprio(0);
   };
 
-  // Software pipeline over K steps: LDS stage ks&1 is multiplied while stage
-  // (ks+1)&1 is written from registers and step ks+2 is in flight from global
-  // memory.  One barrier per step.
   const int nk = K / BK;
   load(0);
   store_lds(0);
@@ -175,14 +179,22 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
   // ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ----------
   const uint32_t q = t.q, qinv = t.qinv;
   uint32_t* dst = t.dst;
+  // Column side with plain output: the tile's outputs run down columns of the
+  // R x C result, so they are staged in LDS (free after the last K step) as
+  // [column v][row u] and written back row by row, 16 bytes per lane.
+  constexpr bool STAGE_OUT = RIGHT && !OUT_PACKED;
+  constexpr int BU = BM / 4;              // outputs per tile column
+  constexpr int SROW = BU + 4;            // padded LDS row (words)
+  uint32_t* so = reinterpret_cast<uint32_t*>(lds_a);   // lds_a spans the whole workgroup allocation
 #pragma unroll
   for (int a = 0; a < MB; ++a) {
     const int u = (m0 + wm * MB * 16 + a * 16) / 4 + (lane >> 4);
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const int n = n0 + wn * NB * 16 + b * 16 + (lane & 15);
-      if (n >= ncols) continue;
-      const int poly = n / V, v = n - poly * V;
+      const int nl = wn * NB * 16 + b * 16 + (lane & 15);
+      const int n = n0 + nl;
+      if (!STAGE_OUT && n >= ncols) continue;
+      const int poly = n >> log_v, v = n & (V - 1);
       v4i s = acc[a][b];
       uint64_t z = (uint64_t)(uint32_t)s.x + ((uint64_t)(uint32_t)s.y << 7) +
                    ((uint64_t)(uint32_t)s.z << 14) + ((uint64_t)(uint32_t)s.w << 21);
@@ -193,11 +205,41 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
       }
       if (r >= q) r -= q;
       if (OUT_PACKED) r = pack_chunks(r);
-      size_t off = RIGHT ? (size_t)v * C + u : (size_t)u * C + v;
-      dst[(size_t)poly * t.dst_stride + off] = r;
+      if (STAGE_OUT) {
+        so[nl * SROW + (u - m0 / 4)] = r;
+      } else {
+        // column side with packed output = the inverse intermediate, stored transposed
+        size_t off = RIGHT ? (size_t)u * R + v : (size_t)u * C + v;
+        dst[(size_t)poly * t.dst_stride + off] = r;
+      }
     }
   }
+  if (STAGE_OUT) {
+    __syncthreads();
+    constexpr int VEC_PER_ROW = BU / 4;
+#pragma unroll
+    for (int i = 0; i < BN * VEC_PER_ROW / NT; ++i) {
+      const int idx = tid + i * NT;
+      const int nl = idx / VEC_PER_ROW, uq = idx % VEC_PER_ROW;
+      const int n = n0 + nl;
+      if (n < ncols) {
+        const int poly = n >> log_v, v = n & (V - 1);
+        const v4i w = *reinterpret_cast<const v4i*>(so + nl * SROW + uq * 4);
+        *reinterpret_cast<v4i*>(dst + (size_t)poly * t.dst_stride + (size_t)v * C + m0 / 4 + uq * 4) = w;
+      }
+    }
+    __syncthreads();   // LDS is reused by the next tile of a work list
+  }
   (void)M;
+}
+
+// LDS bytes of one workgroup: two operand stages, or the output staging tile if larger.
+template <int WM, int WN, int MB, int NB, bool RIGHT, bool OUT_PACKED>
+constexpr int gemm_lds_bytes() {
+  constexpr int BM = WM * MB * 16, BN = WN * NB * 16;
+  constexpr int ops = 2 * (BM + BN) * 64;
+  constexpr int out = (RIGHT && !OUT_PACKED) ? BN * (BM / 4 + 4) * 4 : 0;
+  return ops > out ? ops : out;
 }
 
 template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
@@ -205,9 +247,10 @@ __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   constexpr int BM = WM * MB * 16;
   constexpr int BN = WN * NB * 16;
-  // two LDS stages: the next K step is written while the current one is multiplied
-  __shared__ __attribute__((aligned(16))) int8_t lds_a[2 * BM * LDS_ROW];
-  __shared__ __attribute__((aligned(16))) int8_t lds_b[2 * BN * LDS_ROW];
+  // two LDS stages of operand fragments (A stages then B stages), reused for output staging
+  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, RIGHT, OUT_PACKED>()];
+  int8_t* lds_a = lds;
+  int8_t* lds_b = lds + 2 * BM * 64;
   // XCD-aware tile order: consecutive logical tiles land on the same XCD so a
   // job's table and columns stay in one L2.
   const int total = g.njobs * tiles_m * tiles_n;
@@ -233,8 +276,9 @@ __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles) {
   constexpr int BM = WM * MB * 16;
   constexpr int BN = WN * NB * 16;
-  __shared__ __attribute__((aligned(16))) int8_t lds_a[2 * BM * LDS_ROW];
-  __shared__ __attribute__((aligned(16))) int8_t lds_b[2 * BN * LDS_ROW];
+  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, RIGHT, OUT_PACKED>()];
+  int8_t* lds_a = lds;
+  int8_t* lds_b = lds + 2 * BM * 64;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
   const int lo = (int)((long)ntiles * xcd / 8), hi = (int)((long)ntiles * (xcd + 1) / 8);
   for (int i = lo + local; i < hi; i += per_xcd) {
@@ -283,7 +327,8 @@ hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
 template <bool RIGHT, bool INP, bool OUTP, bool TW>
 hipError_t launch_list_cfg(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
                            hipStream_t s) {
-  hipLaunchKernelGGL((bat_gemm_list_kernel<2, 2, 8, 4, 2, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(256), 0, s,
+  // 256 x 128 tiles, 8 waves of 64 x 64, two workgroups per CU
+  hipLaunchKernelGGL((bat_gemm_list_kernel<4, 2, 4, 4, 4, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(512), 0, s,
                      tasks, tiles, ntiles);
   return hipGetLastError();
 }
@@ -309,14 +354,14 @@ int resolve_gemm_tile(const GemmLaunch& g) {
   const int M = 4 * U;
   const long ncols = (long)g.npoly * V;
   int t = g.tile;
-  if (t == kTile256x256 && M < 256) t = kTileAuto;
+  if ((t == kTile256x256 || t == kTile256x128w8 || t == kTile256x256w16) && M < 256) t = kTileAuto;
   if (t == kTile256x128 && M < 256) t = kTileAuto;
   if (t == kTile128x64 && M < 128) t = kTileAuto;
   if (t != kTileAuto) return t;
   if (M >= 256) {
-    // prefer the large tile when it still gives every CU two workgroups
+    // 8 waves of 64x64 (4 waves per SIMD) when the grid still covers every CU
     long grid = (long)g.njobs * (M / 256) * ((ncols + 127) / 128);
-    if (grid >= 512) return kTile256x128;
+    if (grid >= 256) return kTile256x128w8;
     return kTile128x64;
   }
   if (M >= 128) return kTile128x64;
@@ -330,6 +375,8 @@ hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s) {
     case kTile256x256: return dispatch_flags<2, 4, 8, 4, 2>(g, s);   // 8 waves, one workgroup per CU
     case kTile256x128: return dispatch_flags<2, 2, 8, 4, 2>(g, s);   // 4 waves, two workgroups per CU
     case kTile128x64: return dispatch_flags<2, 2, 4, 2, 2>(g, s);
+    case kTile256x128w8: return dispatch_flags<4, 2, 4, 4, 4>(g, s);   // 8 waves of 64x64
+    case kTile256x256w16: return dispatch_flags<4, 4, 4, 4, 4>(g, s);  // 16 waves of 64x64
     default: return dispatch_flags<2, 2, 2, 2, 2>(g, s);
   }
 }

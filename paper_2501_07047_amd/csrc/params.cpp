@@ -94,7 +94,7 @@ uint32_t bitrev(uint32_t x, int bits) {
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
                 std::vector<int8_t>& out) {
   const int M = kChunks * n_out, K = kChunks * n_in;
-  if (n_in <= 0 || n_out <= 0 || K % kTileK != 0 || (size_t)T.size() != (size_t)n_in * n_out)
+  if (n_in <= 0 || n_out <= 0 || K % kTileK != 0 || M % 16 != 0 || (size_t)T.size() != (size_t)n_in * n_out)
     throw std::invalid_argument("bat_expand: table shape does not tile");
   out.assign((size_t)M * K, 0);
   const uint64_t r32 = ((uint64_t)1 << 32) % q;
@@ -106,7 +106,10 @@ void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
         for (int i = 0; i < kChunks; ++i) {
           int m = o * kChunks + i, k = in * kChunks + j;
           int8_t c = (int8_t)((v >> (kChunkBits * i)) & ((1u << kChunkBits) - 1));
-          out[(size_t)(k / kTileK) * ((size_t)M * kTileK) + (size_t)m * kTileK + (k % kTileK)] = c;
+          // MFMA fragment order: 16 rows x 64 K bytes per 1 KB fragment, lane-major
+          const size_t frag = (size_t)(k / kTileK) * (M / 16) + m / 16;
+          const int lane = (m % 16) + 16 * ((k % kTileK) / 16);
+          out[frag * 1024 + lane * 16 + (k % 16)] = c;
         }
       }
     }

@@ -23,7 +23,11 @@ uint32_t bitrev(uint32_t x, int bits);
 
 // BAT-expanded table of a pre-known residue matrix T (rows = "in", cols = "out"):
 // dense int8 matrix D[m = out*4 + i][k = in*4 + j] = chunk_i((T[in][out] * 2^32 * 2^(7j)) mod q),
-// stored tile-major: offset(m, k) = (k / 64) * (M * 64) + m * 64 + (k % 64), M = 4 * n_out.
+// stored in MFMA fragment order (M = 4 * n_out): the 1 KB fragment
+// f = (k / 64) * (M / 16) + m / 16 holds rows 16*(m/16) .. +15 and K bytes 64*(k/64) .. +63,
+// byte (m, k) at f * 1024 + 16 * (m % 16 + 16 * ((k % 64) / 16)) + k % 16, so a
+// workgroup's slab of one K step is contiguous and loads straight into LDS in
+// the lane order of v_mfma_i32_16x16x64_i8's A operand.
 // The 2^32 is the Montgomery factor removed by the epilogue's REDC.
 // Throws std::invalid_argument unless 4 * n_in is a multiple of 64.
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,

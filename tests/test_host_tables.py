@@ -14,8 +14,9 @@ from oracle.primes import prime_chain, psi as psi_of
 
 
 def _dense(tab, M, K):
-    t = tab.astype(np.int64).reshape(K // 64, M, 64)
-    return t.transpose(1, 0, 2).reshape(M, K)
+    # fragment order: [K/64][M/16][lane = m%16 + 16*kq][16 bytes], kq = (k%64)//16
+    t = tab.astype(np.int64).reshape(K // 64, M // 16, 4, 16, 16)   # [ks][mf][kq][m%16][byte]
+    return t.transpose(1, 3, 0, 2, 4).reshape(M, K)
 
 
 def _chunks_rows(X):
