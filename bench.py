@@ -289,10 +289,13 @@ def main():
     ops = gemm_ops_per_launch(LOG_N, LOG_R, L * POLYS, "left" if fam.endswith("left") else "right")
     achieved = ops / avg_s / 1e12
     khash = source_hash("ntt_mfma.hip")
+    measured_peak = {"mfma_i8_tops": round(B.measure_peak("mfma_i8"), 1),
+                     "hbm_copy_gbs": round(B.measure_peak("hbm_copy"), 1)}
     roof = {"bound": "mfma", "kernel": fam, "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
             "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
             "traffic": traffic_for(fam, khash), "avg_launch_us": round(avg_s * 1e6, 2),
-            "ops_per_launch": ops, "launches_timed": launches,
+            "ops_per_launch": ops, "launches_timed": launches, "measured_peaks": measured_peak,
+            "frac_of_measured_mfma_peak": round(achieved / measured_peak["mfma_i8_tops"], 4),
             "event_ms_by_kernel": {k: [v[0], round(v[1], 3)] for k, v in prof.items()}}
 
     line = {"metric": METRIC, "value": round(value, 1), "unit": "limb-NTT/s", "n_gpus": 1,

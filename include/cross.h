@@ -82,8 +82,8 @@ cross_status cross_autotune(cross_ctx ctx, uint32_t log_n, uint32_t L, uint32_t 
 /* Workgroup tile of the BAT int8 GEMM steps on this context (autotuner knob):
  * 0 = automatic (by shape and grid size), 1 = 256x256 (8 waves of 128x64),
  * 2 = 256x128 (4 waves of 128x64), 3 = 128x64, 4 = 64x64, 5 = 256x128 (8 waves
- * of 64x64), 6 = 256x256 (16 waves of 64x64).  A tile larger than a step's
- * matrix falls back to auto.
+ * of 64x64), 6 = 256x256 (16 waves of 64x64), 7 = as 6 with 128-deep K
+ * stages.  A tile larger than a step's matrix falls back to auto.
  * Results are identical for every tile; only speed changes. */
 cross_status cross_set_gemm_tile(cross_ctx ctx, int tile);
 
@@ -252,6 +252,15 @@ cross_status cross_profile_enable(cross_ctx ctx, int enable);
 cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len);
 
 /*
+ * Measured machine peaks (roofline reference, synchronous): which = 0 -> int8
+ * MFMA TOP/s from registers (v_mfma_i32_16x16x64_i8, 8 independent chains per
+ * wave, 8 waves per SIMD); which = 1 -> streaming copy GB/s (bytes read +
+ * written, 1 GiB buffers, allocated and freed by the call); which = 2 -> int8
+ * MFMA TOP/s with v_mfma_i32_32x32x32_i8.
+ */
+cross_status cross_measure_peak(cross_ctx ctx, int which, double* out);
+
+/*
  * Host-only introspection of the offline-compiled tables (no device work):
  * copies one table of the (q, N = 2^log_n, R = 2^log_r) plan into host memory
  * `out` of `*bytes` bytes.  If out is NULL, *bytes receives the size needed.
@@ -259,10 +268,12 @@ cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len);
  *                  inverse step 3 (applied last) / inverse step 1 (applied first),
  *                  entry chunk_i((T[x][u] * 2^32 * 2^(7j)) mod q), m = 4u+i, k = 4x+j,
  *                  stored in MFMA fragment order: byte (m, k) at
- *                  ((k/64)*(M/16) + m/16)*1024 + 16*(m%16 + 16*((k%64)/16)) + k%16
+ *                  ((k/64)*(M/32) + m/32)*2048 + ((k%64)/32)*1024
+ *                  + 16*(m%32 + 32*((k%32)/16)) + k%16
  *                  (Alg. bat_deployment, DirectScalarBAT with the Montgomery factor folded in)
- *   which 4/5    : uint32 step-2 twiddles in Montgomery form, forward [R][C] and
- *                  inverse transposed [C][R] (Sec. MAT, layout-invariant 3-step NTT)
+ *   which 4/5    : uint32 step-2 twiddles as (w, floor(w*2^32/q)) pairs (Shoup
+ *                  multiplication), forward [R][C][2] and inverse transposed [C][R][2]
+ *                  (Sec. MAT, layout-invariant 3-step NTT)
  * Returns CROSS_EINVAL for a bad `which`, split or buffer size.
  */
 cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,

@@ -56,6 +56,7 @@ SIGNATURES = {
     "cross_batch_run": [c_vp, c_vp],
     "cross_batch_info": [c_vp, ctypes.POINTER(c_u32), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
     "cross_batch_destroy": [c_vp],
+    "cross_measure_peak": [c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
     "cross_profile_enable": [c_vp, ctypes.c_int],
     "cross_profile_report": [c_vp, ctypes.c_char_p, ctypes.c_uint64],
     "cross_host_tables": [c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
@@ -196,6 +197,15 @@ def host_tables(q, log_n, log_r, which):
     if st != 0:
         raise CrossError(st, "cross_host_tables")
     return buf.view(np.int8) if which < 4 else buf.view(np.uint32)
+
+
+def measure_peak(which, device=None):
+    """which: "mfma_i8" -> TOP/s, "hbm_copy" -> GB/s (see cross_measure_peak)."""
+    ctx = context(device)
+    out = ctypes.c_double()
+    _check(lib().cross_measure_peak(ctx, {"mfma_i8": 0, "hbm_copy": 1, "mfma_i8_32x32": 2}[which],
+                                    ctypes.byref(out)), ctx)
+    return out.value
 
 
 def profile_enable(enable=True, device=None):

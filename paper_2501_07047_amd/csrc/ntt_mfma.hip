@@ -16,16 +16,25 @@
 // GEMM view (M x K times K x Ncols):
 //   A[m][k]: pre-known, m = 4*u + i (output u, output chunk i), k = 4*x + j (input x, chunk j)
 //   B[k][n]: chunk j of data element x of column n;  n = poly * V + v
-// MFMA v_mfma_i32_16x16x64_i8: lane l holds rows 4*(l/16) .. +3 of column l%16 of
-// its 16x16 output block, i.e. all four chunk rows of one output: the merge is
-// entirely in-register.
+// Rows order chunks fastest (m = 4u + i) so that the four chunk partial sums of
+// one output land in four consecutive accumulator registers of one lane.
 //
-// Rows of the output block order chunks fastest (m = 4u + i) for exactly that reason.
+// All global accesses go through buffer resources: a wave-uniform base (the
+// tile's first polynomial, the table, the twiddles) in scalar registers, a
+// 32-bit per-lane byte offset, and the per-slab or per-row step in the scalar
+// offset.  Addresses cost no 64-bit vector arithmetic, and a column past the
+// end of the launch falls outside the resource's range: its loads read zero
+// and its stores are dropped by the hardware.
 #include "kernels.h"
+
+#include <type_traits>
 
 namespace cross {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
 namespace {
 
@@ -36,11 +45,10 @@ __device__ __forceinline__ uint32_t pack_chunks(uint32_t x) {
   return (x & 0x7fu) | ((x << 1) & 0x7f00u) | ((x << 2) & 0x7f0000u) | ((x << 3) & 0x7f000000u);
 }
 
-__device__ __forceinline__ uint32_t redc(uint64_t z, uint32_t q, uint32_t qinv) {
-  // z < q * 2^32  ->  z * 2^-32 mod q in (0, 2q)
-  uint32_t t = (uint32_t)z * qinv;
-  uint32_t u = __umulhi(t, q);
-  return (uint32_t)(z >> 32) + q - u;
+// Raw buffer resource over [base, base + bytes): range-checked per access.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
+  const uint32_t n = bytes > 0xfffffff0ull ? 0xfffffff0u : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)n, 0x00020000);
 }
 
 // One BM x BN output tile of one step (all of K).  Shared by the uniform
@@ -56,27 +64,34 @@ struct TileArgs {
   int m0, n0;
 };
 
-// LDS holds two stages of the A tile (BM/16 fragments) and the B tile (BN/16
-// fragments).  A fragment is the 1 KB operand of one 16x16x64 MFMA in lane
-// order (lane l: row l%16, K bytes 16*(l/16) .. +15).  The tables are stored in
-// the same order in global memory, so staging is contiguous 16-byte copies and
-// every LDS access -- staging writes and MFMA operand reads -- is a lane-linear
-// 16-byte access, free of bank conflicts.
+// MFMA v_mfma_i32_32x32x32_i8 (the int8 instruction that reaches the chip's
+// dense int8 rate; the 16x16x64 form runs at half of it).  Lane l of a 32x32
+// output block holds rows 8*(v/4) + 4*(l/32) + v%4 (v < 16) of column l%32:
+// with rows ordered output-major, chunk-minor (m = 4u + i), registers 4g..4g+3
+// are the four chunk partial sums of output u = 2g + l/32 -- the ChunkMerge is
+// entirely in-register.
 //
-// Pipeline over 64-deep K steps with one barrier per step: step k+1 is written
-// to the idle LDS stage from registers while step k is multiplied and step
-// k+2 is loaded from global memory.  Plain residues are cut into 7-bit chunks
-// on the way into LDS; packed data (the intermediate) is copied as is.
-template <int WM, int WN, int MB, int NB, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+// Operand fragments are 1 KB: 32 rows (A) or columns (B) x 32 K bytes, lane l
+// holding row/column l%32 and K bytes 16*(l/32) .. +15.  A 64-deep K slab of a
+// 32-row block is two fragments (K halves).  The tables are stored in global
+// memory in exactly this order, so staging is contiguous 16-byte copies and
+// every LDS access (staging writes and MFMA operand reads) is lane-linear.
+//
+// Pipeline over K stages (KS slabs of 64 each) with one barrier per stage:
+// stage k+1 is written to the idle LDS buffer from registers while stage k is
+// multiplied and stage k+2 is loaded from global memory.  Plain residues are
+// cut into 7-bit chunks on the way into LDS; packed data is copied as is.
+template <int WM, int WN, int MB, int NB, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
 __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8_t* lds_b) {
   constexpr int NW = WM * WN;
   constexpr int NT = NW * 64;
-  constexpr int BM = WM * MB * 16;
-  constexpr int BN = WN * NB * 16;
-  constexpr int FA = BM / 16, FB = BN / 16;          // fragments per stage
-  constexpr int STAGE_A = FA * 1024, STAGE_B = FB * 1024;
-  constexpr int A_PIECES = FA * 64 / NT;             // 16-byte table pieces per thread
-  constexpr int B_PIECES = FB * 64 / NT;             // 16-byte data pieces per thread (4 inputs x 1 column)
+  constexpr int BM = WM * MB * 32;                   // MB, NB count 32 x 32 blocks per wave
+  constexpr int BN = WN * NB * 32;
+  constexpr int FA = 2 * BM / 32, FB = 2 * BN / 32;  // fragments per 64-deep slab
+  constexpr int SLAB_A = FA * 1024, SLAB_B = FB * 1024;
+  constexpr int STAGE_A = KS * SLAB_A, STAGE_B = KS * SLAB_B;
+  constexpr int A_PIECES = FA * 64 / NT;             // 16-byte table pieces per thread per slab
+  constexpr int B_PIECES = FB * 64 / NT;             // 16-byte data pieces (4 inputs x 1 column)
   static_assert(A_PIECES >= 1 && FA * 64 % NT == 0 && B_PIECES >= 1 && FB * 64 % NT == 0, "tile split");
 
   const int R = 1 << t.log_r, C = 1 << t.log_c;
@@ -84,87 +99,111 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
   const int V = RIGHT ? R : C;          // columns per polynomial
   const int log_v = RIGHT ? t.log_r : t.log_c;   // V is a power of two: shifts, not divisions
   const int M = 4 * U, K = 4 * U;
-  const int ncols = t.npoly * V;
   const int m0 = t.m0, n0 = t.n0;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
 
-  v4i acc[MB][NB];
+  v16i acc[MB][NB];
 #pragma unroll
   for (int a = 0; a < MB; ++a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[a][b] = v4i{0, 0, 0, 0};
+    for (int b = 0; b < NB; ++b) acc[a][b] = v16i{};
+
+  // Buffers of this tile: data columns start at the tile's first polynomial.
+  const int poly0 = n0 >> log_v;
+  const int npoly_left = t.npoly - poly0;
+  const __amdgpu_buffer_rsrc_t rs_src =
+      make_rsrc(t.src + (size_t)poly0 * t.src_stride, (uint64_t)npoly_left * t.src_stride * 4);
+  const __amdgpu_buffer_rsrc_t rs_tab = make_rsrc(t.table + (size_t)(m0 / 32) * 2048, (uint64_t)M * K - (uint64_t)(m0 / 32) * 2048);
+  const uint32_t slab_bytes = (uint32_t)(M / 32) * 2048;   // one 64-deep K slab of the whole table
 
   // Element (input x, column v) of one polynomial:
   //   plain, row side   : x*C + v        plain, column side  : v*C + x
   //   packed, row side  : v*R + x (the inverse intermediate is stored transposed)
   //   packed, col side  : v*C + x
-  // Piece p of a stage is lane p%64 of fragment p/64: column n0 + 16*(p/64) + p%16,
-  // inputs 4*((p%64)/16) .. +3 of the K step.  Columns past the end read column 0;
-  // their outputs are never stored.
-  const uint32_t* colbase[B_PIECES];
+  // Piece p of a slab is lane p%64 of fragment f = p/64 = (32-column block f/2,
+  // K half f%2): column n0 + 32*(f/2) + p%32, inputs 8*(f%2) + 4*((p%64)/32) .. +3.
+  uint32_t coloff[B_PIECES];             // byte offset of input gp of the piece's column
 #pragma unroll
   for (int i = 0; i < B_PIECES; ++i) {
     const int piece = tid + i * NT;
-    int n = n0 + (piece >> 6) * 16 + (piece & 15);
-    if (n >= ncols) n = 0;
-    const int gp = ((piece & 63) >> 4) * 4;
-    const int poly = n >> log_v, v = n & (V - 1);
-    size_t off;
-    if (IN_PACKED) off = (size_t)v * (RIGHT ? C : R) + gp;
-    else off = RIGHT ? (size_t)v * C + gp : (size_t)gp * C + v;
-    colbase[i] = t.src + (size_t)poly * t.src_stride + off;
+    const int f = piece >> 6;
+    const int n = n0 + (f >> 1) * 32 + (piece & 31);
+    const int gp = (f & 1) * 8 + ((piece & 63) >> 5) * 4;
+    const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
+    uint32_t off;
+    if (IN_PACKED) off = v * (RIGHT ? C : R) + gp;
+    else off = RIGHT ? v * C + gp : gp * C + v;
+    coloff[i] = (dpoly * (uint32_t)t.src_stride + off) * 4;
   }
-  const int8_t* tab = t.table + (size_t)(m0 / 16) * 1024;
 
-  v4i ra[A_PIECES], rb[B_PIECES];
+  v4i ra[KS][A_PIECES], rb[KS][B_PIECES];
   auto load = [&](int ks) {
-    const int8_t* g = tab + (size_t)ks * ((size_t)(M / 16) * 1024);
 #pragma unroll
-    for (int i = 0; i < A_PIECES; ++i) ra[i] = *reinterpret_cast<const v4i*>(g + (tid + i * NT) * 16);
+    for (int sl = 0; sl < KS; ++sl) {
+      const int k64 = ks * KS + sl;
 #pragma unroll
-    for (int i = 0; i < B_PIECES; ++i) {
-      if (IN_PACKED || RIGHT) {
-        rb[i] = *reinterpret_cast<const v4i*>(colbase[i] + ks * 16);
-      } else {
-        const uint32_t* p = colbase[i] + (size_t)(ks * 16) * C;
-        rb[i] = v4i{(int)p[0], (int)p[C], (int)p[2 * C], (int)p[3 * C]};
+      for (int i = 0; i < A_PIECES; ++i)
+        ra[sl][i] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs_tab, (tid + i * NT) * 16, k64 * slab_bytes, 0);
+#pragma unroll
+      for (int i = 0; i < B_PIECES; ++i) {
+        if (IN_PACKED || RIGHT) {
+          rb[sl][i] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs_src, coloff[i], k64 * 64, 0);
+        } else {
+          // four inputs of one column lie C words apart
+          const int row = k64 * 16 * C * 4;
+          rb[sl][i] = v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row, 0),
+                          (int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row + C * 4, 0),
+                          (int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row + 2 * C * 4, 0),
+                          (int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row + 3 * C * 4, 0)};
+        }
       }
     }
   };
   auto store_lds = [&](int st) {
 #pragma unroll
-    for (int i = 0; i < A_PIECES; ++i)
-      *reinterpret_cast<v4i*>(lds_a + st * STAGE_A + (tid + i * NT) * 16) = ra[i];
+    for (int sl = 0; sl < KS; ++sl) {
 #pragma unroll
-    for (int i = 0; i < B_PIECES; ++i) {
-      v4i w = rb[i];
-      if (!IN_PACKED) {
-        w.x = pack_chunks(w.x);
-        w.y = pack_chunks(w.y);
-        w.z = pack_chunks(w.z);
-        w.w = pack_chunks(w.w);
+      for (int i = 0; i < A_PIECES; ++i)
+        *reinterpret_cast<v4i*>(lds_a + st * STAGE_A + sl * SLAB_A + (tid + i * NT) * 16) = ra[sl][i];
+#pragma unroll
+      for (int i = 0; i < B_PIECES; ++i) {
+        v4i w = rb[sl][i];
+        if (!IN_PACKED) {
+          w.x = pack_chunks(w.x);
+          w.y = pack_chunks(w.y);
+          w.z = pack_chunks(w.z);
+          w.w = pack_chunks(w.w);
+        }
+        *reinterpret_cast<v4i*>(lds_b + st * STAGE_B + sl * SLAB_B + (tid + i * NT) * 16) = w;
       }
-      *reinterpret_cast<v4i*>(lds_b + st * STAGE_B + (tid + i * NT) * 16) = w;
     }
   };
   auto compute = [&](int st) {
-    v4i fa[MB], fb[NB];
 #pragma unroll
-    for (int a = 0; a < MB; ++a)
-      fa[a] = *reinterpret_cast<const v4i*>(lds_a + st * STAGE_A + (wm * MB + a) * 1024 + lane * 16);
+    for (int sl = 0; sl < KS; ++sl) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      fb[b] = *reinterpret_cast<const v4i*>(lds_b + st * STAGE_B + (wn * NB + b) * 1024 + lane * 16);
+      for (int h = 0; h < 2; ++h) {          // K halves of the 64-deep slab
+        v4i fa[MB], fb[NB];
 #pragma unroll
-    for (int a = 0; a < MB; ++a)
+        for (int a = 0; a < MB; ++a)
+          fa[a] = *reinterpret_cast<const v4i*>(lds_a + st * STAGE_A + sl * SLAB_A +
+                                                ((wm * MB + a) * 2 + h) * 1024 + lane * 16);
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < NB; ++b)
+          fb[b] = *reinterpret_cast<const v4i*>(lds_b + st * STAGE_B + sl * SLAB_B +
+                                                ((wn * NB + b) * 2 + h) * 1024 + lane * 16);
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[a], fb[b], acc[a][b], 0, 0, 0);
+      }
+    }
   };
 
-  const int nk = K / BK;
+  const int nk = K / (BK * KS);
   load(0);
   store_lds(0);
   if (nk > 1) load(1);
@@ -178,42 +217,73 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
 
   // ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ----------
   const uint32_t q = t.q, qinv = t.qinv;
-  uint32_t* dst = t.dst;
+  const __amdgpu_buffer_rsrc_t rs_dst =
+      make_rsrc(t.dst + (size_t)poly0 * t.dst_stride, (uint64_t)npoly_left * t.dst_stride * 4);
+  const __amdgpu_buffer_rsrc_t rs_tw = make_rsrc(t.tw, TW ? (uint64_t)U * V * 8 : 0);
   // Column side with plain output: the tile's outputs run down columns of the
-  // R x C result, so they are staged in LDS (free after the last K step) as
+  // R x C result, so they are staged in LDS (free after the last K stage) as
   // [column v][row u] and written back row by row, 16 bytes per lane.
   constexpr bool STAGE_OUT = RIGHT && !OUT_PACKED;
   constexpr int BU = BM / 4;              // outputs per tile column
   constexpr int SROW = BU + 4;            // padded LDS row (words)
   uint32_t* so = reinterpret_cast<uint32_t*>(lds_a);   // lds_a spans the whole workgroup allocation
+  const uint32_t row_words = RIGHT ? R : C;            // output row length (transposed when RIGHT)
+
+  auto epilogue = [&](auto wide_tag) {
+    constexpr bool WIDE = decltype(wide_tag)::value;
 #pragma unroll
-  for (int a = 0; a < MB; ++a) {
-    const int u = (m0 + wm * MB * 16 + a * 16) / 4 + (lane >> 4);
+    for (int a = 0; a < MB; ++a) {
+      const int u0 = (m0 + (wm * MB + a) * 32) / 4 + (lane >> 5);   // output of register group 0
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int nl = wn * NB * 16 + b * 16 + (lane & 15);
-      const int n = n0 + nl;
-      if (!STAGE_OUT && n >= ncols) continue;
-      const int poly = n >> log_v, v = n & (V - 1);
-      v4i s = acc[a][b];
-      uint64_t z = (uint64_t)(uint32_t)s.x + ((uint64_t)(uint32_t)s.y << 7) +
-                   ((uint64_t)(uint32_t)s.z << 14) + ((uint64_t)(uint32_t)s.w << 21);
-      uint32_t r = redc(z, q, qinv);
-      if (TW) {
-        uint32_t w = t.tw[(size_t)u * V + v];
-        r = redc((uint64_t)r * w, q, qinv);
-      }
-      if (r >= q) r -= q;
-      if (OUT_PACKED) r = pack_chunks(r);
-      if (STAGE_OUT) {
-        so[nl * SROW + (u - m0 / 4)] = r;
-      } else {
-        // column side with packed output = the inverse intermediate, stored transposed
-        size_t off = RIGHT ? (size_t)u * R + v : (size_t)u * C + v;
-        dst[(size_t)poly * t.dst_stride + off] = r;
+      for (int b = 0; b < NB; ++b) {
+        const int nl = (wn * NB + b) * 32 + (lane & 31);
+        const int n = n0 + nl;
+        const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
+        // register group g holds output u0 + 2g: consecutive groups are 2 rows apart
+        const uint32_t out_off = (dpoly * (uint32_t)t.dst_stride + (uint32_t)u0 * row_words + v) * 4;
+        const uint32_t tw_off = ((uint32_t)u0 * V + v) * 8;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const v16i& sv = acc[a][b];
+          const uint32_t s0 = (uint32_t)sv[4 * g], s1 = (uint32_t)sv[4 * g + 1];
+          const uint32_t s2 = (uint32_t)sv[4 * g + 2], s3 = (uint32_t)sv[4 * g + 3];
+          uint32_t zlo, zhi;
+          if (!WIDE) {
+            // z = x + w * 2^14 with x = s0 + s1 * 2^7 and w = s2 + s3 * 2^7 (both < 2^32)
+            const uint32_t x = s0 + (s1 << 7), w = s2 + (s3 << 7);
+            const uint32_t wl = w << 14;
+            zlo = x + wl;
+            zhi = (w >> 18) + (zlo < wl ? 1u : 0u);
+          } else {
+            const uint64_t z = (uint64_t)s0 + ((uint64_t)s1 << 7) + ((uint64_t)s2 << 14) + ((uint64_t)s3 << 21);
+            zlo = (uint32_t)z;
+            zhi = (uint32_t)(z >> 32);
+          }
+          // Montgomery REDC of z (the 2^32 factor was folded into the table): (0, 2q)
+          uint32_t r = zhi + q - __umulhi(zlo * qinv, q);
+          if (TW) {
+            // Shoup multiplication by the pre-known twiddle (w, floor(w 2^32 / q)): [0, 2q)
+            const v2u tw = __builtin_amdgcn_raw_buffer_load_b64(rs_tw, tw_off, g * 2 * V * 8, 0);
+            r = r * tw.x - __umulhi(r, tw.y) * q;
+          }
+          r = r >= q ? r - q : r;
+          if (OUT_PACKED) r = pack_chunks(r);
+          if (STAGE_OUT) {
+            so[nl * SROW + (u0 + 2 * g - m0 / 4)] = r;
+          } else {
+            // column side with packed output = the inverse intermediate, stored transposed;
+            // columns past the launch fall outside rs_dst and are dropped
+            __builtin_amdgcn_raw_buffer_store_b32(r, rs_dst, out_off, g * 2 * row_words * 4, 0);
+          }
+        }
       }
     }
-  }
+  };
+  // Chunk partial sums are below K * 127 * 127 = 4U * 127^2; for U <= 512 the
+  // two half-merges x and w fit 32 bits, larger U merges in 64 bits.
+  if (U <= 512) epilogue(std::false_type{});
+  else epilogue(std::true_type{});
+
   if (STAGE_OUT) {
     __syncthreads();
     constexpr int VEC_PER_ROW = BU / 4;
@@ -222,11 +292,10 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
       const int idx = tid + i * NT;
       const int nl = idx / VEC_PER_ROW, uq = idx % VEC_PER_ROW;
       const int n = n0 + nl;
-      if (n < ncols) {
-        const int poly = n >> log_v, v = n & (V - 1);
-        const v4i w = *reinterpret_cast<const v4i*>(so + nl * SROW + uq * 4);
-        *reinterpret_cast<v4i*>(dst + (size_t)poly * t.dst_stride + (size_t)v * C + m0 / 4 + uq * 4) = w;
-      }
+      const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
+      const v4u w = *reinterpret_cast<const v4u*>(so + nl * SROW + uq * 4);
+      const uint32_t off = (dpoly * (uint32_t)t.dst_stride + v * C + m0 / 4 + uq * 4) * 4;
+      __builtin_amdgcn_raw_buffer_store_b128(w, rs_dst, off, 0, 0);
     }
     __syncthreads();   // LDS is reused by the next tile of a work list
   }
@@ -234,23 +303,23 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
 }
 
 // LDS bytes of one workgroup: two operand stages, or the output staging tile if larger.
-template <int WM, int WN, int MB, int NB, bool RIGHT, bool OUT_PACKED>
+template <int WM, int WN, int MB, int NB, int KS, bool RIGHT, bool OUT_PACKED>
 constexpr int gemm_lds_bytes() {
-  constexpr int BM = WM * MB * 16, BN = WN * NB * 16;
-  constexpr int ops = 2 * (BM + BN) * 64;
+  constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
+  constexpr int ops = 2 * (BM + BN) * 64 * KS;
   constexpr int out = (RIGHT && !OUT_PACKED) ? BN * (BM / 4 + 4) * 4 : 0;
   return ops > out ? ops : out;
 }
 
-template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
 __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
-  constexpr int BM = WM * MB * 16;
-  constexpr int BN = WN * NB * 16;
+  constexpr int BM = WM * MB * 32;
+  constexpr int BN = WN * NB * 32;
   // two LDS stages of operand fragments (A stages then B stages), reused for output staging
-  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, RIGHT, OUT_PACKED>()];
+  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
   int8_t* lds_a = lds;
-  int8_t* lds_b = lds + 2 * BM * 64;
+  int8_t* lds_b = lds + 2 * BM * 64 * KS;
   // XCD-aware tile order: consecutive logical tiles land on the same XCD so a
   // job's table and columns stay in one L2.
   const int total = g.njobs * tiles_m * tiles_n;
@@ -265,20 +334,20 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   const GemmJob job = g.jobs[job_id];
   TileArgs t{job.table, job.tw, g.src + job.src_off, g.dst + job.dst_off, g.src_stride, g.dst_stride,
              job.q, job.qinv, g.npoly, g.log_r, g.log_c, tm * BM, tn * BN};
-  gemm_tile<WM, WN, MB, NB, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
+  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
 }
 
 // Work-list form: tiles of many tasks (mixed N, R x C, primes, buffers) in one
 // persistent launch.  The grid is a multiple of 8; XCD x (= blockIdx % 8) walks
 // the x-th eighth of the tile list so each task's tiles share one L2.
-template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
 __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles) {
-  constexpr int BM = WM * MB * 16;
-  constexpr int BN = WN * NB * 16;
-  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, RIGHT, OUT_PACKED>()];
+  constexpr int BM = WM * MB * 32;
+  constexpr int BN = WN * NB * 32;
+  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
   int8_t* lds_a = lds;
-  int8_t* lds_b = lds + 2 * BM * 64;
+  int8_t* lds_b = lds + 2 * BM * 64 * KS;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
   const int lo = (int)((long)ntiles * xcd / 8), hi = (int)((long)ntiles * (xcd + 1) / 8);
   for (int i = lo + local; i < hi; i += per_xcd) {
@@ -286,39 +355,42 @@ bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles
     const GemmTask k = tasks[r.task];
     TileArgs t{k.table, k.tw, k.src, k.dst, k.src_stride, k.dst_stride, k.q, k.qinv, k.npoly,
                k.log_r, k.log_c, (int)r.tm * BM, (int)r.tn * BN};
-    gemm_tile<WM, WN, MB, NB, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
+    gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
   }
 }
 
-template <int WM, int WN, int MB, int NB, int OCC, bool RIGHT, bool INP, bool OUTP, bool TW>
+template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool INP, bool OUTP, bool TW>
 hipError_t launch_cfg(const GemmLaunch& g, hipStream_t s) {
-  constexpr int BM = WM * MB * 16, BN = WN * NB * 16;
+  constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
   const int U = RIGHT ? (1 << g.log_c) : (1 << g.log_r);
   const int V = RIGHT ? (1 << g.log_r) : (1 << g.log_c);
   const int M = 4 * U;
   if (M % BM) return hipErrorInvalidValue;
+  // per-lane byte offsets are 32-bit and span at most BN / V + 1 polynomials of a tile
+  const uint64_t span = (uint64_t)(BN / V + 2) * 4;
+  if (span * g.src_stride >= (1ull << 31) || span * g.dst_stride >= (1ull << 31)) return hipErrorInvalidValue;
   const int tiles_m = M / BM;
   const int ncols = g.npoly * V;
   const int tiles_n = (ncols + BN - 1) / BN;
   const int grid = g.njobs * tiles_m * tiles_n;
-  hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, RIGHT, INP, OUTP, TW>), dim3(grid),
+  hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW>), dim3(grid),
                      dim3(WM * WN * 64), 0, s, g, tiles_m, tiles_n);
   return hipGetLastError();
 }
 
-template <int WM, int WN, int MB, int NB, int OCC>
+template <int WM, int WN, int MB, int NB, int OCC, int KS = 1>
 hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
   // forward: LEFT(plain in, packed out, twiddle) then RIGHT(packed in, plain out)
   // inverse: RIGHT(plain in, packed out, twiddle) then LEFT(packed in, plain out)
   const bool right = g.kind == kRight;
   if (!right && !g.in_packed && g.out_packed && g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, false, false, true, true>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, KS, false, false, true, true>(g, s);
   if (right && g.in_packed && !g.out_packed && !g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, true, true, false, false>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, KS, true, true, false, false>(g, s);
   if (right && !g.in_packed && g.out_packed && g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, true, false, true, true>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, KS, true, false, true, true>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, false, true, false, false>(g, s);
+    return launch_cfg<WM, WN, MB, NB, OCC, KS, false, true, false, false>(g, s);
   return hipErrorInvalidValue;
 }
 
@@ -328,7 +400,7 @@ template <bool RIGHT, bool INP, bool OUTP, bool TW>
 hipError_t launch_list_cfg(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
                            hipStream_t s) {
   // 256 x 128 tiles, 8 waves of 64 x 64, two workgroups per CU
-  hipLaunchKernelGGL((bat_gemm_list_kernel<4, 2, 4, 4, 4, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(512), 0, s,
+  hipLaunchKernelGGL((bat_gemm_list_kernel<4, 2, 2, 2, 4, 1, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(512), 0, s,
                      tasks, tiles, ntiles);
   return hipGetLastError();
 }
@@ -354,7 +426,8 @@ int resolve_gemm_tile(const GemmLaunch& g) {
   const int M = 4 * U;
   const long ncols = (long)g.npoly * V;
   int t = g.tile;
-  if ((t == kTile256x256 || t == kTile256x128w8 || t == kTile256x256w16) && M < 256) t = kTileAuto;
+  if ((t == kTile256x256 || t == kTile256x128w8 || t == kTile256x256w16 || t == kTile256x256w16k2) && M < 256)
+    t = kTileAuto;
   if (t == kTile256x128 && M < 256) t = kTileAuto;
   if (t == kTile128x64 && M < 128) t = kTileAuto;
   if (t != kTileAuto) return t;
@@ -372,12 +445,13 @@ hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s) {
   const int U = (g.kind == kRight) ? (1 << g.log_c) : (1 << g.log_r);
   if (4 * U < 64) return hipErrorInvalidValue;
   switch (resolve_gemm_tile(g)) {
-    case kTile256x256: return dispatch_flags<2, 4, 8, 4, 2>(g, s);   // 8 waves, one workgroup per CU
-    case kTile256x128: return dispatch_flags<2, 2, 8, 4, 2>(g, s);   // 4 waves, two workgroups per CU
-    case kTile128x64: return dispatch_flags<2, 2, 4, 2, 2>(g, s);
-    case kTile256x128w8: return dispatch_flags<4, 2, 4, 4, 4>(g, s);   // 8 waves of 64x64
-    case kTile256x256w16: return dispatch_flags<4, 4, 4, 4, 4>(g, s);  // 16 waves of 64x64
-    default: return dispatch_flags<2, 2, 2, 2, 2>(g, s);
+    case kTile256x256: return dispatch_flags<2, 4, 4, 2, 2>(g, s);     // 8 waves of 128x64
+    case kTile256x128: return dispatch_flags<2, 2, 4, 2, 2>(g, s);     // 4 waves of 128x64
+    case kTile128x64: return dispatch_flags<2, 2, 2, 1, 4>(g, s);      // 4 waves of 64x32
+    case kTile256x128w8: return dispatch_flags<4, 2, 2, 2, 4>(g, s);   // 8 waves of 64x64
+    case kTile256x256w16: return dispatch_flags<4, 4, 2, 2, 4>(g, s);  // 16 waves of 64x64
+    case kTile256x256w16k2: return dispatch_flags<4, 4, 2, 2, 4, 2>(g, s);  // same, 128-deep K stages
+    default: return dispatch_flags<2, 2, 1, 1, 4>(g, s);               // 64 x 64: 4 waves of 32x32
   }
 }
 

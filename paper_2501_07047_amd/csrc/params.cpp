@@ -94,7 +94,7 @@ uint32_t bitrev(uint32_t x, int bits) {
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
                 std::vector<int8_t>& out) {
   const int M = kChunks * n_out, K = kChunks * n_in;
-  if (n_in <= 0 || n_out <= 0 || K % kTileK != 0 || M % 16 != 0 || (size_t)T.size() != (size_t)n_in * n_out)
+  if (n_in <= 0 || n_out <= 0 || K % kTileK != 0 || M % 32 != 0 || (size_t)T.size() != (size_t)n_in * n_out)
     throw std::invalid_argument("bat_expand: table shape does not tile");
   out.assign((size_t)M * K, 0);
   const uint64_t r32 = ((uint64_t)1 << 32) % q;
@@ -106,10 +106,12 @@ void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
         for (int i = 0; i < kChunks; ++i) {
           int m = o * kChunks + i, k = in * kChunks + j;
           int8_t c = (int8_t)((v >> (kChunkBits * i)) & ((1u << kChunkBits) - 1));
-          // MFMA fragment order: 16 rows x 64 K bytes per 1 KB fragment, lane-major
-          const size_t frag = (size_t)(k / kTileK) * (M / 16) + m / 16;
-          const int lane = (m % 16) + 16 * ((k % kTileK) / 16);
-          out[frag * 1024 + lane * 16 + (k % 16)] = c;
+          // MFMA fragment order: per 64-deep K slab and 32-row block, two 1 KB
+          // fragments (K halves) of 32 rows x 32 K bytes, lane-major
+          const size_t blk = (size_t)(k / kTileK) * (M / 32) + m / 32;
+          const int half = (k % kTileK) / 32;
+          const int lane = (m % 32) + 32 * ((k % 32) / 16);
+          out[blk * 2048 + half * 1024 + lane * 16 + (k % 16)] = c;
         }
       }
     }
@@ -170,14 +172,20 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
 
   // Step-2 twiddles T2[k][c] = psi^(c (2 brv_R(k)+1)), stored [k][c] (left kernel epilogue);
   // inverse twiddles IT2[k][c] = psi^(-c (2 brv_R(k)+1)), stored transposed [c][k]
-  // (right kernel epilogue, whose lanes run along k).
-  t.fwd_tw.resize((size_t)R * C);
-  t.inv_tw.resize((size_t)R * C);
+  // (right kernel epilogue, whose lanes run along k).  Each entry is the pair
+  // (w, floor(w * 2^32 / q)) for Shoup multiplication.
+  t.fwd_tw.resize((size_t)2 * R * C);
+  t.inv_tw.resize((size_t)2 * R * C);
+  auto shoup = [&](uint32_t w) { return (uint32_t)(((uint64_t)w << 32) / q); };
   for (uint32_t k = 0; k < R; ++k) {
     int64_t odd = 2 * (int64_t)bitrev(k, (int)log_r) + 1;
     for (uint32_t c = 0; c < C; ++c) {
-      t.fwd_tw[(size_t)k * C + c] = (uint32_t)(P((int64_t)c * odd) * r32 % q);
-      t.inv_tw[(size_t)c * R + k] = (uint32_t)(P(-(int64_t)c * odd) * r32 % q);
+      const uint32_t wf = P((int64_t)c * odd), wi = P(-(int64_t)c * odd);
+      const size_t f = 2 * ((size_t)k * C + c), i = 2 * ((size_t)c * R + k);
+      t.fwd_tw[f] = wf;
+      t.fwd_tw[f + 1] = shoup(wf);
+      t.inv_tw[i] = wi;
+      t.inv_tw[i + 1] = shoup(wi);
     }
   }
 }

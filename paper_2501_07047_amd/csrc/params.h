@@ -23,12 +23,11 @@ uint32_t bitrev(uint32_t x, int bits);
 
 // BAT-expanded table of a pre-known residue matrix T (rows = "in", cols = "out"):
 // dense int8 matrix D[m = out*4 + i][k = in*4 + j] = chunk_i((T[in][out] * 2^32 * 2^(7j)) mod q),
-// stored in MFMA fragment order (M = 4 * n_out): the 1 KB fragment
-// f = (k / 64) * (M / 16) + m / 16 holds rows 16*(m/16) .. +15 and K bytes 64*(k/64) .. +63,
-// byte (m, k) at f * 1024 + 16 * (m % 16 + 16 * ((k % 64) / 16)) + k % 16, so a
-// workgroup's slab of one K step is contiguous and loads straight into LDS in
-// the lane order of v_mfma_i32_16x16x64_i8's A operand.
-// The 2^32 is the Montgomery factor removed by the epilogue's REDC.
+// stored in MFMA fragment order (M = 4 * n_out): for 64-deep K slab s = k / 64 and
+// 32-row block b = m / 32, two 1 KB fragments (K halves h = (k % 64) / 32) of the
+// v_mfma_i32_32x32x32_i8 A operand, byte (m, k) at
+// (s * (M / 32) + b) * 2048 + h * 1024 + 16 * (m % 32 + 32 * ((k % 32) / 16)) + k % 16,
+// so a workgroup's rows of one K slab are contiguous and load in lane order.
 // Throws std::invalid_argument unless 4 * n_in is a multiple of 64.
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
                 std::vector<int8_t>& out);
@@ -36,7 +35,7 @@ void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
 struct NttTables {
   // forward: step 1 (left-known, rows), step 2 twiddle, step 3 (right-known, cols)
   std::vector<int8_t> fwd_left, fwd_right, inv_left, inv_right;
-  std::vector<uint32_t> fwd_tw, inv_tw;      // Montgomery form (x * 2^32 mod q)
+  std::vector<uint32_t> fwd_tw, inv_tw;      // (w, floor(w 2^32 / q)) pairs for Shoup multiplication
   std::vector<uint32_t> bf_fwd, bf_inv;      // butterfly twiddles, Montgomery form
   uint32_t bf_ninv;                          // N^-1 * 2^32 mod q (butterfly inverse scale)
 };

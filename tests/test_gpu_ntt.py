@@ -122,7 +122,7 @@ def test_argument_errors():
         B.ntt_forward(torch.zeros((1, 1, 1000), dtype=torch.int32, device="cuda"), [268042241])
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
 def test_every_tile_shape_is_bit_exact(tile):
     from paper_2501_07047_amd import binding as B
     B.set_gemm_tile(tile)

@@ -14,9 +14,9 @@ from oracle.primes import prime_chain, psi as psi_of
 
 
 def _dense(tab, M, K):
-    # fragment order: [K/64][M/16][lane = m%16 + 16*kq][16 bytes], kq = (k%64)//16
-    t = tab.astype(np.int64).reshape(K // 64, M // 16, 4, 16, 16)   # [ks][mf][kq][m%16][byte]
-    return t.transpose(1, 3, 0, 2, 4).reshape(M, K)
+    # fragment order: [K/64][M/32][K half][lane = m%32 + 32*kq][16 bytes], kq = (k%32)//16
+    t = tab.astype(np.int64).reshape(K // 64, M // 32, 2, 2, 32, 16)   # [s][b][h][kq][m%32][byte]
+    return t.transpose(1, 4, 0, 2, 3, 5).reshape(M, K)
 
 
 def _chunks_rows(X):
@@ -43,7 +43,9 @@ def _emulate(X, q, log_n, log_r, inverse):
     if not inverse:
         t1 = _dense(binding.host_tables(q, log_n, log_r, 0), 4 * R, 4 * R)
         t3 = _dense(binding.host_tables(q, log_n, log_r, 1), 4 * C, 4 * C)
-        tw = binding.host_tables(q, log_n, log_r, 4).reshape(R, C).astype(object)
+        pairs = binding.host_tables(q, log_n, log_r, 4).reshape(R, C, 2)
+        assert np.array_equal(pairs[..., 1].astype(np.uint64), (pairs[..., 0].astype(np.uint64) << 32) // q)
+        tw = (pairs[..., 0].astype(object) * (1 << 32)) % q          # Montgomery form for the emulation
         A = X.reshape(R, C)
         Y = _merge_reduce(t1 @ _chunks_rows(A), q)                 # [k][c]
         Y = np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
@@ -51,7 +53,7 @@ def _emulate(X, q, log_n, log_r, inverse):
         return out.T.reshape(-1)
     t3 = _dense(binding.host_tables(q, log_n, log_r, 3), 4 * C, 4 * C)
     t1 = _dense(binding.host_tables(q, log_n, log_r, 2), 4 * R, 4 * R)
-    tw = binding.host_tables(q, log_n, log_r, 5).reshape(C, R).astype(object)
+    tw = (binding.host_tables(q, log_n, log_r, 5).reshape(C, R, 2)[..., 0].astype(object) * (1 << 32)) % q
     A = X.reshape(R, C)
     Y = _merge_reduce(t3 @ _chunks_rows(A.T), q)                   # [c][k]
     Y = np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
@@ -80,5 +82,5 @@ def test_table_entries_are_7bit_chunks():
         t = binding.host_tables(q, 12, 6, which)
         assert t.min() >= 0 and t.max() <= 127
     for which in (4, 5):
-        t = binding.host_tables(q, 12, 6, which)
-        assert int(t.max()) < q
+        t = binding.host_tables(q, 12, 6, which).reshape(-1, 2)
+        assert int(t[:, 0].max()) < q
