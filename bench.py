@@ -289,7 +289,7 @@ def main():
     ops = gemm_ops_per_launch(LOG_N, LOG_R, L * POLYS, "left" if fam.endswith("left") else "right")
     achieved = ops / avg_s / 1e12
     khash = source_hash("ntt_mfma.hip")
-    measured_peak = {"mfma_i8_tops": round(B.measure_peak("mfma_i8"), 1),
+    measured_peak = {"mfma_i8_tops": round(B.measure_peak("mfma_i8_32x32"), 1),
                      "hbm_copy_gbs": round(B.measure_peak("hbm_copy"), 1)}
     roof = {"bound": "mfma", "kernel": fam, "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
             "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),

@@ -83,7 +83,10 @@ cross_status cross_autotune(cross_ctx ctx, uint32_t log_n, uint32_t L, uint32_t 
  * 0 = automatic (by shape and grid size), 1 = 256x256 (8 waves of 128x64),
  * 2 = 256x128 (4 waves of 128x64), 3 = 128x64, 4 = 64x64, 5 = 256x128 (8 waves
  * of 64x64), 6 = 256x256 (16 waves of 64x64), 7 = as 6 with 128-deep K
- * stages.  A tile larger than a step's matrix falls back to auto.
+ * stages; 8 = 256x128 (8 waves of 64x64) and 9 = 256x128 (4 waves of 64x128),
+ * where each wave reads its rows of the pre-known table straight from global
+ * memory instead of through LDS (steps contracting at most 512 inputs).  A
+ * tile that does not fit a step falls back to auto.
  * Results are identical for every tile; only speed changes. */
 cross_status cross_set_gemm_tile(cross_ctx ctx, int tile);
 

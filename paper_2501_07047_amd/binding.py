@@ -141,7 +141,7 @@ def set_ntt_split(log_n, log_r, device=None):
 
 
 def set_gemm_tile(tile, device=None):
-    """0 = auto, 1..6 = fixed workgroup tiles (see cross_set_gemm_tile)."""
+    """0 = auto, 1..9 = fixed workgroup tiles (see cross_set_gemm_tile)."""
     ctx = context(device)
     _check(lib().cross_set_gemm_tile(ctx, int(tile)), ctx)
 

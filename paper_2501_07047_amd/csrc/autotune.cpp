@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <sstream>
+#include <set>
 #include <string>
 
 #include "context.h"
@@ -100,7 +101,20 @@ cross_status cross_autotune(cross_ctx ctx, uint32_t log_n, uint32_t L, uint32_t 
   const int hi_r = std::min((int)log_n - (log_n >= 12 ? 6 : 4), half + 1);
   for (int lr = lo_r; lr <= hi_r && st == CROSS_OK; ++lr) {
     ctx->split[(int)log_n] = lr;
-    for (int tile = 1; tile <= 4 && st == CROSS_OK; ++tile) {
+    std::set<std::pair<int, int>> timed;   // (row-side, column-side) tiles as launched
+    for (int tile = 1; tile < kTileCount && st == CROSS_OK; ++tile) {
+      // a tile that does not fit this split falls back to another one: time each pair once
+      GemmLaunch g{};
+      g.njobs = (int)L;
+      g.npoly = (int)batch;
+      g.log_r = lr;
+      g.log_c = (int)log_n - lr;
+      g.tile = tile;
+      g.kind = kLeft;
+      const int t_left = resolve_gemm_tile(g);
+      g.kind = kRight;
+      const int t_right = resolve_gemm_tile(g);
+      if (!timed.insert({t_left, t_right}).second) continue;
       ctx->gemm_tile = tile;
       for (int w = 0; w < 2 && st == CROSS_OK; ++w) {
         st = cross_ntt_forward(ctx, log_n, primes.data(), L, batch, (uint32_t*)data, nullptr);

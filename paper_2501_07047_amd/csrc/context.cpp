@@ -317,7 +317,7 @@ cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r) 
 
 cross_status cross_set_gemm_tile(cross_ctx ctx, int tile) {
   if (!ctx) return CROSS_EINVAL;
-  if (tile < 0 || tile > 7) return fail(ctx, CROSS_EINVAL, "tile must be 0 (auto) .. 7");
+  if (tile < 0 || tile >= kTileCount) return fail(ctx, CROSS_EINVAL, "tile must be 0 (auto) .. 9");
   ctx->gemm_tile = tile;
   return CROSS_OK;
 }

@@ -37,7 +37,8 @@ struct GemmLaunch {
 
 // Workgroup tile shapes of the BAT GEMM (rows x columns of the int8 product).
 enum GemmTile { kTileAuto = 0, kTile256x256 = 1, kTile256x128 = 2, kTile128x64 = 3, kTile64x64 = 4,
-                kTile256x128w8 = 5, kTile256x256w16 = 6, kTile256x256w16k2 = 7 };
+                kTile256x128w8 = 5, kTile256x256w16 = 6, kTile256x256w16k2 = 7, kTileDirect256x128 = 8,
+                kTileDirect256x128n = 9, kTileCount = 10 };
 // Tile that launch_bat_gemm would use for g (resolves kTileAuto).
 int resolve_gemm_tile(const GemmLaunch& g);
 

@@ -76,11 +76,171 @@ struct TileArgs {
 // 32-row block is two fragments (K halves).  The tables are stored in global
 // memory in exactly this order, so staging is contiguous 16-byte copies and
 // every LDS access (staging writes and MFMA operand reads) is lane-linear.
-//
-// Pipeline over K stages (KS slabs of 64 each) with one barrier per stage:
-// stage k+1 is written to the idle LDS buffer from registers while stage k is
-// multiplied and stage k+2 is loaded from global memory.  Plain residues are
-// cut into 7-bit chunks on the way into LDS; packed data is copied as is.
+
+// Shape of one step as seen by a tile.
+struct StepShape {
+  int R, C, U, V, log_v, M, K, poly0;
+};
+
+template <bool RIGHT>
+__device__ __forceinline__ StepShape step_shape(const TileArgs& t) {
+  StepShape g;
+  g.R = 1 << t.log_r;
+  g.C = 1 << t.log_c;
+  g.U = RIGHT ? g.C : g.R;              // outputs per column (and inputs per column)
+  g.V = RIGHT ? g.R : g.C;              // columns per polynomial
+  g.log_v = RIGHT ? t.log_r : t.log_c;  // V is a power of two: shifts, not divisions
+  g.M = 4 * g.U;
+  g.K = 4 * g.U;
+  g.poly0 = t.n0 >> g.log_v;            // first polynomial of the tile's columns
+  return g;
+}
+
+// Data buffers of a tile start at its first polynomial.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t data_rsrc(const uint32_t* base, uint64_t stride, int npoly,
+                                                            int poly0) {
+  return make_rsrc(base + (size_t)poly0 * stride, (uint64_t)(npoly - poly0) * stride * 4);
+}
+
+// Byte offset (from the tile's first polynomial) of the first of the four
+// inputs held by B piece p of a 64-deep slab.  Piece p is lane p%64 of
+// fragment f = p/64 = (32-column block f/2, K half f%2): column n0 + 32*(f/2) +
+// p%32, inputs 8*(f%2) + 4*((p%64)/32) .. +3.  Element (input x, column v) of one
+// polynomial lies at
+//   plain, row side   : x*C + v        plain, column side  : v*C + x
+//   packed, row side  : v*R + x (the inverse intermediate is stored transposed)
+//   packed, col side  : v*C + x
+template <bool RIGHT, bool IN_PACKED>
+__device__ __forceinline__ uint32_t b_piece_offset(const TileArgs& t, const StepShape& g, int piece) {
+  const int f = piece >> 6;
+  const int n = t.n0 + (f >> 1) * 32 + (piece & 31);
+  const int gp = (f & 1) * 8 + ((piece & 63) >> 5) * 4;
+  const uint32_t dpoly = (uint32_t)((n >> g.log_v) - g.poly0), v = n & (g.V - 1);
+  uint32_t off;
+  if (IN_PACKED) off = v * (RIGHT ? g.C : g.R) + gp;
+  else off = RIGHT ? v * g.C + gp : gp * g.C + v;
+  return (dpoly * (uint32_t)t.src_stride + off) * 4;
+}
+
+// The four inputs of one B piece of slab k64, cut into 7-bit chunks if plain.
+template <bool RIGHT, bool IN_PACKED>
+__device__ __forceinline__ v4i load_b_piece(__amdgpu_buffer_rsrc_t rs, uint32_t off, int k64, int C) {
+  v4i w;
+  if (IN_PACKED || RIGHT) {
+    w = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs, off, k64 * 64, 0);
+  } else {
+    // four inputs of one column lie C words apart
+    const int row = k64 * 16 * C * 4;
+    w = v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(rs, off, row, 0),
+            (int)__builtin_amdgcn_raw_buffer_load_b32(rs, off, row + C * 4, 0),
+            (int)__builtin_amdgcn_raw_buffer_load_b32(rs, off, row + 2 * C * 4, 0),
+            (int)__builtin_amdgcn_raw_buffer_load_b32(rs, off, row + 3 * C * 4, 0)};
+  }
+  return w;
+}
+
+__device__ __forceinline__ v4i pack4(v4i w) {
+  return v4i{(int)pack_chunks(w.x), (int)pack_chunks(w.y), (int)pack_chunks(w.z), (int)pack_chunks(w.w)};
+}
+
+// ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ------------
+// Wave (wm, wn) holds MB x NB accumulator blocks of 32 x 32.  Column side with
+// plain output: the tile's outputs run down columns of the R x C result, so
+// they are staged in LDS (free after the last K stage; `so` must hold
+// BN x (BM/4 + 4) words) as [column v][row u] and written back row by row, 16
+// bytes per lane.
+template <int NT, int BM, int BN, int MB, int NB, bool RIGHT, bool OUT_PACKED, bool TW, bool NARROW_ONLY = false>
+__device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const TileArgs& t, const StepShape& g,
+                                              int wm, int wn, uint32_t* so) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int m0 = t.m0, n0 = t.n0;
+  const uint32_t q = t.q, qinv = t.qinv;
+  const int V = g.V, log_v = g.log_v, poly0 = g.poly0;
+  const __amdgpu_buffer_rsrc_t rs_dst = data_rsrc(t.dst, t.dst_stride, t.npoly, poly0);
+  const __amdgpu_buffer_rsrc_t rs_tw = make_rsrc(t.tw, TW ? (uint64_t)g.U * V * 8 : 0);
+  constexpr bool STAGE_OUT = RIGHT && !OUT_PACKED;
+  constexpr int BU = BM / 4;              // outputs per tile column
+  constexpr int SROW = BU + 4;            // padded LDS row (words)
+  const uint32_t row_words = RIGHT ? g.R : g.C;         // output row length (transposed when RIGHT)
+
+  auto body = [&](auto wide_tag) {
+    constexpr bool WIDE = decltype(wide_tag)::value;
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+      const int u0 = (m0 + (wm * MB + a) * 32) / 4 + (lane >> 5);   // output of register group 0
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int nl = (wn * NB + b) * 32 + (lane & 31);
+        const int n = n0 + nl;
+        const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
+        // register group j holds output u0 + 2j: consecutive groups are 2 rows apart
+        const uint32_t out_off = (dpoly * (uint32_t)t.dst_stride + (uint32_t)u0 * row_words + v) * 4;
+        const uint32_t tw_off = ((uint32_t)u0 * V + v) * 8;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const v16i& sv = acc[a][b];
+          const uint32_t s0 = (uint32_t)sv[4 * j], s1 = (uint32_t)sv[4 * j + 1];
+          const uint32_t s2 = (uint32_t)sv[4 * j + 2], s3 = (uint32_t)sv[4 * j + 3];
+          uint32_t zlo, zhi;
+          if (!WIDE) {
+            // z = x + w * 2^14 with x = s0 + s1 * 2^7 and w = s2 + s3 * 2^7 (both < 2^32)
+            const uint32_t x = s0 + (s1 << 7), w = s2 + (s3 << 7);
+            const uint32_t wl = w << 14;
+            zlo = x + wl;
+            zhi = (w >> 18) + (zlo < wl ? 1u : 0u);
+          } else {
+            const uint64_t z = (uint64_t)s0 + ((uint64_t)s1 << 7) + ((uint64_t)s2 << 14) + ((uint64_t)s3 << 21);
+            zlo = (uint32_t)z;
+            zhi = (uint32_t)(z >> 32);
+          }
+          // Montgomery REDC of z (the 2^32 factor was folded into the table): (0, 2q)
+          uint32_t r = zhi + q - __umulhi(zlo * qinv, q);
+          if (TW) {
+            // Shoup multiplication by the pre-known twiddle (w, floor(w 2^32 / q)): [0, 2q)
+            const v2u tw = __builtin_amdgcn_raw_buffer_load_b64(rs_tw, tw_off, j * 2 * V * 8, 0);
+            r = r * tw.x - __umulhi(r, tw.y) * q;
+          }
+          r = r >= q ? r - q : r;
+          if (OUT_PACKED) r = pack_chunks(r);
+          if (STAGE_OUT) {
+            so[nl * SROW + (u0 + 2 * j - m0 / 4)] = r;
+          } else {
+            // column side with packed output = the inverse intermediate, stored transposed;
+            // columns past the launch fall outside rs_dst and are dropped
+            __builtin_amdgcn_raw_buffer_store_b32(r, rs_dst, out_off, j * 2 * row_words * 4, 0);
+          }
+        }
+      }
+    }
+  };
+  // Chunk partial sums are below K * 127 * 127 = 4U * 127^2; for U <= 512 the
+  // two half-merges x and w fit 32 bits, larger U merges in 64 bits.
+  if (NARROW_ONLY || g.U <= 512) body(std::false_type{});
+  else body(std::true_type{});
+
+  if (STAGE_OUT) {
+    __syncthreads();
+    constexpr int VEC_PER_ROW = BU / 4;
+#pragma unroll
+    for (int i = 0; i < BN * VEC_PER_ROW / NT; ++i) {
+      const int idx = tid + i * NT;
+      const int nl = idx / VEC_PER_ROW, uq = idx % VEC_PER_ROW;
+      const int n = n0 + nl;
+      const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
+      const v4u w = *reinterpret_cast<const v4u*>(so + nl * SROW + uq * 4);
+      const uint32_t off = (dpoly * (uint32_t)t.dst_stride + v * g.C + m0 / 4 + uq * 4) * 4;
+      __builtin_amdgcn_raw_buffer_store_b128(w, rs_dst, off, 0, 0);
+    }
+    __syncthreads();   // LDS is reused by the next tile of a work list
+  }
+}
+
+// LDS-staged form: both operands go through LDS.  Pipeline over K stages (KS
+// slabs of 64 each) with one barrier per stage: the MFMAs of stage k are issued
+// first, then stage k+1 (loaded one stage earlier) is written from registers
+// to the idle LDS buffer and stage k+2 is loaded from global memory.  Plain
+// residues are cut into 7-bit chunks on the way into LDS; packed data is
+// copied as is.
 template <int WM, int WN, int MB, int NB, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
 __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8_t* lds_b) {
   constexpr int NW = WM * WN;
@@ -94,12 +254,9 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
   constexpr int B_PIECES = FB * 64 / NT;             // 16-byte data pieces (4 inputs x 1 column)
   static_assert(A_PIECES >= 1 && FA * 64 % NT == 0 && B_PIECES >= 1 && FB * 64 % NT == 0, "tile split");
 
-  const int R = 1 << t.log_r, C = 1 << t.log_c;
-  const int U = RIGHT ? C : R;          // outputs per column (and inputs per column)
-  const int V = RIGHT ? R : C;          // columns per polynomial
-  const int log_v = RIGHT ? t.log_r : t.log_c;   // V is a power of two: shifts, not divisions
-  const int M = 4 * U, K = 4 * U;
-  const int m0 = t.m0, n0 = t.n0;
+  const StepShape g = step_shape<RIGHT>(t);
+  const int M = g.M, K = g.K, C = g.C;
+  const int m0 = t.m0;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -110,33 +267,13 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[a][b] = v16i{};
 
-  // Buffers of this tile: data columns start at the tile's first polynomial.
-  const int poly0 = n0 >> log_v;
-  const int npoly_left = t.npoly - poly0;
-  const __amdgpu_buffer_rsrc_t rs_src =
-      make_rsrc(t.src + (size_t)poly0 * t.src_stride, (uint64_t)npoly_left * t.src_stride * 4);
-  const __amdgpu_buffer_rsrc_t rs_tab = make_rsrc(t.table + (size_t)(m0 / 32) * 2048, (uint64_t)M * K - (uint64_t)(m0 / 32) * 2048);
+  const __amdgpu_buffer_rsrc_t rs_src = data_rsrc(t.src, t.src_stride, t.npoly, g.poly0);
+  const __amdgpu_buffer_rsrc_t rs_tab =
+      make_rsrc(t.table + (size_t)(m0 / 32) * 2048, (uint64_t)M * K - (uint64_t)(m0 / 32) * 2048);
   const uint32_t slab_bytes = (uint32_t)(M / 32) * 2048;   // one 64-deep K slab of the whole table
-
-  // Element (input x, column v) of one polynomial:
-  //   plain, row side   : x*C + v        plain, column side  : v*C + x
-  //   packed, row side  : v*R + x (the inverse intermediate is stored transposed)
-  //   packed, col side  : v*C + x
-  // Piece p of a slab is lane p%64 of fragment f = p/64 = (32-column block f/2,
-  // K half f%2): column n0 + 32*(f/2) + p%32, inputs 8*(f%2) + 4*((p%64)/32) .. +3.
-  uint32_t coloff[B_PIECES];             // byte offset of input gp of the piece's column
+  uint32_t coloff[B_PIECES];
 #pragma unroll
-  for (int i = 0; i < B_PIECES; ++i) {
-    const int piece = tid + i * NT;
-    const int f = piece >> 6;
-    const int n = n0 + (f >> 1) * 32 + (piece & 31);
-    const int gp = (f & 1) * 8 + ((piece & 63) >> 5) * 4;
-    const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
-    uint32_t off;
-    if (IN_PACKED) off = v * (RIGHT ? C : R) + gp;
-    else off = RIGHT ? v * C + gp : gp * C + v;
-    coloff[i] = (dpoly * (uint32_t)t.src_stride + off) * 4;
-  }
+  for (int i = 0; i < B_PIECES; ++i) coloff[i] = b_piece_offset<RIGHT, IN_PACKED>(t, g, tid + i * NT);
 
   v4i ra[KS][A_PIECES], rb[KS][B_PIECES];
   auto load = [&](int ks) {
@@ -147,18 +284,7 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
       for (int i = 0; i < A_PIECES; ++i)
         ra[sl][i] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs_tab, (tid + i * NT) * 16, k64 * slab_bytes, 0);
 #pragma unroll
-      for (int i = 0; i < B_PIECES; ++i) {
-        if (IN_PACKED || RIGHT) {
-          rb[sl][i] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs_src, coloff[i], k64 * 64, 0);
-        } else {
-          // four inputs of one column lie C words apart
-          const int row = k64 * 16 * C * 4;
-          rb[sl][i] = v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row, 0),
-                          (int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row + C * 4, 0),
-                          (int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row + 2 * C * 4, 0),
-                          (int)__builtin_amdgcn_raw_buffer_load_b32(rs_src, coloff[i], row + 3 * C * 4, 0)};
-        }
-      }
+      for (int i = 0; i < B_PIECES; ++i) rb[sl][i] = load_b_piece<RIGHT, IN_PACKED>(rs_src, coloff[i], k64, C);
     }
   };
   auto store_lds = [&](int st) {
@@ -168,16 +294,9 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
       for (int i = 0; i < A_PIECES; ++i)
         *reinterpret_cast<v4i*>(lds_a + st * STAGE_A + sl * SLAB_A + (tid + i * NT) * 16) = ra[sl][i];
 #pragma unroll
-      for (int i = 0; i < B_PIECES; ++i) {
-        v4i w = rb[sl][i];
-        if (!IN_PACKED) {
-          w.x = pack_chunks(w.x);
-          w.y = pack_chunks(w.y);
-          w.z = pack_chunks(w.z);
-          w.w = pack_chunks(w.w);
-        }
-        *reinterpret_cast<v4i*>(lds_b + st * STAGE_B + sl * SLAB_B + (tid + i * NT) * 16) = w;
-      }
+      for (int i = 0; i < B_PIECES; ++i)
+        *reinterpret_cast<v4i*>(lds_b + st * STAGE_B + sl * SLAB_B + (tid + i * NT) * 16) =
+            IN_PACKED ? rb[sl][i] : pack4(rb[sl][i]);
     }
   };
   auto compute = [&](int st) {
@@ -209,97 +328,132 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
   if (nk > 1) load(1);
   __syncthreads();
   for (int ks = 0; ks < nk; ++ks) {
+    compute(ks & 1);
     if (ks + 1 < nk) store_lds((ks + 1) & 1);
     if (ks + 2 < nk) load(ks + 2);
-    compute(ks & 1);
     __syncthreads();
   }
+  gemm_epilogue<NT, BM, BN, MB, NB, RIGHT, OUT_PACKED, TW>(acc, t, g, wm, wn, reinterpret_cast<uint32_t*>(lds_a));
+}
 
-  // ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ----------
-  const uint32_t q = t.q, qinv = t.qinv;
-  const __amdgpu_buffer_rsrc_t rs_dst =
-      make_rsrc(t.dst + (size_t)poly0 * t.dst_stride, (uint64_t)npoly_left * t.dst_stride * 4);
-  const __amdgpu_buffer_rsrc_t rs_tw = make_rsrc(t.tw, TW ? (uint64_t)U * V * 8 : 0);
-  // Column side with plain output: the tile's outputs run down columns of the
-  // R x C result, so they are staged in LDS (free after the last K stage) as
-  // [column v][row u] and written back row by row, 16 bytes per lane.
-  constexpr bool STAGE_OUT = RIGHT && !OUT_PACKED;
-  constexpr int BU = BM / 4;              // outputs per tile column
-  constexpr int SROW = BU + 4;            // padded LDS row (words)
-  uint32_t* so = reinterpret_cast<uint32_t*>(lds_a);   // lds_a spans the whole workgroup allocation
-  const uint32_t row_words = RIGHT ? R : C;            // output row length (transposed when RIGHT)
+// Direct-table form (contractions of at most 512 inputs, so the ChunkMerge is
+// 32-bit): WA x WN waves, each a (32 MA) x (32 NBD) block of the output.  Only
+// the data operand goes through LDS (shared by the WA waves of a column
+// group); each wave reads its own rows of the pre-known table straight from
+// global memory (L2) into registers, in fragment order, one stage ahead.  The
+// staged form moves 1 KB through LDS per MFMA with 64 x 64 waves, more than the
+// LDS delivers at the MFMA rate; here half of that goes through the vector
+// memory path instead, and the LDS writes shrink to the data operand.
+template <int WA, int WN, int MA, int NBD, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__device__ __forceinline__ void gemm_tile_direct(const TileArgs& t, int8_t* lds) {
+  constexpr int NT = WA * WN * 64;
+  constexpr int BM = WA * MA * 32;
+  constexpr int BN = WN * NBD * 32;
+  constexpr int FB = 2 * BN / 32;                    // data fragments per 64-deep slab
+  constexpr int SLAB_B = FB * 1024, STAGE_B = KS * SLAB_B;
+  constexpr int B_PIECES = FB * 64 / NT;
+  static_assert(B_PIECES >= 1 && FB * 64 % NT == 0, "tile split");
 
-  auto epilogue = [&](auto wide_tag) {
-    constexpr bool WIDE = decltype(wide_tag)::value;
+  const StepShape g = step_shape<RIGHT>(t);
+  const int M = g.M, K = g.K, C = g.C;
+  const int m0 = t.m0;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the table resource is scalar
+  const int wm = wave / WN, wn = wave % WN;
+
+  v16i acc[MA][NBD];
 #pragma unroll
-    for (int a = 0; a < MB; ++a) {
-      const int u0 = (m0 + (wm * MB + a) * 32) / 4 + (lane >> 5);   // output of register group 0
+  for (int a = 0; a < MA; ++a)
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int nl = (wn * NB + b) * 32 + (lane & 31);
-        const int n = n0 + nl;
-        const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
-        // register group g holds output u0 + 2g: consecutive groups are 2 rows apart
-        const uint32_t out_off = (dpoly * (uint32_t)t.dst_stride + (uint32_t)u0 * row_words + v) * 4;
-        const uint32_t tw_off = ((uint32_t)u0 * V + v) * 8;
+    for (int b = 0; b < NBD; ++b) acc[a][b] = v16i{};
+
+  const __amdgpu_buffer_rsrc_t rs_src = data_rsrc(t.src, t.src_stride, t.npoly, g.poly0);
+  // this wave's rows of the table: fragment (32-row block, slab, half) at
+  // ((slab * M/32 + block) * 2 + half) * 1024
+  const int blk0 = m0 / 32 + wm * MA;
+  const __amdgpu_buffer_rsrc_t rs_tab =
+      make_rsrc(t.table + (size_t)blk0 * 2048, (uint64_t)M * K - (uint64_t)blk0 * 2048);
+  const uint32_t slab_bytes = (uint32_t)(M / 32) * 2048;
+  uint32_t coloff[B_PIECES];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const v16i& sv = acc[a][b];
-          const uint32_t s0 = (uint32_t)sv[4 * g], s1 = (uint32_t)sv[4 * g + 1];
-          const uint32_t s2 = (uint32_t)sv[4 * g + 2], s3 = (uint32_t)sv[4 * g + 3];
-          uint32_t zlo, zhi;
-          if (!WIDE) {
-            // z = x + w * 2^14 with x = s0 + s1 * 2^7 and w = s2 + s3 * 2^7 (both < 2^32)
-            const uint32_t x = s0 + (s1 << 7), w = s2 + (s3 << 7);
-            const uint32_t wl = w << 14;
-            zlo = x + wl;
-            zhi = (w >> 18) + (zlo < wl ? 1u : 0u);
-          } else {
-            const uint64_t z = (uint64_t)s0 + ((uint64_t)s1 << 7) + ((uint64_t)s2 << 14) + ((uint64_t)s3 << 21);
-            zlo = (uint32_t)z;
-            zhi = (uint32_t)(z >> 32);
-          }
-          // Montgomery REDC of z (the 2^32 factor was folded into the table): (0, 2q)
-          uint32_t r = zhi + q - __umulhi(zlo * qinv, q);
-          if (TW) {
-            // Shoup multiplication by the pre-known twiddle (w, floor(w 2^32 / q)): [0, 2q)
-            const v2u tw = __builtin_amdgcn_raw_buffer_load_b64(rs_tw, tw_off, g * 2 * V * 8, 0);
-            r = r * tw.x - __umulhi(r, tw.y) * q;
-          }
-          r = r >= q ? r - q : r;
-          if (OUT_PACKED) r = pack_chunks(r);
-          if (STAGE_OUT) {
-            so[nl * SROW + (u0 + 2 * g - m0 / 4)] = r;
-          } else {
-            // column side with packed output = the inverse intermediate, stored transposed;
-            // columns past the launch fall outside rs_dst and are dropped
-            __builtin_amdgcn_raw_buffer_store_b32(r, rs_dst, out_off, g * 2 * row_words * 4, 0);
-          }
-        }
+  for (int i = 0; i < B_PIECES; ++i) coloff[i] = b_piece_offset<RIGHT, IN_PACKED>(t, g, tid + i * NT);
+
+  v4i fa[2][KS][2][MA];                  // table fragments of two stages
+  v4i rb[KS][B_PIECES];
+  auto load_a = [&](int ks, v4i (&dst)[KS][2][MA]) {
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int a = 0; a < MA; ++a)
+          dst[sl][h][a] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(
+              rs_tab, (a * 2 + h) * 1024 + lane * 16, (ks * KS + sl) * slab_bytes, 0);
+  };
+  auto load_b = [&](int ks) {
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl)
+#pragma unroll
+      for (int i = 0; i < B_PIECES; ++i) rb[sl][i] = load_b_piece<RIGHT, IN_PACKED>(rs_src, coloff[i], ks * KS + sl, C);
+  };
+  auto store_b = [&](int st) {
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl)
+#pragma unroll
+      for (int i = 0; i < B_PIECES; ++i)
+        *reinterpret_cast<v4i*>(lds + st * STAGE_B + sl * SLAB_B + (tid + i * NT) * 16) =
+            IN_PACKED ? rb[sl][i] : pack4(rb[sl][i]);
+  };
+  auto compute = [&](int st, const v4i (&a_frag)[KS][2][MA]) {
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v4i fb[NBD];
+#pragma unroll
+        for (int b = 0; b < NBD; ++b)
+          fb[b] = *reinterpret_cast<const v4i*>(lds + st * STAGE_B + sl * SLAB_B + ((wn * NBD + b) * 2 + h) * 1024 +
+                                                lane * 16);
+#pragma unroll
+        for (int a = 0; a < MA; ++a)
+#pragma unroll
+          for (int b = 0; b < NBD; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a_frag[sl][h][a], fb[b], acc[a][b], 0, 0, 0);
       }
     }
   };
-  // Chunk partial sums are below K * 127 * 127 = 4U * 127^2; for U <= 512 the
-  // two half-merges x and w fit 32 bits, larger U merges in 64 bits.
-  if (U <= 512) epilogue(std::false_type{});
-  else epilogue(std::true_type{});
-
-  if (STAGE_OUT) {
+  const int nk = K / (BK * KS);          // even: K is a multiple of 2 * BK * KS
+  // one stage: MFMAs of stage ks, then stage ks+1 of the data into the idle
+  // LDS buffer, then the loads of stage ks+2 (table fragments into the
+  // registers just consumed).  Every step issues the same loads (the last two
+  // re-read the final stage, unused) so the number of loads in flight is the
+  // same on every path and the waits stay one stage behind.
+  auto step = [&](int ks, v4i (&cur)[KS][2][MA]) {
+    compute(ks & 1, cur);
+    if (ks + 1 < nk) store_b((ks + 1) & 1);
+    const int kn = ks + 2 < nk ? ks + 2 : nk - 1;
+    load_b(kn);
+    load_a(kn, cur);
+    // keep the loads here: left to itself the compiler sinks them to their
+    // first use, a stage later, which leaves their latency exposed
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    constexpr int VEC_PER_ROW = BU / 4;
-#pragma unroll
-    for (int i = 0; i < BN * VEC_PER_ROW / NT; ++i) {
-      const int idx = tid + i * NT;
-      const int nl = idx / VEC_PER_ROW, uq = idx % VEC_PER_ROW;
-      const int n = n0 + nl;
-      const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
-      const v4u w = *reinterpret_cast<const v4u*>(so + nl * SROW + uq * 4);
-      const uint32_t off = (dpoly * (uint32_t)t.dst_stride + v * C + m0 / 4 + uq * 4) * 4;
-      __builtin_amdgcn_raw_buffer_store_b128(w, rs_dst, off, 0, 0);
-    }
-    __syncthreads();   // LDS is reused by the next tile of a work list
+  };
+
+  load_a(0, fa[0]);
+  load_b(0);
+  store_b(0);
+  load_b(1);            // nk >= 2
+  load_a(1, fa[1]);
+  __syncthreads();
+  for (int ks = 0; ks < nk; ks += 2) {
+    step(ks, fa[0]);
+    step(ks + 1, fa[1]);
   }
-  (void)M;
+  gemm_epilogue<NT, BM, BN, MA, NBD, RIGHT, OUT_PACKED, TW, true>(acc, t, g, wm, wn,
+                                                                  reinterpret_cast<uint32_t*>(lds));
 }
 
 // LDS bytes of one workgroup: two operand stages, or the output staging tile if larger.
@@ -311,17 +465,12 @@ constexpr int gemm_lds_bytes() {
   return ops > out ? ops : out;
 }
 
-template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
-__global__ void __launch_bounds__(WM * WN * 64, OCC)
-bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
-  constexpr int BM = WM * MB * 32;
-  constexpr int BN = WN * NB * 32;
-  // two LDS stages of operand fragments (A stages then B stages), reused for output staging
-  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
-  int8_t* lds_a = lds;
-  int8_t* lds_b = lds + 2 * BM * 64 * KS;
-  // XCD-aware tile order: consecutive logical tiles land on the same XCD so a
-  // job's table and columns stay in one L2.
+// Tile (job, tm, tn) of block b of a uniform launch.  XCD-aware order:
+// consecutive logical tiles land on the same XCD so a job's table and columns
+// stay in one L2; within a job m runs fastest so tiles sharing columns run
+// together.
+template <int BM, int BN>
+__device__ __forceinline__ TileArgs uniform_tile(const GemmLaunch& g, int tiles_m, int tiles_n) {
   const int total = g.njobs * tiles_m * tiles_n;
   const int bid = blockIdx.x;
   int logical = bid;
@@ -329,12 +478,42 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   const int per_job = tiles_m * tiles_n;
   const int job_id = logical / per_job;
   const int rem = logical - job_id * per_job;
-  const int tn = rem / tiles_m;          // m fastest: tiles sharing columns run together
+  const int tn = rem / tiles_m;
   const int tm = rem - tn * tiles_m;
   const GemmJob job = g.jobs[job_id];
-  TileArgs t{job.table, job.tw, g.src + job.src_off, g.dst + job.dst_off, g.src_stride, g.dst_stride,
-             job.q, job.qinv, g.npoly, g.log_r, g.log_c, tm * BM, tn * BN};
-  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
+  return TileArgs{job.table, job.tw, g.src + job.src_off, g.dst + job.dst_off, g.src_stride, g.dst_stride,
+                  job.q, job.qinv, g.npoly, g.log_r, g.log_c, tm * BM, tn * BN};
+}
+
+template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__global__ void __launch_bounds__(WM * WN * 64, OCC)
+bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
+  constexpr int BM = WM * MB * 32;
+  constexpr int BN = WN * NB * 32;
+  // two LDS stages of operand fragments (A stages then B stages), reused for output staging
+  __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
+  const TileArgs t = uniform_tile<BM, BN>(g, tiles_m, tiles_n);
+  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds, lds + 2 * BM * 64 * KS);
+}
+
+// LDS bytes of the direct-table form: two stages of data fragments, or the
+// output staging tile if larger.
+template <int WA, int WN, int MA, int NBD, int KS, bool RIGHT, bool OUT_PACKED>
+constexpr int direct_lds_bytes() {
+  constexpr int BM = WA * MA * 32, BN = WN * NBD * 32;
+  constexpr int ops = 2 * KS * BN * 64;
+  constexpr int out = (RIGHT && !OUT_PACKED) ? BN * (BM / 4 + 4) * 4 : 0;
+  return ops > out ? ops : out;
+}
+
+template <int WA, int WN, int MA, int NBD, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+__global__ void __launch_bounds__(WA * WN * 64, OCC)
+bat_gemm_direct_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
+  constexpr int BM = WA * MA * 32;
+  constexpr int BN = WN * NBD * 32;
+  __shared__ __attribute__((aligned(1024))) int8_t lds[direct_lds_bytes<WA, WN, MA, NBD, KS, RIGHT, OUT_PACKED>()];
+  const TileArgs t = uniform_tile<BM, BN>(g, tiles_m, tiles_n);
+  gemm_tile_direct<WA, WN, MA, NBD, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds);
 }
 
 // Work-list form: tiles of many tasks (mixed N, R x C, primes, buffers) in one
@@ -346,8 +525,6 @@ bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles
   constexpr int BM = WM * MB * 32;
   constexpr int BN = WN * NB * 32;
   __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
-  int8_t* lds_a = lds;
-  int8_t* lds_b = lds + 2 * BM * 64 * KS;
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
   const int lo = (int)((long)ntiles * xcd / 8), hi = (int)((long)ntiles * (xcd + 1) / 8);
   for (int i = lo + local; i < hi; i += per_xcd) {
@@ -355,42 +532,68 @@ bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles
     const GemmTask k = tasks[r.task];
     TileArgs t{k.table, k.tw, k.src, k.dst, k.src_stride, k.dst_stride, k.q, k.qinv, k.npoly,
                k.log_r, k.log_c, (int)r.tm * BM, (int)r.tn * BN};
-    gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds_a, lds_b);
+    gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds, lds + 2 * BM * 64 * KS);
   }
 }
 
-template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool INP, bool OUTP, bool TW>
-hipError_t launch_cfg(const GemmLaunch& g, hipStream_t s) {
-  constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
+// Grid of a uniform launch with BM x BN tiles; false if the shape does not tile.
+template <int BM, int BN, bool RIGHT>
+bool uniform_grid(const GemmLaunch& g, int kdiv, int& tiles_m, int& tiles_n, int& grid) {
   const int U = RIGHT ? (1 << g.log_c) : (1 << g.log_r);
   const int V = RIGHT ? (1 << g.log_r) : (1 << g.log_c);
-  const int M = 4 * U;
-  if (M % BM) return hipErrorInvalidValue;
+  const int M = 4 * U, K = 4 * U;
+  if (M % BM || K % kdiv) return false;
   // per-lane byte offsets are 32-bit and span at most BN / V + 1 polynomials of a tile
   const uint64_t span = (uint64_t)(BN / V + 2) * 4;
-  if (span * g.src_stride >= (1ull << 31) || span * g.dst_stride >= (1ull << 31)) return hipErrorInvalidValue;
-  const int tiles_m = M / BM;
+  if (span * g.src_stride >= (1ull << 31) || span * g.dst_stride >= (1ull << 31)) return false;
+  tiles_m = M / BM;
   const int ncols = g.npoly * V;
-  const int tiles_n = (ncols + BN - 1) / BN;
-  const int grid = g.njobs * tiles_m * tiles_n;
-  hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW>), dim3(grid),
-                     dim3(WM * WN * 64), 0, s, g, tiles_m, tiles_n);
-  return hipGetLastError();
+  tiles_n = (ncols + BN - 1) / BN;
+  grid = g.njobs * tiles_m * tiles_n;
+  return true;
 }
 
+// LDS-staged tile: WM x WN waves of MB x NB blocks.
 template <int WM, int WN, int MB, int NB, int OCC, int KS = 1>
+struct StagedCfg {
+  template <bool RIGHT, bool INP, bool OUTP, bool TW>
+  static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
+    constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
+    int tm, tn, grid;
+    if (!uniform_grid<BM, BN, RIGHT>(g, BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW>), dim3(grid),
+                       dim3(WM * WN * 64), 0, s, g, tm, tn);
+    return hipGetLastError();
+  }
+};
+
+// Direct-table tile: WA x WN waves of MA x NBD blocks, stages of KS slabs, unrolled by two.
+template <int WA, int WN, int MA, int NBD, int OCC, int KS>
+struct DirectCfg {
+  template <bool RIGHT, bool INP, bool OUTP, bool TW>
+  static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
+    constexpr int BM = WA * MA * 32, BN = WN * NBD * 32;
+    int tm, tn, grid;
+    if (!uniform_grid<BM, BN, RIGHT>(g, 2 * BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((bat_gemm_direct_kernel<WA, WN, MA, NBD, OCC, KS, RIGHT, INP, OUTP, TW>), dim3(grid),
+                       dim3(WA * WN * 64), 0, s, g, tm, tn);
+    return hipGetLastError();
+  }
+};
+
+template <class Cfg>
 hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
   // forward: LEFT(plain in, packed out, twiddle) then RIGHT(packed in, plain out)
   // inverse: RIGHT(plain in, packed out, twiddle) then LEFT(packed in, plain out)
   const bool right = g.kind == kRight;
   if (!right && !g.in_packed && g.out_packed && g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, KS, false, false, true, true>(g, s);
+    return Cfg::template launch<false, false, true, true>(g, s);
   if (right && g.in_packed && !g.out_packed && !g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, KS, true, true, false, false>(g, s);
+    return Cfg::template launch<true, true, false, false>(g, s);
   if (right && !g.in_packed && g.out_packed && g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, KS, true, false, true, true>(g, s);
+    return Cfg::template launch<true, false, true, true>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle)
-    return launch_cfg<WM, WN, MB, NB, OCC, KS, false, true, false, false>(g, s);
+    return Cfg::template launch<false, true, false, false>(g, s);
   return hipErrorInvalidValue;
 }
 
@@ -430,6 +633,8 @@ int resolve_gemm_tile(const GemmLaunch& g) {
     t = kTileAuto;
   if (t == kTile256x128 && M < 256) t = kTileAuto;
   if (t == kTile128x64 && M < 128) t = kTileAuto;
+  // the direct tiles merge chunk sums in 32 bits only: contractions up to 512 inputs
+  if ((t == kTileDirect256x128 || t == kTileDirect256x128n) && (M < 256 || U > 512)) t = kTileAuto;
   if (t != kTileAuto) return t;
   if (M >= 256) {
     // 8 waves of 64x64 (4 waves per SIMD) when the grid still covers every CU
@@ -445,13 +650,15 @@ hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s) {
   const int U = (g.kind == kRight) ? (1 << g.log_c) : (1 << g.log_r);
   if (4 * U < 64) return hipErrorInvalidValue;
   switch (resolve_gemm_tile(g)) {
-    case kTile256x256: return dispatch_flags<2, 4, 4, 2, 2>(g, s);     // 8 waves of 128x64
-    case kTile256x128: return dispatch_flags<2, 2, 4, 2, 2>(g, s);     // 4 waves of 128x64
-    case kTile128x64: return dispatch_flags<2, 2, 2, 1, 4>(g, s);      // 4 waves of 64x32
-    case kTile256x128w8: return dispatch_flags<4, 2, 2, 2, 4>(g, s);   // 8 waves of 64x64
-    case kTile256x256w16: return dispatch_flags<4, 4, 2, 2, 4>(g, s);  // 16 waves of 64x64
-    case kTile256x256w16k2: return dispatch_flags<4, 4, 2, 2, 4, 2>(g, s);  // same, 128-deep K stages
-    default: return dispatch_flags<2, 2, 1, 1, 4>(g, s);               // 64 x 64: 4 waves of 32x32
+    case kTile256x256: return dispatch_flags<StagedCfg<2, 4, 4, 2, 2>>(g, s);     // 8 waves of 128x64
+    case kTile256x128: return dispatch_flags<StagedCfg<2, 2, 4, 2, 2>>(g, s);     // 4 waves of 128x64
+    case kTile128x64: return dispatch_flags<StagedCfg<2, 2, 2, 1, 4>>(g, s);      // 4 waves of 64x32
+    case kTile256x128w8: return dispatch_flags<StagedCfg<4, 2, 2, 2, 4>>(g, s);   // 8 waves of 64x64
+    case kTile256x256w16: return dispatch_flags<StagedCfg<4, 4, 2, 2, 4>>(g, s);  // 16 waves of 64x64
+    case kTile256x256w16k2: return dispatch_flags<StagedCfg<4, 4, 2, 2, 4, 2>>(g, s);  // same, 128-deep K stages
+    case kTileDirect256x128: return dispatch_flags<DirectCfg<4, 2, 2, 2, 4, 1>>(g, s);   // 8 waves of 64x64, direct table
+    case kTileDirect256x128n: return dispatch_flags<DirectCfg<4, 1, 2, 4, 2, 1>>(g, s);  // 4 waves of 64x128, direct table
+    default: return dispatch_flags<StagedCfg<2, 2, 1, 1, 4>>(g, s);               // 64 x 64: 4 waves of 32x32
   }
 }
 

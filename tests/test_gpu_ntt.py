@@ -122,21 +122,33 @@ def test_argument_errors():
         B.ntt_forward(torch.zeros((1, 1, 1000), dtype=torch.int32, device="cuda"), [268042241])
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_every_tile_shape_is_bit_exact(tile):
     from paper_2501_07047_amd import binding as B
     B.set_gemm_tile(tile)
+    # (log_n, log_r or None for the default split, L, batch).  13 / 7 gives V = 64
+    # columns per polynomial on the row side, so 3 polynomials leave a ragged
+    # last column tile; 16 / 10 and 16 / 6 put a 1024-input contraction (the
+    # 64-bit ChunkMerge) on either side.
+    cases = ((16, None, 2, 3), (12, None, 3, 2), (10, None, 2, 1), (14, None, 3, 1),
+             (13, 7, 3, 1), (16, 10, 1, 1), (16, 6, 1, 1))
     try:
-        for log_n, L, batch in ((16, 2, 3), (12, 3, 2), (10, 2, 1)):
+        for log_n, log_r, L, batch in cases:
+            if log_r is not None:
+                B.set_ntt_split(log_n, log_r)
             primes, x = synthetic.ntt_batch(tile * 10 + log_n, log_n, L, batch)
             ref = _oracle_ntt(x, primes)
             d = to_dev(x)
             B.ntt_forward(d, primes)
-            assert np.array_equal(to_host(d), ref)
+            assert np.array_equal(to_host(d), ref), (log_n, log_r, L, batch)
             B.ntt_inverse(d, primes)
-            assert np.array_equal(to_host(d), x)
+            assert np.array_equal(to_host(d), x), (log_n, log_r, L, batch)
+            if log_r is not None:
+                B.set_ntt_split(log_n, log_n // 2)
     finally:
         B.set_gemm_tile(0)
+        for log_n in (13, 16):
+            B.set_ntt_split(log_n, log_n // 2)
 
 
 def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
@@ -145,7 +157,7 @@ def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
     try:
         for log_n in (12, 13):
             res = B.autotune(log_n, L=2, batch=2, cache_path=cache)
-            assert 4 <= res["log_r"] <= log_n - 4 and 1 <= res["tile"] <= 4 and res["us"] > 0
+            assert 4 <= res["log_r"] <= log_n - 4 and 1 <= res["tile"] <= 9 and res["us"] > 0
             again = B.autotune(log_n, L=2, batch=2, cache_path=cache)
             # served from the cache file (microseconds are stored to 3 decimals)
             assert (again["log_r"], again["tile"]) == (res["log_r"], res["tile"])
