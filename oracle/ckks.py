@@ -102,6 +102,41 @@ def moddown(acc, qs, ps):
     return out
 
 
+def he_add(a, b, qs):
+    """HE-Add: limb-wise sum mod q_i of two polynomials or ciphertexts [..][L][N].
+
+    The RNS isomorphism makes addition limb-wise (Sec. Background); the paper
+    lists HE-Add among its four backbone operators (Sec. Evaluation, Tab.
+    perf_cmp).  Valid in NTT and coefficient form alike.
+    """
+    a = np.asarray(a, dtype=U64)
+    b = np.asarray(b, dtype=U64)
+    out = np.empty_like(a)
+    for i, q in enumerate(qs):
+        out[..., i, :] = (a[..., i, :] + b[..., i, :]) % U64(q)
+    return out
+
+
+def rescale(c, qs, drop=1):
+    """Rescale of one polynomial [L][N] (NTT form over qs) by the product P of its
+    last `drop` primes -> [L - drop][N] over the first L - drop primes.
+
+    The paper names Rescale as a backbone operator (Sec. Evaluation, Tab.
+    perf_cmp) and drops two primes per level when a modulus needs more than
+    32 bits (double rescaling, Sec. Evaluation "Security Parameter
+    Selection"), but does not define it.  Reading G17: RNS rescaling is ModDown
+    with the dropped primes in the role of P -- y = INTT_P(c_P);
+    z_i = NTT_{q_i}(BConv_{P -> q_i}(y)); out_i = (c_i - z_i) P^-1 mod q_i -- with
+    the fast (approximate) conversion and no rounding correction.  For drop = 1
+    this is exactly floor(C / q_{L-1}) of each coefficient's CRT value C; for
+    drop = 2 it is floor(C / P) or one less.
+    """
+    L = len(qs)
+    if not 1 <= drop < L:
+        raise ValueError("need 1 <= drop < L")
+    return moddown(c, list(qs[:L - drop]), list(qs[L - drop:]))
+
+
 def keyswitch(d, key, qs, ps, dnum):
     ext = modup(d, qs, ps, dnum)
     acc = inner_product(ext, key, list(qs) + list(ps))
