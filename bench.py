@@ -89,9 +89,12 @@ def he_mult_bench(B, steps, warmup, batch):
     db = torch.from_numpy(b.view(np.int32)).cuda()
     dk = torch.from_numpy(key.view(np.int32)).cuda()
     out = torch.empty_like(da)
+    out_rs = torch.empty((batch, 2, 23, 1 << 16), dtype=torch.int32, device="cuda")
     res = {}
     for name, fn in (("he_mult", lambda: B.he_mult(da, db, dk, out, qs, ps, 3)),
-                     ("rotate", lambda: B.rotate(da, 1, dk, out, qs, ps, 3))):
+                     ("rotate", lambda: B.rotate(da, 1, dk, out, qs, ps, 3)),
+                     ("rescale", lambda: B.rescale(da, out_rs, qs, 1)),
+                     ("he_add", lambda: B.he_add(da, db, out, qs))):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -320,6 +323,12 @@ def main():
     line["he_mult"] = {"config": "N=2^16, L=24, dnum=3 (alpha=8), K=8 special primes, tensor + relinearisation",
                        "batch1": he1["he_mult"], "batch8": he8["he_mult"]}
     line["rotate"] = {"config": "same parameters, 1 slot", "batch1": he1["rotate"], "batch8": he8["rotate"]}
+    line["rescale"] = {"config": "N=2^16, L=24 -> 23 (divide by the last prime), per ciphertext",
+                       "batch1": he1["rescale"], "batch8": he8["rescale"]}
+    add_bytes = 3 * 2 * 24 * (1 << 16) * 4        # a, b read, out written: one ciphertext pair
+    line["he_add"] = {"config": "N=2^16, L=24, per ciphertext pair", "batch1": he1["he_add"],
+                      "batch8": he8["he_add"], "bytes_per_op": add_bytes,
+                      "hbm_gbs_batch8": round(add_bytes * he8["he_add"]["per_s"] / 1e9, 1)}
     line["uneven_batch"] = uneven_batch_bench(B, max(4, args.steps // 2))
     B.set_ntt_split(LOG_N, LOG_R)
     line["serving"] = serving_bench(200)

@@ -194,6 +194,41 @@ cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* params, int32_
                           void* stream);
 
 /*
+ * HE-Add (Tab. perf_cmp "HE-Add"; limb-wise by the RNS isomorphism, Sec.
+ * Background): out = a + b mod q_i limb by limb.
+ *   a, b, out: device [npoly][L][N], 16-byte aligned; any of them may alias
+ *              (a ciphertext is two consecutive polynomials; NTT or coefficient
+ *              form alike)
+ *   primes   : host array of L primes (as cross_ntt_forward); 4 <= log_n <= 16
+ * Errors: CROSS_EINVAL for null / misaligned pointers or bad shape, prime
+ * checks as cross_ntt_forward.  Asynchronous on `stream`.
+ */
+cross_status cross_he_add(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                          uint32_t npoly, const uint32_t* a, const uint32_t* b, uint32_t* out,
+                          void* stream);
+
+/*
+ * Rescale (Tab. perf_cmp "Rescale"; dropping two primes per level is the
+ * paper's double rescaling, Sec. Evaluation "Security Parameter Selection"):
+ * division by P = product of the last `drop` primes, read as ModDown with
+ * those primes in the role of the special primes:
+ *   out_i = (in_i - NTT_{q_i}(BConv_{P -> q_i}(INTT_P(in_P)))) * P^-1 mod q_i,  i < L - drop.
+ * For drop = 1 each coefficient becomes exactly floor(C / q_{L-1}) of its CRT
+ * value C; for more primes the fast conversion may leave it one lower.
+ *   in     : device [npoly][L][N] NTT form over primes[0..L-1], not modified
+ *   out    : device [npoly][L-drop][N] NTT form over primes[0..L-drop-1];
+ *            must not overlap in (a ciphertext is two consecutive polynomials)
+ *   primes : host array of L distinct primes; 5 <= log_n <= 16; 1 <= drop < L <= 64,
+ *            drop <= 32
+ * Uses context workspace of npoly * N * (L + max(drop, L - drop)) words.
+ * Errors: CROSS_EINVAL (null / misaligned / overlapping buffers, bad shape),
+ * prime checks as cross_he_mult.  Asynchronous on `stream`.
+ */
+cross_status cross_rescale(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                           uint32_t drop, uint32_t npoly, const uint32_t* in, uint32_t* out,
+                           void* stream);
+
+/*
  * Batch runtime (many jobs of uneven N and limb count in one pass).
  * Jobs are lowered onto a fixed sequence of 15 work-list launches (one per
  * step of the hot path, each covering that step for every job; the BAT GEMM

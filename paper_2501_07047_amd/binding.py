@@ -50,6 +50,8 @@ SIGNATURES = {
     "cross_keyswitch_moddown": [c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_he_mult": [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_rotate": [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_u32, c_vp],
+    "cross_he_add": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp],
+    "cross_rescale": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_u32, c_vp, c_vp, c_vp],
     "cross_batch_create": [c_vp, c_vp, c_u32, ctypes.c_int, ctypes.POINTER(c_vp)],
     "cross_batch_workspace_bytes": [c_vp, c_vp, c_u32, ctypes.POINTER(ctypes.c_uint64)],
     "cross_batch_create_in": [c_vp, c_vp, c_u32, ctypes.c_int, c_vp, ctypes.c_uint64, c_vp, ctypes.POINTER(c_vp)],
@@ -310,6 +312,33 @@ def rotate(ct, steps, key, out, qs, ps, dnum):
     ctx = context(ct.device.index)
     _check(lib().cross_rotate(ctx, ctypes.byref(prm), int(steps), _dev_ptr(ct, "ct"), _dev_ptr(key, "key"),
                               _dev_ptr(out, "out"), batch, _stream(ct)), ctx)
+    return out
+
+
+def he_add(a, b, out, primes):
+    """HE-Add (limb-wise sum mod q_i): a, b, out [..][L][N] (polynomials or ciphertexts); may alias."""
+    L, n = a.shape[-2:]
+    _shape(b, a.shape, "b")
+    _shape(out, a.shape, "out")
+    if len(primes) != L:
+        raise ValueError("len(primes) != L")
+    npoly = a.numel() // (L * n)
+    ctx = context(a.device.index)
+    _check(lib().cross_he_add(ctx, _log2(n), _u32_array(primes), L, npoly, _dev_ptr(a, "a"), _dev_ptr(b, "b"),
+                              _dev_ptr(out, "out"), _stream(a)), ctx)
+    return out
+
+
+def rescale(x, out, primes, drop=1):
+    """Rescale by the product of the last `drop` primes: x [..][L][N] -> out [..][L-drop][N], NTT form."""
+    L, n = x.shape[-2:]
+    _shape(out, tuple(x.shape[:-2]) + (L - drop, n), "out")
+    if len(primes) != L:
+        raise ValueError("len(primes) != L")
+    npoly = x.numel() // (L * n)
+    ctx = context(x.device.index)
+    _check(lib().cross_rescale(ctx, _log2(n), _u32_array(primes), L, int(drop), npoly, _dev_ptr(x, "x"),
+                               _dev_ptr(out, "out"), _stream(x)), ctx)
     return out
 
 

@@ -319,6 +319,53 @@ cross_status moddown_core(cross_ctx ctx, const CkksPlan* c, uint32_t* acc, int n
   return CROSS_OK;
 }
 
+// Rescale by the last `drop` primes: the CKKS plan with those primes as P
+// (NTT plans, ModDown tail constants) plus a conversion and copy offsets for a
+// compact [npoly][drop][N] scratch holding the dropped limbs.
+struct RescalePlan {
+  CkksPlan* c = nullptr;
+  BconvStatic bconv;                      // dropped limbs (scratch layout) -> kept limbs
+  const uint64_t* copy_src = nullptr;     // dropped limbs within an input polynomial
+  const uint64_t* copy_dst = nullptr;     // and within the scratch
+};
+
+cross_status get_rescale_plan(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                              uint32_t drop, RescalePlan** out) {
+  const uint32_t Lk = L - drop;
+  // the digit split is unused here; alpha <= 32 keeps the plan within its limits
+  cross_ckks_params prm{log_n, Lk, drop, (Lk + 31) / 32, primes};
+  CkksPlan* c = nullptr;
+  cross_status st = get_ckks_plan(ctx, &prm, &c);
+  if (st != CROSS_OK) return st;
+  const std::string key = "rescale/" + std::to_string(reinterpret_cast<uintptr_t>(c));
+  auto it = ctx->ext_plans.find(key);
+  if (it != ctx->ext_plans.end()) {
+    *out = static_cast<RescalePlan*>(it->second.get());
+    return CROSS_OK;
+  }
+  std::shared_ptr<RescalePlan> holder = std::make_shared<RescalePlan>();
+  RescalePlan* r = holder.get();
+  r->c = c;
+  const uint64_t N = 1ull << log_n;
+  std::vector<uint32_t> sp(primes + Lk, primes + L), dp(primes, primes + Lk);
+  std::vector<uint64_t> so(drop), cs(drop), dof(Lk);
+  for (uint32_t k = 0; k < drop; ++k) {
+    so[k] = (uint64_t)k * N;
+    cs[k] = (uint64_t)(Lk + k) * N;
+  }
+  for (uint32_t i = 0; i < Lk; ++i) dof[i] = (uint64_t)i * N;
+  if ((st = make_bconv(ctx, sp, so, dp, dof, &r->bconv)) != CROSS_OK) return st;
+  void *a = nullptr, *b = nullptr;
+  st = cached_device_copy(ctx, cs.data(), cs.size() * 8, &a);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, so.data(), so.size() * 8, &b);
+  if (st != CROSS_OK) return st;
+  r->copy_src = (const uint64_t*)a;
+  r->copy_dst = (const uint64_t*)b;
+  ctx->ext_plans[key] = holder;
+  *out = r;
+  return CROSS_OK;
+}
+
 struct KsWork {
   uint32_t *d, *ext, *tmp, *acc, *z;
 };
@@ -505,6 +552,76 @@ cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* prm, const ui
     HIPCHK(launch_tensor(ct_a, ct_b, out, w.d, c->mods, c->L, c->log_n, (int)batch, s), "tensor");
   }
   return keyswitch_into(ctx, c, relin_key, (int)batch, w, out, out, false, s);
+}
+
+cross_status cross_he_add(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                          uint32_t npoly, const uint32_t* a, const uint32_t* b, uint32_t* out,
+                          void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  if (!primes || !a || !b || !out || !aligned(a) || !aligned(b) || !aligned(out))
+    return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
+  if (log_n < CROSS_MIN_LOG_N || log_n > CROSS_MAX_LOG_N || L < 1 || L > CROSS_MAX_LIMBS || npoly < 1)
+    return fail(ctx, CROSS_EINVAL, "bad shape");
+  std::vector<LimbMod> mods(L);
+  for (uint32_t i = 0; i < L; ++i) {
+    if ((st = check_prime(ctx, primes[i], log_n)) != CROSS_OK) return st;
+    mods[i] = limb_mod(primes[i]);
+  }
+  void* dm = nullptr;
+  if ((st = cached_device_copy(ctx, mods.data(), mods.size() * sizeof(LimbMod), &dm)) != CROSS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps(ctx, "he_add", s);
+  HIPCHK(launch_pointwise_add(a, b, out, (const LimbMod*)dm, (int)L, (int)log_n, (int)npoly, s), "he_add");
+  return CROSS_OK;
+}
+
+cross_status cross_rescale(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                           uint32_t drop, uint32_t npoly, const uint32_t* in, uint32_t* out,
+                           void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  if (!primes || !in || !out || !aligned(in) || !aligned(out))
+    return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
+  if (log_n < 5 || log_n > CROSS_MAX_LOG_N || L < 2 || L > CROSS_MAX_LIMBS || drop < 1 || drop >= L ||
+      drop > 32 || npoly < 1)
+    return fail(ctx, CROSS_EINVAL, "bad shape (5 <= log_n <= 16, 1 <= drop < L <= 64, drop <= 32)");
+  const uint64_t N = 1ull << log_n, Lk = L - drop;
+  const uintptr_t i0 = reinterpret_cast<uintptr_t>(in), o0 = reinterpret_cast<uintptr_t>(out);
+  if (i0 < o0 + (uint64_t)npoly * Lk * N * 4 && o0 < i0 + (uint64_t)npoly * L * N * 4)
+    return fail(ctx, CROSS_EINVAL, "out must not overlap in");
+  RescalePlan* r = nullptr;
+  if ((st = get_rescale_plan(ctx, log_n, primes, L, drop, &r)) != CROSS_OK) return st;
+  const CkksPlan* c = r->c;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t ny = (uint64_t)npoly * drop * N, nz = (uint64_t)npoly * Lk * N;
+  void* base = nullptr;
+  if ((st = workspace(ctx, s, (ny + nz + std::max(ny, nz)) * 4, &base)) != CROSS_OK) return st;
+  uint32_t* y = (uint32_t*)base;
+  uint32_t* z = y + ny;
+  uint32_t* tmp = z + nz;
+  {
+    ProfScope ps(ctx, "limb_copy", s);
+    HIPCHK(launch_limb_copy(in, (uint64_t)L * N, r->copy_src, y, (uint64_t)drop * N, r->copy_dst, (int)drop,
+                            (int)log_n, (int)npoly, s), "rescale copy");
+  }
+  std::vector<int> pl(drop), ql(Lk);
+  std::vector<uint64_t> po(drop), qo(Lk);
+  for (uint32_t k = 0; k < drop; ++k) {
+    pl[k] = (int)(Lk + k);
+    po[k] = (uint64_t)k * N;
+  }
+  for (uint32_t i = 0; i < Lk; ++i) {
+    ql[i] = (int)i;
+    qo[i] = (uint64_t)i * N;
+  }
+  if ((st = ntt_list(ctx, c, pl, po, y, (uint64_t)drop * N, (int)npoly, true, tmp, s)) != CROSS_OK) return st;
+  HIPCHK(run_bconv(ctx, r->bconv, y, (uint64_t)drop * N, z, Lk * N, (int)npoly, (int)log_n, s), "rescale bconv");
+  if ((st = ntt_list(ctx, c, ql, qo, z, Lk * N, (int)npoly, false, tmp, s)) != CROSS_OK) return st;
+  ProfScope ps(ctx, "rescale_tail", s);
+  HIPCHK(launch_moddown_tail(in, (uint64_t)L * N, z, nullptr, out, Lk * N, c->tail, (int)Lk, (int)log_n,
+                             (int)npoly, false, s), "rescale tail");
+  return CROSS_OK;
 }
 
 cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* prm, int32_t steps, const uint32_t* ct,

@@ -149,6 +149,19 @@ pointwise_kernel(const v4u* a, const v4u* b, v4u* out, const LimbMod* mods, int 
   out[i] = r;
 }
 
+// HE-Add (VecModAdd): out = a + b mod q_limb.
+__global__ void __launch_bounds__(256)
+pointwise_add_kernel(const v4u* a, const v4u* b, v4u* out, const LimbMod* mods, int L, int log_n4,
+                     uint64_t total4) {
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total4) return;
+  const uint32_t q = mods[(int)((i >> log_n4) % L)].q;
+  v4u x = a[i], y = b[i], r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r[k] = addmod(x[k], y[k], q);
+  out[i] = r;
+}
+
 __global__ void __launch_bounds__(256)
 limb_copy_kernel(const v4u* src, uint64_t src_stride4, const uint64_t* src_off, v4u* dst,
                  uint64_t dst_stride4, const uint64_t* dst_off, int nl, int log_n4, uint64_t total4) {
@@ -374,6 +387,14 @@ hipError_t launch_pointwise_mul(const uint32_t* a, const uint32_t* b, uint32_t* 
                                 const LimbMod* mods, int L, int log_n, int B, hipStream_t s) {
   const uint64_t total4 = ((uint64_t)B * L) << (log_n - 2);
   hipLaunchKernelGGL(pointwise_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
+                     (const v4u*)b, (v4u*)out, mods, L, log_n - 2, total4);
+  return hipGetLastError();
+}
+
+hipError_t launch_pointwise_add(const uint32_t* a, const uint32_t* b, uint32_t* out,
+                                const LimbMod* mods, int L, int log_n, int npoly, hipStream_t s) {
+  const uint64_t total4 = ((uint64_t)npoly * L) << (log_n - 2);
+  hipLaunchKernelGGL(pointwise_add_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
                      (const v4u*)b, (v4u*)out, mods, L, log_n - 2, total4);
   return hipGetLastError();
 }

@@ -120,6 +120,10 @@ hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t*
 hipError_t launch_pointwise_mul(const uint32_t* a, const uint32_t* b, uint32_t* out,
                                 const LimbMod* mods, int L, int log_n, int B, hipStream_t s);
 
+// HE-Add (VecModAdd): out = a + b mod q_limb, all [npoly][L][N]; out may alias a or b.
+hipError_t launch_pointwise_add(const uint32_t* a, const uint32_t* b, uint32_t* out,
+                                const LimbMod* mods, int L, int log_n, int npoly, hipStream_t s);
+
 // Strided limb copy / zero: for each poly p < npoly and limb l < nl:
 // dst[p*dst_stride + dst_off[l] ..+N] = src ? src[p*src_stride + src_off[l] ..] : 0.
 hipError_t launch_limb_copy(const uint32_t* src, uint64_t src_stride, const uint64_t* src_off,
