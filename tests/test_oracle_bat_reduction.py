@@ -94,3 +94,46 @@ def test_barrett_matches_modulo():
         pairs += [(int(a), int(b)) for a, b in g.integers(0, q, (3000, 2))]
         for a, b in pairs:
             assert RD.barrett_mulmod(a, b, q) == a * b % q
+
+
+def test_shoup_edges_and_random():
+    from oracle.reduction import shoup_mulmod
+    g = np.random.Generator(np.random.PCG64(21))
+    for q in prime_chain(3) + [97, 257]:
+        for a in (0, 1, q - 1, q, 2 * q - 1, (1 << 32) - 1):
+            for w in (0, 1, 2, q - 1):
+                assert shoup_mulmod(a, w, q) == a * w % q
+        for a, w in zip(g.integers(0, 1 << 32, 500), g.integers(0, q, 500)):
+            assert shoup_mulmod(int(a), int(w), q) == int(a) * int(w) % q
+
+
+@pytest.mark.parametrize("bp,k", [(7, 4), (8, 4), (2, 3)])
+def test_bat_lazy_reduce_is_congruent_and_bounded(bp, k):
+    # the paper's byte form (bp = 8, a 64-bit partial sum), the 7-bit MFMA form, and a tiny case
+    from oracle.reduction import bat_lazy_reduce
+    g = np.random.Generator(np.random.PCG64(22))
+    bound = (1 << (bp * k)) + k * ((1 << bp) - 1) ** 2 * ((1 << (bp * k)) - 1) // ((1 << bp) - 1)
+    qs = [q for q in (prime_chain(2) + [97, 61, 7]) if q < 1 << (bp * k)]
+    top = (1 << (2 * k * bp)) - 1
+    for q in qs:
+        for p in [0, 1, q, (1 << (bp * k)) - 1, 1 << (bp * k), top] + [int(v) for v in g.integers(0, top, 300, dtype=np.uint64)]:
+            r = bat_lazy_reduce(p, q, bp, k)
+            assert r % q == p % q and 0 <= r < bound
+
+
+def test_bat_lazy_tiny_worked_example():
+    # q = 7, bp = 2, k = 2: p = 0b1101_1011 = 219; low = 0b1011 = 11; c_2 = 0b01 = 1, c_3 = 0b11 = 3;
+    # LC_0 = 2^4 mod 7 = 2 = [2, 0], LC_1 = 2^6 mod 7 = 1 = [1, 0];
+    # T_0 = 1*2 + 3*1 = 5, T_1 = 0; r = 11 + 5 = 16 = 219 (mod 7)
+    from oracle.reduction import bat_lazy_reduce, lazy_constants
+    assert lazy_constants(7, 2, 2) == [[2, 0], [1, 0]]
+    assert bat_lazy_reduce(219, 7, 2, 2) == 16
+    assert 16 % 7 == 219 % 7
+
+
+def test_bat_lazy_mulmod_matches_modulo():
+    from oracle.reduction import bat_lazy_mulmod
+    g = np.random.Generator(np.random.PCG64(23))
+    for q in prime_chain(3):
+        for a, w in [(0, 0), (q - 1, q - 1), (1, q - 1)] + list(zip(g.integers(0, q, 300), g.integers(0, q, 300))):
+            assert bat_lazy_mulmod(int(a), int(w), q) == int(a) * int(w) % q
