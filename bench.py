@@ -113,6 +113,40 @@ def he_mult_bench(B, steps, warmup, batch):
     return res
 
 
+def modred_bench(B, reps):
+    """VecModMul a * w mod q (w pre-known, one vector per limb shared by every polynomial) at
+    N=2^16, L=24 under each modular reduction, for 1..64 polynomials (Fig. diff_modred analog)."""
+    import numpy as np
+    import torch
+    import synthetic
+    primes, a = synthetic.ntt_batch(5, 16, 24, 64)
+    _, w = synthetic.ntt_batch(6, 16, 24, 1)
+    da = torch.from_numpy(a.view(np.int32)).cuda()
+    dw = torch.from_numpy(np.ascontiguousarray(w[0]).view(np.int32)).cuda()
+    limb_words = 24 << 16
+    res = {}
+    for method in ("barrett", "montgomery", "shoup", "bat_lazy"):
+        prep = B.vec_modmul_prepare(dw, primes, method)
+        row = {}
+        for npoly in (1, 4, 16, 64):
+            x = da[:npoly]
+            out = torch.empty_like(x)
+            for _ in range(3):
+                B.vec_modmul(x, prep, out, primes, method)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                B.vec_modmul(x, prep, out, primes, method)
+            e1.record()
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            nbytes = 4 * limb_words * (2 * npoly + (2 if method == "shoup" else 1))
+            row[str(npoly)] = {"us": round(us, 2), "gbs": round(nbytes / us / 1e3, 1),
+                               "elements_per_s": round(npoly * limb_words / us * 1e6, 1)}
+        res[method] = row
+    return res
+
+
 def uneven_batch_bench(B, replays):
     """Config C4: 64 ciphertexts, N in {2^13..2^16}, L in [4, 36], HE-Mult (p = 0.5) else
     NTT of both polynomials; one captured graph per pass vs. the per-job calls."""
@@ -325,6 +359,10 @@ def main():
     line["rotate"] = {"config": "same parameters, 1 slot", "batch1": he1["rotate"], "batch8": he8["rotate"]}
     line["rescale"] = {"config": "N=2^16, L=24 -> 23 (divide by the last prime), per ciphertext",
                        "batch1": he1["rescale"], "batch8": he8["rescale"]}
+    line["modred_ablation"] = {"config": "VecModMul a*w mod q, w pre-known per limb, N=2^16, L=24; "
+                                         "key = polynomials per call; us per call and HBM GB/s "
+                                         "(a read + out written + w read once)",
+                               "methods": modred_bench(B, max(10, args.steps))}
     add_bytes = 3 * 2 * 24 * (1 << 16) * 4        # a, b read, out written: one ciphertext pair
     line["he_add"] = {"config": "N=2^16, L=24, per ciphertext pair", "batch1": he1["he_add"],
                       "batch8": he8["he_add"], "bytes_per_op": add_bytes,

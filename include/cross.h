@@ -229,6 +229,47 @@ cross_status cross_rescale(cross_ctx ctx, uint32_t log_n, const uint32_t* primes
                            void* stream);
 
 /*
+ * VecModMul with a pre-known operand under a chosen modular reduction (Sec.
+ * Evaluation "Impact of Modular Reduction Algorithm", Fig. diff_modred:
+ * Barrett, Montgomery, Shoup; App. "BAT for Modular Reduction": the lazy
+ * partial reduction as an int8 matrix product on the MFMA units):
+ *   out[p][l][n] = a[p][l][n] * w[l][n] mod q_l   for p < npoly, l < L, n < N.
+ * Every method returns the canonical residue, so results are identical.
+ *   CROSS_MODRED_BARRETT    Alg. barrett on the 56-bit product
+ *   CROSS_MODRED_MONTGOMERY REDC (Alg. montgomery_reduction) with w in Montgomery form
+ *   CROSS_MODRED_SHOUP      Shoup multiplication with precomputed quotients
+ *   CROSS_MODRED_BAT_LAZY   the product's four 7-bit chunks above bit 28 times the
+ *                           chunk matrix of 2^(7(4+j)) mod q on one int8 MFMA per 256
+ *                           elements, then Barrett on the lazy sum (< 2^38); N >= 256
+ */
+typedef enum {
+  CROSS_MODRED_BARRETT = 0,
+  CROSS_MODRED_MONTGOMERY = 1,
+  CROSS_MODRED_SHOUP = 2,
+  CROSS_MODRED_BAT_LAZY = 3
+} cross_modred;
+
+/*
+ * Prepare the pre-known operand once for `method`.
+ *   w      : device [L][N] residues (not modified)
+ *   w_prep : device 2*L*N words, must not overlap w: [L][N] prepared values
+ *            (w * 2^32 mod q for Montgomery, w otherwise), then [L][N] Shoup
+ *            quotients floor(w * 2^32 / q) (written for Shoup only)
+ * Errors: CROSS_EINVAL (null / overlapping buffers, bad shape or method),
+ * CROSS_EUNSUPPORTED (BAT-lazy with N < 256), prime checks as cross_ntt_forward.
+ */
+cross_status cross_vec_modmul_prepare(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                                      int method, const uint32_t* w, uint32_t* w_prep, void* stream);
+/*
+ * out = a * w mod q limb-wise with w_prep from cross_vec_modmul_prepare (same
+ * method, primes and N).  a, out: device [npoly][L][N] residues, 16-byte
+ * aligned; out may alias a.  Asynchronous on `stream`.
+ */
+cross_status cross_vec_modmul(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
+                              uint32_t npoly, int method, const uint32_t* a, const uint32_t* w_prep,
+                              uint32_t* out, void* stream);
+
+/*
  * Batch runtime (many jobs of uneven N and limb count in one pass).
  * Jobs are lowered onto a fixed sequence of 15 work-list launches (one per
  * step of the hot path, each covering that step for every job; the BAT GEMM
@@ -312,6 +353,11 @@ cross_status cross_measure_peak(cross_ctx ctx, int which, double* out);
  *   which 4/5    : uint32 step-2 twiddles as (w, floor(w*2^32/q)) pairs (Shoup
  *                  multiplication), forward [R][C][2] and inverse transposed [C][R][2]
  *                  (Sec. MAT, layout-invariant 3-step NTT)
+ *   which 6      : the 1 KB int8 A operand of the BAT lazy reduction for q
+ *                  (cross_vec_modmul, CROSS_MODRED_BAT_LAZY): lane l (0..63), byte e
+ *                  at 16*l + e holds, for row = l%32, K byte kb = 16*(l/32) + e,
+ *                  s = kb/4, j = kb%4, chunk row%4 of 2^(7(4+j)) mod q if
+ *                  row/4 == 2*(s%4) + s/4, else 0 (App. "BAT for Modular Reduction")
  * Returns CROSS_EINVAL for a bad `which`, split or buffer size.
  */
 cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,

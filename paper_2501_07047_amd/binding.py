@@ -52,6 +52,8 @@ SIGNATURES = {
     "cross_rotate": [c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_u32, c_vp],
     "cross_he_add": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp, c_vp, c_vp],
     "cross_rescale": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_u32, c_vp, c_vp, c_vp],
+    "cross_vec_modmul_prepare": [c_vp, c_u32, c_u32p, c_u32, ctypes.c_int, c_vp, c_vp, c_vp],
+    "cross_vec_modmul": [c_vp, c_u32, c_u32p, c_u32, c_u32, ctypes.c_int, c_vp, c_vp, c_vp, c_vp],
     "cross_batch_create": [c_vp, c_vp, c_u32, ctypes.c_int, ctypes.POINTER(c_vp)],
     "cross_batch_workspace_bytes": [c_vp, c_vp, c_u32, ctypes.POINTER(ctypes.c_uint64)],
     "cross_batch_create_in": [c_vp, c_vp, c_u32, ctypes.c_int, c_vp, ctypes.c_uint64, c_vp, ctypes.POINTER(c_vp)],
@@ -198,7 +200,7 @@ def host_tables(q, log_n, log_r, which):
     st = lib().cross_host_tables(q, log_n, log_r, which, c_vp(buf.ctypes.data), ctypes.byref(nbytes))
     if st != 0:
         raise CrossError(st, "cross_host_tables")
-    return buf.view(np.int8) if which < 4 else buf.view(np.uint32)
+    return buf.view(np.int8) if which < 4 or which == 6 else buf.view(np.uint32)
 
 
 def measure_peak(which, device=None):
@@ -339,6 +341,37 @@ def rescale(x, out, primes, drop=1):
     ctx = context(x.device.index)
     _check(lib().cross_rescale(ctx, _log2(n), _u32_array(primes), L, int(drop), npoly, _dev_ptr(x, "x"),
                                _dev_ptr(out, "out"), _stream(x)), ctx)
+    return out
+
+
+MODRED = {"barrett": 0, "montgomery": 1, "shoup": 2, "bat_lazy": 3}
+
+
+def vec_modmul_prepare(w, primes, method):
+    """Prepared form of the pre-known operand w [L][N] for `method` (a MODRED key): a new
+    device tensor of 2*L*N words."""
+    import torch
+    L, n = w.shape
+    if len(primes) != L:
+        raise ValueError("len(primes) != L")
+    prep = torch.empty((2, L, n), dtype=torch.int32, device=w.device)
+    ctx = context(w.device.index)
+    _check(lib().cross_vec_modmul_prepare(ctx, _log2(n), _u32_array(primes), L, MODRED[method], _dev_ptr(w, "w"),
+                                          _dev_ptr(prep, "w_prep"), _stream(w)), ctx)
+    return prep
+
+
+def vec_modmul(a, w_prep, out, primes, method):
+    """out = a * w mod q limb-wise: a, out [..][L][N]; w_prep from vec_modmul_prepare (same method)."""
+    L, n = a.shape[-2:]
+    _shape(out, a.shape, "out")
+    _shape(w_prep, (2, L, n), "w_prep")
+    if len(primes) != L:
+        raise ValueError("len(primes) != L")
+    npoly = a.numel() // (L * n)
+    ctx = context(a.device.index)
+    _check(lib().cross_vec_modmul(ctx, _log2(n), _u32_array(primes), L, npoly, MODRED[method], _dev_ptr(a, "a"),
+                                  _dev_ptr(w_prep, "w_prep"), _dev_ptr(out, "out"), _stream(a)), ctx)
     return out
 
 

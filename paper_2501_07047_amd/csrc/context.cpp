@@ -374,15 +374,18 @@ cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len) {
 
 cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,
                                void* out, uint64_t* bytes) {
-  if (!bytes || which > 5 || log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4)
+  if (!bytes || which > 6 || log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4)
     return CROSS_EINVAL;
   cross_status st = check_prime(nullptr, q, log_n);
   if (st != CROSS_OK) return st;
   NttTables t;
-  build_ntt_tables(q, log_n, log_r, t);
+  std::vector<int8_t> lazy;
+  if (which == 6) lazy = lazy_fragment(q);
+  else build_ntt_tables(q, log_n, log_r, t);
   const void* src = nullptr;
   uint64_t n = 0;
   switch (which) {
+    case 6: src = lazy.data(); n = lazy.size(); break;
     case 0: src = t.fwd_left.data(); n = t.fwd_left.size(); break;
     case 1: src = t.fwd_right.data(); n = t.fwd_right.size(); break;
     case 2: src = t.inv_left.data(); n = t.inv_left.size(); break;

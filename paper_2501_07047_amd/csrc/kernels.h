@@ -124,6 +124,22 @@ hipError_t launch_pointwise_mul(const uint32_t* a, const uint32_t* b, uint32_t* 
 hipError_t launch_pointwise_add(const uint32_t* a, const uint32_t* b, uint32_t* out,
                                 const LimbMod* mods, int L, int log_n, int npoly, hipStream_t s);
 
+// VecModMul with a pre-known operand under a chosen modular reduction
+// (out[p][l] = a[p][l] * w[l] mod q_l, all limbs [N]; out may alias a).
+enum Modred { kModredBarrett = 0, kModredMontgomery = 1, kModredShoup = 2, kModredBatLazy = 3 };
+struct ModLimb {
+  uint32_t q, qinv;      // q^-1 mod 2^32 (Montgomery REDC)
+  uint32_t bar_m, bar_k; // Barrett: k = bitlen(q), m = floor(2^(2k) / q)
+  uint32_t r32, pad[3];  // 2^32 mod q
+};
+// w: [L][N] prepared values; w_quot: [L][N] Shoup quotients (Shoup only);
+// lazy: L fragments of 1 KB, the BAT chunk matrix per prime (BAT-lazy only, log_n >= 8).
+hipError_t launch_vec_modmul(const uint32_t* a, const uint32_t* w, const uint32_t* w_quot, uint32_t* out,
+                             const ModLimb* limbs, const int8_t* lazy, int L, int log_n, int npoly, int method,
+                             hipStream_t s);
+hipError_t launch_modmul_prepare(const uint32_t* w, uint32_t* w_prep, uint32_t* w_quot, const ModLimb* limbs,
+                                 int L, int log_n, int method, hipStream_t s);
+
 // Strided limb copy / zero: for each poly p < npoly and limb l < nl:
 // dst[p*dst_stride + dst_off[l] ..+N] = src ? src[p*src_stride + src_off[l] ..] : 0.
 hipError_t launch_limb_copy(const uint32_t* src, uint64_t src_stride, const uint64_t* src_off,

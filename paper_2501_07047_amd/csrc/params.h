@@ -19,6 +19,8 @@ uint32_t smallest_generator(uint32_t q);
 // Canonical primitive 2N-th root: g^((q-1)/2N) for the smallest generator g.
 uint32_t root_2n(uint32_t q, uint32_t log_n);
 uint32_t inv_mod_2_32(uint32_t q);       // q^-1 mod 2^32 (q odd)
+// A operand (1 KB, MFMA fragment order) of the BAT lazy reduction for prime q.
+std::vector<int8_t> lazy_fragment(uint32_t q);
 uint32_t bitrev(uint32_t x, int bits);
 
 // BAT-expanded table of a pre-known residue matrix T (rows = "in", cols = "out"):

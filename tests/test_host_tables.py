@@ -84,3 +84,39 @@ def test_table_entries_are_7bit_chunks():
     for which in (4, 5):
         t = binding.host_tables(q, 12, 6, which).reshape(-1, 2)
         assert int(t[:, 0].max()) < q
+
+
+def test_bat_lazy_fragment_returns_each_lanes_chunk_products_in_lane():
+    # Emulate v_mfma_i32_32x32x32_i8 with the library's BAT-lazy A operand: lane l
+    # supplies A row l%32 / B column l%32 with K bytes 16*(l/32) .. +15, and holds
+    # output rows 8*(v/4) + 4*(l/32) + v%4 of column l%32 in register v.  Lane l puts
+    # the high chunks of its element t in B bytes 4t .. 4t+3 and must get
+    # T_k = sum_j c_(4+j) LC[j][k] of that element back in registers 4t .. 4t+3.
+    from oracle.reduction import bat_lazy_reduce, lazy_constants
+    from paper_2501_07047_amd import binding
+    g = np.random.Generator(np.random.PCG64(31))
+    for q in prime_chain(3):
+        frag = binding.host_tables(q, 16, 8, 6).astype(np.int64)
+        assert frag.shape == (1024,)
+        A = np.zeros((32, 32), dtype=np.int64)
+        for l in range(64):
+            A[l % 32, 16 * (l // 32):16 * (l // 32) + 16] = frag[16 * l:16 * l + 16]
+        a = g.integers(0, q, (64, 4)).astype(np.int64)
+        w = g.integers(0, q, (64, 4)).astype(np.int64)
+        p = a * w
+        hi = p >> 28
+        Bm = np.zeros((32, 32), dtype=np.int64)
+        for l in range(64):
+            for t in range(4):
+                for j in range(4):
+                    Bm[16 * (l // 32) + 4 * t + j, l % 32] = (int(hi[l, t]) >> (7 * j)) & 0x7f
+        C = A @ Bm
+        LC = lazy_constants(q)
+        for l in range(64):
+            regs = [C[8 * (v // 4) + 4 * (l // 32) + v % 4, l % 32] for v in range(16)]
+            for t in range(4):
+                c = [(int(hi[l, t]) >> (7 * j)) & 0x7f for j in range(4)]
+                T = [sum(c[j] * LC[j][k] for j in range(4)) for k in range(4)]
+                assert regs[4 * t:4 * t + 4] == T
+                lazy = (int(p[l, t]) & 0x0fffffff) + sum(T[k] << (7 * k) for k in range(4))
+                assert lazy == bat_lazy_reduce(int(p[l, t]), q) and lazy % q == int(p[l, t]) % q
