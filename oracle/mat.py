@@ -91,3 +91,65 @@ def three_step_intt(ahat, q: int, psi: int, R: int, C: int) -> np.ndarray:
     y = modmatmul(A, itf3, q)
     y = (y * it2) % U64(q)
     return modmatmul(itf1, y, q).reshape(-1)
+
+
+# ---- three factors: the C-point row transform of step 3 split once more ----------
+#
+# MAT extends to multi-dimensional tensors with one permutation per dimension
+# (Sec. MAT).  Step 3 is a cyclic C-point DFT of every row with root
+# w = psi^(2R) and bit-reversed output; with C = C1*C2, c = c1*C2 + c2 and
+# output position c' = m*C2 + c2', brv_C(c') = brv_C2(c2')*C1 + brv_C1(m), so
+#     w^(c * brv_C(c')) = w^(C2 c1 brv_C1(m)) * w^(c2 brv_C1(m)) * w^(C1 c2 brv_C2(c2'))
+# (the cross term is a power of w^C = 1).  Each row, viewed as a C1 x C2 matrix
+# (row-major, layout unchanged), is transformed by a left product over c1, an
+# element-wise twiddle, and a right product over c2:
+#
+#     TB[m][c1]   = psi^(2R * C2 * c1 * brv_C1(m))
+#     T3[m][c2]   = psi^(2R * c2 * brv_C1(m))
+#     TC[c2][c2'] = psi^(2R * C1 * c2 * brv_C2(c2'))
+#     row out     = ((TB @ Y_row) * T3) @ TC
+#
+# Inverse (no scaling: N^-1 stays in ITF1): ITC[c2'][c2] = TC^-1-conjugate
+# psi^(-2R C1 c2 brv_C2(c2')), IT3 = psi^(-2R c2 brv_C1(m)),
+# ITB[c1][m] = psi^(-2R C2 c1 brv_C1(m)); row = ITB @ ((Xrow @ ITC) * IT3), which is
+# C times the forward input, absorbed by N^-1.
+
+def row_twiddles(q: int, psi: int, R: int, C1: int, C2: int):
+    """Forward (TB, T3, TC) and inverse (ITB, IT3, ITC) factors of the row transform."""
+    n2 = 2 * R * C1 * C2
+    b1 = bitrev_table(C1)
+    b2 = bitrev_table(C2)
+    c1 = np.arange(C1, dtype=np.int64)
+    c2 = np.arange(C2, dtype=np.int64)
+    tb = _pow_matrix(psi, 2 * R * C2 * b1[:, None] * c1[None, :], q, n2)
+    t3 = _pow_matrix(psi, 2 * R * b1[:, None] * c2[None, :], q, n2)
+    tc = _pow_matrix(psi, 2 * R * C1 * c2[:, None] * b2[None, :], q, n2)
+    itb = _pow_matrix(psi, -(2 * R * C2) * c1[:, None] * b1[None, :], q, n2)
+    it3 = _pow_matrix(psi, -(2 * R) * b1[:, None] * c2[None, :], q, n2)
+    itc = _pow_matrix(psi, -(2 * R * C1) * b2[:, None] * c2[None, :], q, n2)
+    return (tb, t3, tc), (itb, it3, itc)
+
+
+def three_factor_ntt(a, q: int, psi: int, R: int, C1: int, C2: int) -> np.ndarray:
+    C = C1 * C2
+    (tf1, t2, _), _ = twiddles(q, psi, R, C)
+    (tb, t3, tc), _ = row_twiddles(q, psi, R, C1, C2)
+    y = (modmatmul(tf1, np.asarray(a, dtype=U64).reshape(R, C), q) * t2) % U64(q)
+    out = np.empty((R, C1, C2), dtype=U64)
+    for k in range(R):
+        z = (modmatmul(tb, y[k].reshape(C1, C2), q) * t3) % U64(q)
+        out[k] = modmatmul(z, tc, q)
+    return out.reshape(-1)
+
+
+def three_factor_intt(ahat, q: int, psi: int, R: int, C1: int, C2: int) -> np.ndarray:
+    C = C1 * C2
+    _, (itf1, it2, _) = twiddles(q, psi, R, C)
+    _, (itb, it3, itc) = row_twiddles(q, psi, R, C1, C2)
+    x = np.asarray(ahat, dtype=U64).reshape(R, C1, C2)
+    y = np.empty((R, C), dtype=U64)
+    for k in range(R):
+        z = (modmatmul(x[k], itc, q) * it3) % U64(q)
+        y[k] = modmatmul(itb, z, q).reshape(-1)
+    y = (y * it2) % U64(q)
+    return modmatmul(itf1, y, q).reshape(-1)

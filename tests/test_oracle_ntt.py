@@ -165,6 +165,33 @@ def test_three_step_twiddle_structure():
     assert np.array_equal((t2 * it2) % q, np.ones((R, C), dtype=np.uint64))
 
 
+@pytest.mark.parametrize("R,C1,C2", [(4, 4, 4), (8, 2, 4), (2, 8, 4), (4, 4, 8), (16, 2, 8), (2, 4, 32)])
+def test_three_factor_matches_definition(R, C1, C2):
+    n = R * C1 * C2
+    q = Q0
+    psi = psi_of(q, n)
+    g = np.random.Generator(np.random.PCG64(R * 1000 + C1 * 10 + C2))
+    a = g.integers(0, q, n)
+    ref = T.ntt_def(a, q, psi)
+    assert np.array_equal(M.three_factor_ntt(a, q, psi, R, C1, C2), ref)
+    assert np.array_equal(M.three_factor_intt(ref, q, psi, R, C1, C2), a)
+
+
+def test_three_factor_degenerate_and_structure():
+    # C1 = 1 (or C2 = 1) is the two-factor form; the row factors invert to C1 * I and C2 * I
+    q, R, C1, C2 = Q0, 4, 8, 4
+    n = R * C1 * C2
+    psi = psi_of(q, n)
+    g = np.random.Generator(np.random.PCG64(77))
+    a = g.integers(0, q, n)
+    assert np.array_equal(M.three_factor_ntt(a, q, psi, R, 1, C1 * C2), M.three_step_ntt(a, q, psi, R, C1 * C2))
+    assert np.array_equal(M.three_factor_ntt(a, q, psi, R, C1 * C2, 1), M.three_step_ntt(a, q, psi, R, C1 * C2))
+    (tb, t3, tc), (itb, it3, itc) = M.row_twiddles(q, psi, R, C1, C2)
+    assert np.array_equal(M.modmatmul(itb, tb, q), np.eye(C1, dtype=np.uint64) * np.uint64(C1))
+    assert np.array_equal(M.modmatmul(tc, itc, q), np.eye(C2, dtype=np.uint64) * np.uint64(C2))
+    assert np.array_equal((t3 * it3) % q, np.ones((C1, C2), dtype=np.uint64))
+
+
 def test_golden_regression_fixture():
     import json
     import os
