@@ -67,6 +67,19 @@ cross_status cross_root(uint32_t q, uint32_t log_n, uint32_t* psi_out);
  * R = 2^floor(log_n/2)).  4 <= log_r and 4 <= log_n - log_r. */
 cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r);
 
+/*
+ * Three-factor NTT for size 2^log_n (MAT applied to a third dimension, Sec.
+ * MAT): the R x C split with R = 2^log_r, and the C-point row transform of
+ * step 3 split once more as C1 x C2 (C1 = 2^log_c1) -- same input/output layout
+ * and bit-reversed order as the two-factor form, about (R + C1 + C2) / (R + C)
+ * of its int8 MAC work.  Needs 16 <= C1, C2 <= 64, R >= 16 and R * C1 * C2 >=
+ * 8192 (the row kernel takes 8192 / C rows per workgroup).  log_c1 = 0 returns
+ * log_n to the two-factor form.  Applies to cross_ntt_forward/inverse, the CKKS
+ * entry points and cross_poly_mul; the batch runtime keeps two factors.
+ * Errors: CROSS_EINVAL for an unsupported split.
+ */
+cross_status cross_set_ntt_split3(cross_ctx ctx, uint32_t log_n, uint32_t log_r, uint32_t log_c1);
+
 /* Autotuner: time forward + inverse NTTs of `batch` x L limbs of size 2^log_n
  * (8 <= log_n <= 16) for every split R = 2^log_r with 4 <= log_r <= log_n - 4
  * within a factor of four of square, and R, C >= 64 from log_n = 12 up so the
@@ -362,6 +375,18 @@ cross_status cross_measure_peak(cross_ctx ctx, int which, double* out);
  */
 cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,
                                void* out, uint64_t* bytes);
+
+/*
+ * Host-only introspection of the three-factor row tables (split as in
+ * cross_set_ntt_split3), same calling convention as cross_host_tables:
+ *   which 0/1 : int8 BAT tables of the forward row sub-steps, TB (over c1, 4C1 x 4C1)
+ *               and TC (over c2, 4C2 x 4C2), in the fragment order of cross_host_tables
+ *   which 2/3 : the inverse ones, ITC (over c2', first) and ITB (over m, second)
+ *   which 4/5 : uint32 (w, floor(w*2^32/q)) pairs of T3 / IT3, [C1][C2][2]
+ *   which 6/7 : uint32 pairs of the inverse / forward step-2 twiddles, row-major [R][C][2]
+ */
+cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,
+                                   void* out, uint64_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -38,6 +38,8 @@ SIGNATURES = {
     "cross_root": [c_u32, c_u32, c_u32p],
     "cross_set_ntt_split": [c_vp, c_u32, c_u32],
     "cross_set_gemm_tile": [c_vp, ctypes.c_int],
+    "cross_set_ntt_split3": [c_vp, c_u32, c_u32, c_u32],
+    "cross_host_row_tables": [c_u32, c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
     "cross_autotune": [c_vp, c_u32, c_u32, c_u32, ctypes.c_char_p, ctypes.POINTER(c_u32),
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
     "cross_ntt_forward": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
@@ -142,6 +144,26 @@ def root(q, log_n):
 def set_ntt_split(log_n, log_r, device=None):
     ctx = context(device)
     _check(lib().cross_set_ntt_split(ctx, log_n, log_r), ctx)
+
+
+def set_ntt_split3(log_n, log_r, log_c1, device=None):
+    """Three-factor NTT split for size 2^log_n (log_c1 = 0: back to two factors)."""
+    ctx = context(device)
+    _check(lib().cross_set_ntt_split3(ctx, log_n, log_r, log_c1), ctx)
+
+
+def host_row_tables(q, log_n, log_r, log_c1, which):
+    """Copy one three-factor row table into a numpy array (host only, no GPU)."""
+    import numpy as np
+    nbytes = ctypes.c_uint64(0)
+    st = lib().cross_host_row_tables(q, log_n, log_r, log_c1, which, None, ctypes.byref(nbytes))
+    if st != 0:
+        raise CrossError(st, "cross_host_row_tables")
+    buf = np.empty(nbytes.value, dtype=np.uint8)
+    st = lib().cross_host_row_tables(q, log_n, log_r, log_c1, which, c_vp(buf.ctypes.data), ctypes.byref(nbytes))
+    if st != 0:
+        raise CrossError(st, "cross_host_row_tables")
+    return buf.view(np.int8) if which < 4 else buf.view(np.uint32)
 
 
 def set_gemm_tile(tile, device=None):

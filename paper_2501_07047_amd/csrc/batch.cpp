@@ -250,7 +250,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
         cross_status st = check_prime(ctx, P.primes[i], P.log_n);
         if (st != CROSS_OK) return st;
         Plan* p = nullptr;
-        if ((st = get_plan(ctx, P.primes[i], (int)P.log_n, &p)) != CROSS_OK) return st;
+        if ((st = get_plan(ctx, P.primes[i], (int)P.log_n, &p, false)) != CROSS_OK) return st;
         if (!split_ok(p)) return fail(ctx, CROSS_EUNSUPPORTED, "batch runtime needs R, C >= 64");
         jp[j].plans.push_back(p);
       }
@@ -258,7 +258,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     } else if (J.op == CROSS_OP_HE_MULT || J.op == CROSS_OP_ROTATE) {
       cross_status st = get_ckks_plan(ctx, &P, &jp[j].c);
       if (st != CROSS_OK) return st;
-      for (Plan* p : jp[j].c->plans)
+      for (Plan* p : jp[j].c->plans2)
         if (!split_ok(p)) return fail(ctx, CROSS_EUNSUPPORTED, "batch runtime needs R, C >= 64");
       const bool he = J.op == CROSS_OP_HE_MULT;
       if (!J.ct_a || !J.key || !J.out || (he && !J.ct_b) || !aligned16(J.ct_a) || !aligned16(J.key) ||
@@ -360,7 +360,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       }
     }
     // INTT of d (all L limbs)
-    std::vector<Plan*> qp(c->plans.begin(), c->plans.begin() + L);
+    std::vector<Plan*> qp(c->plans2.begin(), c->plans2.begin() + L);
     std::vector<uint64_t> qo(L);
     for (int i = 0; i < L; ++i) qo[i] = i * N;
     add_ntt(b.get(), kInv1, qp, qo, d, tmp, nd, B, true);
@@ -373,13 +373,13 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       b->bconv_up.push_back(g);
       b->max_waves_up = std::max(b->max_waves_up, ((uint64_t)B << c->log_n) / 32);
       for (int t : c->targets[dj]) {
-        ep.push_back(c->plans[t]);
+        ep.push_back(c->plans2[t]);
         eo.push_back(((uint64_t)dj * LK + t) * N);
       }
     }
     add_ntt(b.get(), kFwd1, ep, eo, ext, tmp, next, B, false);
     // ModDown of both accumulators: INTT of P limbs, BConv P -> Q, NTT of Q limbs
-    std::vector<Plan*> pp(c->plans.begin() + L, c->plans.end());
+    std::vector<Plan*> pp(c->plans2.begin() + L, c->plans2.end());
     std::vector<uint64_t> po(K);
     for (int k = 0; k < K; ++k) po[k] = (uint64_t)(L + k) * N;
     add_ntt(b.get(), kInv1P, pp, po, acc, tmp, (uint64_t)LK * N, 2 * B, true);

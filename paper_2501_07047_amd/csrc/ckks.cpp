@@ -127,6 +127,11 @@ cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan
   std::string key((const char*)prm->primes, (L + K) * 4);
   key += std::to_string(prm->log_n) + "/" + std::to_string(L) + "/" + std::to_string(K) + "/" +
          std::to_string(dnum) + "/" + std::to_string(split_of(ctx, (int)prm->log_n));
+  {
+    auto s3 = ctx->split3.find((int)prm->log_n);
+    if (s3 != ctx->split3.end())
+      key += "/" + std::to_string(s3->second.first) + "x" + std::to_string(s3->second.second);
+  }
   auto it = ctx->ext_plans.find(key);
   if (it != ctx->ext_plans.end()) {
     *out = static_cast<CkksPlan*>(it->second.get());
@@ -149,6 +154,10 @@ cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan
     st = get_plan(ctx, c->primes[i], c->log_n, &p);
     if (st != CROSS_OK) return st;
     c->plans.push_back(p);
+    Plan* p2 = nullptr;
+    st = get_plan(ctx, c->primes[i], c->log_n, &p2, false);
+    if (st != CROSS_OK) return st;
+    c->plans2.push_back(p2);
   }
   std::vector<LimbMod> mods(L + K);
   for (int i = 0; i < L + K; ++i) mods[i] = limb_mod(c->primes[i]);

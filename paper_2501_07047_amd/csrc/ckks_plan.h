@@ -19,6 +19,7 @@ struct CkksPlan {
   int log_n = 0, L = 0, K = 0, dnum = 0, alpha = 0, ndig = 0;
   std::vector<uint32_t> primes;
   std::vector<Plan*> plans;               // L + K
+  std::vector<Plan*> plans2;              // the same primes in the two-factor form (batch runtime)
   const LimbMod* mods = nullptr;          // L + K, device
   const TailConst* tail = nullptr;        // L, device
   std::vector<BconvStatic> modup;         // per active digit: digit limbs -> all other limbs

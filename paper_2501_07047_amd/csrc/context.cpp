@@ -48,9 +48,17 @@ static cross_status dev_alloc(cross_ctx ctx, size_t bytes, void** out) {
   return CROSS_OK;
 }
 
-cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out) {
-  const int log_r = (log_n >= 8) ? split_of(ctx, log_n) : 0;
-  auto key = std::make_tuple(q, log_n, log_r);
+cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3) {
+  int log_r = (log_n >= 8) ? split_of(ctx, log_n) : 0;
+  int log_c1 = 0;
+  if (allow3) {
+    auto s3 = ctx->split3.find(log_n);
+    if (s3 != ctx->split3.end()) {
+      log_r = s3->second.first;
+      log_c1 = s3->second.second;
+    }
+  }
+  auto key = std::make_tuple(q, log_n, log_r, log_c1);
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end()) {
     *out = it->second;
@@ -59,14 +67,16 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out) {
   NttTables t;
   try {
     // below N = 2^8 a 3-step split cannot fill one 64-deep MFMA step: butterfly twiddles only
-    build_ntt_tables(q, log_n, log_r, t, log_n >= 8);
+    build_ntt_tables(q, log_n, log_r, t, log_n >= 8, (uint32_t)log_c1);
   } catch (const std::exception& e) {
     return fail(ctx, CROSS_EINVAL, e.what());
   }
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   size_t sz = al(t.fwd_left.size()) + al(t.fwd_right.size()) + al(t.inv_left.size()) +
               al(t.inv_right.size()) + al(t.fwd_tw.size() * 4) + al(t.inv_tw.size() * 4) +
-              al(t.bf_fwd.size() * 4) + al(t.bf_inv.size() * 4);
+              al(t.bf_fwd.size() * 4) + al(t.bf_inv.size() * 4) + al(t.row_fwd_b.size()) +
+              al(t.row_fwd_c.size()) + al(t.row_inv_c.size()) + al(t.row_inv_b.size()) +
+              al(t.row_fwd_t3.size() * 4) + al(t.row_inv_t3.size() * 4) + al(t.inv_tw_rows.size() * 4);
   Plan* p = new Plan();
   cross_status st = dev_alloc(ctx, sz, &p->block);
   if (st != CROSS_OK) {
@@ -89,6 +99,13 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out) {
   p->inv_tw = (uint32_t*)put(t.inv_tw.data(), t.inv_tw.size() * 4);
   p->bf_fwd = (uint32_t*)put(t.bf_fwd.data(), t.bf_fwd.size() * 4);
   p->bf_inv = (uint32_t*)put(t.bf_inv.data(), t.bf_inv.size() * 4);
+  p->row_fwd_b = (int8_t*)put(t.row_fwd_b.data(), t.row_fwd_b.size());
+  p->row_fwd_c = (int8_t*)put(t.row_fwd_c.data(), t.row_fwd_c.size());
+  p->row_inv_c = (int8_t*)put(t.row_inv_c.data(), t.row_inv_c.size());
+  p->row_inv_b = (int8_t*)put(t.row_inv_b.data(), t.row_inv_b.size());
+  p->row_fwd_t3 = (uint32_t*)put(t.row_fwd_t3.data(), t.row_fwd_t3.size() * 4);
+  p->row_inv_t3 = (uint32_t*)put(t.row_inv_t3.data(), t.row_inv_t3.size() * 4);
+  p->inv_tw_rows = (uint32_t*)put(t.inv_tw_rows.data(), t.inv_tw_rows.size() * 4);
   if (hipGetLastError() != hipSuccess) {
     (void)hipFree(p->block);
     delete p;
@@ -99,6 +116,7 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out) {
   p->psi = root_2n(q, log_n);
   p->log_n = log_n;
   p->log_r = log_r;
+  p->log_c1 = log_c1;
   p->bf_ninv = t.bf_ninv;
   ctx->plans[key] = p;
   *out = p;
@@ -142,6 +160,76 @@ cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out) {
   return CROSS_OK;
 }
 
+// Three factors (plans with log_c1 > 0): forward = row-side step 1 (R-point,
+// fused step-2 twiddle, packed output) then the row kernel (C1 x C2 transform
+// of every row, plain output); inverse = the inverse row kernel (packed output
+// with the inverse step-2 twiddle) then the row-side step 1 inverse on packed
+// row-major input (N^-1 folded in).
+static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+                              uint32_t* data, uint64_t stride, int npoly, bool inverse, uint32_t* tmp,
+                              hipStream_t s) {
+  const int log_n = plans[0]->log_n, log_r = plans[0]->log_r, log_c1 = plans[0]->log_c1;
+  const int log_c2 = log_n - log_r - log_c1;
+  std::vector<RowsJob> rj(plans.size());
+  std::vector<GemmJob> gj(plans.size());
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    if (p->log_r != log_r || p->log_c1 != log_c1) return fail(ctx, CROSS_EINVAL, "mixed NTT splits in one call");
+    rj[i] = inverse ? RowsJob{p->row_inv_c, p->row_inv_b, p->row_inv_t3, p->inv_tw_rows, offs[i], p->q, p->qinv}
+                    : RowsJob{p->row_fwd_b, p->row_fwd_c, p->row_fwd_t3, nullptr, offs[i], p->q, p->qinv};
+    gj[i] = GemmJob{inverse ? p->inv_left : p->fwd_left, inverse ? nullptr : p->fwd_tw, offs[i], offs[i], p->q,
+                    p->qinv};
+  }
+  void *dr = nullptr, *dg = nullptr;
+  cross_status st = cached_device_copy(ctx, rj.data(), rj.size() * sizeof(RowsJob), &dr);
+  if (st == CROSS_OK) st = cached_device_copy(ctx, gj.data(), gj.size() * sizeof(GemmJob), &dg);
+  if (st != CROSS_OK) return st;
+  GemmLaunch g{};
+  g.jobs = (const GemmJob*)dg;
+  g.njobs = (int)plans.size();
+  g.src_stride = g.dst_stride = stride;
+  g.npoly = npoly;
+  g.log_r = log_r;
+  g.log_c = log_n - log_r;
+  g.kind = kLeft;
+  g.tile = ctx->gemm_tile;
+  if (g.tile == 0) {
+    auto it = ctx->tile_by_logn.find(log_n);
+    if (it != ctx->tile_by_logn.end()) g.tile = it->second;
+  }
+  auto rows = [&](const uint32_t* in, uint32_t* out) -> cross_status {
+    hipError_t e;
+    {
+      ProfScope ps(ctx, "ntt_rows", s);
+      e = launch_ntt_rows((const RowsJob*)dr, (int)plans.size(), in, out, stride, npoly, log_r, log_c1, log_c2,
+                          inverse, s);
+    }
+    if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("row transform launch: ") + hipGetErrorString(e));
+    return CROSS_OK;
+  };
+  auto left = [&]() -> cross_status {
+    hipError_t e;
+    {
+      ProfScope ps(ctx, "bat_gemm_left", s);
+      e = launch_bat_gemm(g, s);
+    }
+    if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("row-side step launch: ") + hipGetErrorString(e));
+    return CROSS_OK;
+  };
+  if (!inverse) {
+    g.src = data;
+    g.dst = tmp;
+    g.out_packed = g.twiddle = true;
+    if ((st = left()) != CROSS_OK) return st;
+    return rows(tmp, data);
+  }
+  if ((st = rows(data, tmp)) != CROSS_OK) return st;
+  g.src = tmp;
+  g.dst = data;
+  g.in_packed = g.in_rows = true;
+  return left();
+}
+
 cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
                        const std::vector<uint64_t>& offs, uint32_t* data, uint64_t stride,
                        int npoly, bool inverse, uint32_t* tmp, hipStream_t s) {
@@ -165,6 +253,7 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
     if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("butterfly launch: ") + hipGetErrorString(e));
     return CROSS_OK;
   }
+  if (plans[0]->log_c1 > 0) return ntt_three(ctx, plans, offs, data, stride, npoly, inverse, tmp, s);
   std::vector<GemmJob> j1(plans.size()), j2(plans.size());
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];
@@ -315,6 +404,19 @@ cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r) 
   return CROSS_OK;
 }
 
+cross_status cross_set_ntt_split3(cross_ctx ctx, uint32_t log_n, uint32_t log_r, uint32_t log_c1) {
+  if (!ctx) return CROSS_EINVAL;
+  if (log_n < 8 || log_n > CROSS_MAX_LOG_N) return fail(ctx, CROSS_EINVAL, "log_n out of range");
+  if (log_c1 == 0) {
+    ctx->split3.erase((int)log_n);
+    return CROSS_OK;
+  }
+  if (log_r > log_n || !rows_split_supported((int)log_n, (int)log_r, (int)log_c1))
+    return fail(ctx, CROSS_EINVAL, "three-factor split needs 16 <= C1, C2 <= 64 and R >= max(16, 8192 / (C1 C2))");
+  ctx->split3[(int)log_n] = std::make_pair((int)log_r, (int)log_c1);
+  return CROSS_OK;
+}
+
 cross_status cross_set_gemm_tile(cross_ctx ctx, int tile) {
   if (!ctx) return CROSS_EINVAL;
   if (tile < 0 || tile >= kTileCount) return fail(ctx, CROSS_EINVAL, "tile must be 0 (auto) .. 9");
@@ -369,6 +471,41 @@ cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len) {
   size_t n = out.size() < len - 1 ? out.size() : (size_t)(len - 1);
   std::memcpy(buf, out.data(), n);
   buf[n] = 0;
+  return CROSS_OK;
+}
+
+cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,
+                                   void* out, uint64_t* bytes) {
+  if (!bytes || which > 7 || log_n > CROSS_MAX_LOG_N || log_r > log_n ||
+      !rows_split_supported((int)log_n, (int)log_r, (int)log_c1))
+    return CROSS_EINVAL;
+  cross_status st = check_prime(nullptr, q, log_n);
+  if (st != CROSS_OK) return st;
+  NttTables t;
+  try {
+    build_ntt_tables(q, log_n, log_r, t, true, log_c1);
+  } catch (const std::exception&) {
+    return CROSS_EINVAL;
+  }
+  const void* src = nullptr;
+  uint64_t n = 0;
+  switch (which) {
+    case 0: src = t.row_fwd_b.data(); n = t.row_fwd_b.size(); break;
+    case 1: src = t.row_fwd_c.data(); n = t.row_fwd_c.size(); break;
+    case 2: src = t.row_inv_c.data(); n = t.row_inv_c.size(); break;
+    case 3: src = t.row_inv_b.data(); n = t.row_inv_b.size(); break;
+    case 4: src = t.row_fwd_t3.data(); n = t.row_fwd_t3.size() * 4; break;
+    case 5: src = t.row_inv_t3.data(); n = t.row_inv_t3.size() * 4; break;
+    case 6: src = t.inv_tw_rows.data(); n = t.inv_tw_rows.size() * 4; break;
+    default: src = t.fwd_tw.data(); n = t.fwd_tw.size() * 4; break;
+  }
+  if (!out) {
+    *bytes = n;
+    return CROSS_OK;
+  }
+  if (*bytes < n) return CROSS_EINVAL;
+  std::memcpy(out, src, n);
+  *bytes = n;
   return CROSS_OK;
 }
 

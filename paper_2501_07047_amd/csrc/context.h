@@ -18,8 +18,11 @@ namespace cross {
 struct Plan {
   uint32_t q = 0, qinv = 0, psi = 0;
   int log_n = 0, log_r = 0;
+  int log_c1 = 0;           // > 0: three factors, the row transform split as C1 x C2
   int8_t *fwd_left = nullptr, *fwd_right = nullptr, *inv_left = nullptr, *inv_right = nullptr;
   uint32_t *fwd_tw = nullptr, *inv_tw = nullptr, *bf_fwd = nullptr, *bf_inv = nullptr;
+  int8_t *row_fwd_b = nullptr, *row_fwd_c = nullptr, *row_inv_c = nullptr, *row_inv_b = nullptr;
+  uint32_t *row_fwd_t3 = nullptr, *row_inv_t3 = nullptr, *inv_tw_rows = nullptr;
   uint32_t bf_ninv = 0;
   void* block = nullptr;
 };
@@ -49,10 +52,11 @@ struct ProfScope {
 struct cross_ctx_s {
   int device = 0;
   std::string err;
-  std::map<std::tuple<uint32_t, int, int>, cross::Plan*> plans;
+  std::map<std::tuple<uint32_t, int, int, int>, cross::Plan*> plans;   // (q, log_n, log_r, log_c1)
   std::map<std::string, void*> job_cache;     // serialised job list -> device copy
   std::map<hipStream_t, cross::DevBuf> workspace;
-  std::map<int, int> split;                   // log_n -> log_r override
+  std::map<int, int> split;                   // log_n -> log_r override (two factors)
+  std::map<int, std::pair<int, int>> split3;  // log_n -> (log_r, log_c1): three factors
   int gemm_tile = 0;                          // GemmTile override (0 = auto)
   std::map<int, int> tile_by_logn;            // autotuned GemmTile per transform size
   std::map<std::string, void*> const_cache;   // other device-resident constants
@@ -69,7 +73,9 @@ namespace cross {
 
 cross_status fail(cross_ctx ctx, cross_status code, const std::string& msg);
 cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n);
-cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out);
+// allow3 = false keeps the two-factor form even where a three-factor split is set
+// (the batch runtime's work lists implement two factors only).
+cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3 = true);
 int split_of(cross_ctx ctx, int log_n);
 // Device copy of a POD array, cached by content.
 cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, void** out);

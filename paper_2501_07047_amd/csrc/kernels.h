@@ -33,6 +33,7 @@ struct GemmLaunch {
   int kind;                // StepKind
   bool in_packed, out_packed, twiddle;
   int tile;                // GemmTile; kTileAuto picks by shape and grid size
+  bool in_rows;            // row side, packed input stored row-major (three-factor inverse)
 };
 
 // Workgroup tile shapes of the BAT GEMM (rows x columns of the int8 product).
@@ -43,6 +44,24 @@ enum GemmTile { kTileAuto = 0, kTile256x256 = 1, kTile256x128 = 2, kTile128x64 =
 int resolve_gemm_tile(const GemmLaunch& g);
 
 hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s);
+
+// Three-factor NTT: the row transform with C-point rows split as C1 x C2, for
+// every row of every polynomial of every job (ntt_rows.hip).  Forward: in =
+// packed step-1 output, out = plain result; inverse: in = plain, out = packed
+// rows with the inverse step-2 twiddle applied.  in / out: same layout as the
+// polynomials (job offset + poly * stride + row * C).
+struct RowsJob {
+  const int8_t* tab1;       // first sub-step table (fragment order)
+  const int8_t* tab2;       // second sub-step table
+  const uint32_t* tw1;      // (w, w') pairs [C1][C2] after the first sub-step
+  const uint32_t* tw2;      // inverse only: (w, w') pairs [R][C] after the second sub-step
+  uint64_t off;             // element offset of the job's limb
+  uint32_t q, qinv;
+};
+hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
+                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, hipStream_t s);
+// Whether (log_r, log_c1, log_n - log_r - log_c1) is a split the row kernels implement.
+bool rows_split_supported(int log_n, int log_r, int log_c1);
 
 // Work-list GEMM step (batch runtime): each task is one limb list of one
 // transform with its own shape and buffers; each tile ref names (task, tm, tn)

@@ -241,7 +241,8 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
 // to the idle LDS buffer and stage k+2 is loaded from global memory.  Plain
 // residues are cut into 7-bit chunks on the way into LDS; packed data is
 // copied as is.
-template <int WM, int WN, int MB, int NB, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+template <int WM, int WN, int MB, int NB, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
+          bool PROWS = false>
 __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8_t* lds_b) {
   constexpr int NW = WM * WN;
   constexpr int NT = NW * 64;
@@ -273,7 +274,7 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
   const uint32_t slab_bytes = (uint32_t)(M / 32) * 2048;   // one 64-deep K slab of the whole table
   uint32_t coloff[B_PIECES];
 #pragma unroll
-  for (int i = 0; i < B_PIECES; ++i) coloff[i] = b_piece_offset<RIGHT, IN_PACKED>(t, g, tid + i * NT);
+  for (int i = 0; i < B_PIECES; ++i) coloff[i] = b_piece_offset<RIGHT, IN_PACKED && !PROWS>(t, g, tid + i * NT);
 
   v4i ra[KS][A_PIECES], rb[KS][B_PIECES];
   auto load = [&](int ks) {
@@ -284,7 +285,7 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
       for (int i = 0; i < A_PIECES; ++i)
         ra[sl][i] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs_tab, (tid + i * NT) * 16, k64 * slab_bytes, 0);
 #pragma unroll
-      for (int i = 0; i < B_PIECES; ++i) rb[sl][i] = load_b_piece<RIGHT, IN_PACKED>(rs_src, coloff[i], k64, C);
+      for (int i = 0; i < B_PIECES; ++i) rb[sl][i] = load_b_piece<RIGHT, IN_PACKED && !PROWS>(rs_src, coloff[i], k64, C);
     }
   };
   auto store_lds = [&](int st) {
@@ -344,7 +345,8 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
 // staged form moves 1 KB through LDS per MFMA with 64 x 64 waves, more than the
 // LDS delivers at the MFMA rate; here half of that goes through the vector
 // memory path instead, and the LDS writes shrink to the data operand.
-template <int WA, int WN, int MA, int NBD, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+template <int WA, int WN, int MA, int NBD, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
+          bool PROWS = false>
 __device__ __forceinline__ void gemm_tile_direct(const TileArgs& t, int8_t* lds) {
   constexpr int NT = WA * WN * 64;
   constexpr int BM = WA * MA * 32;
@@ -377,7 +379,7 @@ __device__ __forceinline__ void gemm_tile_direct(const TileArgs& t, int8_t* lds)
   const uint32_t slab_bytes = (uint32_t)(M / 32) * 2048;
   uint32_t coloff[B_PIECES];
 #pragma unroll
-  for (int i = 0; i < B_PIECES; ++i) coloff[i] = b_piece_offset<RIGHT, IN_PACKED>(t, g, tid + i * NT);
+  for (int i = 0; i < B_PIECES; ++i) coloff[i] = b_piece_offset<RIGHT, IN_PACKED && !PROWS>(t, g, tid + i * NT);
 
   v4i fa[2][KS][2][MA];                  // table fragments of two stages
   v4i rb[KS][B_PIECES];
@@ -395,7 +397,7 @@ __device__ __forceinline__ void gemm_tile_direct(const TileArgs& t, int8_t* lds)
 #pragma unroll
     for (int sl = 0; sl < KS; ++sl)
 #pragma unroll
-      for (int i = 0; i < B_PIECES; ++i) rb[sl][i] = load_b_piece<RIGHT, IN_PACKED>(rs_src, coloff[i], ks * KS + sl, C);
+      for (int i = 0; i < B_PIECES; ++i) rb[sl][i] = load_b_piece<RIGHT, IN_PACKED && !PROWS>(rs_src, coloff[i], ks * KS + sl, C);
   };
   auto store_b = [&](int st) {
 #pragma unroll
@@ -485,7 +487,8 @@ __device__ __forceinline__ TileArgs uniform_tile(const GemmLaunch& g, int tiles_
                   job.q, job.qinv, g.npoly, g.log_r, g.log_c, tm * BM, tn * BN};
 }
 
-template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
+          bool PROWS>
 __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   constexpr int BM = WM * MB * 32;
@@ -493,7 +496,7 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   // two LDS stages of operand fragments (A stages then B stages), reused for output staging
   __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
   const TileArgs t = uniform_tile<BM, BN>(g, tiles_m, tiles_n);
-  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds, lds + 2 * BM * 64 * KS);
+  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW, PROWS>(t, lds, lds + 2 * BM * 64 * KS);
 }
 
 // LDS bytes of the direct-table form: two stages of data fragments, or the
@@ -506,14 +509,15 @@ constexpr int direct_lds_bytes() {
   return ops > out ? ops : out;
 }
 
-template <int WA, int WN, int MA, int NBD, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+template <int WA, int WN, int MA, int NBD, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
+          bool PROWS>
 __global__ void __launch_bounds__(WA * WN * 64, OCC)
 bat_gemm_direct_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   constexpr int BM = WA * MA * 32;
   constexpr int BN = WN * NBD * 32;
   __shared__ __attribute__((aligned(1024))) int8_t lds[direct_lds_bytes<WA, WN, MA, NBD, KS, RIGHT, OUT_PACKED>()];
   const TileArgs t = uniform_tile<BM, BN>(g, tiles_m, tiles_n);
-  gemm_tile_direct<WA, WN, MA, NBD, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds);
+  gemm_tile_direct<WA, WN, MA, NBD, KS, RIGHT, IN_PACKED, OUT_PACKED, TW, PROWS>(t, lds);
 }
 
 // Work-list form: tiles of many tasks (mixed N, R x C, primes, buffers) in one
@@ -556,12 +560,12 @@ bool uniform_grid(const GemmLaunch& g, int kdiv, int& tiles_m, int& tiles_n, int
 // LDS-staged tile: WM x WN waves of MB x NB blocks.
 template <int WM, int WN, int MB, int NB, int OCC, int KS = 1>
 struct StagedCfg {
-  template <bool RIGHT, bool INP, bool OUTP, bool TW>
+  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false>
   static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
     constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW>), dim3(grid),
+    hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
                        dim3(WM * WN * 64), 0, s, g, tm, tn);
     return hipGetLastError();
   }
@@ -570,12 +574,12 @@ struct StagedCfg {
 // Direct-table tile: WA x WN waves of MA x NBD blocks, stages of KS slabs, unrolled by two.
 template <int WA, int WN, int MA, int NBD, int OCC, int KS>
 struct DirectCfg {
-  template <bool RIGHT, bool INP, bool OUTP, bool TW>
+  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false>
   static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
     constexpr int BM = WA * MA * 32, BN = WN * NBD * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, 2 * BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((bat_gemm_direct_kernel<WA, WN, MA, NBD, OCC, KS, RIGHT, INP, OUTP, TW>), dim3(grid),
+    hipLaunchKernelGGL((bat_gemm_direct_kernel<WA, WN, MA, NBD, OCC, KS, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
                        dim3(WA * WN * 64), 0, s, g, tm, tn);
     return hipGetLastError();
   }
@@ -592,6 +596,8 @@ hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
     return Cfg::template launch<true, true, false, false>(g, s);
   if (right && !g.in_packed && g.out_packed && g.twiddle)
     return Cfg::template launch<true, false, true, true>(g, s);
+  if (!right && g.in_packed && !g.out_packed && !g.twiddle && g.in_rows)
+    return Cfg::template launch<false, true, false, false, true>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle)
     return Cfg::template launch<false, true, false, false>(g, s);
   return hipErrorInvalidValue;

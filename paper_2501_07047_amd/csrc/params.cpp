@@ -118,7 +118,8 @@ void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
   }
 }
 
-void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, bool with_bat) {
+void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, bool with_bat,
+                      uint32_t log_c1) {
   const uint32_t N = 1u << log_n, R = 1u << log_r, C = N / R, N2 = 2 * N;
   const int log_c = (int)(log_n - log_r);
   const uint32_t psi = root_2n(q, log_n);
@@ -157,6 +158,63 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
   bat_expand(m1, R, R, q, t.fwd_left);
   bat_expand(im1, R, R, q, t.inv_left);
 
+  auto shoup = [&](uint32_t w) { return (uint32_t)(((uint64_t)w << 32) / q); };
+  if (log_c1 > 0) {
+    if (log_c1 >= (uint32_t)log_c) throw std::invalid_argument("three-factor split needs C1 < C");
+    // Row transform split as C1 x C2 (c = c1 C2 + c2, c' = m C2 + c2'):
+    //   TB[m][c1] = psi^(2R C2 c1 brv_C1(m))    (left product over c1: "in" = c1, "out" = m)
+    //   T3[m][c2] = psi^(2R c2 brv_C1(m))       (twiddle, pairs [m][c2])
+    //   TC[c2][c2'] = psi^(2R C1 c2 brv_C2(c2')) (right product over c2: "in" = c2, "out" = c2')
+    // inverse (no scaling; N^-1 is in the step-1 matrix): ITC over c2' then IT3, ITB over m.
+    const uint32_t C1 = 1u << log_c1, C2 = C / C1;
+    const int lc1 = (int)log_c1, lc2 = log_c - (int)log_c1;
+    std::vector<uint32_t> tb((size_t)C1 * C1), itb((size_t)C1 * C1), tc((size_t)C2 * C2), itc((size_t)C2 * C2);
+    for (uint32_t c1 = 0; c1 < C1; ++c1)
+      for (uint32_t m = 0; m < C1; ++m) {
+        const int64_t e = 2 * (int64_t)R * C2 * c1 * bitrev(m, lc1);
+        tb[(size_t)c1 * C1 + m] = P(e);      // in c1, out m
+        itb[(size_t)m * C1 + c1] = P(-e);    // in m, out c1
+      }
+    for (uint32_t c2 = 0; c2 < C2; ++c2)
+      for (uint32_t cp = 0; cp < C2; ++cp) {
+        const int64_t e = 2 * (int64_t)R * C1 * c2 * bitrev(cp, lc2);
+        tc[(size_t)c2 * C2 + cp] = P(e);     // in c2, out c2'
+        itc[(size_t)cp * C2 + c2] = P(-e);   // in c2', out c2
+      }
+    bat_expand(tb, C1, C1, q, t.row_fwd_b);
+    bat_expand(tc, C2, C2, q, t.row_fwd_c);
+    bat_expand(itc, C2, C2, q, t.row_inv_c);
+    bat_expand(itb, C1, C1, q, t.row_inv_b);
+    t.row_fwd_t3.resize((size_t)2 * C);
+    t.row_inv_t3.resize((size_t)2 * C);
+    for (uint32_t m = 0; m < C1; ++m)
+      for (uint32_t c2 = 0; c2 < C2; ++c2) {
+        const int64_t e = 2 * (int64_t)R * c2 * bitrev(m, lc1);
+        const uint32_t wf = P(e), wi = P(-e);
+        const size_t f = 2 * ((size_t)m * C2 + c2);
+        t.row_fwd_t3[f] = wf;
+        t.row_fwd_t3[f + 1] = shoup(wf);
+        t.row_inv_t3[f] = wi;
+        t.row_inv_t3[f + 1] = shoup(wi);
+      }
+    // step-2 twiddles: forward [k][c] as in the two-factor form; the inverse ones
+    // row-major too (applied by the row kernel's last epilogue)
+    t.fwd_tw.resize((size_t)2 * R * C);
+    t.inv_tw_rows.resize((size_t)2 * R * C);
+    for (uint32_t k = 0; k < R; ++k) {
+      int64_t odd = 2 * (int64_t)bitrev(k, (int)log_r) + 1;
+      for (uint32_t c = 0; c < C; ++c) {
+        const uint32_t wf = P((int64_t)c * odd), wi = P(-(int64_t)c * odd);
+        const size_t f = 2 * ((size_t)k * C + c);
+        t.fwd_tw[f] = wf;
+        t.fwd_tw[f + 1] = shoup(wf);
+        t.inv_tw_rows[f] = wi;
+        t.inv_tw_rows[f + 1] = shoup(wi);
+      }
+    }
+    return;
+  }
+
   // Step-3 matrix TF3[c][c'] = psi^(2R c brv_C(c')): out[k][c'] = sum_c Y[k][c] TF3[c][c'],
   // "in" = c, "out" = c'.  Inverse step 1: Y[k][c] = sum_c' Ahat[k][c'] ITF3[c'][c].
   std::vector<uint32_t> m3((size_t)C * C), im3((size_t)C * C);
@@ -176,7 +234,6 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
   // (w, floor(w * 2^32 / q)) for Shoup multiplication.
   t.fwd_tw.resize((size_t)2 * R * C);
   t.inv_tw.resize((size_t)2 * R * C);
-  auto shoup = [&](uint32_t w) { return (uint32_t)(((uint64_t)w << 32) / q); };
   for (uint32_t k = 0; k < R; ++k) {
     int64_t odd = 2 * (int64_t)bitrev(k, (int)log_r) + 1;
     for (uint32_t c = 0; c < C; ++c) {

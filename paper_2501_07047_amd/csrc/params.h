@@ -40,8 +40,15 @@ struct NttTables {
   std::vector<uint32_t> fwd_tw, inv_tw;      // (w, floor(w 2^32 / q)) pairs for Shoup multiplication
   std::vector<uint32_t> bf_fwd, bf_inv;      // butterfly twiddles, Montgomery form
   uint32_t bf_ninv;                          // N^-1 * 2^32 mod q (butterfly inverse scale)
+  // three factors (row transform split as C1 x C2): BAT tables of the two row
+  // sub-steps and their twiddle pairs, plus the inverse step-2 twiddles row-major
+  std::vector<int8_t> row_fwd_b, row_fwd_c, row_inv_c, row_inv_b;
+  std::vector<uint32_t> row_fwd_t3, row_inv_t3, inv_tw_rows;
 };
 // with_bat = false builds only the butterfly twiddles (sizes below the MFMA minimum).
-void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, bool with_bat = true);
+// log_c1 > 0 selects the three-factor form: the C-point row transform is split as
+// C1 x C2 (C1 = 2^log_c1) and the C x C step-3 tables are not built.
+void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, bool with_bat = true,
+                      uint32_t log_c1 = 0);
 
 }  // namespace cross

@@ -172,3 +172,71 @@ def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
     finally:
         for log_n in (12, 13):
             B.set_ntt_split(log_n, log_n // 2)
+
+
+@pytest.mark.parametrize("log_n,log_r,log_c1,L,batch", [(13, 5, 4, 2, 1), (14, 6, 4, 3, 2), (15, 5, 5, 2, 1),
+                                                        (16, 6, 5, 3, 2), (16, 4, 6, 1, 1), (16, 8, 4, 2, 1)])
+def test_three_factor_ntt_matches_oracle(log_n, log_r, log_c1, L, batch):
+    from paper_2501_07047_amd import binding as B
+    B.set_ntt_split3(log_n, log_r, log_c1)
+    try:
+        primes, x = synthetic.ntt_batch(200 + log_n + log_c1, log_n, L, batch)
+        ref = _oracle_ntt(x, primes)
+        d = to_dev(x)
+        B.ntt_forward(d, primes)
+        assert np.array_equal(to_host(d), ref)
+        B.ntt_inverse(d, primes)
+        assert np.array_equal(to_host(d), x)
+    finally:
+        B.set_ntt_split3(log_n, 0, 0)
+
+
+def test_three_factor_full_size_spot_checks_and_ckks():
+    # the benchmarked shape (N = 2^16, L = 24, 16 polynomials) with R x C1 x C2 = 64 x 32 x 32:
+    # Horner spot checks of every limb, exact inverse, and HE-Mult through the same split
+    from oracle import ckks as CK
+    from oracle.ntt import horner_eval
+    from oracle.primes import psi as psi_of
+    from paper_2501_07047_amd import binding as B
+    B.set_ntt_split3(16, 6, 5)
+    try:
+        primes, x = synthetic.ntt_batch(0, 16, 24, 16)
+        d = to_dev(x)
+        B.ntt_forward(d, primes)
+        got = to_host(d)
+        g = np.random.Generator(np.random.PCG64(5))
+        n = 1 << 16
+        for b in (0, 15):
+            for i, q in enumerate(primes):
+                psi = psi_of(q, n)
+                for p in g.integers(0, n, 4):
+                    e = (2 * int(bitrev_int(int(p), 16)) + 1)
+                    assert int(got[b, i, p]) == int(horner_eval(x[b, i], q, [pow(psi, e, q)])[0])
+        B.ntt_inverse(d, primes)
+        assert np.array_equal(to_host(d), x)
+        qs, ps, a, bb, key = synthetic.ckks_pair(3, 16, 24, 3, 8, 1)
+        out = torch_empty(a.shape)
+        B.he_mult(to_dev(a), to_dev(bb), to_dev(key), out, qs, ps, 3)
+        assert np.array_equal(to_host(out)[0], CK.he_mult(a[0], bb[0], key, qs, ps, 3))
+    finally:
+        B.set_ntt_split3(16, 0, 0)
+
+
+def bitrev_int(v, bits):
+    r = 0
+    for _ in range(bits):
+        r = (r << 1) | (v & 1)
+        v >>= 1
+    return r
+
+
+def torch_empty(shape):
+    import torch
+    return torch.empty(shape, dtype=torch.int32, device="cuda")
+
+
+def test_three_factor_split_errors():
+    from paper_2501_07047_amd import binding as B
+    for bad in ((12, 4, 4), (16, 6, 3), (16, 3, 6)):
+        with pytest.raises(B.CrossError):
+            B.set_ntt_split3(*bad)

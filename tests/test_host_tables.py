@@ -120,3 +120,65 @@ def test_bat_lazy_fragment_returns_each_lanes_chunk_products_in_lane():
                 assert regs[4 * t:4 * t + 4] == T
                 lazy = (int(p[l, t]) & 0x0fffffff) + sum(T[k] << (7 * k) for k in range(4))
                 assert lazy == bat_lazy_reduce(int(p[l, t]), q) and lazy % q == int(p[l, t]) % q
+
+
+def _emulate3(X, q, log_n, log_r, log_c1, inverse):
+    # three factors: the row-side step with the library's step-1 tables, then the
+    # row transform with its row tables (cross_host_row_tables), in the kernels'
+    # operand roles; Montgomery factors as in _emulate
+    from paper_2501_07047_amd import binding
+    R = 1 << log_r
+    C1 = 1 << log_c1
+    C = (1 << log_n) // R
+    C2 = C // C1
+    rinv = pow(1 << 32, -1, q)
+
+    def mont(pairs):
+        return (pairs[..., 0].astype(object) * (1 << 32)) % q
+
+    def twist(Y, tw):
+        return np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
+
+    rt = lambda w: binding.host_row_tables(q, log_n, log_r, log_c1, w)
+    if not inverse:
+        t1 = _dense(binding.host_tables(q, log_n, log_r, 0), 4 * R, 4 * R)
+        Y = twist(_merge_reduce(t1 @ _chunks_rows(X.reshape(R, C)), q), mont(rt(7).reshape(R, C, 2)))
+        tb, tc = _dense(rt(0), 4 * C1, 4 * C1), _dense(rt(1), 4 * C2, 4 * C2)
+        t3 = mont(rt(4).reshape(C1, C2, 2))
+        out = np.empty((R, C), dtype=np.uint64)
+        for k in range(R):
+            Z = twist(_merge_reduce(tb @ _chunks_rows(Y[k].reshape(C1, C2)), q), t3)     # [m][c2]
+            out[k] = _merge_reduce(tc @ _chunks_rows(Z.T), q).T.reshape(-1)             # [m][c2']
+        return out.reshape(-1)
+    itc, itb = _dense(rt(2), 4 * C2, 4 * C2), _dense(rt(3), 4 * C1, 4 * C1)
+    it3 = mont(rt(5).reshape(C1, C2, 2))
+    it2 = mont(rt(6).reshape(R, C, 2))
+    X = X.reshape(R, C1, C2)
+    Y = np.empty((R, C), dtype=np.uint64)
+    for k in range(R):
+        Z = twist(_merge_reduce(itc @ _chunks_rows(X[k].T), q), it3.T)                   # [c2][m]
+        Yk = _merge_reduce(itb @ _chunks_rows(Z.T), q)                                   # [c1][c2]
+        Y[k] = twist(Yk.reshape(-1), it2[k])
+    t1 = _dense(binding.host_tables(q, log_n, log_r, 2), 4 * R, 4 * R)
+    return _merge_reduce(t1 @ _chunks_rows(Y), q).reshape(-1)
+
+
+@pytest.mark.parametrize("log_n,log_r,log_c1", [(13, 5, 4), (14, 6, 4), (15, 5, 5), (16, 6, 5), (14, 4, 5)])
+def test_emulated_three_factor_ntt_matches_oracle(log_n, log_r, log_c1):
+    n = 1 << log_n
+    q = prime_chain(1)[0]
+    psi = psi_of(q, n)
+    g = np.random.Generator(np.random.PCG64(log_n * 11 + log_c1))
+    a = g.integers(0, q, n).astype(np.uint64)
+    a[0] = q - 1
+    ref = ntt_ct(a, q, psi)
+    assert np.array_equal(_emulate3(a, q, log_n, log_r, log_c1, False), ref)
+    assert np.array_equal(_emulate3(ref, q, log_n, log_r, log_c1, True), a)
+
+
+def test_row_split_limits():
+    from paper_2501_07047_amd import binding
+    q = prime_chain(1)[0]
+    for bad in ((12, 4, 4), (16, 6, 3), (16, 3, 6), (16, 4, 7)):     # R*C < 8192, C1 < 16, R < 16, C1 > 64
+        with pytest.raises(binding.CrossError):
+            binding.host_row_tables(q, *bad, 0)
