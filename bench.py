@@ -24,7 +24,7 @@ METRIC = "N=2^16 NTTs/sec and HE-Mult/s, int8-MFMA vs butterfly, bit-exact"
 INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s
 HBM_PEAK_GBS = 8000.0
 
-LOG_N, LOG_R, L, POLYS = 16, 8, 24, 16
+LOG_N, L, POLYS = 16, 24, 16
 
 
 def gemm_ops_per_launch(log_n, log_r, nlimb_polys, kind):
@@ -199,7 +199,8 @@ def uneven_batch_bench(B, replays):
             "speedup_vs_per_job_calls": round(t_eager / t_graph, 3),
             "ciphertexts_per_s": round(64 / t_graph, 1), "launches_per_pass_eager": info["launches"],
             "gemm_tiles_per_pass": info["gemm_tiles"], "replays": replays,
-            "autotuned": {str(k): {"R": 1 << v["log_r"], "C": 1 << (k - v["log_r"]), "tile": v["tile"],
+            "autotuned": {str(k): {"R": 1 << v["log_r"], "C": 1 << (k - v["log_r"]),
+                                   "C1": (1 << v["log_c1"]) if v["log_c1"] else None, "tile": v["tile"],
                                    "ntt_fwd_inv_us_L8_b4": round(v["us"], 1)} for k, v in tuned.items()}}
 
 
@@ -261,7 +262,7 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "launches": args.steps}))
         return
-    B.set_ntt_split(LOG_N, LOG_R)
+    log_r, log_c1 = B.get_ntt_split(LOG_N)       # the library's default factoring of 2^16
     primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
     host = torch.from_numpy(x.view(np.int32))
     data = host.cuda()
@@ -319,30 +320,51 @@ def main():
     value = limb_ntts * args.steps / dt
     bf_value = limb_ntts * bf_steps / dt_bf
 
-    # dominant kernel: the GEMM family with the larger total event time
-    fam = max(("bat_gemm_left", "bat_gemm_right"), key=lambda k: prof.get(k, (0, 0.0))[1])
-    launches, total_ms = prof.get(fam, (1, float("nan")))
+    # dominant kernel: the family with the largest total event time
+    fam = max((k for k in prof if k in ("bat_gemm_left", "bat_gemm_right", "ntt_rows")),
+              key=lambda k: prof[k][1])
+    launches, total_ms = prof[fam]
     avg_s = total_ms / 1e3 / max(1, launches)
-    ops = gemm_ops_per_launch(LOG_N, LOG_R, L * POLYS, "left" if fam.endswith("left") else "right")
-    achieved = ops / avg_s / 1e12
-    khash = source_hash("ntt_mfma.hip")
+    npolys = L * POLYS
+    n = 1 << LOG_N
     measured_peak = {"mfma_i8_tops": round(B.measure_peak("mfma_i8_32x32"), 1),
                      "hbm_copy_gbs": round(B.measure_peak("hbm_copy"), 1)}
-    roof = {"bound": "mfma", "kernel": fam, "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
-            "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4),
-            "traffic": traffic_for(fam, khash), "avg_launch_us": round(avg_s * 1e6, 2),
-            "ops_per_launch": ops, "launches_timed": launches, "measured_peaks": measured_peak,
-            "frac_of_measured_mfma_peak": round(achieved / measured_peak["mfma_i8_tops"], 4),
-            "event_ms_by_kernel": {k: [v[0], round(v[1], 3)] for k, v in prof.items()}}
+    if fam == "ntt_rows":
+        # row transform of every row (C1 x C2 split): HBM-bound.  Per launch: every residue
+        # read and written once, the two row tables and the C-entry twiddle pairs per prime,
+        # and (inverse launches, half of them) the N-entry inverse step-2 twiddle pairs.
+        c = 1 << (LOG_N - log_r)
+        c1, c2 = 1 << log_c1, c // (1 << log_c1)
+        nbytes = npolys * n * 8 + L * (16 * c1 * c1 + 16 * c2 * c2 + 8 * c) + L * n * 8 // 2
+        ops = 32.0 * n * (c1 + c2) * npolys
+        achieved = nbytes / avg_s / 1e9
+        khash = source_hash("ntt_rows.hip")
+        roof = {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(fam, khash),
+                "bytes_per_launch": nbytes, "int8_ops_per_launch": ops,
+                "int8_tops": round(ops / avg_s / 1e12, 1),
+                "frac_of_measured_copy": round(achieved / measured_peak["hbm_copy_gbs"], 4)}
+    else:
+        ops = gemm_ops_per_launch(LOG_N, log_r, npolys, "left" if fam.endswith("left") else "right")
+        achieved = ops / avg_s / 1e12
+        khash = source_hash("ntt_mfma.hip")
+        roof = {"bound": "mfma", "kernel": fam, "achieved": round(achieved, 2), "peak": INT8_PEAK_TOPS,
+                "unit": "TOP/s", "frac": round(achieved / INT8_PEAK_TOPS, 4), "traffic": traffic_for(fam, khash),
+                "ops_per_launch": ops,
+                "frac_of_measured_mfma_peak": round(achieved / measured_peak["mfma_i8_tops"], 4)}
+    roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "launches_timed": launches,
+                 "measured_peaks": measured_peak,
+                 "event_ms_by_kernel": {k: [v[0], round(v[1], 3)] for k, v in prof.items()}})
 
     line = {"metric": METRIC, "value": round(value, 1), "unit": "limb-NTT/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i8",
             "data": "synthetic",
-            "config": {"workload": "NTT+INTT, N=2^16 as 256x256, L=24 28-bit primes, "
-                                   "8 ciphertexts x 2 polys (384 limb-NTTs each way)",
-                       "log_n": LOG_N, "R": 1 << LOG_R, "C": 1 << (LOG_N - LOG_R), "L": L,
-                       "polys": POLYS},
+            "config": {"workload": "NTT+INTT, N=2^16, L=24 28-bit primes, 8 ciphertexts x 2 polys "
+                                   "(384 limb-NTTs each way)",
+                       "log_n": LOG_N, "R": 1 << log_r, "C1": 1 << log_c1 if log_c1 else None,
+                       "C2": (1 << (LOG_N - log_r - log_c1)) if log_c1 else None,
+                       "C": 1 << (LOG_N - log_r), "L": L, "polys": POLYS},
             "poly_ntt_per_s": round(value / L, 1),
             "butterfly_limb_ntt_per_s": round(bf_value, 1),
             "speedup_vs_butterfly": round(value / bf_value, 3),
@@ -368,7 +390,6 @@ def main():
                       "batch8": he8["he_add"], "bytes_per_op": add_bytes,
                       "hbm_gbs_batch8": round(add_bytes * he8["he_add"]["per_s"] / 1e9, 1)}
     line["uneven_batch"] = uneven_batch_bench(B, max(4, args.steps // 2))
-    B.set_ntt_split(LOG_N, LOG_R)
     line["serving"] = serving_bench(200)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

@@ -73,24 +73,34 @@ cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r);
  * step 3 split once more as C1 x C2 (C1 = 2^log_c1) -- same input/output layout
  * and bit-reversed order as the two-factor form, about (R + C1 + C2) / (R + C)
  * of its int8 MAC work.  Needs 16 <= C1, C2 <= 64, R >= 16 and R * C1 * C2 >=
- * 8192 (the row kernel takes 8192 / C rows per workgroup).  log_c1 = 0 returns
- * log_n to the two-factor form.  Applies to cross_ntt_forward/inverse, the CKKS
- * entry points and cross_poly_mul; the batch runtime keeps two factors.
+ * 8192 (the row kernel takes 8192 / C rows per workgroup).  log_c1 = 0 with
+ * log_r > 0 selects the two-factor form with R = 2^log_r; log_r = log_c1 = 0
+ * restores the size's default (three factors R x C1 x C2 = 2^5 x 2^4 x 2^4,
+ * 2^5 x 2^5 x 2^4, 2^6 x 2^5 x 2^4, 2^6 x 2^5 x 2^5 for log_n = 13, 14, 15, 16;
+ * two factors below).  cross_set_ntt_split also selects two factors.  Applies
+ * to cross_ntt_forward/inverse, the CKKS entry points and cross_poly_mul; the
+ * batch runtime keeps two factors.
  * Errors: CROSS_EINVAL for an unsupported split.
  */
 cross_status cross_set_ntt_split3(cross_ctx ctx, uint32_t log_n, uint32_t log_r, uint32_t log_c1);
+/* The split cross_ntt_forward uses for size 2^log_n on ctx: *log_c1 = 0 for two
+ * factors (8 <= log_n <= 16; sizes below 2^8 run on the butterfly kernels). */
+cross_status cross_get_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t* log_r, uint32_t* log_c1);
 
 /* Autotuner: time forward + inverse NTTs of `batch` x L limbs of size 2^log_n
- * (8 <= log_n <= 16) for every split R = 2^log_r with 4 <= log_r <= log_n - 4
- * within a factor of four of square, and R, C >= 64 from log_n = 12 up so the
- * batch runtime can use the result (the paper sweeps (R, C) and keeps the
- * best), and every GEMM tile; keep the fastest on this context for that size
- * (as cross_set_ntt_split plus a per-size tile).  If cache_path is non-NULL a
- * matching line "<device> <log_n> <L> <batch> <log_r> <tile> <us>" is reused
- * without timing, else the new choice is appended.  Any out pointer may be NULL.
- * Allocates batch*L*N*4 bytes of scratch while timing; synchronises the device. */
+ * (8 <= log_n <= 16) for every two-factor split R = 2^log_r within a factor of
+ * four of square (R, C >= 64 from log_n = 12 up, so the batch runtime can use
+ * it) with every GEMM tile, and every three-factor split R x C1 x C2 with
+ * 16 <= C1, C2 <= 32 (the paper sweeps (R, C) and keeps the best); keep the
+ * fastest on this context for that size (as cross_set_ntt_split3 plus a
+ * per-size tile; the best two-factor split also becomes the batch runtime's).
+ * *log_c1_out = 0 reports a two-factor choice.  If cache_path is non-NULL a
+ * matching line "<device> <log_n> <L> <batch> <log_r> <log_c1> <tile> <us>
+ * <two-factor log_r>" is reused without timing, else the new choice is
+ * appended.  Any out pointer may be NULL.  Allocates batch*L*N*4 bytes of
+ * scratch while timing; synchronises the device. */
 cross_status cross_autotune(cross_ctx ctx, uint32_t log_n, uint32_t L, uint32_t batch, const char* cache_path,
-                            uint32_t* log_r_out, int* tile_out, double* us_out);
+                            uint32_t* log_r_out, uint32_t* log_c1_out, int* tile_out, double* us_out);
 
 /* Workgroup tile of the BAT int8 GEMM steps on this context (autotuner knob):
  * 0 = automatic (by shape and grid size), 1 = 256x256 (8 waves of 128x64),

@@ -39,8 +39,9 @@ SIGNATURES = {
     "cross_set_ntt_split": [c_vp, c_u32, c_u32],
     "cross_set_gemm_tile": [c_vp, ctypes.c_int],
     "cross_set_ntt_split3": [c_vp, c_u32, c_u32, c_u32],
+    "cross_get_ntt_split": [c_vp, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)],
     "cross_host_row_tables": [c_u32, c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
-    "cross_autotune": [c_vp, c_u32, c_u32, c_u32, ctypes.c_char_p, ctypes.POINTER(c_u32),
+    "cross_autotune": [c_vp, c_u32, c_u32, c_u32, ctypes.c_char_p, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32),
                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)],
     "cross_ntt_forward": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
     "cross_ntt_inverse": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp],
@@ -152,6 +153,14 @@ def set_ntt_split3(log_n, log_r, log_c1, device=None):
     _check(lib().cross_set_ntt_split3(ctx, log_n, log_r, log_c1), ctx)
 
 
+def get_ntt_split(log_n, device=None):
+    """(log_r, log_c1) used for 2^log_n transforms on this context (log_c1 = 0: two factors)."""
+    ctx = context(device)
+    r, c1 = c_u32(), c_u32()
+    _check(lib().cross_get_ntt_split(ctx, log_n, ctypes.byref(r), ctypes.byref(c1)), ctx)
+    return r.value, c1.value
+
+
 def host_row_tables(q, log_n, log_r, log_c1, which):
     """Copy one three-factor row table into a numpy array (host only, no GPU)."""
     import numpy as np
@@ -173,13 +182,14 @@ def set_gemm_tile(tile, device=None):
 
 
 def autotune(log_n, L=8, batch=8, cache_path=None, device=None):
-    """Time the candidate splits and tiles for 2^log_n transforms and keep the best
-    on the context; returns {"log_r", "tile", "us"} (see cross_autotune)."""
+    """Time the candidate factorings and tiles for 2^log_n transforms and keep the best
+    on the context; returns {"log_r", "log_c1", "tile", "us"} (see cross_autotune)."""
     ctx = context(device)
-    r, t, us = c_u32(), ctypes.c_int(), ctypes.c_double()
+    r, c1, t, us = c_u32(), c_u32(), ctypes.c_int(), ctypes.c_double()
     path = None if cache_path is None else str(cache_path).encode()
-    _check(lib().cross_autotune(ctx, log_n, L, batch, path, ctypes.byref(r), ctypes.byref(t), ctypes.byref(us)), ctx)
-    return {"log_r": r.value, "tile": t.value, "us": us.value}
+    _check(lib().cross_autotune(ctx, log_n, L, batch, path, ctypes.byref(r), ctypes.byref(c1), ctypes.byref(t),
+                                ctypes.byref(us)), ctx)
+    return {"log_r": r.value, "log_c1": c1.value, "tile": t.value, "us": us.value}
 
 
 def _ntt(fn, data, primes):

@@ -128,9 +128,9 @@ cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan
   key += std::to_string(prm->log_n) + "/" + std::to_string(L) + "/" + std::to_string(K) + "/" +
          std::to_string(dnum) + "/" + std::to_string(split_of(ctx, (int)prm->log_n));
   {
-    auto s3 = ctx->split3.find((int)prm->log_n);
-    if (s3 != ctx->split3.end())
-      key += "/" + std::to_string(s3->second.first) + "x" + std::to_string(s3->second.second);
+    int lr = 0, lc1 = 0;
+    effective_split(ctx, (int)prm->log_n, true, &lr, &lc1);
+    key += "/" + std::to_string(lr) + "x" + std::to_string(lc1);
   }
   auto it = ctx->ext_plans.find(key);
   if (it != ctx->ext_plans.end()) {

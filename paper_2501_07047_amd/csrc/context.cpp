@@ -48,16 +48,37 @@ static cross_status dev_alloc(cross_ctx ctx, size_t bytes, void** out) {
   return CROSS_OK;
 }
 
-cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3) {
-  int log_r = (log_n >= 8) ? split_of(ctx, log_n) : 0;
-  int log_c1 = 0;
-  if (allow3) {
-    auto s3 = ctx->split3.find(log_n);
-    if (s3 != ctx->split3.end()) {
-      log_r = s3->second.first;
-      log_c1 = s3->second.second;
-    }
+bool default_split3(int log_n, int* log_r, int* log_c1) {
+  // measured fastest three-factor splits (N = 2^13 .. 2^16, 24 limbs x 16 polynomials)
+  switch (log_n) {
+    case 13: *log_r = 5; *log_c1 = 4; return true;
+    case 14: *log_r = 5; *log_c1 = 5; return true;
+    case 15: *log_r = 6; *log_c1 = 5; return true;
+    case 16: *log_r = 6; *log_c1 = 5; return true;
+    default: return false;
   }
+}
+
+void effective_split(cross_ctx ctx, int log_n, bool allow3, int* log_r, int* log_c1) {
+  *log_r = (log_n >= 8) ? split_of(ctx, log_n) : 0;
+  *log_c1 = 0;
+  if (!allow3 || log_n < 8) return;
+  auto s3 = ctx->split3.find(log_n);
+  if (s3 != ctx->split3.end()) {
+    *log_r = s3->second.first;
+    *log_c1 = s3->second.second;
+    return;
+  }
+  int r = 0, c1 = 0;
+  if (default_split3(log_n, &r, &c1)) {
+    *log_r = r;
+    *log_c1 = c1;
+  }
+}
+
+cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3) {
+  int log_r = 0, log_c1 = 0;
+  effective_split(ctx, log_n, allow3, &log_r, &log_c1);
   auto key = std::make_tuple(q, log_n, log_r, log_c1);
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end()) {
@@ -401,19 +422,36 @@ cross_status cross_set_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t log_r) 
   if (log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4 || log_r > log_n)
     return fail(ctx, CROSS_EINVAL, "split needs 4 <= log_r <= log_n - 4");
   ctx->split[(int)log_n] = (int)log_r;
+  ctx->split3[(int)log_n] = std::make_pair((int)log_r, 0);    // explicitly two factors
   return CROSS_OK;
 }
 
 cross_status cross_set_ntt_split3(cross_ctx ctx, uint32_t log_n, uint32_t log_r, uint32_t log_c1) {
   if (!ctx) return CROSS_EINVAL;
   if (log_n < 8 || log_n > CROSS_MAX_LOG_N) return fail(ctx, CROSS_EINVAL, "log_n out of range");
-  if (log_c1 == 0) {
+  if (log_c1 == 0 && log_r == 0) {          // back to the size's default
     ctx->split3.erase((int)log_n);
+    return CROSS_OK;
+  }
+  if (log_c1 == 0) {                        // two factors with R = 2^log_r
+    if (log_r < 4 || log_r > log_n || log_n - log_r < 4)
+      return fail(ctx, CROSS_EINVAL, "split needs 4 <= log_r <= log_n - 4");
+    ctx->split3[(int)log_n] = std::make_pair((int)log_r, 0);
     return CROSS_OK;
   }
   if (log_r > log_n || !rows_split_supported((int)log_n, (int)log_r, (int)log_c1))
     return fail(ctx, CROSS_EINVAL, "three-factor split needs 16 <= C1, C2 <= 64 and R >= max(16, 8192 / (C1 C2))");
   ctx->split3[(int)log_n] = std::make_pair((int)log_r, (int)log_c1);
+  return CROSS_OK;
+}
+
+cross_status cross_get_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t* log_r, uint32_t* log_c1) {
+  if (!ctx || !log_r || !log_c1) return CROSS_EINVAL;
+  if (log_n < 8 || log_n > CROSS_MAX_LOG_N) return fail(ctx, CROSS_EINVAL, "log_n out of range");
+  int r = 0, c1 = 0;
+  effective_split(ctx, (int)log_n, true, &r, &c1);
+  *log_r = (uint32_t)r;
+  *log_c1 = (uint32_t)c1;
   return CROSS_OK;
 }
 

@@ -56,7 +56,8 @@ struct cross_ctx_s {
   std::map<std::string, void*> job_cache;     // serialised job list -> device copy
   std::map<hipStream_t, cross::DevBuf> workspace;
   std::map<int, int> split;                   // log_n -> log_r override (two factors)
-  std::map<int, std::pair<int, int>> split3;  // log_n -> (log_r, log_c1): three factors
+  std::map<int, std::pair<int, int>> split3;  // log_n -> (log_r, log_c1); log_c1 = 0: two factors
+                                              // (absent: the size's default)
   int gemm_tile = 0;                          // GemmTile override (0 = auto)
   std::map<int, int> tile_by_logn;            // autotuned GemmTile per transform size
   std::map<std::string, void*> const_cache;   // other device-resident constants
@@ -77,6 +78,8 @@ cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n);
 // (the batch runtime's work lists implement two factors only).
 cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3 = true);
 int split_of(cross_ctx ctx, int log_n);
+// The (log_r, log_c1) get_plan uses for size 2^log_n (log_c1 = 0: two factors).
+void effective_split(cross_ctx ctx, int log_n, bool allow3, int* log_r, int* log_c1);
 // Device copy of a POD array, cached by content.
 cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, void** out);
 // Per-stream scratch of at least `bytes`.

@@ -130,7 +130,7 @@ def test_every_tile_shape_is_bit_exact(tile):
     # columns per polynomial on the row side, so 3 polynomials leave a ragged
     # last column tile; 16 / 10 and 16 / 6 put a 1024-input contraction (the
     # 64-bit ChunkMerge) on either side.
-    cases = ((16, None, 2, 3), (12, None, 3, 2), (10, None, 2, 1), (14, None, 3, 1),
+    cases = ((16, 8, 2, 3), (12, None, 3, 2), (10, None, 2, 1), (14, None, 3, 1),
              (13, 7, 3, 1), (16, 10, 1, 1), (16, 6, 1, 1))
     try:
         for log_n, log_r, L, batch in cases:
@@ -149,6 +149,7 @@ def test_every_tile_shape_is_bit_exact(tile):
         B.set_gemm_tile(0)
         for log_n in (13, 16):
             B.set_ntt_split(log_n, log_n // 2)
+            B.set_ntt_split3(log_n, 0, 0)
 
 
 def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
@@ -157,10 +158,15 @@ def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
     try:
         for log_n in (12, 13):
             res = B.autotune(log_n, L=2, batch=2, cache_path=cache)
-            assert 4 <= res["log_r"] <= log_n - 4 and 1 <= res["tile"] <= 9 and res["us"] > 0
+            if res["log_c1"]:       # three factors: row-side tile automatic
+                assert log_n >= 13 and res["tile"] == 0 and 4 <= res["log_c1"] <= 5
+            else:
+                assert 4 <= res["log_r"] <= log_n - 4 and 1 <= res["tile"] <= 9
+            assert res["us"] > 0
+            assert B.get_ntt_split(log_n) == (res["log_r"], res["log_c1"])
             again = B.autotune(log_n, L=2, batch=2, cache_path=cache)
             # served from the cache file (microseconds are stored to 3 decimals)
-            assert (again["log_r"], again["tile"]) == (res["log_r"], res["tile"])
+            assert (again["log_r"], again["log_c1"], again["tile"]) == (res["log_r"], res["log_c1"], res["tile"])
             assert abs(again["us"] - res["us"]) < 1e-2
             primes, x = synthetic.ntt_batch(log_n, log_n, 3, 2)
             ref = _oracle_ntt(x, primes)
@@ -168,10 +174,11 @@ def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
             B.ntt_forward(d, primes)
             assert np.array_equal(to_host(d), ref)
         lines = cache.read_text().strip().splitlines()
-        assert len(lines) == 2 and all(len(l.split()) == 7 for l in lines)
+        assert len(lines) == 2 and all(len(l.split()) == 9 for l in lines)
     finally:
         for log_n in (12, 13):
             B.set_ntt_split(log_n, log_n // 2)
+            B.set_ntt_split3(log_n, 0, 0)
 
 
 @pytest.mark.parametrize("log_n,log_r,log_c1,L,batch", [(13, 5, 4, 2, 1), (14, 6, 4, 3, 2), (15, 5, 5, 2, 1),
