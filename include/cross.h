@@ -392,7 +392,8 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
  *   which 0/1 : int8 BAT tables of the forward row sub-steps, TB (over c1, 4C1 x 4C1)
  *               and TC (over c2, 4C2 x 4C2), in the fragment order of cross_host_tables
  *   which 2/3 : the inverse ones, ITC (over c2', first) and ITB (over m, second)
- *   which 4/5 : uint32 (w, floor(w*2^32/q)) pairs of T3 / IT3, [C1][C2][2]
+ *   which 4/5 : uint32 (w, floor(w*2^32/q)) pairs of T3, [C1][C2][2] (m, c2), and of
+ *               IT3, [C2][C1][2] (c2, m)
  *   which 6/7 : uint32 pairs of the inverse / forward step-2 twiddles, row-major [R][C][2]
  */
 cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,

@@ -11,12 +11,16 @@
 // epilogue as the step GEMMs (ChunkMerge, REDC with the Montgomery factor folded
 // into the tables, Shoup twiddle, one conditional subtraction, 7-bit packing).
 //
-// One workgroup (8 waves) takes BR = 8192 / C rows of one polynomial and prime:
-// the input rows are read once from HBM, the intermediate Z lives in LDS, and
-// the output rows are staged in LDS and written back as 16-byte row segments.
-// Each wave owns whole 32-column blocks of a sub-step (all of its M rows), so a
-// B fragment is loaded once; table fragments (16 KB per table at C1 = 32) are
-// read from global memory in fragment order and stay in L1 / L2.
+// One workgroup (kRowsWaves waves) takes kRowsWaves * 1024 / C rows of one
+// polynomial and prime: the input rows are read once from HBM, the intermediate
+// Z lives in LDS, and the output rows are staged in LDS (over Z) and written
+// back as 16-byte row segments.  Each wave owns whole 32-column blocks of a
+// sub-step (all of its M rows), so a B fragment is loaded once.  The two
+// tables (16 C1^2 and 16 C2^2 bytes in fragment order) and the first
+// epilogue's twiddle pairs are copied into LDS once per workgroup with 16-byte
+// loads, so the per-wave memory instructions are the data rows alone (plus the
+// inverse step-2 twiddles); only at C1 = C2 = 64, where the tables do not fit
+// beside the Z tile, are table fragments read from global memory (L1 / L2).
 #include "kernels.h"
 
 namespace cross {
@@ -28,13 +32,24 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef unsigned int v2u __attribute__((ext_vector_type(2)));
 
+constexpr int kRowsWaves = 8;          // waves per workgroup
+constexpr int kLdsBytes = 160 * 1024;  // LDS per CU
+
+// Buffer descriptor of a workgroup-uniform range (base and size are read from
+// the first lane, so the descriptor always lives in SGPRs).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rows_rsrc(const void* base, uint64_t bytes) {
-  const uint32_t n = bytes > 0xfffffff0ull ? 0xfffffff0u : (uint32_t)bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)n, 0x00020000);
+  const uint64_t v = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  const uint32_t n = __builtin_amdgcn_readfirstlane(bytes > 0xfffffff0ull ? 0xfffffff0u : (uint32_t)bytes);
+  void* p = reinterpret_cast<void*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(p, 0, (int)n, 0x00020000);
 }
 
 __device__ __forceinline__ uint32_t pack7(uint32_t x) {
-  return (x & 0x7fu) | ((x << 1) & 0x7f00u) | ((x << 2) & 0x7f0000u) | ((x << 3) & 0x7f000000u);
+  // (x & 0x7f) | (x & 0x3f80) << 1 | (x & 0x1fc000) << 2 | (x & 0xfe00000) << 3, as
+  // x plus each chunk times 2^i - 1
+  return x + (x & ~0x7fu) + ((x & ~0x3fffu) << 1) + ((x & ~0x1fffffu) << 2);
 }
 
 // ChunkMerge of register group j (the four chunk sums of one output) and REDC:
@@ -54,11 +69,31 @@ __device__ __forceinline__ uint32_t shoup_tw(uint32_t r, v2u tw, uint32_t q) {
   return v >= q ? v - q : v;
 }
 
+// Table fragment sources: LDS (staged once per workgroup) or global memory.
+struct LdsTab {
+  const int8_t* p;
+  __device__ __forceinline__ v4i operator()(int off) const { return *reinterpret_cast<const v4i*>(p + off); }
+};
+struct GlobalTab {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ v4i operator()(int off) const {
+    return (v4i)__builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+  }
+};
+
+template <bool IN_LDS>
+__device__ __forceinline__ auto table(const int8_t* lds, const int8_t* global, int bytes) {
+  if constexpr (IN_LDS)
+    return LdsTab{lds};
+  else
+    return GlobalTab{rows_rsrc(global, (uint64_t)bytes)};
+}
+
 // acc[mb] = sum over KS K-steps of table fragment (mb, ks) x B fragment bfrag(ks):
-// the M x K table (M = 32 MB) is in fragment order, fragment (mb, ks) at
+// the M x K table (M = 32 MB) is in fragment order, fragment (mb, ks) at byte
 // ((ks / 2) * MB + mb) * 2048 + (ks % 2) * 1024, 16 bytes per lane.
-template <int MB, int KS, class BF>
-__device__ __forceinline__ void block_gemm(v16i (&acc)[MB], __amdgpu_buffer_rsrc_t tab, int lane, BF bfrag) {
+template <int MB, int KS, class TAB, class BF>
+__device__ __forceinline__ void block_gemm(v16i (&acc)[MB], const TAB& tab, int lane, BF bfrag) {
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb) acc[mb] = v16i{};
 #pragma unroll
@@ -66,27 +101,34 @@ __device__ __forceinline__ void block_gemm(v16i (&acc)[MB], __amdgpu_buffer_rsrc
     const v4i b = bfrag(ks);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb) {
-      const v4i a = (v4i)__builtin_amdgcn_raw_buffer_load_b128(
-          tab, (((ks >> 1) * MB + mb) * 2048 + (ks & 1) * 1024 + lane * 16), 0, 0);
+      const v4i a = tab(((ks >> 1) * MB + mb) * 2048 + (ks & 1) * 1024 + lane * 16);
       acc[mb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[mb], 0, 0, 0);
     }
+    // keep each K-step's table reads next to its products (bounds the registers
+    // held by fragments read ahead)
+    __builtin_amdgcn_sched_group_barrier(0x100, MB, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, MB, 0);
   }
 }
 
 template <int C1, int C2>
 struct RowsShape {
   static constexpr int C = C1 * C2;
-  static constexpr int BR = 8192 / C;           // rows per workgroup (32 KB of residues)
-  static constexpr int NT = 512, NW = 8;
+  static constexpr int NW = kRowsWaves, NT = 64 * kRowsWaves;
+  static constexpr int BR = NW * 1024 / C;      // rows per workgroup
   static constexpr int ZP1 = C2 + 4;            // forward Z line [row][m][.] (words, 16-byte rows)
   static constexpr int ZP2 = C1 + 4;            // inverse Z line [row][c2][.]
   static constexpr int XP = C2 + 1;             // output staging line [row][c1 or m][.]
-  static constexpr int ZWORDS = BR * (C1 * ZP1 > C2 * ZP2 ? C1 * ZP1 : C2 * ZP2);
-  static constexpr int XWORDS = BR * C1 * XP;
+  static constexpr int ZA = BR * C1 * ZP1, ZB = BR * C2 * ZP2, XW = BR * C1 * XP;
+  // Z tile, reused for the output staging once every wave has read it
+  static constexpr int ZWORDS = (ZA > ZB ? ZA : ZB) > XW ? (ZA > ZB ? ZA : ZB) : XW;
   // two workgroups per CU (4 waves per SIMD, at most 128 registers) where the
   // accumulators allow; the 64-wide splits keep more registers at one
   static constexpr int OCC = (C1 <= 32 && C2 <= 32) ? 4 : 2;
-  static_assert(C1 >= 16 && C2 >= 16 && BR >= 1 && 8192 % C == 0, "row split");
+  // both tables in LDS where they fit beside the Z tile and the twiddles
+  static constexpr bool TAB_LDS = 16 * (C1 * C1 + C2 * C2) + 8 * C + 4 * ZWORDS <= kLdsBytes;
+  static constexpr int T1 = TAB_LDS ? 16 * C1 * C1 : 16, T2 = TAB_LDS ? 16 * C2 * C2 : 16;
+  static_assert(C1 >= 16 && C2 >= 16 && BR >= 1 && (NW * 1024) % C == 0, "row split");
 };
 
 // Locate the workgroup's rows: block = (job, poly, row block).
@@ -98,16 +140,28 @@ struct RowsPos {
 
 template <int BR, int C>
 __device__ __forceinline__ RowsPos rows_pos(const RowsJob* jobs, uint64_t stride, int npoly, int log_r) {
-  const int per_poly = (1 << log_r) / BR;
-  int b = blockIdx.x;
-  const int rb = b % per_poly;
-  b /= per_poly;
-  const int poly = b % npoly;
+  // R / BR row blocks per polynomial (both powers of two); the quotient is made
+  // explicitly wave-uniform so that the row buffers' descriptors stay in SGPRs
+  constexpr int kLogBr = __builtin_ctz(BR);
+  const int lpp = log_r - kLogBr;
+  const int b = blockIdx.x;
+  const int rb = b & ((1 << lpp) - 1);
+  const int pj = b >> lpp;
+  const int jb = __builtin_amdgcn_readfirstlane(pj / npoly);
+  const int poly = pj - jb * npoly;
   RowsPos p;
-  p.job = jobs[b / npoly];
+  p.job = jobs[jb];
   p.row0 = rb * BR;
   p.base = p.job.off + (uint64_t)poly * stride + (uint64_t)p.row0 * C;
   return p;
+}
+
+// Copy `bytes` (a multiple of 16) from global memory to LDS with 16-byte loads.
+template <int NT>
+__device__ __forceinline__ void stage(void* lds, const void* src, int bytes) {
+  const __amdgpu_buffer_rsrc_t r = rows_rsrc(src, (uint64_t)bytes);
+  for (int o = threadIdx.x * 16; o < bytes; o += NT * 16)
+    *reinterpret_cast<v4u*>(static_cast<char*>(lds) + o) = __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0);
 }
 
 // Write the staged output rows [row][line][.] (line = c1 or m, XP words) back to
@@ -127,123 +181,177 @@ __device__ __forceinline__ void write_rows(const uint32_t* xs, __amdgpu_buffer_r
 }
 
 template <int C1, int C2>
-__global__ void __launch_bounds__(512, (RowsShape<C1, C2>::OCC))
+__global__ void __launch_bounds__(64 * kRowsWaves, (RowsShape<C1, C2>::OCC))
 ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly, int log_r) {
   using S = RowsShape<C1, C2>;
   constexpr int C = S::C, BR = S::BR;
   constexpr int MB1 = C1 / 8, MB2 = C2 / 8;                 // 32-row blocks (M = 4 C1, 4 C2)
   constexpr int NB1 = BR * C2 / 32, NB2 = BR * C1 / 32;     // 32-column blocks of the two sub-steps
+  constexpr int NBW2 = (NB2 + S::NW - 1) / S::NW;           // sub-step 2 blocks per wave
+  __shared__ __attribute__((aligned(16))) int8_t tab1s[S::T1];
+  __shared__ __attribute__((aligned(16))) int8_t tab2s[S::T2];
+  __shared__ __attribute__((aligned(16))) uint32_t tws[2 * C];
   __shared__ __attribute__((aligned(16))) uint32_t zs[S::ZWORDS];
-  __shared__ __attribute__((aligned(16))) uint32_t xs[S::XWORDS];
   const RowsPos P = rows_pos<BR, C>(jobs, stride, npoly, log_r);
   const __amdgpu_buffer_rsrc_t rin = rows_rsrc(in + P.base, (uint64_t)BR * C * 4);
   const __amdgpu_buffer_rsrc_t rout = rows_rsrc(out + P.base, (uint64_t)BR * C * 4);
-  const __amdgpu_buffer_rsrc_t t1 = rows_rsrc(P.job.tab1, (uint64_t)16 * C1 * C1);
-  const __amdgpu_buffer_rsrc_t t2 = rows_rsrc(P.job.tab2, (uint64_t)16 * C2 * C2);
-  const __amdgpu_buffer_rsrc_t tw = rows_rsrc(P.job.tw1, (uint64_t)8 * C);
+  const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, 16 * C1 * C1);
+  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, 16 * C2 * C2);
+  if constexpr (S::TAB_LDS) {
+    stage<S::NT>(tab1s, P.job.tab1, 16 * C1 * C1);
+    stage<S::NT>(tab2s, P.job.tab2, 16 * C2 * C2);
+  }
+  stage<S::NT>(tws, P.job.tw1, 8 * C);
   const uint32_t q = P.job.q, qinv = P.job.qinv;
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __syncthreads();
 
   // sub-step 1: columns (row, c2), contraction over c1 (packed input, 4 words C2 apart)
   for (int cb = wave; cb < NB1; cb += S::NW) {
     const int col = cb * 32 + (lane & 31);
     const int row = col / C2, c2 = col % C2;
     v16i acc[MB1];
-    block_gemm<MB1, MB1>(acc, t1, lane, [&](int ks) {
+    block_gemm<MB1, MB1>(acc, tab1, lane, [&](int ks) {
       const uint32_t o = (uint32_t)(row * C + (8 * ks + 4 * h) * C2 + c2) * 4;
       return v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(rin, o, 0, 0),
                  (int)__builtin_amdgcn_raw_buffer_load_b32(rin, o, C2 * 4, 0),
                  (int)__builtin_amdgcn_raw_buffer_load_b32(rin, o, 2 * C2 * 4, 0),
                  (int)__builtin_amdgcn_raw_buffer_load_b32(rin, o, 3 * C2 * 4, 0)};
     });
+    // output m = mb * 8 + 2 j + h: lane bases plus compile-time offsets
+    const uint32_t* twl = &tws[(h * C2 + c2) * 2];
+    uint32_t* zl = &zs[(row * C1 + h) * S::ZP1 + c2];
 #pragma unroll
     for (int mb = 0; mb < MB1; ++mb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int m = mb * 8 + 2 * j + h;
-        const v2u w = __builtin_amdgcn_raw_buffer_load_b64(tw, (uint32_t)(m * C2 + c2) * 8, 0, 0);
-        zs[(row * C1 + m) * S::ZP1 + c2] = pack7(shoup_tw(merge_redc(acc[mb], j, q, qinv), w, q));
+        const int m0 = mb * 8 + 2 * j;
+        const v2u w = *reinterpret_cast<const v2u*>(&twl[m0 * C2 * 2]);
+        zl[m0 * S::ZP1] = pack7(shoup_tw(merge_redc(acc[mb], j, q, qinv), w, q));
       }
   }
   __syncthreads();
-  // sub-step 2: columns (row, m), contraction over c2 (16 contiguous bytes of a Z line)
-  for (int cb = wave; cb < NB2; cb += S::NW) {
-    const int col = cb * 32 + (lane & 31);
-    const int row = col / C1, m = col % C1;
-    v16i acc[MB2];
-    block_gemm<MB2, MB2>(acc, t2, lane, [&](int ks) {
-      return *reinterpret_cast<const v4i*>(&zs[(row * C1 + m) * S::ZP1 + 8 * ks + 4 * h]);
-    });
+  // sub-step 2: columns (row, m), contraction over c2 (16 contiguous bytes of a Z line);
+  // every block of the wave is multiplied before the Z tile is overwritten
+  v16i acc2[NBW2][MB2];
 #pragma unroll
-    for (int mb = 0; mb < MB2; ++mb)
+  for (int i = 0; i < NBW2; ++i) {
+    const int cb = wave + i * S::NW;
+    if (cb < NB2) {
+      const int col = cb * 32 + (lane & 31);
+      const int row = col / C1, m = col % C1;
+      block_gemm<MB2, MB2>(acc2[i], tab2, lane, [&](int ks) {
+        return *reinterpret_cast<const v4i*>(&zs[(row * C1 + m) * S::ZP1 + 8 * ks + 4 * h]);
+      });
+    }
+  }
+  __syncthreads();
+  uint32_t* xs = zs;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c2p = mb * 8 + 2 * j + h;
-        const uint32_t r = merge_redc(acc[mb], j, q, qinv);
-        xs[(row * C1 + m) * S::XP + c2p] = r >= q ? r - q : r;
-      }
+  for (int i = 0; i < NBW2; ++i) {
+    const int cb = wave + i * S::NW;
+    if (cb < NB2) {
+      const int col = cb * 32 + (lane & 31);
+      const int row = col / C1, m = col % C1;
+      uint32_t* xl = &xs[(row * C1 + m) * S::XP + h];     // output c2' = mb * 8 + 2 j + h
+#pragma unroll
+      for (int mb = 0; mb < MB2; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t r = merge_redc(acc2[i][mb], j, q, qinv);
+          xl[mb * 8 + 2 * j] = r >= q ? r - q : r;
+        }
+    }
   }
   __syncthreads();
   write_rows<C1, C2>(xs, rout);
 }
 
 template <int C1, int C2>
-__global__ void __launch_bounds__(512, (RowsShape<C1, C2>::OCC))
+__global__ void __launch_bounds__(64 * kRowsWaves, (RowsShape<C1, C2>::OCC))
 ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly, int log_r) {
   using S = RowsShape<C1, C2>;
   constexpr int C = S::C, BR = S::BR;
   constexpr int MB1 = C2 / 8, MB2 = C1 / 8;                 // sub-step 1 over c2', sub-step 2 over m
   constexpr int NB1 = BR * C1 / 32, NB2 = BR * C2 / 32;
+  constexpr int NBW2 = (NB2 + S::NW - 1) / S::NW;
+  __shared__ __attribute__((aligned(16))) int8_t tab1s[S::T2];
+  __shared__ __attribute__((aligned(16))) int8_t tab2s[S::T1];
+  __shared__ __attribute__((aligned(16))) uint32_t tws[2 * C];
   __shared__ __attribute__((aligned(16))) uint32_t zs[S::ZWORDS];
-  __shared__ __attribute__((aligned(16))) uint32_t xs[S::XWORDS];
   const RowsPos P = rows_pos<BR, C>(jobs, stride, npoly, log_r);
   const __amdgpu_buffer_rsrc_t rin = rows_rsrc(in + P.base, (uint64_t)BR * C * 4);
   const __amdgpu_buffer_rsrc_t rout = rows_rsrc(out + P.base, (uint64_t)BR * C * 4);
-  const __amdgpu_buffer_rsrc_t t1 = rows_rsrc(P.job.tab1, (uint64_t)16 * C2 * C2);
-  const __amdgpu_buffer_rsrc_t t2 = rows_rsrc(P.job.tab2, (uint64_t)16 * C1 * C1);
-  const __amdgpu_buffer_rsrc_t tw = rows_rsrc(P.job.tw1, (uint64_t)8 * C);
   // inverse step-2 twiddles of this workgroup's rows: pairs [row][c]
   const __amdgpu_buffer_rsrc_t tw2 = rows_rsrc(P.job.tw2 + (uint64_t)P.row0 * C * 2, (uint64_t)8 * BR * C);
+  const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, 16 * C2 * C2);
+  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, 16 * C1 * C1);
+  if constexpr (S::TAB_LDS) {
+    stage<S::NT>(tab1s, P.job.tab1, 16 * C2 * C2);
+    stage<S::NT>(tab2s, P.job.tab2, 16 * C1 * C1);
+  }
+  stage<S::NT>(tws, P.job.tw1, 8 * C);
   const uint32_t q = P.job.q, qinv = P.job.qinv;
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __syncthreads();
 
   // sub-step 1: columns (row, m), contraction over c2' (plain input, 16 contiguous bytes)
   for (int cb = wave; cb < NB1; cb += S::NW) {
     const int col = cb * 32 + (lane & 31);
     const int row = col / C1, m = col % C1;
     v16i acc[MB1];
-    block_gemm<MB1, MB1>(acc, t1, lane, [&](int ks) {
+    block_gemm<MB1, MB1>(acc, tab1, lane, [&](int ks) {
       const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rin, (uint32_t)(row * C + m * C2 + 8 * ks + 4 * h) * 4, 0, 0);
       return v4i{(int)pack7(x.x), (int)pack7(x.y), (int)pack7(x.z), (int)pack7(x.w)};
     });
+    // output c2 = mb * 8 + 2 j + h: lane bases plus compile-time offsets (IT3 pairs [c2][m])
+    const uint32_t* twl = &tws[(h * C1 + m) * 2];
+    uint32_t* zl = &zs[(row * C2 + h) * S::ZP2 + m];
 #pragma unroll
     for (int mb = 0; mb < MB1; ++mb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int c2 = mb * 8 + 2 * j + h;
-        const v2u w = __builtin_amdgcn_raw_buffer_load_b64(tw, (uint32_t)(m * C2 + c2) * 8, 0, 0);
-        zs[(row * C2 + c2) * S::ZP2 + m] = pack7(shoup_tw(merge_redc(acc[mb], j, q, qinv), w, q));
+        const int c0 = mb * 8 + 2 * j;
+        const v2u w = *reinterpret_cast<const v2u*>(&twl[c0 * C1 * 2]);
+        zl[c0 * S::ZP2] = pack7(shoup_tw(merge_redc(acc[mb], j, q, qinv), w, q));
       }
   }
   __syncthreads();
   // sub-step 2: columns (row, c2), contraction over m (16 contiguous bytes of a Z line)
-  for (int cb = wave; cb < NB2; cb += S::NW) {
-    const int col = cb * 32 + (lane & 31);
-    const int row = col / C2, c2 = col % C2;
-    v16i acc[MB2];
-    block_gemm<MB2, MB2>(acc, t2, lane, [&](int ks) {
-      return *reinterpret_cast<const v4i*>(&zs[(row * C2 + c2) * S::ZP2 + 8 * ks + 4 * h]);
-    });
+  v16i acc2[NBW2][MB2];
 #pragma unroll
-    for (int mb = 0; mb < MB2; ++mb)
+  for (int i = 0; i < NBW2; ++i) {
+    const int cb = wave + i * S::NW;
+    if (cb < NB2) {
+      const int col = cb * 32 + (lane & 31);
+      const int row = col / C2, c2 = col % C2;
+      block_gemm<MB2, MB2>(acc2[i], tab2, lane, [&](int ks) {
+        return *reinterpret_cast<const v4i*>(&zs[(row * C2 + c2) * S::ZP2 + 8 * ks + 4 * h]);
+      });
+    }
+  }
+  __syncthreads();
+  uint32_t* xs = zs;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c1 = mb * 8 + 2 * j + h;
-        const v2u w = __builtin_amdgcn_raw_buffer_load_b64(tw2, (uint32_t)(row * C + c1 * C2 + c2) * 8, 0, 0);
-        xs[(row * C1 + c1) * S::XP + c2] = pack7(shoup_tw(merge_redc(acc[mb], j, q, qinv), w, q));
-      }
+  for (int i = 0; i < NBW2; ++i) {
+    const int cb = wave + i * S::NW;
+    if (cb < NB2) {
+      const int col = cb * 32 + (lane & 31);
+      const int row = col / C2, c2 = col % C2;
+      // output c1 = mb * 8 + 2 j + h: lane bases plus compile-time offsets
+      const uint32_t twl = (uint32_t)(row * C + h * C2 + c2) * 8;
+      uint32_t* xl = &xs[(row * C1 + h) * S::XP + c2];
+#pragma unroll
+      for (int mb = 0; mb < MB2; ++mb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int c0 = mb * 8 + 2 * j;
+          const v2u w = __builtin_amdgcn_raw_buffer_load_b64(tw2, twl, c0 * C2 * 8, 0);
+          xl[c0 * S::XP] = pack7(shoup_tw(merge_redc(acc2[i][mb], j, q, qinv), w, q));
+        }
+    }
   }
   __syncthreads();
   write_rows<C1, C2>(xs, rout);
@@ -289,7 +397,9 @@ hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, u
 bool rows_split_supported(int log_n, int log_r, int log_c1) {
   const int log_c2 = log_n - log_r - log_c1;
   if (log_c1 < 4 || log_c1 > 6 || log_c2 < 4 || log_c2 > 6) return false;
-  const int log_br = 13 - (log_c1 + log_c2);      // rows per workgroup: 8192 / C
+  int log_w = 0;
+  while ((1 << log_w) < kRowsWaves) ++log_w;
+  const int log_br = log_w + 10 - (log_c1 + log_c2);   // rows per workgroup: kRowsWaves * 1024 / C
   return log_br >= 0 && log_r >= log_br && log_r >= 4;
 }
 

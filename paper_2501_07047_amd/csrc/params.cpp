@@ -191,11 +191,13 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
       for (uint32_t c2 = 0; c2 < C2; ++c2) {
         const int64_t e = 2 * (int64_t)R * c2 * bitrev(m, lc1);
         const uint32_t wf = P(e), wi = P(-e);
-        const size_t f = 2 * ((size_t)m * C2 + c2);
+        // T3 pairs [m][c2], IT3 pairs [c2][m]: each in the order the kernel's
+        // lanes read them (consecutive c2, resp. consecutive m, across a wave)
+        const size_t f = 2 * ((size_t)m * C2 + c2), g = 2 * ((size_t)c2 * C1 + m);
         t.row_fwd_t3[f] = wf;
         t.row_fwd_t3[f + 1] = shoup(wf);
-        t.row_inv_t3[f] = wi;
-        t.row_inv_t3[f + 1] = shoup(wi);
+        t.row_inv_t3[g] = wi;
+        t.row_inv_t3[g + 1] = shoup(wi);
       }
     // step-2 twiddles: forward [k][c] as in the two-factor form; the inverse ones
     // row-major too (applied by the row kernel's last epilogue)

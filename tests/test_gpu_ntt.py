@@ -181,8 +181,12 @@ def test_autotune_picks_valid_split_caches_and_stays_exact(tmp_path):
             B.set_ntt_split3(log_n, 0, 0)
 
 
+# every row-kernel shape C1 x C2 with C1, C2 in {16, 32, 64}: 64 x 64 reads its
+# tables from global memory, the others stage them in LDS
 @pytest.mark.parametrize("log_n,log_r,log_c1,L,batch", [(13, 5, 4, 2, 1), (14, 6, 4, 3, 2), (15, 5, 5, 2, 1),
-                                                        (16, 6, 5, 3, 2), (16, 4, 6, 1, 1), (16, 8, 4, 2, 1)])
+                                                        (16, 6, 5, 3, 2), (16, 4, 6, 1, 1), (16, 8, 4, 2, 1),
+                                                        (14, 5, 5, 2, 1), (14, 5, 4, 2, 1), (16, 5, 5, 1, 1),
+                                                        (16, 5, 6, 1, 1), (14, 4, 6, 1, 2), (14, 4, 4, 1, 1)])
 def test_three_factor_ntt_matches_oracle(log_n, log_r, log_c1, L, batch):
     from paper_2501_07047_amd import binding as B
     B.set_ntt_split3(log_n, log_r, log_c1)

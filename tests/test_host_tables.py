@@ -151,12 +151,12 @@ def _emulate3(X, q, log_n, log_r, log_c1, inverse):
             out[k] = _merge_reduce(tc @ _chunks_rows(Z.T), q).T.reshape(-1)             # [m][c2']
         return out.reshape(-1)
     itc, itb = _dense(rt(2), 4 * C2, 4 * C2), _dense(rt(3), 4 * C1, 4 * C1)
-    it3 = mont(rt(5).reshape(C1, C2, 2))
+    it3 = mont(rt(5).reshape(C2, C1, 2))         # [c2][m]
     it2 = mont(rt(6).reshape(R, C, 2))
     X = X.reshape(R, C1, C2)
     Y = np.empty((R, C), dtype=np.uint64)
     for k in range(R):
-        Z = twist(_merge_reduce(itc @ _chunks_rows(X[k].T), q), it3.T)                   # [c2][m]
+        Z = twist(_merge_reduce(itc @ _chunks_rows(X[k].T), q), it3)                     # [c2][m]
         Yk = _merge_reduce(itb @ _chunks_rows(Z.T), q)                                   # [c1][c2]
         Y[k] = twist(Yk.reshape(-1), it2[k])
     t1 = _dense(binding.host_tables(q, log_n, log_r, 2), 4 * R, 4 * R)
