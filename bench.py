@@ -147,6 +147,55 @@ def modred_bench(B, reps):
     return res
 
 
+def stream_bench(B, reps):
+    """Key-switching streams in both forms at the HE-Mult shape (N=2^16, L=24, K=8,
+    dnum=3): the inner product with the plain and the BAT-expanded evaluation key, and
+    the tensor product with 32-bit products and with byte-convolution products, for
+    1 and 8 ciphertexts; microseconds per call and algorithmic HBM rate."""
+    import numpy as np
+    import torch
+    import synthetic
+    n, L, LK, dnum = 1 << 16, 24, 32, 3
+    p = synthetic.primes(LK)
+    g = synthetic.rng(9)
+    ext = torch.from_numpy(synthetic.residues(g, (8, dnum), p, n).view(np.int32)).cuda()
+    key = torch.from_numpy(synthetic.residues(g, (dnum, 2), p, n).view(np.int32)).cuda()
+    kbat = B.evk_bat_prepare(key, p)
+    ct = torch.from_numpy(synthetic.residues(g, (8, 2), p[:L], n).view(np.int32)).cuda()
+    ct2 = torch.from_numpy(synthetic.residues(g, (8, 2), p[:L], n).view(np.int32)).cuda()
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / reps
+
+    res = {"inner_product": {}, "tensor": {}}
+    for form in ("valu", "chunked"):
+        k = kbat if form == "chunked" else key
+        row = {}
+        for b in (1, 8):
+            out = torch.empty((b, 2, LK, n), dtype=torch.int32, device="cuda")
+            us = timed(lambda: B.keyswitch_inner_product(ext[:b], k, out, p, form))
+            nbytes = 4 * LK * n * (b * dnum + dnum * 2 * (4 if form == "chunked" else 1) + b * 2)
+            row[str(b)] = {"us": round(us, 2), "gbs": round(nbytes / us / 1e3, 1)}
+        res["inner_product"][form] = row
+        row = {}
+        for b in (1, 8):
+            out = torch.empty((b, 2, L, n), dtype=torch.int32, device="cuda")
+            d2 = torch.empty((b, L, n), dtype=torch.int32, device="cuda")
+            us = timed(lambda: B.tensor(ct[:b], ct2[:b], out, d2, p[:L], form))
+            nbytes = 4 * L * n * b * 7
+            row[str(b)] = {"us": round(us, 2), "gbs": round(nbytes / us / 1e3, 1)}
+        res["tensor"][form] = row
+    return res
+
+
 def uneven_batch_bench(B, replays):
     """Config C4: 64 ciphertexts, N in {2^13..2^16}, L in [4, 36], HE-Mult (p = 0.5) else
     NTT of both polynomials; one captured graph per pass vs. the per-job calls."""
@@ -385,6 +434,11 @@ def main():
                                          "key = polynomials per call; us per call and HBM GB/s "
                                          "(a read + out written + w read once)",
                                "methods": modred_bench(B, max(10, args.steps))}
+    line["stream_ablation"] = {"config": "key-switch inner product (N=2^16, L+K=32, dnum=3; key plain vs "
+                                         "BAT-expanded, 16 B per residue) and tensor product (N=2^16, L=24; "
+                                         "32-bit vs byte-convolution products), per call for 1 and 8 "
+                                         "ciphertexts: us and algorithmic HBM GB/s",
+                               "forms": stream_bench(B, max(10, args.steps))}
     add_bytes = 3 * 2 * 24 * (1 << 16) * 4        # a, b read, out written: one ciphertext pair
     line["he_add"] = {"config": "N=2^16, L=24, per ciphertext pair", "batch1": he1["he_add"],
                       "batch8": he8["he_add"], "bytes_per_op": add_bytes,

@@ -293,6 +293,54 @@ cross_status cross_vec_modmul(cross_ctx ctx, uint32_t log_n, const uint32_t* pri
                               uint32_t* out, void* stream);
 
 /*
+ * Chunked forms of the two key-switching vector streams, beside their plain VALU
+ * forms (App. "Applying BAT to Preknown Parameters", closing remark: evaluation
+ * keys through BAT on a fine-grained matrix engine; App. "Fall-back Algorithm for
+ * unknown parameters": runtime x runtime products as a chunk-wise 1D convolution).
+ * Both chunked forms use 8-bit chunks on the VALU byte dot product; every form
+ * returns the canonical residues, so the results are identical.
+ *   CROSS_STREAM_VALU    : 32-bit products with Barrett reduction (Alg. barrett)
+ *   CROSS_STREAM_CHUNKED : inner product from the BAT-expanded key (E[l][i] = byte l
+ *                          of k 2^(32+8i) mod p, dot products over dnum x 4 bytes,
+ *                          ChunkMerge, Montgomery reduction); tensor product from
+ *                          the seven partial sums of the byte convolution, then Barrett
+ */
+typedef enum { CROSS_STREAM_VALU = 0, CROSS_STREAM_CHUNKED = 1 } cross_stream_form;
+
+/*
+ * Expand an evaluation key for CROSS_STREAM_CHUNKED (once per key).
+ *   primes  : host, LK limb primes (Q then P), as cross_ntt_forward
+ *   key     : device [dnum][2][LK][N] residues
+ *   key_bat : device [dnum][2][LK][N][4] words (16 bytes per residue), must not
+ *             overlap key; word l packs bytes E[l][0..3]
+ * Errors: CROSS_EINVAL (null, misaligned or overlapping buffers, bad shape:
+ * 1 <= LK <= CROSS_MAX_LIMBS, 1 <= dnum <= 64), prime checks as cross_ntt_forward.
+ */
+cross_status cross_evk_bat_prepare(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t LK,
+                                   uint32_t dnum, const uint32_t* key, uint32_t* key_bat, void* stream);
+/*
+ * Key-switch inner product: out[b][s][t] = sum_j ext[b][j][t] * key_j.s[t] mod p_t
+ * (s = 0 for b, 1 for a; the step between ModUp and ModDown of the hybrid key switch).
+ *   ext : device [batch][dnum][LK][N];  out : device [batch][2][LK][N], must not
+ *         overlap ext or key
+ *   key : device [dnum][2][LK][N] (CROSS_STREAM_VALU) or the cross_evk_bat_prepare
+ *         output (CROSS_STREAM_CHUNKED)
+ * All buffers 16-byte aligned.  Asynchronous on `stream`.
+ */
+cross_status cross_keyswitch_inner_product(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t LK,
+                                           uint32_t dnum, uint32_t batch, int form, const uint32_t* ext,
+                                           const uint32_t* key, uint32_t* out, void* stream);
+/*
+ * HE-Mult tensor product limb-wise mod q_l: out[b][0] = a0 b0, out[b][1] = a0 b1 +
+ * a1 b0, d2[b] = a1 b1.  a, b, out: device [batch][2][L][N]; d2: device
+ * [batch][L][N]; out and d2 must not overlap each other or the inputs; 16-byte
+ * aligned.  Asynchronous on `stream`.
+ */
+cross_status cross_tensor(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L, uint32_t batch,
+                          int form, const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
+                          void* stream);
+
+/*
  * Batch runtime (many jobs of uneven N and limb count in one pass).
  * Jobs are lowered onto a fixed sequence of 15 work-list launches (one per
  * step of the hot path, each covering that step for every job; the BAT GEMM

@@ -57,6 +57,10 @@ SIGNATURES = {
     "cross_rescale": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_u32, c_vp, c_vp, c_vp],
     "cross_vec_modmul_prepare": [c_vp, c_u32, c_u32p, c_u32, ctypes.c_int, c_vp, c_vp, c_vp],
     "cross_vec_modmul": [c_vp, c_u32, c_u32p, c_u32, c_u32, ctypes.c_int, c_vp, c_vp, c_vp, c_vp],
+    "cross_evk_bat_prepare": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, c_vp, c_vp],
+    "cross_keyswitch_inner_product": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_u32, ctypes.c_int, c_vp, c_vp, c_vp,
+                                      c_vp],
+    "cross_tensor": [c_vp, c_u32, c_u32p, c_u32, c_u32, ctypes.c_int, c_vp, c_vp, c_vp, c_vp, c_vp],
     "cross_batch_create": [c_vp, c_vp, c_u32, ctypes.c_int, ctypes.POINTER(c_vp)],
     "cross_batch_workspace_bytes": [c_vp, c_vp, c_u32, ctypes.POINTER(ctypes.c_uint64)],
     "cross_batch_create_in": [c_vp, c_vp, c_u32, ctypes.c_int, c_vp, ctypes.c_uint64, c_vp, ctypes.POINTER(c_vp)],
@@ -405,6 +409,55 @@ def vec_modmul(a, w_prep, out, primes, method):
     _check(lib().cross_vec_modmul(ctx, _log2(n), _u32_array(primes), L, npoly, MODRED[method], _dev_ptr(a, "a"),
                                   _dev_ptr(w_prep, "w_prep"), _dev_ptr(out, "out"), _stream(a)), ctx)
     return out
+
+
+STREAM_FORM = {"valu": 0, "chunked": 1}
+
+
+def evk_bat_prepare(key, primes):
+    """BAT-expanded evaluation key for the chunked inner product: key [dnum][2][LK][N] ->
+    a new device tensor [dnum][2][LK][N][4] of words."""
+    import torch
+    dnum, two, LK, n = key.shape
+    if two != 2 or len(primes) != LK:
+        raise ValueError("key must be [dnum][2][LK][N] with LK primes")
+    kb = torch.empty((dnum, 2, LK, n, 4), dtype=torch.int32, device=key.device)
+    ctx = context(key.device.index)
+    _check(lib().cross_evk_bat_prepare(ctx, _log2(n), _u32_array(primes), LK, dnum, _dev_ptr(key, "key"),
+                                       _dev_ptr(kb, "key_bat"), _stream(key)), ctx)
+    return kb
+
+
+def keyswitch_inner_product(ext, key, out, primes, form="valu"):
+    """out[b][s] = sum_j ext[b][j] key_j.s limb-wise: ext [B][dnum][LK][N], out [B][2][LK][N];
+    key [dnum][2][LK][N] ("valu") or the evk_bat_prepare output ("chunked")."""
+    B, dnum, LK, n = ext.shape
+    _shape(out, (B, 2, LK, n), "out")
+    _shape(key, (dnum, 2, LK, n) + ((4,) if form == "chunked" else ()), "key")
+    if len(primes) != LK:
+        raise ValueError("len(primes) != LK")
+    ctx = context(ext.device.index)
+    _check(lib().cross_keyswitch_inner_product(ctx, _log2(n), _u32_array(primes), LK, dnum, B, STREAM_FORM[form],
+                                               _dev_ptr(ext, "ext"), _dev_ptr(key, "key"), _dev_ptr(out, "out"),
+                                               _stream(ext)), ctx)
+    return out
+
+
+def tensor(a, b, out, d2, primes, form="valu"):
+    """HE-Mult tensor product: a, b, out [B][2][L][N], d2 [B][L][N] (out = (a0 b0, a0 b1 + a1 b0),
+    d2 = a1 b1 limb-wise)."""
+    B, two, L, n = a.shape
+    if two != 2:
+        raise ValueError("a must be [B][2][L][N]")
+    _shape(b, a.shape, "b")
+    _shape(out, a.shape, "out")
+    _shape(d2, (B, L, n), "d2")
+    if len(primes) != L:
+        raise ValueError("len(primes) != L")
+    ctx = context(a.device.index)
+    _check(lib().cross_tensor(ctx, _log2(n), _u32_array(primes), L, B, STREAM_FORM[form], _dev_ptr(a, "a"),
+                              _dev_ptr(b, "b"), _dev_ptr(out, "out"), _dev_ptr(d2, "d2"), _stream(a)), ctx)
+    return out, d2
 
 
 OP_NTT_FORWARD, OP_NTT_INVERSE, OP_HE_MULT, OP_ROTATE = 1, 2, 3, 4

@@ -33,6 +33,17 @@ LimbMod limb_mod(uint32_t q) {
 
 uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
 
+StreamMod stream_mod(uint32_t q) {
+  const LimbMod l = limb_mod(q);
+  StreamMod m{};
+  m.q = q;
+  m.bar_m = l.bar_m;
+  m.bar_k = l.bar_k;
+  m.qneg = (uint32_t)(0u - inv_mod_2_32(q));
+  for (int i = 0; i < 4; ++i) m.pow2[i] = powmod(2, 32 + 8 * i, q);
+  return m;
+}
+
 // Fragment-ordered BAT table of the BConv matrix [qhat_i]_t (see bconv_kernel).
 std::vector<int8_t> bconv_table(const std::vector<uint32_t>& src, const std::vector<uint32_t>& dst) {
   const int ns = (int)src.size(), nd = (int)dst.size();
@@ -659,6 +670,127 @@ cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* prm, int32_t s
     HIPCHK(launch_automorphism(ct + L * N, 2 * L * N, w.d, L * N, perm, c->log_n, (int)L, (int)batch, s), "sigma c1");
   }
   return keyswitch_into(ctx, c, rot_key, (int)batch, w, out, out, true, s);
+}
+
+}  // extern "C"
+
+/* ---- chunked forms of the key-switching streams (stream ablation) ---- */
+
+namespace {
+
+cross_status stream_mods(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L, const StreamMod** out) {
+  std::vector<StreamMod> m(L);
+  for (uint32_t i = 0; i < L; ++i) {
+    cross_status st = check_prime(ctx, primes[i], log_n);
+    if (st != CROSS_OK) return st;
+    m[i] = stream_mod(primes[i]);
+  }
+  void* d = nullptr;
+  cross_status st = cached_device_copy(ctx, m.data(), m.size() * sizeof(StreamMod), &d);
+  *out = (const StreamMod*)d;
+  return st;
+}
+
+bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+cross_status cross_evk_bat_prepare(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t LK,
+                                   uint32_t dnum, const uint32_t* key, uint32_t* key_bat, void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  if (!primes || !key || !key_bat || !aligned(key) || !aligned(key_bat))
+    return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
+  if (log_n < CROSS_MIN_LOG_N || log_n > CROSS_MAX_LOG_N || LK < 1 || LK > CROSS_MAX_LIMBS || dnum < 1 || dnum > 64)
+    return fail(ctx, CROSS_EINVAL, "bad shape");
+  const uint64_t n = ((uint64_t)dnum * 2 * LK) << log_n;
+  if (overlaps(key, n * 4, key_bat, n * 16)) return fail(ctx, CROSS_EINVAL, "key_bat must not overlap key");
+  const StreamMod* m = nullptr;
+  if ((st = stream_mods(ctx, log_n, primes, LK, &m)) != CROSS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  ProfScope ps(ctx, "evk_bat_prepare", s);
+  HIPCHK(launch_evk_bat_prepare(key, key_bat, m, (int)LK, (int)dnum, (int)log_n, s), "evk_bat_prepare");
+  return CROSS_OK;
+}
+
+cross_status cross_keyswitch_inner_product(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t LK,
+                                           uint32_t dnum, uint32_t batch, int form, const uint32_t* ext,
+                                           const uint32_t* key, uint32_t* out, void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  if (!primes || !ext || !key || !out || !aligned(ext) || !aligned(key) || !aligned(out))
+    return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
+  if (log_n < CROSS_MIN_LOG_N || log_n > CROSS_MAX_LOG_N || LK < 1 || LK > CROSS_MAX_LIMBS || dnum < 1 ||
+      dnum > 64 || batch < 1)
+    return fail(ctx, CROSS_EINVAL, "bad shape");
+  if (form != CROSS_STREAM_VALU && form != CROSS_STREAM_CHUNKED) return fail(ctx, CROSS_EINVAL, "unknown form");
+  const uint64_t N = 1ull << log_n;
+  const uint64_t n_ext = (uint64_t)batch * dnum * LK * N, n_out = (uint64_t)batch * 2 * LK * N;
+  const uint64_t n_key = (uint64_t)dnum * 2 * LK * N * (form == CROSS_STREAM_CHUNKED ? 4 : 1);
+  if (overlaps(out, n_out * 4, ext, n_ext * 4) || overlaps(out, n_out * 4, key, n_key * 4))
+    return fail(ctx, CROSS_EINVAL, "out must not overlap ext or key");
+  hipStream_t s = (hipStream_t)stream;
+  if (form == CROSS_STREAM_CHUNKED) {
+    const StreamMod* m = nullptr;
+    if ((st = stream_mods(ctx, log_n, primes, LK, &m)) != CROSS_OK) return st;
+    ProfScope ps(ctx, "inner_product_bat", s);
+    HIPCHK(launch_inner_product_bat(ext, key, out, m, (int)LK, (int)dnum, (int)log_n, (int)batch, s),
+           "inner_product_bat");
+    return CROSS_OK;
+  }
+  if (log_n < 2) return fail(ctx, CROSS_EINVAL, "bad shape");
+  std::vector<LimbMod> mods(LK);
+  for (uint32_t i = 0; i < LK; ++i) {
+    if ((st = check_prime(ctx, primes[i], log_n)) != CROSS_OK) return st;
+    mods[i] = limb_mod(primes[i]);
+  }
+  void* dm = nullptr;
+  if ((st = cached_device_copy(ctx, mods.data(), mods.size() * sizeof(LimbMod), &dm)) != CROSS_OK) return st;
+  ProfScope ps(ctx, "inner_product", s);
+  HIPCHK(launch_inner_product(ext, key, out, (const LimbMod*)dm, (int)LK, (int)dnum, (int)dnum, (int)log_n,
+                              (int)batch, s),
+         "inner_product");
+  return CROSS_OK;
+}
+
+cross_status cross_tensor(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L, uint32_t batch,
+                          int form, const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
+                          void* stream) {
+  cross_status st = begin(ctx);
+  if (st != CROSS_OK) return st;
+  if (!primes || !a || !b || !out || !d2 || !aligned(a) || !aligned(b) || !aligned(out) || !aligned(d2))
+    return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
+  if (log_n < CROSS_MIN_LOG_N || log_n > CROSS_MAX_LOG_N || L < 1 || L > CROSS_MAX_LIMBS || batch < 1)
+    return fail(ctx, CROSS_EINVAL, "bad shape");
+  if (form != CROSS_STREAM_VALU && form != CROSS_STREAM_CHUNKED) return fail(ctx, CROSS_EINVAL, "unknown form");
+  const uint64_t N = 1ull << log_n, n_ct = (uint64_t)batch * 2 * L * N, n_d2 = (uint64_t)batch * L * N;
+  if (overlaps(out, n_ct * 4, a, n_ct * 4) || overlaps(out, n_ct * 4, b, n_ct * 4) ||
+      overlaps(d2, n_d2 * 4, a, n_ct * 4) || overlaps(d2, n_d2 * 4, b, n_ct * 4) ||
+      overlaps(d2, n_d2 * 4, out, n_ct * 4))
+    return fail(ctx, CROSS_EINVAL, "out and d2 must not overlap each other or the inputs");
+  hipStream_t s = (hipStream_t)stream;
+  if (form == CROSS_STREAM_CHUNKED) {
+    const StreamMod* m = nullptr;
+    if ((st = stream_mods(ctx, log_n, primes, L, &m)) != CROSS_OK) return st;
+    ProfScope ps(ctx, "tensor_conv", s);
+    HIPCHK(launch_tensor_conv(a, b, out, d2, m, (int)L, (int)log_n, (int)batch, s), "tensor_conv");
+    return CROSS_OK;
+  }
+  std::vector<LimbMod> mods(L);
+  for (uint32_t i = 0; i < L; ++i) {
+    if ((st = check_prime(ctx, primes[i], log_n)) != CROSS_OK) return st;
+    mods[i] = limb_mod(primes[i]);
+  }
+  void* dm = nullptr;
+  if ((st = cached_device_copy(ctx, mods.data(), mods.size() * sizeof(LimbMod), &dm)) != CROSS_OK) return st;
+  ProfScope ps(ctx, "tensor", s);
+  HIPCHK(launch_tensor(a, b, out, d2, (const LimbMod*)dm, (int)L, (int)log_n, (int)batch, s), "tensor");
+  return CROSS_OK;
 }
 
 }  // extern "C"

@@ -71,30 +71,48 @@ tensor_kernel(const v4u* a, const v4u* b, v4u* out, v4u* d2, const LimbMod* mods
   d2[(bb * L + limb) * per_limb + w] = r2;
 }
 
+// A thread takes four residues (t, 4w..4w+3) of kIpCts ciphertexts, so every key
+// vector is read once per kIpCts ciphertexts rather than once per ciphertext.
+constexpr int kIpCts = 4;
+
 __global__ void __launch_bounds__(256)
 inner_product_kernel(const v4u* ext, const v4u* key, v4u* acc, const LimbMod* mods, int LK,
-                     int dnum, int ndig, int log_n4, uint64_t total4) {
+                     int dnum, int ndig, int log_n4, int B, uint64_t total4) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total4) return;
   const uint64_t per_limb = 1ull << log_n4;
   const uint64_t limb_all = i >> log_n4;
   const int t = (int)(limb_all % LK);
-  const uint64_t bb = limb_all / LK;
+  const int b0 = (int)(limb_all / LK) * kIpCts;
+  const int nb = B - b0 < kIpCts ? B - b0 : kIpCts;
   const uint64_t w = i & (per_limb - 1);
   const LimbMod md = mods[t];
-  v4u s0 = {0, 0, 0, 0}, s1 = {0, 0, 0, 0};
-  for (int j = 0; j < ndig; ++j) {
-    v4u e = ext[((bb * dnum + j) * LK + t) * per_limb + w];
-    v4u k0 = key[((uint64_t)(j * 2 + 0) * LK + t) * per_limb + w];
-    v4u k1 = key[((uint64_t)(j * 2 + 1) * LK + t) * per_limb + w];
+  v4u s0[kIpCts], s1[kIpCts];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      s0[k] = addmod(s0[k], mulmod(e[k], k0[k], md), md.q);
-      s1[k] = addmod(s1[k], mulmod(e[k], k1[k], md), md.q);
+  for (int c = 0; c < kIpCts; ++c) s0[c] = s1[c] = v4u{0, 0, 0, 0};
+  for (int j = 0; j < ndig; ++j) {
+    const v4u k0 = key[((uint64_t)(j * 2 + 0) * LK + t) * per_limb + w];
+    const v4u k1 = key[((uint64_t)(j * 2 + 1) * LK + t) * per_limb + w];
+#pragma unroll
+    for (int c = 0; c < kIpCts; ++c) {
+      if (c < nb) {
+        const v4u e = ext[(((uint64_t)(b0 + c) * dnum + j) * LK + t) * per_limb + w];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          s0[c][k] = addmod(s0[c][k], mulmod(e[k], k0[k], md), md.q);
+          s1[c][k] = addmod(s1[c][k], mulmod(e[k], k1[k], md), md.q);
+        }
+      }
     }
   }
-  acc[((bb * 2 + 0) * LK + t) * per_limb + w] = s0;
-  acc[((bb * 2 + 1) * LK + t) * per_limb + w] = s1;
+#pragma unroll
+  for (int c = 0; c < kIpCts; ++c) {
+    if (c < nb) {
+      const uint64_t bb = (uint64_t)(b0 + c);
+      acc[((bb * 2 + 0) * LK + t) * per_limb + w] = s0[c];
+      acc[((bb * 2 + 1) * LK + t) * per_limb + w] = s1[c];
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -356,9 +374,10 @@ hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, ui
 hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32_t* acc,
                                 const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
                                 hipStream_t s) {
-  const uint64_t total4 = ((uint64_t)B * LK) << (log_n - 2);
+  const uint64_t groups = (uint64_t)(B + kIpCts - 1) / kIpCts;
+  const uint64_t total4 = (groups * LK) << (log_n - 2);
   hipLaunchKernelGGL(inner_product_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
-                     (const v4u*)ext, (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2,
+                     (const v4u*)ext, (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2, B,
                      total4);
   return hipGetLastError();
 }

@@ -119,6 +119,27 @@ hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32
                                 const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
                                 hipStream_t s);
 
+// Per-limb constants of the chunked stream forms (streams.hip).
+struct StreamMod {
+  uint32_t q;
+  uint32_t qneg;      // -q^-1 mod 2^32 (Montgomery reduction)
+  uint32_t bar_m;     // floor(2^(2k) / q), k = bit length of q (Barrett, Alg. barrett)
+  uint32_t bar_k;     // k
+  uint32_t pow2[4];   // 2^(32 + 8 i) mod q: the evaluation-key BAT expansion
+};
+
+// Evaluation-key BAT expansion: key [dnum][2][LK][N] -> key_bat [dnum][2][LK][N][4 words].
+hipError_t launch_evk_bat_prepare(const uint32_t* key, uint32_t* key_bat, const StreamMod* mods, int LK, int dnum,
+                                  int log_n, hipStream_t s);
+// Key-switch inner product from the expanded key (same result as launch_inner_product
+// with ndig = dnum).
+hipError_t launch_inner_product_bat(const uint32_t* ext, const uint32_t* key_bat, uint32_t* acc,
+                                    const StreamMod* mods, int LK, int dnum, int log_n, int B, hipStream_t s);
+// Tensor product with every product taken as a chunk-wise convolution (same result
+// as launch_tensor).
+hipError_t launch_tensor_conv(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
+                              const StreamMod* mods, int L, int log_n, int B, hipStream_t s);
+
 // ModDown tail: out[p][i] = (base[p][i] + (acc[p][i] - z[p][i]) * Pinv_i) mod q_i for the
 // first L limbs of every polynomial p < npoly.  base may be null (treated as 0) or alias out.
 // acc stride: acc_stride elements per poly; z and out/base: L*N per poly.
