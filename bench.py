@@ -147,6 +147,47 @@ def modred_bench(B, reps):
     return res
 
 
+def ntt_reduction_bench(B, reps):
+    """Forward + inverse NTT at N=2^16, L=24 (64 x 32 x 32) with the row kernels' epilogue
+    reduction Montgomery vs Barrett, for 1, 4 and 16 polynomials (the NTT side of
+    Fig. diff_modred); microseconds per pair and the row-kernel share."""
+    import numpy as np
+    import torch
+    import synthetic
+    primes, x = synthetic.ntt_batch(11, LOG_N, L, 16)
+    res = {}
+    try:
+        for method in ("montgomery", "barrett"):
+            B.set_ntt_reduction(method)
+            row = {}
+            for npoly in (1, 4, 16):
+                d = torch.from_numpy(np.ascontiguousarray(x[:npoly]).view(np.int32)).cuda()
+                for _ in range(3):
+                    B.ntt_forward(d, primes)
+                    B.ntt_inverse(d, primes)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    B.ntt_forward(d, primes)
+                    B.ntt_inverse(d, primes)
+                e1.record()
+                e1.synchronize()
+                B.profile_report()
+                B.profile_enable(True)             # a second, event-bracketed pass for the row kernels
+                for _ in range(reps):
+                    B.ntt_forward(d, primes)
+                    B.ntt_inverse(d, primes)
+                prof = B.profile_report()
+                B.profile_enable(False)
+                rows = prof.get("ntt_rows", (1, 0.0))
+                row[str(npoly)] = {"us_fwd_inv": round(e0.elapsed_time(e1) * 1e3 / reps, 2),
+                                   "row_kernel_us_avg": round(rows[1] * 1e3 / max(1, rows[0]), 2)}
+            res[method] = row
+    finally:
+        B.set_ntt_reduction("montgomery")
+    return res
+
+
 def stream_bench(B, reps):
     """Key-switching streams in both forms at the HE-Mult shape (N=2^16, L=24, K=8,
     dnum=3): the inner product with the plain and the BAT-expanded evaluation key, and
@@ -434,6 +475,10 @@ def main():
                                          "key = polynomials per call; us per call and HBM GB/s "
                                          "(a read + out written + w read once)",
                                "methods": modred_bench(B, max(10, args.steps))}
+    line["ntt_reduction_ablation"] = {"config": "NTT+INTT at N=2^16, L=24 (64 x 32 x 32); row-kernel "
+                                               "epilogue Montgomery (tables x 2^32, REDC) vs Barrett "
+                                               "(plain tables); key = polynomials per call",
+                                     "methods": ntt_reduction_bench(B, max(10, args.steps))}
     line["stream_ablation"] = {"config": "key-switch inner product (N=2^16, L+K=32, dnum=3; key plain vs "
                                          "BAT-expanded, 16 B per residue) and tensor product (N=2^16, L=24; "
                                          "32-bit vs byte-convolution products), per call for 1 and 8 "

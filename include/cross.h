@@ -435,6 +435,21 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
                                void* out, uint64_t* bytes);
 
 /*
+ * Epilogue reduction of the three-factor row kernels (both sub-steps), for the
+ * NTT side of the modular-reduction comparison (Sec. Evaluation, Fig.
+ * diff_modred).  The row-side GEMM step and the two-factor form always use
+ * Montgomery reduction.  Results are identical either way.
+ *   CROSS_NTT_RED_MONTGOMERY (default): tables carry the factor 2^32, REDC of the
+ *                            merged chunk sums (Alg. montgomery_reduction)
+ *   CROSS_NTT_RED_BARRETT    : tables without the factor, Barrett reduction of the
+ *                            merged sums (Alg. barrett); NTT calls whose primes lie
+ *                            below 2^21 then fail with CROSS_EUNSUPPORTED
+ * Returns CROSS_EINVAL for another method.
+ */
+typedef enum { CROSS_NTT_RED_MONTGOMERY = 0, CROSS_NTT_RED_BARRETT = 1 } cross_ntt_reduction;
+cross_status cross_set_ntt_reduction(cross_ctx ctx, int method);
+
+/*
  * Host-only introspection of the three-factor row tables (split as in
  * cross_set_ntt_split3), same calling convention as cross_host_tables:
  *   which 0/1 : int8 BAT tables of the forward row sub-steps, TB (over c1, 4C1 x 4C1)
@@ -443,6 +458,8 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
  *   which 4/5 : uint32 (w, floor(w*2^32/q)) pairs of T3, [C1][C2][2] (m, c2), and of
  *               IT3, [C2][C1][2] (c2, m)
  *   which 6/7 : uint32 pairs of the inverse / forward step-2 twiddles, row-major [R][C][2]
+ *   which 8-11: the tables of which 0-3 without the Montgomery factor 2^32
+ *               (CROSS_NTT_RED_BARRETT)
  */
 cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,
                                    void* out, uint64_t* bytes);

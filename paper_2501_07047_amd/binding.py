@@ -39,6 +39,7 @@ SIGNATURES = {
     "cross_set_ntt_split": [c_vp, c_u32, c_u32],
     "cross_set_gemm_tile": [c_vp, ctypes.c_int],
     "cross_set_ntt_split3": [c_vp, c_u32, c_u32, c_u32],
+    "cross_set_ntt_reduction": [c_vp, ctypes.c_int],
     "cross_get_ntt_split": [c_vp, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)],
     "cross_host_row_tables": [c_u32, c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
     "cross_autotune": [c_vp, c_u32, c_u32, c_u32, ctypes.c_char_p, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32),
@@ -157,6 +158,15 @@ def set_ntt_split3(log_n, log_r, log_c1, device=None):
     _check(lib().cross_set_ntt_split3(ctx, log_n, log_r, log_c1), ctx)
 
 
+NTT_REDUCTION = {"montgomery": 0, "barrett": 1}
+
+
+def set_ntt_reduction(method, device=None):
+    """Epilogue reduction of the three-factor row kernels ("montgomery" or "barrett")."""
+    ctx = context(device)
+    _check(lib().cross_set_ntt_reduction(ctx, NTT_REDUCTION[method]), ctx)
+
+
 def get_ntt_split(log_n, device=None):
     """(log_r, log_c1) used for 2^log_n transforms on this context (log_c1 = 0: two factors)."""
     ctx = context(device)
@@ -176,7 +186,7 @@ def host_row_tables(q, log_n, log_r, log_c1, which):
     st = lib().cross_host_row_tables(q, log_n, log_r, log_c1, which, c_vp(buf.ctypes.data), ctypes.byref(nbytes))
     if st != 0:
         raise CrossError(st, "cross_host_row_tables")
-    return buf.view(np.int8) if which < 4 else buf.view(np.uint32)
+    return buf.view(np.int8) if which < 4 or which >= 8 else buf.view(np.uint32)
 
 
 def set_gemm_tile(tile, device=None):

@@ -97,7 +97,9 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool all
               al(t.inv_right.size()) + al(t.fwd_tw.size() * 4) + al(t.inv_tw.size() * 4) +
               al(t.bf_fwd.size() * 4) + al(t.bf_inv.size() * 4) + al(t.row_fwd_b.size()) +
               al(t.row_fwd_c.size()) + al(t.row_inv_c.size()) + al(t.row_inv_b.size()) +
-              al(t.row_fwd_t3.size() * 4) + al(t.row_inv_t3.size() * 4) + al(t.inv_tw_rows.size() * 4);
+              al(t.row_fwd_t3.size() * 4) + al(t.row_inv_t3.size() * 4) + al(t.inv_tw_rows.size() * 4) +
+              al(t.row_fwd_b_plain.size()) + al(t.row_fwd_c_plain.size()) + al(t.row_inv_c_plain.size()) +
+              al(t.row_inv_b_plain.size());
   Plan* p = new Plan();
   cross_status st = dev_alloc(ctx, sz, &p->block);
   if (st != CROSS_OK) {
@@ -127,6 +129,16 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool all
   p->row_fwd_t3 = (uint32_t*)put(t.row_fwd_t3.data(), t.row_fwd_t3.size() * 4);
   p->row_inv_t3 = (uint32_t*)put(t.row_inv_t3.data(), t.row_inv_t3.size() * 4);
   p->inv_tw_rows = (uint32_t*)put(t.inv_tw_rows.data(), t.inv_tw_rows.size() * 4);
+  p->row_fwd_b_plain = (int8_t*)put(t.row_fwd_b_plain.data(), t.row_fwd_b_plain.size());
+  p->row_fwd_c_plain = (int8_t*)put(t.row_fwd_c_plain.data(), t.row_fwd_c_plain.size());
+  p->row_inv_c_plain = (int8_t*)put(t.row_inv_c_plain.data(), t.row_inv_c_plain.size());
+  p->row_inv_b_plain = (int8_t*)put(t.row_inv_b_plain.data(), t.row_inv_b_plain.size());
+  {
+    uint32_t k = 0;
+    while ((1ull << k) <= q) ++k;
+    p->bar_k = k;
+    p->bar_m = (uint32_t)(((unsigned __int128)1 << (2 * k)) / q);
+  }
   if (hipGetLastError() != hipSuccess) {
     (void)hipFree(p->block);
     delete p;
@@ -191,13 +203,20 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
                               hipStream_t s) {
   const int log_n = plans[0]->log_n, log_r = plans[0]->log_r, log_c1 = plans[0]->log_c1;
   const int log_c2 = log_n - log_r - log_c1;
+  const int red = ctx->ntt_reduction;
+  if (red == 1)
+    for (const Plan* p : plans)
+      if (p->bar_k < 22) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett row epilogue needs primes >= 2^21");
   std::vector<RowsJob> rj(plans.size());
   std::vector<GemmJob> gj(plans.size());
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];
     if (p->log_r != log_r || p->log_c1 != log_c1) return fail(ctx, CROSS_EINVAL, "mixed NTT splits in one call");
-    rj[i] = inverse ? RowsJob{p->row_inv_c, p->row_inv_b, p->row_inv_t3, p->inv_tw_rows, offs[i], p->q, p->qinv}
-                    : RowsJob{p->row_fwd_b, p->row_fwd_c, p->row_fwd_t3, nullptr, offs[i], p->q, p->qinv};
+    const bool bar = red == 1;
+    rj[i] = inverse ? RowsJob{bar ? p->row_inv_c_plain : p->row_inv_c, bar ? p->row_inv_b_plain : p->row_inv_b,
+                              p->row_inv_t3, p->inv_tw_rows, offs[i], p->q, p->qinv, p->bar_m, p->bar_k}
+                    : RowsJob{bar ? p->row_fwd_b_plain : p->row_fwd_b, bar ? p->row_fwd_c_plain : p->row_fwd_c,
+                              p->row_fwd_t3, nullptr, offs[i], p->q, p->qinv, p->bar_m, p->bar_k};
     gj[i] = GemmJob{inverse ? p->inv_left : p->fwd_left, inverse ? nullptr : p->fwd_tw, offs[i], offs[i], p->q,
                     p->qinv};
   }
@@ -223,7 +242,7 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
     {
       ProfScope ps(ctx, "ntt_rows", s);
       e = launch_ntt_rows((const RowsJob*)dr, (int)plans.size(), in, out, stride, npoly, log_r, log_c1, log_c2,
-                          inverse, s);
+                          inverse, red, s);
     }
     if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("row transform launch: ") + hipGetErrorString(e));
     return CROSS_OK;
@@ -445,6 +464,14 @@ cross_status cross_set_ntt_split3(cross_ctx ctx, uint32_t log_n, uint32_t log_r,
   return CROSS_OK;
 }
 
+cross_status cross_set_ntt_reduction(cross_ctx ctx, int method) {
+  if (!ctx) return CROSS_EINVAL;
+  if (method != CROSS_NTT_RED_MONTGOMERY && method != CROSS_NTT_RED_BARRETT)
+    return fail(ctx, CROSS_EINVAL, "unknown NTT reduction");
+  ctx->ntt_reduction = method;
+  return CROSS_OK;
+}
+
 cross_status cross_get_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t* log_r, uint32_t* log_c1) {
   if (!ctx || !log_r || !log_c1) return CROSS_EINVAL;
   if (log_n < 8 || log_n > CROSS_MAX_LOG_N) return fail(ctx, CROSS_EINVAL, "log_n out of range");
@@ -514,7 +541,7 @@ cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len) {
 
 cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,
                                    void* out, uint64_t* bytes) {
-  if (!bytes || which > 7 || log_n > CROSS_MAX_LOG_N || log_r > log_n ||
+  if (!bytes || which > 11 || log_n > CROSS_MAX_LOG_N || log_r > log_n ||
       !rows_split_supported((int)log_n, (int)log_r, (int)log_c1))
     return CROSS_EINVAL;
   cross_status st = check_prime(nullptr, q, log_n);
@@ -535,7 +562,11 @@ cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, u
     case 4: src = t.row_fwd_t3.data(); n = t.row_fwd_t3.size() * 4; break;
     case 5: src = t.row_inv_t3.data(); n = t.row_inv_t3.size() * 4; break;
     case 6: src = t.inv_tw_rows.data(); n = t.inv_tw_rows.size() * 4; break;
-    default: src = t.fwd_tw.data(); n = t.fwd_tw.size() * 4; break;
+    case 7: src = t.fwd_tw.data(); n = t.fwd_tw.size() * 4; break;
+    case 8: src = t.row_fwd_b_plain.data(); n = t.row_fwd_b_plain.size(); break;
+    case 9: src = t.row_fwd_c_plain.data(); n = t.row_fwd_c_plain.size(); break;
+    case 10: src = t.row_inv_c_plain.data(); n = t.row_inv_c_plain.size(); break;
+    default: src = t.row_inv_b_plain.data(); n = t.row_inv_b_plain.size(); break;
   }
   if (!out) {
     *bytes = n;

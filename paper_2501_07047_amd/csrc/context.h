@@ -22,6 +22,9 @@ struct Plan {
   int8_t *fwd_left = nullptr, *fwd_right = nullptr, *inv_left = nullptr, *inv_right = nullptr;
   uint32_t *fwd_tw = nullptr, *inv_tw = nullptr, *bf_fwd = nullptr, *bf_inv = nullptr;
   int8_t *row_fwd_b = nullptr, *row_fwd_c = nullptr, *row_inv_c = nullptr, *row_inv_b = nullptr;
+  int8_t *row_fwd_b_plain = nullptr, *row_fwd_c_plain = nullptr;   // without the Montgomery factor
+  int8_t *row_inv_c_plain = nullptr, *row_inv_b_plain = nullptr;
+  uint32_t bar_m = 0, bar_k = 0;              // Barrett constants: floor(2^(2k) / q), k = bit length
   uint32_t *row_fwd_t3 = nullptr, *row_inv_t3 = nullptr, *inv_tw_rows = nullptr;
   uint32_t bf_ninv = 0;
   void* block = nullptr;
@@ -59,6 +62,7 @@ struct cross_ctx_s {
   std::map<int, std::pair<int, int>> split3;  // log_n -> (log_r, log_c1); log_c1 = 0: two factors
                                               // (absent: the size's default)
   int gemm_tile = 0;                          // GemmTile override (0 = auto)
+  int ntt_reduction = 0;                      // row-kernel epilogue: 0 Montgomery, 1 Barrett
   std::map<int, int> tile_by_logn;            // autotuned GemmTile per transform size
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)

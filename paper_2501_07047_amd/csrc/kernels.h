@@ -57,9 +57,12 @@ struct RowsJob {
   const uint32_t* tw2;      // inverse only: (w, w') pairs [R][C] after the second sub-step
   uint64_t off;             // element offset of the job's limb
   uint32_t q, qinv;
+  uint32_t bar_m, bar_k;    // Barrett epilogue: floor(2^(2k) / q), k = bit length of q
 };
+// red: epilogue reduction of both sub-steps, 0 = Montgomery REDC (tables carry 2^32),
+// 1 = Barrett (plain tables).
 hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
-                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, hipStream_t s);
+                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, int red, hipStream_t s);
 // Whether (log_r, log_c1, log_n - log_r - log_c1) is a split the row kernels implement.
 bool rows_split_supported(int log_n, int log_r, int log_c1);
 

@@ -64,6 +64,31 @@ __device__ __forceinline__ uint32_t merge_redc(const v16i& a, int j, uint32_t q,
   return hi + q - __umulhi(lo * qinv, q);
 }
 
+// ChunkMerge and Barrett reduction (Alg. barrett) for plain tables: with k = bit
+// length of q, z = x + w 2^14 < 2^44 <= 2^(2k), the quotient estimate
+// ((z >> (k - 1)) * floor(2^(2k) / q)) >> (k + 1) is short by at most 2: [0, q).
+__device__ __forceinline__ uint32_t merge_barrett(const v16i& a, int j, uint32_t q, uint32_t bar_m, uint32_t bar_k) {
+  const uint32_t x = (uint32_t)a[4 * j] + ((uint32_t)a[4 * j + 1] << 7);
+  const uint32_t w = (uint32_t)a[4 * j + 2] + ((uint32_t)a[4 * j + 3] << 7);
+  const uint32_t wl = w << 14;
+  const uint32_t lo = x + wl;
+  const uint32_t hi = (w >> 18) + (lo < wl ? 1u : 0u);
+  const uint32_t zh = (hi << (33 - bar_k)) | (lo >> (bar_k - 1));
+  const uint32_t t = (uint32_t)(((uint64_t)zh * bar_m) >> (bar_k + 1));
+  uint32_t r = lo - t * q;
+  r = r >= q ? r - q : r;
+  return r >= q ? r - q : r;
+}
+
+// Epilogue reduction of register group j: RED = 0 Montgomery (0, 2q), 1 Barrett [0, q).
+template <int RED>
+__device__ __forceinline__ uint32_t merge_reduce(const v16i& a, int j, const RowsJob& jb) {
+  if constexpr (RED == 0)
+    return merge_redc(a, j, jb.q, jb.qinv);
+  else
+    return merge_barrett(a, j, jb.q, jb.bar_m, jb.bar_k);
+}
+
 __device__ __forceinline__ uint32_t shoup_tw(uint32_t r, v2u tw, uint32_t q) {
   const uint32_t v = r * tw.x - __umulhi(r, tw.y) * q;      // [0, 2q)
   return v >= q ? v - q : v;
@@ -180,7 +205,7 @@ __device__ __forceinline__ void write_rows(const uint32_t* xs, __amdgpu_buffer_r
   }
 }
 
-template <int C1, int C2>
+template <int C1, int C2, int RED>
 __global__ void __launch_bounds__(64 * kRowsWaves, (RowsShape<C1, C2>::OCC))
 ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly, int log_r) {
   using S = RowsShape<C1, C2>;
@@ -202,7 +227,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
     stage<S::NT>(tab2s, P.job.tab2, 16 * C2 * C2);
   }
   stage<S::NT>(tws, P.job.tw1, 8 * C);
-  const uint32_t q = P.job.q, qinv = P.job.qinv;
+  const uint32_t q = P.job.q;
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   __syncthreads();
@@ -228,7 +253,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
       for (int j = 0; j < 4; ++j) {
         const int m0 = mb * 8 + 2 * j;
         const v2u w = *reinterpret_cast<const v2u*>(&twl[m0 * C2 * 2]);
-        zl[m0 * S::ZP1] = pack7(shoup_tw(merge_redc(acc[mb], j, q, qinv), w, q));
+        zl[m0 * S::ZP1] = pack7(shoup_tw(merge_reduce<RED>(acc[mb], j, P.job), w, q));
       }
   }
   __syncthreads();
@@ -259,7 +284,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
       for (int mb = 0; mb < MB2; ++mb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint32_t r = merge_redc(acc2[i][mb], j, q, qinv);
+          const uint32_t r = merge_reduce<RED>(acc2[i][mb], j, P.job);
           xl[mb * 8 + 2 * j] = r >= q ? r - q : r;
         }
     }
@@ -268,7 +293,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   write_rows<C1, C2>(xs, rout);
 }
 
-template <int C1, int C2>
+template <int C1, int C2, int RED>
 __global__ void __launch_bounds__(64 * kRowsWaves, (RowsShape<C1, C2>::OCC))
 ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly, int log_r) {
   using S = RowsShape<C1, C2>;
@@ -292,7 +317,7 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
     stage<S::NT>(tab2s, P.job.tab2, 16 * C1 * C1);
   }
   stage<S::NT>(tws, P.job.tw1, 8 * C);
-  const uint32_t q = P.job.q, qinv = P.job.qinv;
+  const uint32_t q = P.job.q;
   const int lane = threadIdx.x & 63, h = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   __syncthreads();
@@ -315,7 +340,7 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
       for (int j = 0; j < 4; ++j) {
         const int c0 = mb * 8 + 2 * j;
         const v2u w = *reinterpret_cast<const v2u*>(&twl[c0 * C1 * 2]);
-        zl[c0 * S::ZP2] = pack7(shoup_tw(merge_redc(acc[mb], j, q, qinv), w, q));
+        zl[c0 * S::ZP2] = pack7(shoup_tw(merge_reduce<RED>(acc[mb], j, P.job), w, q));
       }
   }
   __syncthreads();
@@ -349,7 +374,7 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
         for (int j = 0; j < 4; ++j) {
           const int c0 = mb * 8 + 2 * j;
           const v2u w = __builtin_amdgcn_raw_buffer_load_b64(tw2, twl, c0 * C2 * 8, 0);
-          xl[c0 * S::XP] = pack7(shoup_tw(merge_redc(acc2[i][mb], j, q, qinv), w, q));
+          xl[c0 * S::XP] = pack7(shoup_tw(merge_reduce<RED>(acc2[i][mb], j, P.job), w, q));
         }
     }
   }
@@ -357,17 +382,17 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   write_rows<C1, C2>(xs, rout);
 }
 
-template <int C1, int C2>
+template <int C1, int C2, int RED>
 hipError_t rows_cfg(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
                     int npoly, int log_r, bool inverse, hipStream_t s) {
   using S = RowsShape<C1, C2>;
   if ((1 << log_r) % S::BR) return hipErrorInvalidValue;
   const int grid = njobs * npoly * ((1 << log_r) / S::BR);
   if (inverse)
-    hipLaunchKernelGGL((ntt_rows_inv_kernel<C1, C2>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
+    hipLaunchKernelGGL((ntt_rows_inv_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
                        log_r);
   else
-    hipLaunchKernelGGL((ntt_rows_fwd_kernel<C1, C2>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
+    hipLaunchKernelGGL((ntt_rows_fwd_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
                        log_r);
   return hipGetLastError();
 }
@@ -375,12 +400,15 @@ hipError_t rows_cfg(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t
 }  // namespace
 
 hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
-                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, hipStream_t s) {
+                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, int red, hipStream_t s) {
+  if (red != 0 && red != 1) return hipErrorInvalidValue;
   if (njobs <= 0 || npoly <= 0) return hipSuccess;
   // per-lane offsets are 32-bit within a workgroup's 32 KB of rows
   if (stride >= (1ull << 40)) return hipErrorInvalidValue;
-#define CROSS_ROWS(a, b) \
-  if (log_c1 == a && log_c2 == b) return rows_cfg<(1 << a), (1 << b)>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s);
+#define CROSS_ROWS(a, b)                                                                                    \
+  if (log_c1 == a && log_c2 == b)                                                                         \
+    return red ? rows_cfg<(1 << a), (1 << b), 1>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s)   \
+               : rows_cfg<(1 << a), (1 << b), 0>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s);
   CROSS_ROWS(4, 4)
   CROSS_ROWS(4, 5)
   CROSS_ROWS(5, 4)

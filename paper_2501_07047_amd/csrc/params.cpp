@@ -92,15 +92,15 @@ uint32_t bitrev(uint32_t x, int bits) {
 }
 
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
-                std::vector<int8_t>& out) {
+                std::vector<int8_t>& out, bool montgomery) {
   const int M = kChunks * n_out, K = kChunks * n_in;
   if (n_in <= 0 || n_out <= 0 || K % kTileK != 0 || M % 32 != 0 || (size_t)T.size() != (size_t)n_in * n_out)
     throw std::invalid_argument("bat_expand: table shape does not tile");
   out.assign((size_t)M * K, 0);
-  const uint64_t r32 = ((uint64_t)1 << 32) % q;
+  const uint64_t r32 = montgomery ? ((uint64_t)1 << 32) % q : 1;
   for (int in = 0; in < n_in; ++in) {
     for (int o = 0; o < n_out; ++o) {
-      uint64_t t = (uint64_t)T[(size_t)in * n_out + o] * r32 % q;  // Montgomery form
+      uint64_t t = (uint64_t)T[(size_t)in * n_out + o] * r32 % q;  // Montgomery form unless plain
       for (int j = 0; j < kChunks; ++j) {
         uint64_t v = (t << (kChunkBits * j)) % q;                 // a * 2^(bp j) mod q
         for (int i = 0; i < kChunks; ++i) {
@@ -185,6 +185,11 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
     bat_expand(tc, C2, C2, q, t.row_fwd_c);
     bat_expand(itc, C2, C2, q, t.row_inv_c);
     bat_expand(itb, C1, C1, q, t.row_inv_b);
+    // the same four without the Montgomery factor, for the Barrett epilogue
+    bat_expand(tb, C1, C1, q, t.row_fwd_b_plain, false);
+    bat_expand(tc, C2, C2, q, t.row_fwd_c_plain, false);
+    bat_expand(itc, C2, C2, q, t.row_inv_c_plain, false);
+    bat_expand(itb, C1, C1, q, t.row_inv_b_plain, false);
     t.row_fwd_t3.resize((size_t)2 * C);
     t.row_inv_t3.resize((size_t)2 * C);
     for (uint32_t m = 0; m < C1; ++m)

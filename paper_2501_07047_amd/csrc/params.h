@@ -24,7 +24,8 @@ std::vector<int8_t> lazy_fragment(uint32_t q);
 uint32_t bitrev(uint32_t x, int bits);
 
 // BAT-expanded table of a pre-known residue matrix T (rows = "in", cols = "out"):
-// dense int8 matrix D[m = out*4 + i][k = in*4 + j] = chunk_i((T[in][out] * 2^32 * 2^(7j)) mod q),
+// dense int8 matrix D[m = out*4 + i][k = in*4 + j] = chunk_i((T[in][out] * 2^32 * 2^(7j)) mod q)
+// (without the factor 2^32 when montgomery is false),
 // stored in MFMA fragment order (M = 4 * n_out): for 64-deep K slab s = k / 64 and
 // 32-row block b = m / 32, two 1 KB fragments (K halves h = (k % 64) / 32) of the
 // v_mfma_i32_32x32x32_i8 A operand, byte (m, k) at
@@ -32,7 +33,7 @@ uint32_t bitrev(uint32_t x, int bits);
 // so a workgroup's rows of one K slab are contiguous and load in lane order.
 // Throws std::invalid_argument unless 4 * n_in is a multiple of 64.
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
-                std::vector<int8_t>& out);
+                std::vector<int8_t>& out, bool montgomery = true);
 
 struct NttTables {
   // forward: step 1 (left-known, rows), step 2 twiddle, step 3 (right-known, cols)
@@ -43,6 +44,8 @@ struct NttTables {
   // three factors (row transform split as C1 x C2): BAT tables of the two row
   // sub-steps and their twiddle pairs, plus the inverse step-2 twiddles row-major
   std::vector<int8_t> row_fwd_b, row_fwd_c, row_inv_c, row_inv_b;
+  // the same four without the Montgomery factor (Barrett epilogue)
+  std::vector<int8_t> row_fwd_b_plain, row_fwd_c_plain, row_inv_c_plain, row_inv_b_plain;
   std::vector<uint32_t> row_fwd_t3, row_inv_t3, inv_tw_rows;
 };
 // with_bat = false builds only the butterfly twiddles (sizes below the MFMA minimum).

@@ -251,3 +251,42 @@ def test_three_factor_split_errors():
     for bad in ((12, 4, 4), (16, 6, 3), (16, 3, 6)):
         with pytest.raises(B.CrossError):
             B.set_ntt_split3(*bad)
+
+
+# Barrett epilogue in the row kernels (plain tables) for every row-kernel family:
+# LDS tables (16 x 16, 32 x 32, 64 x 32) and global-memory tables (64 x 64)
+@pytest.mark.parametrize("log_n,log_r,log_c1,L,batch", [(13, 5, 4, 2, 1), (16, 6, 5, 3, 2), (16, 5, 6, 1, 1),
+                                                        (16, 4, 6, 1, 1)])
+def test_three_factor_barrett_epilogue_matches_oracle(log_n, log_r, log_c1, L, batch):
+    from paper_2501_07047_amd import binding as B
+    B.set_ntt_split3(log_n, log_r, log_c1)
+    B.set_ntt_reduction("barrett")
+    try:
+        primes, x = synthetic.ntt_batch(300 + log_n + log_c1, log_n, L, batch)
+        x[0, :, 0] = [q - 1 for q in primes]
+        ref = _oracle_ntt(x, primes)
+        d = to_dev(x)
+        B.ntt_forward(d, primes)
+        assert np.array_equal(to_host(d), ref)
+        B.ntt_inverse(d, primes)
+        assert np.array_equal(to_host(d), x)
+    finally:
+        B.set_ntt_reduction("montgomery")
+        B.set_ntt_split3(log_n, 0, 0)
+
+
+def test_barrett_epilogue_rejects_small_primes():
+    # 65537 = 2^16 + 1 is NTT-friendly for N = 2^13 but below the 2^21 the Barrett epilogue needs
+    from paper_2501_07047_amd import binding as B
+    B.set_ntt_split3(13, 5, 4)
+    B.set_ntt_reduction("barrett")
+    try:
+        d = to_dev(np.zeros((1, 1, 1 << 13), dtype=np.uint32))
+        with pytest.raises(B.CrossError) as e:
+            B.ntt_forward(d, [65537])
+        assert e.value.code == -7
+    finally:
+        B.set_ntt_reduction("montgomery")
+        B.set_ntt_split3(13, 0, 0)
+    with pytest.raises(KeyError):
+        B.set_ntt_reduction("shoup")

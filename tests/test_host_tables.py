@@ -28,11 +28,12 @@ def _chunks_rows(X):
     return out
 
 
-def _merge_reduce(P, q):
+def _merge_reduce(P, q, plain=False):
+    # ChunkMerge, then the tables' Montgomery factor 2^32 divided out (plain tables: none)
     U = P.shape[0] // 4
     Z = sum(P[i::4].astype(object) << (7 * i) for i in range(4))
     assert int(np.max(P)) < (1 << 31) and int(np.min(P)) >= 0
-    rinv = pow(1 << 32, -1, q)
+    rinv = 1 if plain else pow(1 << 32, -1, q)
     return np.array((Z * rinv) % q, dtype=np.uint64).reshape(U, -1)
 
 
@@ -122,7 +123,7 @@ def test_bat_lazy_fragment_returns_each_lanes_chunk_products_in_lane():
                 assert lazy == bat_lazy_reduce(int(p[l, t]), q) and lazy % q == int(p[l, t]) % q
 
 
-def _emulate3(X, q, log_n, log_r, log_c1, inverse):
+def _emulate3(X, q, log_n, log_r, log_c1, inverse, plain=False):
     # three factors: the row-side step with the library's step-1 tables, then the
     # row transform with its row tables (cross_host_row_tables), in the kernels'
     # operand roles; Montgomery factors as in _emulate
@@ -139,7 +140,9 @@ def _emulate3(X, q, log_n, log_r, log_c1, inverse):
     def twist(Y, tw):
         return np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
 
-    rt = lambda w: binding.host_row_tables(q, log_n, log_r, log_c1, w)
+    # row tables 0-3, or their plain forms 8-11 (Barrett epilogue)
+    rt = lambda w: binding.host_row_tables(q, log_n, log_r, log_c1, w + 8 if plain and w < 4 else w)
+    mr = lambda P: _merge_reduce(P, q, plain)
     if not inverse:
         t1 = _dense(binding.host_tables(q, log_n, log_r, 0), 4 * R, 4 * R)
         Y = twist(_merge_reduce(t1 @ _chunks_rows(X.reshape(R, C)), q), mont(rt(7).reshape(R, C, 2)))
@@ -147,8 +150,8 @@ def _emulate3(X, q, log_n, log_r, log_c1, inverse):
         t3 = mont(rt(4).reshape(C1, C2, 2))
         out = np.empty((R, C), dtype=np.uint64)
         for k in range(R):
-            Z = twist(_merge_reduce(tb @ _chunks_rows(Y[k].reshape(C1, C2)), q), t3)     # [m][c2]
-            out[k] = _merge_reduce(tc @ _chunks_rows(Z.T), q).T.reshape(-1)             # [m][c2']
+            Z = twist(mr(tb @ _chunks_rows(Y[k].reshape(C1, C2))), t3)                   # [m][c2]
+            out[k] = mr(tc @ _chunks_rows(Z.T)).T.reshape(-1)                           # [m][c2']
         return out.reshape(-1)
     itc, itb = _dense(rt(2), 4 * C2, 4 * C2), _dense(rt(3), 4 * C1, 4 * C1)
     it3 = mont(rt(5).reshape(C2, C1, 2))         # [c2][m]
@@ -156,15 +159,16 @@ def _emulate3(X, q, log_n, log_r, log_c1, inverse):
     X = X.reshape(R, C1, C2)
     Y = np.empty((R, C), dtype=np.uint64)
     for k in range(R):
-        Z = twist(_merge_reduce(itc @ _chunks_rows(X[k].T), q), it3)                     # [c2][m]
-        Yk = _merge_reduce(itb @ _chunks_rows(Z.T), q)                                   # [c1][c2]
+        Z = twist(mr(itc @ _chunks_rows(X[k].T)), it3)                                   # [c2][m]
+        Yk = mr(itb @ _chunks_rows(Z.T))                                                 # [c1][c2]
         Y[k] = twist(Yk.reshape(-1), it2[k])
     t1 = _dense(binding.host_tables(q, log_n, log_r, 2), 4 * R, 4 * R)
     return _merge_reduce(t1 @ _chunks_rows(Y), q).reshape(-1)
 
 
+@pytest.mark.parametrize("plain", [False, True])
 @pytest.mark.parametrize("log_n,log_r,log_c1", [(13, 5, 4), (14, 6, 4), (15, 5, 5), (16, 6, 5), (14, 4, 5)])
-def test_emulated_three_factor_ntt_matches_oracle(log_n, log_r, log_c1):
+def test_emulated_three_factor_ntt_matches_oracle(log_n, log_r, log_c1, plain):
     n = 1 << log_n
     q = prime_chain(1)[0]
     psi = psi_of(q, n)
@@ -172,8 +176,8 @@ def test_emulated_three_factor_ntt_matches_oracle(log_n, log_r, log_c1):
     a = g.integers(0, q, n).astype(np.uint64)
     a[0] = q - 1
     ref = ntt_ct(a, q, psi)
-    assert np.array_equal(_emulate3(a, q, log_n, log_r, log_c1, False), ref)
-    assert np.array_equal(_emulate3(ref, q, log_n, log_r, log_c1, True), a)
+    assert np.array_equal(_emulate3(a, q, log_n, log_r, log_c1, False, plain), ref)
+    assert np.array_equal(_emulate3(ref, q, log_n, log_r, log_c1, True, plain), a)
 
 
 def test_row_split_limits():
