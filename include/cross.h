@@ -393,12 +393,17 @@ void cross_batch_destroy(cross_batch batch);
 
 /*
  * Kernel timing with HIP events (tracing aid).  While enabled, every kernel
- * launch the library makes is bracketed by a pair of events recorded on the
- * launch stream.  cross_profile_report synchronises on the recorded events
- * and writes one line per kernel family, "name launches total_ms\n", into
- * `buf` (NUL-terminated, truncated to `len`), then clears the record.
+ * launch the library makes (or, after cross_profile_only, every launch of one
+ * kernel family) carries a pair of events that the dispatch itself stamps at
+ * kernel start and end on the launch stream (hipExtLaunchKernel; graph launches
+ * of the batch runtime are bracketed by recorded events instead).
+ * cross_profile_report synchronises on the events and writes one line per
+ * kernel family, "name launches total_ms\n", into `buf` (NUL-terminated,
+ * truncated to `len`), then clears the record.  cross_profile_only(ctx, name)
+ * limits timing to the family `name` (NULL or "": all families).
  */
 cross_status cross_profile_enable(cross_ctx ctx, int enable);
+cross_status cross_profile_only(cross_ctx ctx, const char* family);
 cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len);
 
 /*

@@ -70,6 +70,7 @@ SIGNATURES = {
     "cross_batch_destroy": [c_vp],
     "cross_measure_peak": [c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
     "cross_profile_enable": [c_vp, ctypes.c_int],
+    "cross_profile_only": [c_vp, ctypes.c_char_p],
     "cross_profile_report": [c_vp, ctypes.c_char_p, ctypes.c_uint64],
     "cross_host_tables": [c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
 }
@@ -261,6 +262,12 @@ def measure_peak(which, device=None):
 def profile_enable(enable=True, device=None):
     ctx = context(device)
     _check(lib().cross_profile_enable(ctx, 1 if enable else 0), ctx)
+
+
+def profile_only(family=None, device=None):
+    """Time only the kernel family `family` (None: all families)."""
+    ctx = context(device)
+    _check(lib().cross_profile_only(ctx, (family or "").encode()), ctx)
 
 
 def profile_report(device=None):

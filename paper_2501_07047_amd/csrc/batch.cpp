@@ -466,7 +466,7 @@ cross_status cross_batch_run(cross_batch b, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (b->exec) {
-    ProfScope ps(ctx, "batch_graph", s);
+    ProfScope ps(ctx, "batch_graph", s, true);
     e = hipGraphLaunch(b->exec, s);
   } else {
     e = run_phases(b, s, true);

@@ -366,7 +366,7 @@ inline unsigned blocks_for(uint64_t total, int per = 256) { return (unsigned)((t
 hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
                          const LimbMod* mods, int L, int log_n, int B, hipStream_t s) {
   const uint64_t total4 = ((uint64_t)B * L) << (log_n - 2);
-  hipLaunchKernelGGL(tensor_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
+  launch_kernel(tensor_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
                      (const v4u*)b, (v4u*)out, (v4u*)d2, mods, L, log_n - 2, total4);
   return hipGetLastError();
 }
@@ -376,7 +376,7 @@ hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32
                                 hipStream_t s) {
   const uint64_t groups = (uint64_t)(B + kIpCts - 1) / kIpCts;
   const uint64_t total4 = (groups * LK) << (log_n - 2);
-  hipLaunchKernelGGL(inner_product_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
+  launch_kernel(inner_product_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
                      (const v4u*)ext, (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2, B,
                      total4);
   return hipGetLastError();
@@ -387,7 +387,7 @@ hipError_t launch_moddown_tail(const uint32_t* acc, uint64_t acc_stride, const u
                                const TailConst* tc, int L, int log_n, int npoly,
                                bool base_only_even, hipStream_t s) {
   const uint64_t total4 = ((uint64_t)npoly * L) << (log_n - 2);
-  hipLaunchKernelGGL(moddown_tail_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
+  launch_kernel(moddown_tail_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
                      (const v4u*)acc, acc_stride / 4, (const v4u*)z, (const v4u*)base, (v4u*)out,
                      out_stride / 4, tc, L, log_n - 2, total4, base_only_even);
   return hipGetLastError();
@@ -397,7 +397,7 @@ hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t*
                                uint64_t out_stride, const uint32_t* perm, int log_n, int L,
                                int npoly, hipStream_t s) {
   const uint64_t total = ((uint64_t)npoly * L) << log_n;
-  hipLaunchKernelGGL(automorphism_kernel, dim3(blocks_for(total)), dim3(256), 0, s, in, in_stride,
+  launch_kernel(automorphism_kernel, dim3(blocks_for(total)), dim3(256), 0, s, in, in_stride,
                      out, out_stride, perm, log_n, L, total);
   return hipGetLastError();
 }
@@ -405,7 +405,7 @@ hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t*
 hipError_t launch_pointwise_mul(const uint32_t* a, const uint32_t* b, uint32_t* out,
                                 const LimbMod* mods, int L, int log_n, int B, hipStream_t s) {
   const uint64_t total4 = ((uint64_t)B * L) << (log_n - 2);
-  hipLaunchKernelGGL(pointwise_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
+  launch_kernel(pointwise_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
                      (const v4u*)b, (v4u*)out, mods, L, log_n - 2, total4);
   return hipGetLastError();
 }
@@ -413,7 +413,7 @@ hipError_t launch_pointwise_mul(const uint32_t* a, const uint32_t* b, uint32_t* 
 hipError_t launch_pointwise_add(const uint32_t* a, const uint32_t* b, uint32_t* out,
                                 const LimbMod* mods, int L, int log_n, int npoly, hipStream_t s) {
   const uint64_t total4 = ((uint64_t)npoly * L) << (log_n - 2);
-  hipLaunchKernelGGL(pointwise_add_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
+  launch_kernel(pointwise_add_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
                      (const v4u*)b, (v4u*)out, mods, L, log_n - 2, total4);
   return hipGetLastError();
 }
@@ -422,7 +422,7 @@ hipError_t launch_limb_copy(const uint32_t* src, uint64_t src_stride, const uint
                             uint32_t* dst, uint64_t dst_stride, const uint64_t* dst_off, int nl,
                             int log_n, int npoly, hipStream_t s) {
   const uint64_t total4 = ((uint64_t)npoly * nl) << (log_n - 2);
-  hipLaunchKernelGGL(limb_copy_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)src,
+  launch_kernel(limb_copy_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)src,
                      src_stride / 4, src_off, (v4u*)dst, dst_stride / 4, dst_off, nl, log_n - 2,
                      total4);
   return hipGetLastError();
@@ -430,39 +430,39 @@ hipError_t launch_limb_copy(const uint32_t* src, uint64_t src_stride, const uint
 
 hipError_t launch_tensor_list(const TensorTask* t, int n, uint64_t max4, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tensor_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  launch_kernel(tensor_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 hipError_t launch_auto_list(const AutoTask* t, int n, uint64_t max_count, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(auto_list_kernel, dim3(blocks_for(max_count), n), dim3(256), 0, s, t);
+  launch_kernel(auto_list_kernel, dim3(blocks_for(max_count), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 hipError_t launch_copy_list(const CopyTask* t, int n, uint64_t max4, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  launch_kernel(copy_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 hipError_t launch_inner_list(const InnerTask* t, int n, uint64_t max4, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(inner_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  launch_kernel(inner_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 hipError_t launch_tail_list(const TailTask* t, int n, uint64_t max4, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(tail_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
+  launch_kernel(tail_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_waves, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bconv_list_kernel, dim3(blocks_for(max_waves * 64), n), dim3(256), 0, s, t);
+  launch_kernel(bconv_list_kernel, dim3(blocks_for(max_waves * 64), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
 
 hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s) {
   if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5) return hipErrorInvalidValue;
   const uint64_t waves = ((uint64_t)b.npoly << b.log_n) / 32;
-  hipLaunchKernelGGL(bconv_kernel, dim3(blocks_for(waves * 64)), dim3(256), 0, s, b);
+  launch_kernel(bconv_kernel, dim3(blocks_for(waves * 64)), dim3(256), 0, s, b);
   return hipGetLastError();
 }
 

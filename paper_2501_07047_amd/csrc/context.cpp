@@ -21,17 +21,48 @@ cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n) {
   return CROSS_OK;
 }
 
-ProfScope::ProfScope(cross_ctx c, const char* name, hipStream_t st) : ctx(c), s(st) {
-  if (!ctx || !ctx->prof) return;
-  cross_ctx_s::ProfRec r{name, nullptr, nullptr};
-  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
-  (void)hipEventRecord(r.a, s);
+LaunchEvents& launch_events() {
+  thread_local LaunchEvents ev;
+  return ev;
+}
+
+ProfScope::ProfScope(cross_ctx c, const char* name, hipStream_t st, bool mk) : ctx(c), s(st), markers(mk) {
+  if (!ctx || !ctx->prof || (!ctx->prof_only.empty() && ctx->prof_only != name)) return;
+  cross_ctx_s::ProfRec r{name, nullptr, nullptr, false};
+  // events come from the context's pool (creating events per launch costs more host
+  // time than the launches themselves)
+  auto take = [&](hipEvent_t* e) {
+    if (!ctx->prof_pool.empty()) {
+      *e = ctx->prof_pool.back();
+      ctx->prof_pool.pop_back();
+      return true;
+    }
+    return hipEventCreate(e) == hipSuccess;
+  };
+  if (!take(&r.a)) return;
+  if (!take(&r.b)) {
+    ctx->prof_pool.push_back(r.a);
+    return;
+  }
+  if (markers) {
+    (void)hipEventRecord(r.a, s);
+  } else {
+    prev = launch_events();
+    launch_events() = LaunchEvents{r.a, r.b, 0};
+  }
   idx = (int)ctx->prof_recs.size();
   ctx->prof_recs.push_back(r);
 }
 
 ProfScope::~ProfScope() {
-  if (idx >= 0) (void)hipEventRecord(ctx->prof_recs[idx].b, s);
+  if (idx < 0) return;
+  auto& r = ctx->prof_recs[idx];
+  if (markers) {
+    r.valid = hipEventRecord(r.b, s) == hipSuccess;
+  } else {
+    r.valid = launch_events().stamped > 0;
+    launch_events() = prev;
+  }
 }
 
 int split_of(cross_ctx ctx, int log_n) {
@@ -423,6 +454,11 @@ void cross_ctx_destroy(cross_ctx ctx) {
   for (auto& kv : ctx->job_cache) (void)hipFree(kv.second);
   for (auto& kv : ctx->const_cache) (void)hipFree(kv.second);
   for (auto& kv : ctx->workspace) (void)hipFree(kv.second.ptr);
+  for (auto& r : ctx->prof_recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -512,19 +548,24 @@ cross_status cross_profile_enable(cross_ctx ctx, int enable) {
   return CROSS_OK;
 }
 
+cross_status cross_profile_only(cross_ctx ctx, const char* family) {
+  if (!ctx) return CROSS_EINVAL;
+  ctx->prof_only = family ? family : "";
+  return CROSS_OK;
+}
+
 cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len) {
   if (!ctx || !buf || len == 0) return CROSS_EINVAL;
   std::map<std::string, std::pair<long, double>> agg;
   for (auto& r : ctx->prof_recs) {
     float ms = 0.f;
-    (void)hipEventSynchronize(r.b);
-    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+    if (r.valid && hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       auto& x = agg[r.name];
       x.first += 1;
       x.second += ms;
     }
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+    ctx->prof_pool.push_back(r.a);
+    ctx->prof_pool.push_back(r.b);
   }
   ctx->prof_recs.clear();
   std::string out;

@@ -42,11 +42,17 @@ struct Status {
 };
 
 // Event bracket around one kernel launch (no-op unless profiling is enabled).
+// The library's kernel launches inside the scope stamp its events from their
+// dispatches (no extra queue packets); with markers = true (a scope around work
+// that is not launched by the library, such as a graph launch) the events are
+// recorded on the stream instead.
 struct ProfScope {
   cross_ctx ctx;
   hipStream_t s;
   int idx = -1;
-  ProfScope(cross_ctx c, const char* name, hipStream_t st);
+  bool markers = false;
+  LaunchEvents prev;
+  ProfScope(cross_ctx c, const char* name, hipStream_t st, bool markers = false);
   ~ProfScope();
 };
 
@@ -67,11 +73,14 @@ struct cross_ctx_s {
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)
   bool prof = false;
+  std::string prof_only;                      // time only this kernel family ("" = all)
   struct ProfRec {
     std::string name;
     hipEvent_t a, b;
+    bool valid;           // both events were stamped by this scope
   };
   std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> prof_pool;          // events of finished reports, reused
 };
 
 namespace cross {

@@ -1,9 +1,33 @@
 // Internal interface between the host library and the HIP kernels.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 
 namespace cross {
+
+// Profiling events of the innermost enabled ProfScope of this thread (null when
+// profiling is off).  The scope's first launch stamps `start`, every launch
+// stamps `stop`, both from the dispatch itself (hipExtLaunchKernel), so timing
+// adds no packets to the queue.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int stamped = 0;          // launches that stamped the events
+};
+LaunchEvents& launch_events();
+
+template <typename F, typename... Args>
+inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+  LaunchEvents& ev = launch_events();
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (ev.stop && hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, ev.start, ev.stop, 0u, args...);
+    ev.start = nullptr;
+    ++ev.stamped;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+  }
+}
 
 // One limb of one BAT NTT step: all `npoly` polynomials of the limb share the
 // prime and therefore the table.  Offsets are in uint32 elements from the

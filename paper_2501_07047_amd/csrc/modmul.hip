@@ -131,20 +131,20 @@ hipError_t launch_vec_modmul(const uint32_t* a, const uint32_t* w, const uint32_
   v4u* vo = (v4u*)out;
   switch (method) {
     case kModredBarrett:
-      hipLaunchKernelGGL(vec_modmul_kernel<kModredBarrett>, grid, block, 0, s, va, vw, vq, vo, limbs,
+      launch_kernel(vec_modmul_kernel<kModredBarrett>, grid, block, 0, s, va, vw, vq, vo, limbs,
                          (const v4i*)lazy, L, log_n - 2, total4);
       break;
     case kModredMontgomery:
-      hipLaunchKernelGGL(vec_modmul_kernel<kModredMontgomery>, grid, block, 0, s, va, vw, vq, vo, limbs,
+      launch_kernel(vec_modmul_kernel<kModredMontgomery>, grid, block, 0, s, va, vw, vq, vo, limbs,
                          (const v4i*)lazy, L, log_n - 2, total4);
       break;
     case kModredShoup:
-      hipLaunchKernelGGL(vec_modmul_kernel<kModredShoup>, grid, block, 0, s, va, vw, vq, vo, limbs,
+      launch_kernel(vec_modmul_kernel<kModredShoup>, grid, block, 0, s, va, vw, vq, vo, limbs,
                          (const v4i*)lazy, L, log_n - 2, total4);
       break;
     case kModredBatLazy:
       if (log_n < 8) return hipErrorInvalidValue;
-      hipLaunchKernelGGL(vec_modmul_kernel<kModredBatLazy>, grid, block, 0, s, va, vw, vq, vo, limbs,
+      launch_kernel(vec_modmul_kernel<kModredBatLazy>, grid, block, 0, s, va, vw, vq, vo, limbs,
                          (const v4i*)lazy, L, log_n - 2, total4);
       break;
     default:
@@ -156,7 +156,7 @@ hipError_t launch_vec_modmul(const uint32_t* a, const uint32_t* w, const uint32_
 hipError_t launch_modmul_prepare(const uint32_t* w, uint32_t* w_prep, uint32_t* w_quot, const ModLimb* limbs,
                                  int L, int log_n, int method, hipStream_t s) {
   const uint64_t total = (uint64_t)L << log_n;
-  hipLaunchKernelGGL(modmul_prepare_kernel, dim3(blocks_for(total)), dim3(256), 0, s, w, w_prep, w_quot, limbs,
+  launch_kernel(modmul_prepare_kernel, dim3(blocks_for(total)), dim3(256), 0, s, w, w_prep, w_quot, limbs,
                      log_n, method, total);
   return hipGetLastError();
 }

@@ -76,7 +76,7 @@ hipError_t launch_butterfly(const ButterflyJob* jobs, int njobs, uint32_t* data,
   for (int st = 0; st < log_n; ++st) {
     // forward: m = 1, 2, ..., N/2; inverse: m = N/2, ..., 1
     int log_m = inverse ? (log_n - 1 - st) : st;
-    hipLaunchKernelGGL(bf_stage_kernel, grid, dim3(256), 0, s, jobs, data, stride, npoly, log_n,
+    launch_kernel(bf_stage_kernel, grid, dim3(256), 0, s, jobs, data, stride, npoly, log_n,
                        log_m, inverse, inverse && st == log_n - 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -565,7 +565,7 @@ struct StagedCfg {
     constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
+    launch_kernel((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
                        dim3(WM * WN * 64), 0, s, g, tm, tn);
     return hipGetLastError();
   }
@@ -579,7 +579,7 @@ struct DirectCfg {
     constexpr int BM = WA * MA * 32, BN = WN * NBD * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, 2 * BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((bat_gemm_direct_kernel<WA, WN, MA, NBD, OCC, KS, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
+    launch_kernel((bat_gemm_direct_kernel<WA, WN, MA, NBD, OCC, KS, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
                        dim3(WA * WN * 64), 0, s, g, tm, tn);
     return hipGetLastError();
   }
@@ -609,7 +609,7 @@ template <bool RIGHT, bool INP, bool OUTP, bool TW>
 hipError_t launch_list_cfg(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
                            hipStream_t s) {
   // 256 x 128 tiles, 8 waves of 64 x 64, two workgroups per CU
-  hipLaunchKernelGGL((bat_gemm_list_kernel<4, 2, 2, 2, 4, 1, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(512), 0, s,
+  launch_kernel((bat_gemm_list_kernel<4, 2, 2, 2, 4, 1, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(512), 0, s,
                      tasks, tiles, ntiles);
   return hipGetLastError();
 }

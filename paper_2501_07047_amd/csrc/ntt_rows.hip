@@ -389,10 +389,10 @@ hipError_t rows_cfg(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t
   if ((1 << log_r) % S::BR) return hipErrorInvalidValue;
   const int grid = njobs * npoly * ((1 << log_r) / S::BR);
   if (inverse)
-    hipLaunchKernelGGL((ntt_rows_inv_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
+    launch_kernel((ntt_rows_inv_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
                        log_r);
   else
-    hipLaunchKernelGGL((ntt_rows_fwd_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
+    launch_kernel((ntt_rows_fwd_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
                        log_r);
   return hipGetLastError();
 }

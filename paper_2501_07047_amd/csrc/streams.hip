@@ -155,7 +155,7 @@ inline unsigned blocks_for(uint64_t total) { return (unsigned)((total + 255) / 2
 hipError_t launch_evk_bat_prepare(const uint32_t* key, uint32_t* key_bat, const StreamMod* mods, int LK, int dnum,
                                   int log_n, hipStream_t s) {
   const uint64_t total = ((uint64_t)dnum * 2 * LK) << log_n;
-  hipLaunchKernelGGL(evk_bat_prepare_kernel, dim3(blocks_for(total)), dim3(256), 0, s, key, (v4u*)key_bat, mods,
+  launch_kernel(evk_bat_prepare_kernel, dim3(blocks_for(total)), dim3(256), 0, s, key, (v4u*)key_bat, mods,
                      LK, log_n, total);
   return hipGetLastError();
 }
@@ -164,7 +164,7 @@ hipError_t launch_inner_product_bat(const uint32_t* ext, const uint32_t* key_bat
                                     const StreamMod* mods, int LK, int dnum, int log_n, int B, hipStream_t s) {
   const uint64_t groups = (uint64_t)(B + kIpBatch - 1) / kIpBatch;
   const uint64_t total = (groups * LK) << log_n;
-  hipLaunchKernelGGL(inner_product_bat_kernel, dim3(blocks_for(total)), dim3(256), 0, s, ext, (const v4u*)key_bat,
+  launch_kernel(inner_product_bat_kernel, dim3(blocks_for(total)), dim3(256), 0, s, ext, (const v4u*)key_bat,
                      acc, mods, LK, dnum, log_n, B, total);
   return hipGetLastError();
 }
@@ -173,7 +173,7 @@ hipError_t launch_tensor_conv(const uint32_t* a, const uint32_t* b, uint32_t* ou
                               const StreamMod* mods, int L, int log_n, int B, hipStream_t s) {
   if (log_n < 2) return hipErrorInvalidValue;
   const uint64_t total4 = ((uint64_t)B * L) << (log_n - 2);
-  hipLaunchKernelGGL(tensor_conv_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a, (const v4u*)b,
+  launch_kernel(tensor_conv_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a, (const v4u*)b,
                      (v4u*)out, (v4u*)d2, mods, L, log_n - 2, total4);
   return hipGetLastError();
 }
