@@ -234,6 +234,14 @@ cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan
 }
 
 cross_status perm_table(cross_ctx ctx, int log_n, uint32_t g, const uint32_t** out) {
+  // one device table per (N, g), looked up by that key: building and hashing the
+  // N-entry permutation on every call would cost more than the automorphism itself
+  const std::string key = "perm:" + std::to_string(log_n) + ":" + std::to_string(g);
+  auto it = ctx->const_cache.find(key);
+  if (it != ctx->const_cache.end()) {
+    *out = (const uint32_t*)it->second;
+    return CROSS_OK;
+  }
   const uint32_t N = 1u << log_n;
   std::vector<uint32_t> perm(N);
   for (uint32_t p = 0; p < N; ++p) {
@@ -241,9 +249,17 @@ cross_status perm_table(cross_ctx ctx, int log_n, uint32_t g, const uint32_t** o
     perm[p] = bitrev((uint32_t)((e - 1) / 2), log_n);
   }
   void* d = nullptr;
-  cross_status st = cached_device_copy(ctx, perm.data(), perm.size() * 4, &d);
+  if (hipMalloc(&d, perm.size() * 4) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, CROSS_ENOMEM, "hipMalloc of the automorphism table failed");
+  }
+  if (hipMemcpy(d, perm.data(), perm.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return fail(ctx, CROSS_EDEVICE, "automorphism table upload failed");
+  }
+  ctx->const_cache[key] = d;
   *out = (const uint32_t*)d;
-  return st;
+  return CROSS_OK;
 }
 
 namespace {
