@@ -163,6 +163,24 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
   constexpr int SROW = BU + 4;            // padded LDS row (words)
   const uint32_t row_words = RIGHT ? g.R : g.C;         // output row length (transposed when RIGHT)
 
+  // All twiddle pairs of this lane are loaded before the first store: issued next
+  // to their use, each load would wait behind the stores before it (the compiler
+  // cannot tell the twiddle table from the output), one round trip per output.
+  v2u twv[TW ? MB : 1][TW ? NB : 1][4];
+  if constexpr (TW) {
+#pragma unroll
+    for (int a = 0; a < MB; ++a) {
+      const int u0 = (m0 + (wm * MB + a) * 32) / 4 + (lane >> 5);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int n = n0 + (wn * NB + b) * 32 + (lane & 31);
+        const uint32_t tw_off = ((uint32_t)u0 * V + (n & (V - 1))) * 8;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) twv[a][b][j] = __builtin_amdgcn_raw_buffer_load_b64(rs_tw, tw_off, j * 2 * V * 8, 0);
+      }
+    }
+  }
+
   auto body = [&](auto wide_tag) {
     constexpr bool WIDE = decltype(wide_tag)::value;
 #pragma unroll
@@ -197,7 +215,7 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
           uint32_t r = zhi + q - __umulhi(zlo * qinv, q);
           if (TW) {
             // Shoup multiplication by the pre-known twiddle (w, floor(w 2^32 / q)): [0, 2q)
-            const v2u tw = __builtin_amdgcn_raw_buffer_load_b64(rs_tw, tw_off, j * 2 * V * 8, 0);
+            const v2u tw = twv[TW ? a : 0][TW ? b : 0][j];
             r = r * tw.x - __umulhi(r, tw.y) * q;
           }
           r = r >= q ? r - q : r;
