@@ -290,3 +290,22 @@ def test_barrett_epilogue_rejects_small_primes():
         B.set_ntt_split3(13, 0, 0)
     with pytest.raises(KeyError):
         B.set_ntt_reduction("shoup")
+
+
+@pytest.mark.parametrize("log_n,batch", [(13, 3), (16, 1)])
+def test_max_limbs_three_factor(log_n, batch):
+    # L = 64 limbs (the library's limit) through the default three-factor split; an odd
+    # polynomial count at N = 2^13, spot limbs at N = 2^16
+    from paper_2501_07047_amd import binding as B
+    primes, x = synthetic.ntt_batch(400 + log_n, log_n, 64, batch)
+    d = to_dev(x)
+    B.ntt_forward(d, primes)
+    got = to_host(d)
+    limbs = range(64) if log_n == 13 else (0, 31, 63)
+    for i in limbs:
+        assert np.array_equal(got[:, i], _oracle_ntt(x[:, i:i + 1], primes[i:i + 1])[:, 0])
+    B.ntt_inverse(d, primes)
+    assert np.array_equal(to_host(d), x)
+    with pytest.raises(B.CrossError):
+        p65, x65 = synthetic.ntt_batch(1, 13, 65, 1)
+        B.ntt_forward(to_dev(x65), p65)
