@@ -150,6 +150,33 @@ def modred_bench(B, reps):
     return res
 
 
+def wide_prime_bench(B, reps):
+    """Forward + inverse NTT at N=2^16, L=24, 16 polynomials with the largest primes below
+    2^28 (narrow form) and below 2^31 (wide form: byte operands, signed-digit tables);
+    microseconds per pair, both measured in the same run."""
+    import numpy as np
+    import torch
+    import synthetic
+    res = {}
+    for name, primes in (("narrow_28bit", synthetic.primes(L)), ("wide_31bit", synthetic.wide_primes(L))):
+        x = synthetic.residues(synthetic.rng(12), (16,), primes, 1 << LOG_N)
+        d = torch.from_numpy(x.view(np.int32)).cuda()
+        for _ in range(3):
+            B.ntt_forward(d, primes)
+            B.ntt_inverse(d, primes)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            B.ntt_forward(d, primes)
+            B.ntt_inverse(d, primes)
+        e1.record()
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        res[name] = {"us_fwd_inv": round(us, 2), "limb_ntt_per_s": round(2 * L * 16 / us * 1e6),
+                     "bits_per_limb": max(primes).bit_length()}
+    return res
+
+
 def ntt_reduction_bench(B, reps):
     """Forward + inverse NTT at N=2^16, L=24 (64 x 32 x 32) with the row kernels' epilogue
     reduction Montgomery vs Barrett, for 1, 4 and 16 polynomials (the NTT side of
@@ -493,6 +520,9 @@ def main():
                                                "epilogue Montgomery (tables x 2^32, REDC) vs Barrett "
                                                "(plain tables); key = polynomials per call",
                                      "methods": ntt_reduction_bench(B, max(10, args.steps))}
+    line["wide_prime_ntt"] = {"config": "NTT+INTT at N=2^16, L=24, 16 polynomials, default split; "
+                                        "largest primes < 2^28 vs < 2^31 (1 mod 2^17)",
+                              "forms": wide_prime_bench(B, max(10, args.steps))}
     line["stream_ablation"] = {"config": "key-switch inner product (N=2^16, L+K=32, dnum=3; key plain vs "
                                          "BAT-expanded, 16 B per residue) and tensor product (N=2^16, L=24; "
                                          "32-bit vs byte-convolution products), per call for 1 and 8 "

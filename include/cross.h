@@ -15,7 +15,9 @@
  *    NTT delivers its output directly in bit-reversed order).  psi is the
  *    canonical primitive 2N-th root g^((q-1)/2N), g the smallest generator of
  *    Z_q^* (see cross_root).
- *  - Primes: 2 < q < 2^28, prime, q = 1 (mod 2N).  Arrays of primes are host
+ *  - Primes: 2 < q < 2^28, prime, q = 1 (mod 2N).  The NTT entry points
+ *    (cross_ntt_forward/inverse and their butterfly forms) also take wide
+ *    primes 2^28 <= q < 2^31 (see cross_ntt_forward).  Arrays of primes are host
  *    memory.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls return
  *    after enqueueing; argument errors are reported synchronously and nothing
@@ -40,7 +42,8 @@ typedef enum cross_status {
   CROSS_EINVAL = -1,       /* bad argument (null pointer, size, alignment, layout) */
   CROSS_ENOTPRIME = -2,    /* a modulus is not prime */
   CROSS_ENOROOT = -3,      /* q != 1 (mod 2N): no primitive 2N-th root of unity */
-  CROSS_ERANGE = -4,       /* q >= 2^28 (residues must split into four 7-bit chunks) */
+  CROSS_ERANGE = -4,       /* q >= 2^28 (residues must split into four 7-bit chunks); for
+                              the NTT entry points q >= 2^31 */
   CROSS_ENOMEM = -5,       /* device allocation failed */
   CROSS_EDEVICE = -6,      /* HIP runtime error while enqueueing */
   CROSS_EUNSUPPORTED = -7  /* valid but unsupported shape */
@@ -59,7 +62,8 @@ void cross_ctx_destroy(cross_ctx ctx);
 /* Text of the last error on ctx (valid until the next call on ctx). */
 const char* cross_last_error(cross_ctx ctx);
 
-/* Canonical psi for (q, N = 2^log_n): *psi_out = g^((q-1)/2N).  Validates q. */
+/* Canonical psi for (q, N = 2^log_n): *psi_out = g^((q-1)/2N).  Validates q
+ * (any prime the NTT takes, q < 2^31). */
 cross_status cross_root(uint32_t q, uint32_t log_n, uint32_t* psi_out);
 
 /* Force the 3-step split N = R x C with R = 2^log_r for transforms of size
@@ -121,9 +125,16 @@ cross_status cross_set_gemm_tile(cross_ctx ctx, int tile);
  * Steps 1 and 3 run as BAT-expanded int8 MFMA GEMMs; step 2 is fused into the
  * epilogue of step 1.  Uses batch*L*N*4 bytes of context workspace.
  *   log_n  : 4..16 (log_n >= 8 runs on MFMA; smaller sizes use the butterfly kernels)
- *   primes : host array of L primes (see conventions)
+ *   primes : host array of L primes (see conventions); q < 2^31
  *   L      : 1..CROSS_MAX_LIMBS;  batch >= 1
  *   data   : device, uint32 [batch][L][2^log_n]
+ * Wide primes (2^28 <= q < 2^31; Sec. BAT with bp = 8 as the paper uses it):
+ * the runtime side is cut into its four bytes, fed to the signed int8 MFMA as
+ * b - 128, the pre-known side into balanced signed 8-bit digits, and each
+ * accumulator starts at a per-row correction 128 * (row sum); the partial sums
+ * are merged in 64 bits and reduced with a signed Montgomery step.  Limbs of
+ * both kinds may be mixed in one call (they run as two groups).  With
+ * CROSS_NTT_RED_BARRETT, wide primes fail with CROSS_EUNSUPPORTED.
  */
 cross_status cross_ntt_forward(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
                                uint32_t batch, uint32_t* data, void* stream);
@@ -426,6 +437,11 @@ cross_status cross_measure_peak(cross_ctx ctx, int which, double* out);
  *                  ((k/64)*(M/32) + m/32)*2048 + ((k%64)/32)*1024
  *                  + 16*(m%32 + 32*((k%32)/16)) + k%16
  *                  (Alg. bat_deployment, DirectScalarBAT with the Montgomery factor folded in)
+ *                  For a wide prime (2^28 <= q < 2^31): entry = balanced digit i (in
+ *                  [-128, 127]) of the representative of (T[x][u] * 2^32 * 2^(8j)) mod q
+ *                  in [-128*0x1010101, 127*0x1010101] (the residue itself unless above
+ *                  that range), same order, followed by M int32 row corrections
+ *                  128 * sum_k (m, k) at byte M*K + 4m
  *   which 4/5    : uint32 step-2 twiddles as (w, floor(w*2^32/q)) pairs (Shoup
  *                  multiplication), forward [R][C][2] and inverse transposed [C][R][2]
  *                  (Sec. MAT, layout-invariant 3-step NTT)
@@ -434,7 +450,8 @@ cross_status cross_measure_peak(cross_ctx ctx, int which, double* out);
  *                  at 16*l + e holds, for row = l%32, K byte kb = 16*(l/32) + e,
  *                  s = kb/4, j = kb%4, chunk row%4 of 2^(7(4+j)) mod q if
  *                  row/4 == 2*(s%4) + s/4, else 0 (App. "BAT for Modular Reduction")
- * Returns CROSS_EINVAL for a bad `which`, split or buffer size.
+ * Returns CROSS_EINVAL for a bad `which`, split or buffer size, CROSS_ERANGE for
+ * q >= 2^31 (which 6: q >= 2^28).
  */
 cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,
                                void* out, uint64_t* bytes);
@@ -448,7 +465,8 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
  *                            merged chunk sums (Alg. montgomery_reduction)
  *   CROSS_NTT_RED_BARRETT    : tables without the factor, Barrett reduction of the
  *                            merged sums (Alg. barrett); NTT calls whose primes lie
- *                            below 2^21 then fail with CROSS_EUNSUPPORTED
+ *                            below 2^21 or at or above 2^28 then fail with
+ *                            CROSS_EUNSUPPORTED
  * Returns CROSS_EINVAL for another method.
  */
 typedef enum { CROSS_NTT_RED_MONTGOMERY = 0, CROSS_NTT_RED_BARRETT = 1 } cross_ntt_reduction;
@@ -464,7 +482,7 @@ cross_status cross_set_ntt_reduction(cross_ctx ctx, int method);
  *               IT3, [C2][C1][2] (c2, m)
  *   which 6/7 : uint32 pairs of the inverse / forward step-2 twiddles, row-major [R][C][2]
  *   which 8-11: the tables of which 0-3 without the Montgomery factor 2^32
- *               (CROSS_NTT_RED_BARRETT)
+ *               (CROSS_NTT_RED_BARRETT; CROSS_EINVAL for wide primes, which have none)
  */
 cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,
                                    void* out, uint64_t* bytes);

@@ -14,8 +14,9 @@ cross_status fail(cross_ctx ctx, cross_status code, const std::string& msg) {
   return code;
 }
 
-cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n) {
-  if (q >= (1u << 28)) return fail(ctx, CROSS_ERANGE, "modulus " + std::to_string(q) + " >= 2^28");
+cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n, bool wide_ok) {
+  if (q >= kWidePrimeLimit || (!wide_ok && wide_prime(q)))
+    return fail(ctx, CROSS_ERANGE, "modulus " + std::to_string(q) + (wide_ok ? " >= 2^31" : " >= 2^28"));
   if (q < 3 || !is_prime_u32(q)) return fail(ctx, CROSS_ENOTPRIME, "modulus " + std::to_string(q) + " is not prime");
   if ((q - 1) % (2ull << log_n)) return fail(ctx, CROSS_ENOROOT, "modulus " + std::to_string(q) + " != 1 mod 2N");
   return CROSS_OK;
@@ -182,6 +183,7 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool all
   p->log_r = log_r;
   p->log_c1 = log_c1;
   p->bf_ninv = t.bf_ninv;
+  p->wide = wide_prime(q);
   ctx->plans[key] = p;
   *out = p;
   return CROSS_OK;
@@ -235,9 +237,12 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
   const int log_n = plans[0]->log_n, log_r = plans[0]->log_r, log_c1 = plans[0]->log_c1;
   const int log_c2 = log_n - log_r - log_c1;
   const int red = ctx->ntt_reduction;
+  const bool wide = plans[0]->wide;
   if (red == 1)
-    for (const Plan* p : plans)
+    for (const Plan* p : plans) {
       if (p->bar_k < 22) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett row epilogue needs primes >= 2^21");
+      if (p->wide) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett row epilogue needs primes < 2^28");
+    }
   std::vector<RowsJob> rj(plans.size());
   std::vector<GemmJob> gj(plans.size());
   for (size_t i = 0; i < plans.size(); ++i) {
@@ -263,6 +268,7 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
   g.log_r = log_r;
   g.log_c = log_n - log_r;
   g.kind = kLeft;
+  g.wide = wide;
   g.tile = ctx->gemm_tile;
   if (g.tile == 0) {
     auto it = ctx->tile_by_logn.find(log_n);
@@ -273,7 +279,7 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
     {
       ProfScope ps(ctx, "ntt_rows", s);
       e = launch_ntt_rows((const RowsJob*)dr, (int)plans.size(), in, out, stride, npoly, log_r, log_c1, log_c2,
-                          inverse, red, s);
+                          inverse, red, wide, s);
     }
     if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("row transform launch: ") + hipGetErrorString(e));
     return CROSS_OK;
@@ -307,6 +313,21 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   if (plans.empty()) return CROSS_OK;
   const int log_n = plans[0]->log_n;
   const int log_r = plans[0]->log_r;
+  if (log_n >= 8) {
+    // one launch takes one operand form: wide and narrow limbs go in two groups
+    bool mixed = false;
+    for (const Plan* p : plans) mixed |= p->wide != plans[0]->wide;
+    if (mixed) {
+      std::vector<Plan*> pw, pn;
+      std::vector<uint64_t> ow, on;
+      for (size_t i = 0; i < plans.size(); ++i) {
+        (plans[i]->wide ? pw : pn).push_back(plans[i]);
+        (plans[i]->wide ? ow : on).push_back(offs[i]);
+      }
+      cross_status st = ntt_limbs(ctx, pn, on, data, stride, npoly, inverse, tmp, s);
+      return st != CROSS_OK ? st : ntt_limbs(ctx, pw, ow, data, stride, npoly, inverse, tmp, s);
+    }
+  }
   if (log_n < 8) {
     // below the MFMA minimum (4R >= 64): radix-2 kernels, in place
     std::vector<ButterflyJob> jobs(plans.size());
@@ -342,6 +363,7 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   g.npoly = npoly;
   g.log_r = log_r;
   g.log_c = log_n - log_r;
+  g.wide = plans[0]->wide;
   g.tile = ctx->gemm_tile;
   if (g.tile == 0) {
     auto it = ctx->tile_by_logn.find(log_n);
@@ -387,7 +409,7 @@ static cross_status ntt_common(cross_ctx ctx, uint32_t log_n, const uint32_t* pr
   if (batch < 1) return fail(ctx, CROSS_EINVAL, "batch must be >= 1");
   if (reinterpret_cast<uintptr_t>(data) & 15) return fail(ctx, CROSS_EINVAL, "data not 16-byte aligned");
   for (uint32_t i = 0; i < L; ++i) {
-    cross_status st = check_prime(ctx, primes[i], log_n);
+    cross_status st = check_prime(ctx, primes[i], log_n, true);
     if (st != CROSS_OK) return st;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
@@ -466,7 +488,7 @@ const char* cross_last_error(cross_ctx ctx) { return ctx ? ctx->err.c_str() : "n
 
 cross_status cross_root(uint32_t q, uint32_t log_n, uint32_t* psi_out) {
   if (!psi_out || log_n < 1 || log_n > 26) return CROSS_EINVAL;
-  cross_status st = check_prime(nullptr, q, log_n);
+  cross_status st = check_prime(nullptr, q, log_n, true);
   if (st != CROSS_OK) return st;
   *psi_out = root_2n(q, log_n);
   return CROSS_OK;
@@ -585,8 +607,9 @@ cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, u
   if (!bytes || which > 11 || log_n > CROSS_MAX_LOG_N || log_r > log_n ||
       !rows_split_supported((int)log_n, (int)log_r, (int)log_c1))
     return CROSS_EINVAL;
-  cross_status st = check_prime(nullptr, q, log_n);
+  cross_status st = check_prime(nullptr, q, log_n, true);
   if (st != CROSS_OK) return st;
+  if (which >= 8 && wide_prime(q)) return CROSS_EINVAL;     // no plain tables in the wide form
   NttTables t;
   try {
     build_ntt_tables(q, log_n, log_r, t, true, log_c1);
@@ -623,7 +646,7 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
                                void* out, uint64_t* bytes) {
   if (!bytes || which > 6 || log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4)
     return CROSS_EINVAL;
-  cross_status st = check_prime(nullptr, q, log_n);
+  cross_status st = check_prime(nullptr, q, log_n, which != 6);
   if (st != CROSS_OK) return st;
   NttTables t;
   std::vector<int8_t> lazy;

@@ -27,6 +27,7 @@ struct Plan {
   uint32_t bar_m = 0, bar_k = 0;              // Barrett constants: floor(2^(2k) / q), k = bit length
   uint32_t *row_fwd_t3 = nullptr, *row_inv_t3 = nullptr, *inv_tw_rows = nullptr;
   uint32_t bf_ninv = 0;
+  bool wide = false;        // 2^28 <= q < 2^31: signed-digit tables, byte operands
   void* block = nullptr;
 };
 
@@ -86,7 +87,9 @@ struct cross_ctx_s {
 namespace cross {
 
 cross_status fail(cross_ctx ctx, cross_status code, const std::string& msg);
-cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n);
+// wide_ok: the NTT also takes wide primes, 2^28 <= q < 2^31 (every other operation
+// needs q < 2^28).
+cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n, bool wide_ok = false);
 // allow3 = false keeps the two-factor form even where a three-factor split is set
 // (the batch runtime's work lists implement two factors only).
 cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3 = true);

@@ -58,6 +58,7 @@ struct GemmLaunch {
   bool in_packed, out_packed, twiddle;
   int tile;                // GemmTile; kTileAuto picks by shape and grid size
   bool in_rows;            // row side, packed input stored row-major (three-factor inverse)
+  bool wide;               // wide primes (2^28 <= q < 2^31): byte operands, signed-digit tables
 };
 
 // Workgroup tile shapes of the BAT GEMM (rows x columns of the int8 product).
@@ -84,9 +85,11 @@ struct RowsJob {
   uint32_t bar_m, bar_k;    // Barrett epilogue: floor(2^(2k) / q), k = bit length of q
 };
 // red: epilogue reduction of both sub-steps, 0 = Montgomery REDC (tables carry 2^32),
-// 1 = Barrett (plain tables).
+// 1 = Barrett (plain tables).  wide: primes 2^28 <= q < 2^31 (byte operands,
+// signed-digit tables with row corrections; red must be 0).
 hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
-                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, int red, hipStream_t s);
+                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, int red, bool wide,
+                           hipStream_t s);
 // Whether (log_r, log_c1, log_n - log_r - log_c1) is a split the row kernels implement.
 bool rows_split_supported(int log_n, int log_r, int log_c1);
 

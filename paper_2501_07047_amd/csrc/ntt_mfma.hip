@@ -13,6 +13,14 @@
 // step-2 twiddle, and finishes with one conditional subtraction (the final
 // reduction the paper assigns to Barrett; one subtraction suffices here).
 //
+// Wide primes (2^28 <= q < 2^31, template flag WIDE): residues are cut into
+// their four bytes instead, each entering the signed MFMA as b - 128 (one XOR
+// per word); the table holds balanced signed 8-bit digits and, after its bytes,
+// one int32 correction 128 * (row sum) per row, which starts the accumulator;
+// the epilogue merges the four signed sums with weights 2^(8i) in 64 bits and
+// reduces with a signed Montgomery step.  Intermediates ("packed") are then
+// the biased bytes.
+//
 // GEMM view (M x K times K x Ncols):
 //   A[m][k]: pre-known, m = 4*u + i (output u, output chunk i), k = 4*x + j (input x, chunk j)
 //   B[k][n]: chunk j of data element x of column n;  n = poly * V + v
@@ -43,6 +51,18 @@ constexpr int BK = 64;            // K per MFMA step
 __device__ __forceinline__ uint32_t pack_chunks(uint32_t x) {
   // four 7-bit chunks of x (< 2^28) in the four bytes of one word
   return (x & 0x7fu) | ((x << 1) & 0x7f00u) | ((x << 2) & 0x7f0000u) | ((x << 3) & 0x7f000000u);
+}
+
+// Wide form: the four bytes of x, each biased to b - 128.
+__device__ __forceinline__ uint32_t bias_bytes(uint32_t x) { return x ^ 0x80808080u; }
+
+// Data operand of a residue in either form.
+template <bool WIDE>
+__device__ __forceinline__ uint32_t to_operand(uint32_t x) {
+  if constexpr (WIDE)
+    return bias_bytes(x);
+  else
+    return pack_chunks(x);
 }
 
 // Raw buffer resource over [base, base + bytes): range-checked per access.
@@ -139,8 +159,40 @@ __device__ __forceinline__ v4i load_b_piece(__amdgpu_buffer_rsrc_t rs, uint32_t 
   return w;
 }
 
+template <bool WIDE>
 __device__ __forceinline__ v4i pack4(v4i w) {
-  return v4i{(int)pack_chunks(w.x), (int)pack_chunks(w.y), (int)pack_chunks(w.z), (int)pack_chunks(w.w)};
+  return v4i{(int)to_operand<WIDE>(w.x), (int)to_operand<WIDE>(w.y), (int)to_operand<WIDE>(w.z),
+             (int)to_operand<WIDE>(w.w)};
+}
+
+// Wide form: accumulator start of NA 32-row blocks from table row row0 on, the
+// row corrections (int32, after the M x K table bytes) of the rows lane `lane`
+// holds, 8 (v / 4) + 4 (lane / 32) + v % 4 of each block.
+template <int NA>
+__device__ __forceinline__ void corr_init(v16i (&init)[NA], const int8_t* table, int M, int K, int row0, int lane) {
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(table + (size_t)M * K, (uint64_t)M * 4);
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const v4i c = (v4i)__builtin_amdgcn_raw_buffer_load_b128(
+          rs, (uint32_t)(row0 + a * 32 + 8 * j + 4 * (lane >> 5)) * 4, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) init[a][4 * j + i] = c[i];
+    }
+}
+
+// Wide form: merge of the four signed digit sums (weights 2^(8i)) and signed
+// Montgomery reduction to [0, q).  |z| < U * 1020 * 2^31.01 < 2^53 for U <= 4096,
+// so (z - m q) / 2^32 = (z >> 32) - umulhi(m, q) lies in (-q - 2^21, 2^21], and
+// two conditional additions of q (q > 2^21) bring it to [0, q).
+__device__ __forceinline__ uint32_t merge_redc_wide(int s0, int s1, int s2, int s3, uint32_t q, uint32_t qinv) {
+  const int64_t z = (int64_t)s0 + ((int64_t)s1 << 8) + ((int64_t)s2 << 16) + ((int64_t)s3 << 24);
+  const uint32_t m = (uint32_t)z * qinv;
+  int64_t r = (z >> 32) - (int64_t)__umulhi(m, q);
+  if (r < 0) r += q;
+  if (r < 0) r += q;
+  return (uint32_t)r;
 }
 
 // ---- epilogue: ChunkMerge + REDC (+ twiddle) + final subtraction ------------
@@ -149,7 +201,8 @@ __device__ __forceinline__ v4i pack4(v4i w) {
 // they are staged in LDS (free after the last K stage; `so` must hold
 // BN x (BM/4 + 4) words) as [column v][row u] and written back row by row, 16
 // bytes per lane.
-template <int NT, int BM, int BN, int MB, int NB, bool RIGHT, bool OUT_PACKED, bool TW, bool NARROW_ONLY = false>
+template <int NT, int BM, int BN, int MB, int NB, bool RIGHT, bool OUT_PACKED, bool TW, bool NARROW_ONLY = false,
+          bool WIDE = false>
 __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const TileArgs& t, const StepShape& g,
                                               int wm, int wn, uint32_t* so) {
   const int tid = threadIdx.x, lane = tid & 63;
@@ -182,7 +235,7 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
   }
 
   auto body = [&](auto wide_tag) {
-    constexpr bool WIDE = decltype(wide_tag)::value;
+    constexpr bool WIDE_MERGE = decltype(wide_tag)::value;   // 64-bit ChunkMerge (narrow primes, U > 512)
 #pragma unroll
     for (int a = 0; a < MB; ++a) {
       const int u0 = (m0 + (wm * MB + a) * 32) / 4 + (lane >> 5);   // output of register group 0
@@ -193,14 +246,17 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
         const uint32_t dpoly = (uint32_t)((n >> log_v) - poly0), v = n & (V - 1);
         // register group j holds output u0 + 2j: consecutive groups are 2 rows apart
         const uint32_t out_off = (dpoly * (uint32_t)t.dst_stride + (uint32_t)u0 * row_words + v) * 4;
-        const uint32_t tw_off = ((uint32_t)u0 * V + v) * 8;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const v16i& sv = acc[a][b];
           const uint32_t s0 = (uint32_t)sv[4 * j], s1 = (uint32_t)sv[4 * j + 1];
           const uint32_t s2 = (uint32_t)sv[4 * j + 2], s3 = (uint32_t)sv[4 * j + 3];
+          uint32_t r;
+          if constexpr (WIDE) {
+            r = merge_redc_wide(sv[4 * j], sv[4 * j + 1], sv[4 * j + 2], sv[4 * j + 3], q, qinv);   // [0, q)
+          } else {
           uint32_t zlo, zhi;
-          if (!WIDE) {
+          if (!WIDE_MERGE) {
             // z = x + w * 2^14 with x = s0 + s1 * 2^7 and w = s2 + s3 * 2^7 (both < 2^32)
             const uint32_t x = s0 + (s1 << 7), w = s2 + (s3 << 7);
             const uint32_t wl = w << 14;
@@ -212,14 +268,15 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
             zhi = (uint32_t)(z >> 32);
           }
           // Montgomery REDC of z (the 2^32 factor was folded into the table): (0, 2q)
-          uint32_t r = zhi + q - __umulhi(zlo * qinv, q);
+          r = zhi + q - __umulhi(zlo * qinv, q);
+          }
           if (TW) {
             // Shoup multiplication by the pre-known twiddle (w, floor(w 2^32 / q)): [0, 2q)
             const v2u tw = twv[TW ? a : 0][TW ? b : 0][j];
             r = r * tw.x - __umulhi(r, tw.y) * q;
           }
           r = r >= q ? r - q : r;
-          if (OUT_PACKED) r = pack_chunks(r);
+          if (OUT_PACKED) r = to_operand<WIDE>(r);
           if (STAGE_OUT) {
             so[nl * SROW + (u0 + 2 * j - m0 / 4)] = r;
           } else {
@@ -233,7 +290,7 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
   };
   // Chunk partial sums are below K * 127 * 127 = 4U * 127^2; for U <= 512 the
   // two half-merges x and w fit 32 bits, larger U merges in 64 bits.
-  if (NARROW_ONLY || g.U <= 512) body(std::false_type{});
+  if (NARROW_ONLY || WIDE || g.U <= 512) body(std::false_type{});
   else body(std::true_type{});
 
   if (STAGE_OUT) {
@@ -260,7 +317,7 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
 // residues are cut into 7-bit chunks on the way into LDS; packed data is
 // copied as is.
 template <int WM, int WN, int MB, int NB, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
-          bool PROWS = false>
+          bool PROWS = false, bool WIDE = false>
 __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8_t* lds_b) {
   constexpr int NW = WM * WN;
   constexpr int NT = NW * 64;
@@ -315,7 +372,7 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
 #pragma unroll
       for (int i = 0; i < B_PIECES; ++i)
         *reinterpret_cast<v4i*>(lds_b + st * STAGE_B + sl * SLAB_B + (tid + i * NT) * 16) =
-            IN_PACKED ? rb[sl][i] : pack4(rb[sl][i]);
+            IN_PACKED ? rb[sl][i] : pack4<WIDE>(rb[sl][i]);
     }
   };
   auto compute = [&](int st) {
@@ -345,6 +402,16 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
   load(0);
   store_lds(0);
   if (nk > 1) load(1);
+  if constexpr (WIDE) {
+    // accumulators start at the row corrections (loaded after the first stages,
+    // so they do not add to the prologue's live registers)
+    v16i init[MB];
+    corr_init<MB>(init, t.table, M, K, m0 + wm * MB * 32, lane);
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[a][b] = init[a];
+  }
   __syncthreads();
   for (int ks = 0; ks < nk; ++ks) {
     compute(ks & 1);
@@ -352,7 +419,8 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
     if (ks + 2 < nk) load(ks + 2);
     __syncthreads();
   }
-  gemm_epilogue<NT, BM, BN, MB, NB, RIGHT, OUT_PACKED, TW>(acc, t, g, wm, wn, reinterpret_cast<uint32_t*>(lds_a));
+  gemm_epilogue<NT, BM, BN, MB, NB, RIGHT, OUT_PACKED, TW, false, WIDE>(acc, t, g, wm, wn,
+                                                                        reinterpret_cast<uint32_t*>(lds_a));
 }
 
 // Direct-table form (contractions of at most 512 inputs, so the ChunkMerge is
@@ -423,7 +491,7 @@ __device__ __forceinline__ void gemm_tile_direct(const TileArgs& t, int8_t* lds)
 #pragma unroll
       for (int i = 0; i < B_PIECES; ++i)
         *reinterpret_cast<v4i*>(lds + st * STAGE_B + sl * SLAB_B + (tid + i * NT) * 16) =
-            IN_PACKED ? rb[sl][i] : pack4(rb[sl][i]);
+            IN_PACKED ? rb[sl][i] : pack4<false>(rb[sl][i]);
   };
   auto compute = [&](int st, const v4i (&a_frag)[KS][2][MA]) {
 #pragma unroll
@@ -506,7 +574,7 @@ __device__ __forceinline__ TileArgs uniform_tile(const GemmLaunch& g, int tiles_
 }
 
 template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
-          bool PROWS>
+          bool PROWS, bool WIDE>
 __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   constexpr int BM = WM * MB * 32;
@@ -514,7 +582,7 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   // two LDS stages of operand fragments (A stages then B stages), reused for output staging
   __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
   const TileArgs t = uniform_tile<BM, BN>(g, tiles_m, tiles_n);
-  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW, PROWS>(t, lds, lds + 2 * BM * 64 * KS);
+  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW, PROWS, WIDE>(t, lds, lds + 2 * BM * 64 * KS);
 }
 
 // LDS bytes of the direct-table form: two stages of data fragments, or the
@@ -578,12 +646,12 @@ bool uniform_grid(const GemmLaunch& g, int kdiv, int& tiles_m, int& tiles_n, int
 // LDS-staged tile: WM x WN waves of MB x NB blocks.
 template <int WM, int WN, int MB, int NB, int OCC, int KS = 1>
 struct StagedCfg {
-  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false>
+  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false, bool WIDE = false>
   static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
     constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
-    launch_kernel((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
+    launch_kernel((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW, PROWS, WIDE>), dim3(grid),
                        dim3(WM * WN * 64), 0, s, g, tm, tn);
     return hipGetLastError();
   }
@@ -592,8 +660,9 @@ struct StagedCfg {
 // Direct-table tile: WA x WN waves of MA x NBD blocks, stages of KS slabs, unrolled by two.
 template <int WA, int WN, int MA, int NBD, int OCC, int KS>
 struct DirectCfg {
-  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false>
+  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false, bool WIDE = false>
   static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
+    static_assert(!WIDE, "the direct tiles merge narrow chunk sums only");
     constexpr int BM = WA * MA * 32, BN = WN * NBD * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, 2 * BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
@@ -603,21 +672,21 @@ struct DirectCfg {
   }
 };
 
-template <class Cfg>
+template <class Cfg, bool WIDE = false>
 hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
   // forward: LEFT(plain in, packed out, twiddle) then RIGHT(packed in, plain out)
   // inverse: RIGHT(plain in, packed out, twiddle) then LEFT(packed in, plain out)
   const bool right = g.kind == kRight;
   if (!right && !g.in_packed && g.out_packed && g.twiddle)
-    return Cfg::template launch<false, false, true, true>(g, s);
+    return Cfg::template launch<false, false, true, true, false, WIDE>(g, s);
   if (right && g.in_packed && !g.out_packed && !g.twiddle)
-    return Cfg::template launch<true, true, false, false>(g, s);
+    return Cfg::template launch<true, true, false, false, false, WIDE>(g, s);
   if (right && !g.in_packed && g.out_packed && g.twiddle)
-    return Cfg::template launch<true, false, true, true>(g, s);
+    return Cfg::template launch<true, false, true, true, false, WIDE>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle && g.in_rows)
-    return Cfg::template launch<false, true, false, false, true>(g, s);
+    return Cfg::template launch<false, true, false, false, true, WIDE>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle)
-    return Cfg::template launch<false, true, false, false>(g, s);
+    return Cfg::template launch<false, true, false, false, false, WIDE>(g, s);
   return hipErrorInvalidValue;
 }
 
@@ -653,6 +722,8 @@ int resolve_gemm_tile(const GemmLaunch& g) {
   const int M = 4 * U;
   const long ncols = (long)g.npoly * V;
   int t = g.tile;
+  // wide primes: the staged 256 x 128 (8 waves), 128 x 64 and 64 x 64 tiles only
+  if (g.wide && t != kTile256x128w8 && t != kTile128x64 && t != kTile64x64) t = kTileAuto;
   if ((t == kTile256x256 || t == kTile256x128w8 || t == kTile256x256w16 || t == kTile256x256w16k2) && M < 256)
     t = kTileAuto;
   if (t == kTile256x128 && M < 256) t = kTileAuto;
@@ -673,6 +744,15 @@ int resolve_gemm_tile(const GemmLaunch& g) {
 hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s) {
   const int U = (g.kind == kRight) ? (1 << g.log_c) : (1 << g.log_r);
   if (4 * U < 64) return hipErrorInvalidValue;
+  if (g.wide) {
+    // wide primes: LDS-staged tiles only (the direct tiles merge in 32 bits)
+    if (U > 4096) return hipErrorInvalidValue;   // the 64-bit merge bound
+    switch (resolve_gemm_tile(g)) {
+      case kTile256x128w8: return dispatch_flags<StagedCfg<4, 2, 2, 2, 4>, true>(g, s);
+      case kTile128x64: return dispatch_flags<StagedCfg<2, 2, 2, 1, 4>, true>(g, s);
+      default: return dispatch_flags<StagedCfg<2, 2, 1, 1, 4>, true>(g, s);
+    }
+  }
   switch (resolve_gemm_tile(g)) {
     case kTile256x256: return dispatch_flags<StagedCfg<2, 4, 4, 2, 2>>(g, s);     // 8 waves of 128x64
     case kTile256x128: return dispatch_flags<StagedCfg<2, 2, 4, 2, 2>>(g, s);     // 4 waves of 128x64

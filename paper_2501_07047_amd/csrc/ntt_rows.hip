@@ -21,6 +21,13 @@
 // loads, so the per-wave memory instructions are the data rows alone (plus the
 // inverse step-2 twiddles); only at C1 = C2 = 64, where the tables do not fit
 // beside the Z tile, are table fragments read from global memory (L1 / L2).
+//
+// Wide primes (2^28 <= q < 2^31, template flag WIDE): the data operand is the
+// four bytes of a residue, each fed as b - 128 (one XOR instead of the 7-bit
+// packing); the tables hold balanced signed 8-bit digits followed by one int32
+// row correction 128 * (row sum) per row, staged with them and used as the
+// accumulators' start; the epilogue merges with weights 2^(8i) in 64 bits and
+// reduces with a signed Montgomery step (Montgomery epilogue only).
 #include "kernels.h"
 
 namespace cross {
@@ -52,6 +59,16 @@ __device__ __forceinline__ uint32_t pack7(uint32_t x) {
   return x + (x & ~0x7fu) + ((x & ~0x3fffu) << 1) + ((x & ~0x1fffffu) << 2);
 }
 
+// Data operand of a residue: four 7-bit chunks, or (wide primes) its four bytes
+// each biased to b - 128.
+template <bool WIDE>
+__device__ __forceinline__ uint32_t operand(uint32_t x) {
+  if constexpr (WIDE)
+    return x ^ 0x80808080u;
+  else
+    return pack7(x);
+}
+
 // ChunkMerge of register group j (the four chunk sums of one output) and REDC:
 // (0, 2q).  Contractions here are at most 256 chunks deep, so both half-merges
 // fit 32 bits.
@@ -80,10 +97,27 @@ __device__ __forceinline__ uint32_t merge_barrett(const v16i& a, int j, uint32_t
   return r >= q ? r - q : r;
 }
 
-// Epilogue reduction of register group j: RED = 0 Montgomery (0, 2q), 1 Barrett [0, q).
-template <int RED>
+// Wide primes: merge of the four signed digit sums (weights 2^(8i)) and signed
+// Montgomery reduction to [0, q).  |z| < 64 * 1020 * 2^31.01 < 2^48, so
+// (z - m q) / 2^32 = (z >> 32) - umulhi(m, q) lies in (-q - 2^16, 2^16], and two
+// conditional additions of q bring it to [0, q).
+__device__ __forceinline__ uint32_t merge_redc_wide(const v16i& a, int j, uint32_t q, uint32_t qinv) {
+  const int64_t z = (int64_t)a[4 * j] + ((int64_t)a[4 * j + 1] << 8) + ((int64_t)a[4 * j + 2] << 16) +
+                    ((int64_t)a[4 * j + 3] << 24);
+  const uint32_t m = (uint32_t)z * qinv;
+  int64_t r = (z >> 32) - (int64_t)__umulhi(m, q);
+  if (r < 0) r += q;
+  if (r < 0) r += q;
+  return (uint32_t)r;
+}
+
+// Epilogue reduction of register group j: RED = 0 Montgomery (0, 2q), 1 Barrett
+// [0, q); wide primes (Montgomery only) [0, q).
+template <int RED, bool WIDE>
 __device__ __forceinline__ uint32_t merge_reduce(const v16i& a, int j, const RowsJob& jb) {
-  if constexpr (RED == 0)
+  if constexpr (WIDE)
+    return merge_redc_wide(a, j, jb.q, jb.qinv);
+  else if constexpr (RED == 0)
     return merge_redc(a, j, jb.q, jb.qinv);
   else
     return merge_barrett(a, j, jb.q, jb.bar_m, jb.bar_k);
@@ -117,10 +151,28 @@ __device__ __forceinline__ auto table(const int8_t* lds, const int8_t* global, i
 // acc[mb] = sum over KS K-steps of table fragment (mb, ks) x B fragment bfrag(ks):
 // the M x K table (M = 32 MB) is in fragment order, fragment (mb, ks) at byte
 // ((ks / 2) * MB + mb) * 2048 + (ks % 2) * 1024, 16 bytes per lane.
-template <int MB, int KS, class TAB, class BF>
+//
+// Wide primes: the M int32 row corrections follow the table (at byte M * K) and
+// start the accumulators; lane l starts register v of block mb at the correction
+// of row mb * 32 + 8 (v / 4) + 4 (l / 32) + v % 4.
+template <int MB, int KS, bool WIDE, class TAB, class BF>
 __device__ __forceinline__ void block_gemm(v16i (&acc)[MB], const TAB& tab, int lane, BF bfrag) {
+  if constexpr (WIDE) {
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb) acc[mb] = v16i{};
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const v4i c = tab(MB * KS * 1024 + (mb * 32 + 8 * j + 4 * (lane >> 5)) * 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[mb][4 * j + i] = c[i];
+      }
+    // the K-step groups below pair table reads with products; the correction
+    // reads stay out of them
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) acc[mb] = v16i{};
+  }
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     const v4i b = bfrag(ks);
@@ -136,7 +188,7 @@ __device__ __forceinline__ void block_gemm(v16i (&acc)[MB], const TAB& tab, int 
   }
 }
 
-template <int C1, int C2>
+template <int C1, int C2, bool WIDE = false>
 struct RowsShape {
   static constexpr int C = C1 * C2;
   static constexpr int NW = kRowsWaves, NT = 64 * kRowsWaves;
@@ -150,9 +202,11 @@ struct RowsShape {
   // two workgroups per CU (4 waves per SIMD, at most 128 registers) where the
   // accumulators allow; the 64-wide splits keep more registers at one
   static constexpr int OCC = (C1 <= 32 && C2 <= 32) ? 4 : 2;
+  // table bytes (wide primes: with their row corrections)
+  static constexpr int TB1 = 16 * C1 * C1 + (WIDE ? 16 * C1 : 0), TB2 = 16 * C2 * C2 + (WIDE ? 16 * C2 : 0);
   // both tables in LDS where they fit beside the Z tile and the twiddles
-  static constexpr bool TAB_LDS = 16 * (C1 * C1 + C2 * C2) + 8 * C + 4 * ZWORDS <= kLdsBytes;
-  static constexpr int T1 = TAB_LDS ? 16 * C1 * C1 : 16, T2 = TAB_LDS ? 16 * C2 * C2 : 16;
+  static constexpr bool TAB_LDS = TB1 + TB2 + 8 * C + 4 * ZWORDS <= kLdsBytes;
+  static constexpr int T1 = TAB_LDS ? TB1 : 16, T2 = TAB_LDS ? TB2 : 16;
   static_assert(C1 >= 16 && C2 >= 16 && BR >= 1 && (NW * 1024) % C == 0, "row split");
 };
 
@@ -205,10 +259,10 @@ __device__ __forceinline__ void write_rows(const uint32_t* xs, __amdgpu_buffer_r
   }
 }
 
-template <int C1, int C2, int RED>
+template <int C1, int C2, int RED, bool WIDE>
 __global__ void __launch_bounds__(64 * kRowsWaves, (RowsShape<C1, C2>::OCC))
 ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly, int log_r) {
-  using S = RowsShape<C1, C2>;
+  using S = RowsShape<C1, C2, WIDE>;
   constexpr int C = S::C, BR = S::BR;
   constexpr int MB1 = C1 / 8, MB2 = C2 / 8;                 // 32-row blocks (M = 4 C1, 4 C2)
   constexpr int NB1 = BR * C2 / 32, NB2 = BR * C1 / 32;     // 32-column blocks of the two sub-steps
@@ -220,11 +274,11 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   const RowsPos P = rows_pos<BR, C>(jobs, stride, npoly, log_r);
   const __amdgpu_buffer_rsrc_t rin = rows_rsrc(in + P.base, (uint64_t)BR * C * 4);
   const __amdgpu_buffer_rsrc_t rout = rows_rsrc(out + P.base, (uint64_t)BR * C * 4);
-  const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, 16 * C1 * C1);
-  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, 16 * C2 * C2);
+  const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, S::TB1);
+  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, S::TB2);
   if constexpr (S::TAB_LDS) {
-    stage<S::NT>(tab1s, P.job.tab1, 16 * C1 * C1);
-    stage<S::NT>(tab2s, P.job.tab2, 16 * C2 * C2);
+    stage<S::NT>(tab1s, P.job.tab1, S::TB1);
+    stage<S::NT>(tab2s, P.job.tab2, S::TB2);
   }
   stage<S::NT>(tws, P.job.tw1, 8 * C);
   const uint32_t q = P.job.q;
@@ -237,7 +291,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
     const int col = cb * 32 + (lane & 31);
     const int row = col / C2, c2 = col % C2;
     v16i acc[MB1];
-    block_gemm<MB1, MB1>(acc, tab1, lane, [&](int ks) {
+    block_gemm<MB1, MB1, WIDE>(acc, tab1, lane, [&](int ks) {
       const uint32_t o = (uint32_t)(row * C + (8 * ks + 4 * h) * C2 + c2) * 4;
       return v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(rin, o, 0, 0),
                  (int)__builtin_amdgcn_raw_buffer_load_b32(rin, o, C2 * 4, 0),
@@ -253,7 +307,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
       for (int j = 0; j < 4; ++j) {
         const int m0 = mb * 8 + 2 * j;
         const v2u w = *reinterpret_cast<const v2u*>(&twl[m0 * C2 * 2]);
-        zl[m0 * S::ZP1] = pack7(shoup_tw(merge_reduce<RED>(acc[mb], j, P.job), w, q));
+        zl[m0 * S::ZP1] = operand<WIDE>(shoup_tw(merge_reduce<RED, WIDE>(acc[mb], j, P.job), w, q));
       }
   }
   __syncthreads();
@@ -266,7 +320,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
     if (cb < NB2) {
       const int col = cb * 32 + (lane & 31);
       const int row = col / C1, m = col % C1;
-      block_gemm<MB2, MB2>(acc2[i], tab2, lane, [&](int ks) {
+      block_gemm<MB2, MB2, WIDE>(acc2[i], tab2, lane, [&](int ks) {
         return *reinterpret_cast<const v4i*>(&zs[(row * C1 + m) * S::ZP1 + 8 * ks + 4 * h]);
       });
     }
@@ -284,7 +338,7 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
       for (int mb = 0; mb < MB2; ++mb)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint32_t r = merge_reduce<RED>(acc2[i][mb], j, P.job);
+          const uint32_t r = merge_reduce<RED, WIDE>(acc2[i][mb], j, P.job);
           xl[mb * 8 + 2 * j] = r >= q ? r - q : r;
         }
     }
@@ -293,10 +347,10 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   write_rows<C1, C2>(xs, rout);
 }
 
-template <int C1, int C2, int RED>
+template <int C1, int C2, int RED, bool WIDE>
 __global__ void __launch_bounds__(64 * kRowsWaves, (RowsShape<C1, C2>::OCC))
 ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly, int log_r) {
-  using S = RowsShape<C1, C2>;
+  using S = RowsShape<C1, C2, WIDE>;
   constexpr int C = S::C, BR = S::BR;
   constexpr int MB1 = C2 / 8, MB2 = C1 / 8;                 // sub-step 1 over c2', sub-step 2 over m
   constexpr int NB1 = BR * C1 / 32, NB2 = BR * C2 / 32;
@@ -310,11 +364,11 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   const __amdgpu_buffer_rsrc_t rout = rows_rsrc(out + P.base, (uint64_t)BR * C * 4);
   // inverse step-2 twiddles of this workgroup's rows: pairs [row][c]
   const __amdgpu_buffer_rsrc_t tw2 = rows_rsrc(P.job.tw2 + (uint64_t)P.row0 * C * 2, (uint64_t)8 * BR * C);
-  const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, 16 * C2 * C2);
-  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, 16 * C1 * C1);
+  const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, S::TB2);
+  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, S::TB1);
   if constexpr (S::TAB_LDS) {
-    stage<S::NT>(tab1s, P.job.tab1, 16 * C2 * C2);
-    stage<S::NT>(tab2s, P.job.tab2, 16 * C1 * C1);
+    stage<S::NT>(tab1s, P.job.tab1, S::TB2);
+    stage<S::NT>(tab2s, P.job.tab2, S::TB1);
   }
   stage<S::NT>(tws, P.job.tw1, 8 * C);
   const uint32_t q = P.job.q;
@@ -327,9 +381,9 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
     const int col = cb * 32 + (lane & 31);
     const int row = col / C1, m = col % C1;
     v16i acc[MB1];
-    block_gemm<MB1, MB1>(acc, tab1, lane, [&](int ks) {
+    block_gemm<MB1, MB1, WIDE>(acc, tab1, lane, [&](int ks) {
       const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rin, (uint32_t)(row * C + m * C2 + 8 * ks + 4 * h) * 4, 0, 0);
-      return v4i{(int)pack7(x.x), (int)pack7(x.y), (int)pack7(x.z), (int)pack7(x.w)};
+      return v4i{(int)operand<WIDE>(x.x), (int)operand<WIDE>(x.y), (int)operand<WIDE>(x.z), (int)operand<WIDE>(x.w)};
     });
     // output c2 = mb * 8 + 2 j + h: lane bases plus compile-time offsets (IT3 pairs [c2][m])
     const uint32_t* twl = &tws[(h * C1 + m) * 2];
@@ -340,7 +394,7 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
       for (int j = 0; j < 4; ++j) {
         const int c0 = mb * 8 + 2 * j;
         const v2u w = *reinterpret_cast<const v2u*>(&twl[c0 * C1 * 2]);
-        zl[c0 * S::ZP2] = pack7(shoup_tw(merge_reduce<RED>(acc[mb], j, P.job), w, q));
+        zl[c0 * S::ZP2] = operand<WIDE>(shoup_tw(merge_reduce<RED, WIDE>(acc[mb], j, P.job), w, q));
       }
   }
   __syncthreads();
@@ -352,7 +406,7 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
     if (cb < NB2) {
       const int col = cb * 32 + (lane & 31);
       const int row = col / C2, c2 = col % C2;
-      block_gemm<MB2, MB2>(acc2[i], tab2, lane, [&](int ks) {
+      block_gemm<MB2, MB2, WIDE>(acc2[i], tab2, lane, [&](int ks) {
         return *reinterpret_cast<const v4i*>(&zs[(row * C2 + c2) * S::ZP2 + 8 * ks + 4 * h]);
       });
     }
@@ -374,7 +428,7 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
         for (int j = 0; j < 4; ++j) {
           const int c0 = mb * 8 + 2 * j;
           const v2u w = __builtin_amdgcn_raw_buffer_load_b64(tw2, twl, c0 * C2 * 8, 0);
-          xl[c0 * S::XP] = pack7(shoup_tw(merge_reduce<RED>(acc2[i][mb], j, P.job), w, q));
+          xl[c0 * S::XP] = operand<WIDE>(shoup_tw(merge_reduce<RED, WIDE>(acc2[i][mb], j, P.job), w, q));
         }
     }
   }
@@ -382,17 +436,17 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   write_rows<C1, C2>(xs, rout);
 }
 
-template <int C1, int C2, int RED>
+template <int C1, int C2, int RED, bool WIDE = false>
 hipError_t rows_cfg(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
                     int npoly, int log_r, bool inverse, hipStream_t s) {
-  using S = RowsShape<C1, C2>;
+  using S = RowsShape<C1, C2, WIDE>;
   if ((1 << log_r) % S::BR) return hipErrorInvalidValue;
   const int grid = njobs * npoly * ((1 << log_r) / S::BR);
   if (inverse)
-    launch_kernel((ntt_rows_inv_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
+    launch_kernel((ntt_rows_inv_kernel<C1, C2, RED, WIDE>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
                        log_r);
   else
-    launch_kernel((ntt_rows_fwd_kernel<C1, C2, RED>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
+    launch_kernel((ntt_rows_fwd_kernel<C1, C2, RED, WIDE>), dim3(grid), dim3(S::NT), 0, s, jobs, in, out, stride, npoly,
                        log_r);
   return hipGetLastError();
 }
@@ -400,15 +454,18 @@ hipError_t rows_cfg(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t
 }  // namespace
 
 hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
-                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, int red, hipStream_t s) {
+                           int npoly, int log_r, int log_c1, int log_c2, bool inverse, int red, bool wide,
+                           hipStream_t s) {
   if (red != 0 && red != 1) return hipErrorInvalidValue;
+  if (wide && red != 0) return hipErrorInvalidValue;   // the wide form has a Montgomery epilogue only
   if (njobs <= 0 || npoly <= 0) return hipSuccess;
   // per-lane offsets are 32-bit within a workgroup's 32 KB of rows
   if (stride >= (1ull << 40)) return hipErrorInvalidValue;
 #define CROSS_ROWS(a, b)                                                                                    \
   if (log_c1 == a && log_c2 == b)                                                                         \
-    return red ? rows_cfg<(1 << a), (1 << b), 1>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s)   \
-               : rows_cfg<(1 << a), (1 << b), 0>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s);
+    return red    ? rows_cfg<(1 << a), (1 << b), 1>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s)      \
+           : wide ? rows_cfg<(1 << a), (1 << b), 0, true>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s) \
+                  : rows_cfg<(1 << a), (1 << b), 0>(jobs, njobs, in, out, stride, npoly, log_r, inverse, s);
   CROSS_ROWS(4, 4)
   CROSS_ROWS(4, 5)
   CROSS_ROWS(5, 4)

@@ -4,6 +4,7 @@
 // procedures DirectScalarBAT / OfflineCompileLeft).
 #include "params.h"
 
+#include <cstring>
 #include <stdexcept>
 
 namespace cross {
@@ -91,30 +92,56 @@ uint32_t bitrev(uint32_t x, int bits) {
   return r;
 }
 
+// Balanced base-256 digits of v: v = sum_i d_i 256^i, d_i in [-128, 127].
+static void balanced_digits(int64_t v, int8_t (&d)[kChunks]) {
+  for (int i = 0; i < kChunks; ++i) {
+    int64_t r = ((v % 256) + 256) % 256;     // v mod 256 in [0, 256)
+    if (r >= 128) r -= 256;
+    d[i] = (int8_t)r;
+    v = (v - r) / 256;
+  }
+  if (v != 0) throw std::logic_error("balanced_digits: value out of range");
+}
+
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
                 std::vector<int8_t>& out, bool montgomery) {
   const int M = kChunks * n_out, K = kChunks * n_in;
   if (n_in <= 0 || n_out <= 0 || K % kTileK != 0 || M % 32 != 0 || (size_t)T.size() != (size_t)n_in * n_out)
     throw std::invalid_argument("bat_expand: table shape does not tile");
-  out.assign((size_t)M * K, 0);
+  const bool wide = wide_prime(q);
+  out.assign((size_t)M * K + (wide ? 4 * (size_t)M : 0), 0);
+  std::vector<int64_t> rowsum(wide ? M : 0, 0);
   const uint64_t r32 = montgomery ? ((uint64_t)1 << 32) % q : 1;
+  // balanced 4-digit range: [-128 * (2^32 - 1) / 255, 127 * (2^32 - 1) / 255]
+  const int64_t hi = 127 * (int64_t)0x1010101;
   for (int in = 0; in < n_in; ++in) {
     for (int o = 0; o < n_out; ++o) {
       uint64_t t = (uint64_t)T[(size_t)in * n_out + o] * r32 % q;  // Montgomery form unless plain
       for (int j = 0; j < kChunks; ++j) {
-        uint64_t v = (t << (kChunkBits * j)) % q;                 // a * 2^(bp j) mod q
+        int8_t c[kChunks];
+        if (wide) {
+          const uint64_t v = (t << (8 * j)) % q;                      // a * 2^(8 j) mod q: byte j of the input
+          balanced_digits((int64_t)v > hi ? (int64_t)v - (int64_t)q : (int64_t)v, c);
+        } else {
+          const uint64_t v = (t << (kChunkBits * j)) % q;             // a * 2^(bp j) mod q
+          for (int i = 0; i < kChunks; ++i) c[i] = (int8_t)((v >> (kChunkBits * i)) & ((1u << kChunkBits) - 1));
+        }
         for (int i = 0; i < kChunks; ++i) {
           int m = o * kChunks + i, k = in * kChunks + j;
-          int8_t c = (int8_t)((v >> (kChunkBits * i)) & ((1u << kChunkBits) - 1));
+          if (wide) rowsum[m] += c[i];
           // MFMA fragment order: per 64-deep K slab and 32-row block, two 1 KB
           // fragments (K halves) of 32 rows x 32 K bytes, lane-major
           const size_t blk = (size_t)(k / kTileK) * (M / 32) + m / 32;
           const int half = (k % kTileK) / 32;
           const int lane = (m % 32) + 32 * ((k % 32) / 16);
-          out[blk * 2048 + half * 1024 + lane * 16 + (k % 16)] = c;
+          out[blk * 2048 + half * 1024 + lane * 16 + (k % 16)] = c[i];
         }
       }
     }
+  }
+  for (int m = 0; wide && m < M; ++m) {
+    const int32_t corr = (int32_t)(128 * rowsum[m]);
+    std::memcpy(&out[(size_t)M * K + 4 * (size_t)m], &corr, 4);
   }
 }
 
@@ -186,10 +213,13 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
     bat_expand(itc, C2, C2, q, t.row_inv_c);
     bat_expand(itb, C1, C1, q, t.row_inv_b);
     // the same four without the Montgomery factor, for the Barrett epilogue
-    bat_expand(tb, C1, C1, q, t.row_fwd_b_plain, false);
-    bat_expand(tc, C2, C2, q, t.row_fwd_c_plain, false);
-    bat_expand(itc, C2, C2, q, t.row_inv_c_plain, false);
-    bat_expand(itb, C1, C1, q, t.row_inv_b_plain, false);
+    // (narrow primes only: the wide form has no Barrett epilogue)
+    if (!wide_prime(q)) {
+      bat_expand(tb, C1, C1, q, t.row_fwd_b_plain, false);
+      bat_expand(tc, C2, C2, q, t.row_fwd_c_plain, false);
+      bat_expand(itc, C2, C2, q, t.row_inv_c_plain, false);
+      bat_expand(itb, C1, C1, q, t.row_inv_b_plain, false);
+    }
     t.row_fwd_t3.resize((size_t)2 * C);
     t.row_inv_t3.resize((size_t)2 * C);
     for (uint32_t m = 0; m < C1; ++m)

@@ -13,6 +13,13 @@ constexpr int kChunkBits = 7;   // bp: 7-bit chunks fit non-negative int8 MFMA o
 constexpr int kChunks = 4;      // Kc: four 7-bit chunks hold a residue below 2^28
 constexpr int kTileK = 64;      // K extent of one table tile (one 16x16x64 MFMA step)
 
+// Wide primes (2^28 <= q < 2^31) do not fit four 7-bit chunks.  Their tables
+// use balanced signed 8-bit digits and the runtime side its four bytes, each
+// fed to the MFMA as b - 128 (see bat_expand).  Only the NTT takes them.
+constexpr uint32_t kNarrowPrimeLimit = 1u << 28;
+constexpr uint32_t kWidePrimeLimit = 1u << 31;
+inline bool wide_prime(uint32_t q) { return q >= kNarrowPrimeLimit; }
+
 uint32_t powmod(uint64_t b, uint64_t e, uint32_t q);
 bool is_prime_u32(uint32_t n);
 uint32_t smallest_generator(uint32_t q);
@@ -31,6 +38,15 @@ uint32_t bitrev(uint32_t x, int bits);
 // v_mfma_i32_32x32x32_i8 A operand, byte (m, k) at
 // (s * (M / 32) + b) * 2048 + h * 1024 + 16 * (m % 32 + 32 * ((k % 32) / 16)) + k % 16,
 // so a workgroup's rows of one K slab are contiguous and load in lane order.
+//
+// For a wide prime (wide_prime(q)) the same layout holds with
+// D[m = out*4 + i][k = in*4 + j] = digit_i(v), v = (T[in][out] * 2^32 * 2^(8j)) mod q,
+// where digit_0..3 are the balanced base-256 digits (each in [-128, 127]) of
+// the representative of v in [-2155905152, 2139062143] (such a representative
+// exists for every residue class, since that range holds 2^32 > q integers),
+// and the M * K bytes are followed by M int32 row corrections 128 * sum_k D[m][k]:
+// the runtime bytes b enter the MFMA as b - 128, and an accumulator started at
+// the correction ends at sum_k D[m][k] * b_k.
 // Throws std::invalid_argument unless 4 * n_in is a multiple of 64.
 void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
                 std::vector<int8_t>& out, bool montgomery = true);

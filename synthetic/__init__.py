@@ -55,6 +55,26 @@ def primes(count: int):
     return list(_CHAIN[:count])
 
 
+_WIDE = None
+
+
+def wide_primes(count: int):
+    """Largest ``count`` primes q < 2^31 with q = 1 mod 2^17, largest first (the NTT's
+    wide form: residues that do not fit four 7-bit chunks)."""
+    global _WIDE
+    if _WIDE is None or len(_WIDE) < count:
+        step = 1 << TWO_ADICITY
+        m = ((1 << 31) - 2) // step
+        out = []
+        while len(out) < max(count, 8) and m > 0:
+            q = m * step + 1
+            if _is_prime_trial(q):
+                out.append(q)
+            m -= 1
+        _WIDE = out
+    return list(_WIDE[:count])
+
+
 def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 

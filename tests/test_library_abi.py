@@ -36,8 +36,10 @@ def test_root_matches_definition_and_validates():
     with pytest.raises(binding.CrossError) as e:
         binding.root(268042241 + 2, 12)
     assert e.value.code in (-2, -3)
+    for q in prime_chain(2, bits=31) + [2013265921]:     # wide primes (the NTT takes q < 2^31)
+        assert binding.root(q, 12) == psi(q, 1 << 12)
     with pytest.raises(binding.CrossError) as e:
-        binding.root(2013265921, 12)        # prime, 31 bits
+        binding.root(3221225473, 12)        # prime, 3 * 2^30 + 1 >= 2^31
     assert e.value.code == -4
     with pytest.raises(binding.CrossError) as e:
         binding.root(7681, 12)              # prime, 7681 - 1 = 2^9 * 15: no 2^13-th root

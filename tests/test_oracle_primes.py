@@ -46,6 +46,20 @@ def test_chain_properties():
     assert ch == sorted(ch, reverse=True)
 
 
+def test_wide_chain_two_derivations_agree():
+    # 31-bit primes (the NTT's wide form): Miller-Rabin chain = trial-division chain
+    ch = P.prime_chain(8, bits=31)
+    assert ch == synthetic.wide_primes(8)
+    for q in ch:
+        assert (1 << 28) <= q < (1 << 31) and q % (1 << 17) == 1 and _trial(q)
+    assert ch == sorted(ch, reverse=True)
+    # and nothing skipped: every m * 2^17 + 1 between them that is not listed is composite
+    for m in range(ch[-1] >> 17, (1 << 31) >> 17):
+        q = (m << 17) + 1
+        if q < (1 << 31):
+            assert (q in ch) == _trial(q)
+
+
 def test_smallest_generator_brute_force():
     for q in (17, 97, 193, 257, 7681, 12289):
         g = P.smallest_generator(q)
@@ -62,7 +76,7 @@ def test_smallest_generator_brute_force():
 
 
 def test_psi_is_primitive_2n_root():
-    for q in P.prime_chain(6):
+    for q in P.prime_chain(6) + P.prime_chain(2, bits=31):
         for log_n in (4, 8, 12, 16):
             n = 1 << log_n
             s = P.psi(q, n)
