@@ -204,9 +204,13 @@ struct RowsShape {
   static constexpr int OCC = (C1 <= 32 && C2 <= 32) ? 4 : 2;
   // table bytes (wide primes: with their row corrections)
   static constexpr int TB1 = 16 * C1 * C1 + (WIDE ? 16 * C1 : 0), TB2 = 16 * C2 * C2 + (WIDE ? 16 * C2 : 0);
-  // both tables in LDS where they fit beside the Z tile and the twiddles
-  static constexpr bool TAB_LDS = TB1 + TB2 + 8 * C + 4 * ZWORDS <= kLdsBytes;
-  static constexpr int T1 = TAB_LDS ? TB1 : 16, T2 = TAB_LDS ? TB2 : 16;
+  // C1 = C2: the two sub-step tables are one matrix (TB[m][c1] = psi^(2R C2 c1 brv(m))
+  // and TC[c2][c2'] = psi^(2R C1 c2 brv(c2')) coincide, as do ITC and ITB), so a
+  // single copy is staged
+  static constexpr bool SHARED = C1 == C2;
+  // the tables in LDS where they fit beside the Z tile and the twiddles
+  static constexpr bool TAB_LDS = (SHARED ? TB1 : TB1 + TB2) + 8 * C + 4 * ZWORDS <= kLdsBytes;
+  static constexpr int T1 = TAB_LDS ? TB1 : 16, T2 = (TAB_LDS && !SHARED) ? TB2 : 16;
   static_assert(C1 >= 16 && C2 >= 16 && BR >= 1 && (NW * 1024) % C == 0, "row split");
 };
 
@@ -275,10 +279,10 @@ ntt_rows_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   const __amdgpu_buffer_rsrc_t rin = rows_rsrc(in + P.base, (uint64_t)BR * C * 4);
   const __amdgpu_buffer_rsrc_t rout = rows_rsrc(out + P.base, (uint64_t)BR * C * 4);
   const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, S::TB1);
-  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, S::TB2);
+  const auto tab2 = table<S::TAB_LDS>(S::SHARED ? tab1s : tab2s, S::SHARED ? P.job.tab1 : P.job.tab2, S::TB2);
   if constexpr (S::TAB_LDS) {
     stage<S::NT>(tab1s, P.job.tab1, S::TB1);
-    stage<S::NT>(tab2s, P.job.tab2, S::TB2);
+    if constexpr (!S::SHARED) stage<S::NT>(tab2s, P.job.tab2, S::TB2);
   }
   stage<S::NT>(tws, P.job.tw1, 8 * C);
   const uint32_t q = P.job.q;
@@ -355,8 +359,8 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   constexpr int MB1 = C2 / 8, MB2 = C1 / 8;                 // sub-step 1 over c2', sub-step 2 over m
   constexpr int NB1 = BR * C1 / 32, NB2 = BR * C2 / 32;
   constexpr int NBW2 = (NB2 + S::NW - 1) / S::NW;
-  __shared__ __attribute__((aligned(16))) int8_t tab1s[S::T2];
-  __shared__ __attribute__((aligned(16))) int8_t tab2s[S::T1];
+  __shared__ __attribute__((aligned(16))) int8_t tab1s[S::SHARED ? S::T1 : S::T2];
+  __shared__ __attribute__((aligned(16))) int8_t tab2s[S::SHARED ? S::T2 : S::T1];
   __shared__ __attribute__((aligned(16))) uint32_t tws[2 * C];
   __shared__ __attribute__((aligned(16))) uint32_t zs[S::ZWORDS];
   const RowsPos P = rows_pos<BR, C>(jobs, stride, npoly, log_r);
@@ -365,10 +369,10 @@ ntt_rows_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint
   // inverse step-2 twiddles of this workgroup's rows: pairs [row][c]
   const __amdgpu_buffer_rsrc_t tw2 = rows_rsrc(P.job.tw2 + (uint64_t)P.row0 * C * 2, (uint64_t)8 * BR * C);
   const auto tab1 = table<S::TAB_LDS>(tab1s, P.job.tab1, S::TB2);
-  const auto tab2 = table<S::TAB_LDS>(tab2s, P.job.tab2, S::TB1);
+  const auto tab2 = table<S::TAB_LDS>(S::SHARED ? tab1s : tab2s, S::SHARED ? P.job.tab1 : P.job.tab2, S::TB1);
   if constexpr (S::TAB_LDS) {
     stage<S::NT>(tab1s, P.job.tab1, S::TB2);
-    stage<S::NT>(tab2s, P.job.tab2, S::TB1);
+    if constexpr (!S::SHARED) stage<S::NT>(tab2s, P.job.tab2, S::TB1);
   }
   stage<S::NT>(tws, P.job.tw1, 8 * C);
   const uint32_t q = P.job.q;

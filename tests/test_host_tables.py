@@ -260,6 +260,19 @@ def test_emulated_three_factor_ntt_matches_oracle(log_n, log_r, log_c1, plain, w
     assert np.array_equal(_emulate3(ref, q, log_n, log_r, log_c1, True, plain), a)
 
 
+@pytest.mark.parametrize("wide", [False, True])
+def test_equal_row_splits_share_one_table(wide):
+    # C1 = C2: the row kernels stage one table for both sub-steps (forward TB and TC,
+    # inverse ITC and ITB), so the library's two tables must be byte-identical
+    from paper_2501_07047_amd import binding
+    q = WIDE[0] if wide else prime_chain(1)[0]
+    for log_n, log_r, log_c1 in ((13, 5, 4), (14, 4, 5), (16, 6, 5), (16, 4, 6)):
+        rt = lambda w: binding.host_row_tables(q, log_n, log_r, log_c1, w)
+        assert np.array_equal(rt(0), rt(1)) and np.array_equal(rt(2), rt(3))
+        if not wide:
+            assert np.array_equal(rt(8), rt(9)) and np.array_equal(rt(10), rt(11))
+
+
 def test_row_split_limits():
     from paper_2501_07047_amd import binding
     q = prime_chain(1)[0]
