@@ -462,11 +462,13 @@ def main():
                      "hbm_copy_gbs": round(B.measure_peak("hbm_copy"), 1)}
     if fam == "ntt_rows":
         # row transform of every row (C1 x C2 split): HBM-bound.  Per launch: every residue
-        # read and written once, the two row tables and the C-entry twiddle pairs per prime,
-        # and (inverse launches, half of them) the N-entry inverse step-2 twiddle pairs.
+        # read and written once, the row tables (one matrix when C1 = C2) and the C-entry
+        # twiddle pairs per prime, and (inverse launches, half of them) the N-entry inverse
+        # step-2 twiddle pairs.
         c = 1 << (LOG_N - log_r)
         c1, c2 = 1 << log_c1, c // (1 << log_c1)
-        nbytes = npolys * n * 8 + L * (16 * c1 * c1 + 16 * c2 * c2 + 8 * c) + L * n * 8 // 2
+        tables = 16 * c1 * c1 if c1 == c2 else 16 * c1 * c1 + 16 * c2 * c2
+        nbytes = npolys * n * 8 + L * (tables + 8 * c) + L * n * 8 // 2
         ops = 32.0 * n * (c1 + c2) * npolys
         achieved = nbytes / avg_s / 1e9
         khash = source_hash("ntt_rows.hip")
