@@ -143,6 +143,18 @@ def poisson_requests(seed: int, count: int, rate: float, log_ns=(14, 15, 16), L_
     return out
 
 
+def device_residues(seed: int, batch: int, plist, n: int):
+    """int32 CUDA tensor [batch][len(plist)][n], limb i uniform in [0, plist[i]) from a
+    seeded torch generator on the GPU (for inputs too large to draw on the host)."""
+    import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed & 0x7FFFFFFF)
+    out = torch.empty((batch, len(plist), n), dtype=torch.int32, device="cuda")
+    for i, q in enumerate(plist):
+        out[:, i, :] = torch.randint(0, q, (batch, n), generator=gen, device="cuda", dtype=torch.int64).to(torch.int32)
+    return out
+
+
 class DevicePool:
     """Seeded synthetic ciphertexts and keys generated on the GPU, per parameter set.
 

@@ -309,3 +309,26 @@ def test_max_limbs_three_factor(log_n, batch):
     with pytest.raises(B.CrossError):
         p65, x65 = synthetic.ntt_batch(1, 13, 65, 1)
         B.ntt_forward(to_dev(x65), p65)
+
+
+def test_buffer_beyond_4gib():
+    # N = 2^16, 24 limbs x 700 polynomials: a 4.4 GB buffer (and as much workspace), so
+    # any 32-bit byte offset that is not relative to a nearby base would wrap; spot
+    # polynomials at the start, middle and end against the oracle, exact round trip
+    import torch
+    from paper_2501_07047_amd import binding as B
+    primes = synthetic.primes(24)
+    batch, n = 700, 1 << 16
+    assert batch * 24 * n * 4 > 1 << 32
+    d = synthetic.device_residues(11, batch, primes, n)
+    x = d.clone()
+    B.ntt_forward(d, primes)
+    for b in (0, 349, 699):
+        for i in (0, 23):
+            xi = x[b, i].cpu().numpy().view(np.uint32).astype(np.uint64)
+            got = d[b, i].cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, ntt_ct(xi, primes[i], psi_of(primes[i], n)))
+    B.ntt_inverse(d, primes)
+    assert torch.equal(d, x)
+    del d, x
+    torch.cuda.empty_cache()
