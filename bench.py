@@ -178,9 +178,9 @@ def wide_prime_bench(B, reps):
 
 
 def ntt_reduction_bench(B, reps):
-    """Forward + inverse NTT at N=2^16, L=24 (64 x 32 x 32) with the row kernels' epilogue
+    """Forward + inverse NTT at N=2^16, L=24 (64 x 32 x 32) with every step's epilogue
     reduction Montgomery vs Barrett, for 1, 4 and 16 polynomials (the NTT side of
-    Fig. diff_modred); microseconds per pair and the row-kernel share."""
+    Fig. diff_modred); microseconds per pair and the row-kernel and row-side-step shares."""
     import numpy as np
     import torch
     import synthetic
@@ -210,8 +210,10 @@ def ntt_reduction_bench(B, reps):
                 prof = B.profile_report()
                 B.profile_enable(False)
                 rows = prof.get("ntt_rows", (1, 0.0))
+                left = prof.get("bat_gemm_left", (1, 0.0))
                 row[str(npoly)] = {"us_fwd_inv": round(e0.elapsed_time(e1) * 1e3 / reps, 2),
-                                   "row_kernel_us_avg": round(rows[1] * 1e3 / max(1, rows[0]), 2)}
+                                   "row_kernel_us_avg": round(rows[1] * 1e3 / max(1, rows[0]), 2),
+                                   "row_side_step_us_avg": round(left[1] * 1e3 / max(1, left[0]), 2)}
             res[method] = row
     finally:
         B.set_ntt_reduction("montgomery")
@@ -518,8 +520,8 @@ def main():
                                          "key = polynomials per call; us per call and HBM GB/s "
                                          "(a read + out written + w read once)",
                                "methods": modred_bench(B, max(10, args.steps))}
-    line["ntt_reduction_ablation"] = {"config": "NTT+INTT at N=2^16, L=24 (64 x 32 x 32); row-kernel "
-                                               "epilogue Montgomery (tables x 2^32, REDC) vs Barrett "
+    line["ntt_reduction_ablation"] = {"config": "NTT+INTT at N=2^16, L=24 (64 x 32 x 32); epilogue of "
+                                               "every step Montgomery (tables x 2^32, REDC) vs Barrett "
                                                "(plain tables); key = polynomials per call",
                                      "methods": ntt_reduction_bench(B, max(10, args.steps))}
     line["wide_prime_ntt"] = {"config": "NTT+INTT at N=2^16, L=24, 16 polynomials, default split; "

@@ -445,6 +445,8 @@ cross_status cross_measure_peak(cross_ctx ctx, int which, double* out);
  *   which 4/5    : uint32 step-2 twiddles as (w, floor(w*2^32/q)) pairs (Shoup
  *                  multiplication), forward [R][C][2] and inverse transposed [C][R][2]
  *                  (Sec. MAT, layout-invariant 3-step NTT)
+ *   which 7/8/9/10: the tables of which 0/1/2/3 without the Montgomery factor 2^32
+ *                  (CROSS_NTT_RED_BARRETT; CROSS_EINVAL for wide primes)
  *   which 6      : the 1 KB int8 A operand of the BAT lazy reduction for q
  *                  (cross_vec_modmul, CROSS_MODRED_BAT_LAZY): lane l (0..63), byte e
  *                  at 16*l + e holds, for row = l%32, K byte kb = 16*(l/32) + e,
@@ -457,10 +459,12 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
                                void* out, uint64_t* bytes);
 
 /*
- * Epilogue reduction of the three-factor row kernels (both sub-steps), for the
- * NTT side of the modular-reduction comparison (Sec. Evaluation, Fig.
- * diff_modred).  The row-side GEMM step and the two-factor form always use
- * Montgomery reduction.  Results are identical either way.
+ * Epilogue reduction of every MFMA NTT step on ctx (the row-side step and both
+ * row-kernel sub-steps of the three-factor form, both steps of the two-factor
+ * form), for the NTT side of the modular-reduction comparison (Sec. Evaluation,
+ * Fig. diff_modred).  The butterfly kernels (N < 2^8 and the butterfly entry
+ * points) and the batch runtime always use Montgomery reduction.  Results are
+ * identical either way.
  *   CROSS_NTT_RED_MONTGOMERY (default): tables carry the factor 2^32, REDC of the
  *                            merged chunk sums (Alg. montgomery_reduction)
  *   CROSS_NTT_RED_BARRETT    : tables without the factor, Barrett reduction of the

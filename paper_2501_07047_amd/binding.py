@@ -247,7 +247,7 @@ def host_tables(q, log_n, log_r, which):
     st = lib().cross_host_tables(q, log_n, log_r, which, c_vp(buf.ctypes.data), ctypes.byref(nbytes))
     if st != 0:
         raise CrossError(st, "cross_host_tables")
-    return buf.view(np.int8) if which < 4 or which == 6 else buf.view(np.uint32)
+    return buf.view(np.int8) if which < 4 or which >= 6 else buf.view(np.uint32)
 
 
 def measure_peak(which, device=None):

@@ -131,7 +131,8 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool all
               al(t.row_fwd_c.size()) + al(t.row_inv_c.size()) + al(t.row_inv_b.size()) +
               al(t.row_fwd_t3.size() * 4) + al(t.row_inv_t3.size() * 4) + al(t.inv_tw_rows.size() * 4) +
               al(t.row_fwd_b_plain.size()) + al(t.row_fwd_c_plain.size()) + al(t.row_inv_c_plain.size()) +
-              al(t.row_inv_b_plain.size());
+              al(t.row_inv_b_plain.size()) + al(t.fwd_left_plain.size()) + al(t.fwd_right_plain.size()) +
+              al(t.inv_left_plain.size()) + al(t.inv_right_plain.size());
   Plan* p = new Plan();
   cross_status st = dev_alloc(ctx, sz, &p->block);
   if (st != CROSS_OK) {
@@ -150,6 +151,10 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool all
   p->fwd_right = (int8_t*)put(t.fwd_right.data(), t.fwd_right.size());
   p->inv_left = (int8_t*)put(t.inv_left.data(), t.inv_left.size());
   p->inv_right = (int8_t*)put(t.inv_right.data(), t.inv_right.size());
+  p->fwd_left_plain = (int8_t*)put(t.fwd_left_plain.data(), t.fwd_left_plain.size());
+  p->fwd_right_plain = (int8_t*)put(t.fwd_right_plain.data(), t.fwd_right_plain.size());
+  p->inv_left_plain = (int8_t*)put(t.inv_left_plain.data(), t.inv_left_plain.size());
+  p->inv_right_plain = (int8_t*)put(t.inv_right_plain.data(), t.inv_right_plain.size());
   p->fwd_tw = (uint32_t*)put(t.fwd_tw.data(), t.fwd_tw.size() * 4);
   p->inv_tw = (uint32_t*)put(t.inv_tw.data(), t.inv_tw.size() * 4);
   p->bf_fwd = (uint32_t*)put(t.bf_fwd.data(), t.bf_fwd.size() * 4);
@@ -240,8 +245,8 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
   const bool wide = plans[0]->wide;
   if (red == 1)
     for (const Plan* p : plans) {
-      if (p->bar_k < 22) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett row epilogue needs primes >= 2^21");
-      if (p->wide) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett row epilogue needs primes < 2^28");
+      if (p->bar_k < 22) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett NTT epilogue needs primes >= 2^21");
+      if (p->wide) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett NTT epilogue needs primes < 2^28");
     }
   std::vector<RowsJob> rj(plans.size());
   std::vector<GemmJob> gj(plans.size());
@@ -253,8 +258,8 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
                               p->row_inv_t3, p->inv_tw_rows, offs[i], p->q, p->qinv, p->bar_m, p->bar_k}
                     : RowsJob{bar ? p->row_fwd_b_plain : p->row_fwd_b, bar ? p->row_fwd_c_plain : p->row_fwd_c,
                               p->row_fwd_t3, nullptr, offs[i], p->q, p->qinv, p->bar_m, p->bar_k};
-    gj[i] = GemmJob{inverse ? p->inv_left : p->fwd_left, inverse ? nullptr : p->fwd_tw, offs[i], offs[i], p->q,
-                    p->qinv};
+    gj[i] = GemmJob{bar ? (inverse ? p->inv_left_plain : p->fwd_left_plain) : (inverse ? p->inv_left : p->fwd_left),
+                    inverse ? nullptr : p->fwd_tw, offs[i], offs[i], p->q, p->qinv, p->bar_m, p->bar_k};
   }
   void *dr = nullptr, *dg = nullptr;
   cross_status st = cached_device_copy(ctx, rj.data(), rj.size() * sizeof(RowsJob), &dr);
@@ -269,6 +274,7 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
   g.log_c = log_n - log_r;
   g.kind = kLeft;
   g.wide = wide;
+  g.red = red;
   g.tile = ctx->gemm_tile;
   if (g.tile == 0) {
     auto it = ctx->tile_by_logn.find(log_n);
@@ -346,12 +352,20 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
     return CROSS_OK;
   }
   if (plans[0]->log_c1 > 0) return ntt_three(ctx, plans, offs, data, stride, npoly, inverse, tmp, s);
+  const int red = ctx->ntt_reduction;
+  if (red == 1)
+    for (const Plan* p : plans) {
+      if (p->bar_k < 22) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett NTT epilogue needs primes >= 2^21");
+      if (p->wide) return fail(ctx, CROSS_EUNSUPPORTED, "Barrett NTT epilogue needs primes < 2^28");
+    }
+  const bool bar = red == 1;
   std::vector<GemmJob> j1(plans.size()), j2(plans.size());
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];
-    j1[i] = GemmJob{inverse ? p->inv_right : p->fwd_left, inverse ? p->inv_tw : p->fwd_tw,
-                    offs[i], offs[i], p->q, p->qinv};
-    j2[i] = GemmJob{inverse ? p->inv_left : p->fwd_right, nullptr, offs[i], offs[i], p->q, p->qinv};
+    j1[i] = GemmJob{bar ? (inverse ? p->inv_right_plain : p->fwd_left_plain) : (inverse ? p->inv_right : p->fwd_left),
+                    inverse ? p->inv_tw : p->fwd_tw, offs[i], offs[i], p->q, p->qinv, p->bar_m, p->bar_k};
+    j2[i] = GemmJob{bar ? (inverse ? p->inv_left_plain : p->fwd_right_plain) : (inverse ? p->inv_left : p->fwd_right),
+                    nullptr, offs[i], offs[i], p->q, p->qinv, p->bar_m, p->bar_k};
   }
   void *d1 = nullptr, *d2 = nullptr;
   cross_status st = cached_device_copy(ctx, j1.data(), j1.size() * sizeof(GemmJob), &d1);
@@ -364,6 +378,7 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   g.log_r = log_r;
   g.log_c = log_n - log_r;
   g.wide = plans[0]->wide;
+  g.red = red;
   g.tile = ctx->gemm_tile;
   if (g.tile == 0) {
     auto it = ctx->tile_by_logn.find(log_n);
@@ -644,10 +659,11 @@ cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, u
 
 cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t which,
                                void* out, uint64_t* bytes) {
-  if (!bytes || which > 6 || log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4)
+  if (!bytes || which > 10 || log_n < 8 || log_n > CROSS_MAX_LOG_N || log_r < 4 || log_n - log_r < 4)
     return CROSS_EINVAL;
   cross_status st = check_prime(nullptr, q, log_n, which != 6);
   if (st != CROSS_OK) return st;
+  if (which >= 7 && wide_prime(q)) return CROSS_EINVAL;     // no plain tables in the wide form
   NttTables t;
   std::vector<int8_t> lazy;
   if (which == 6) lazy = lazy_fragment(q);
@@ -661,7 +677,11 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
     case 2: src = t.inv_left.data(); n = t.inv_left.size(); break;
     case 3: src = t.inv_right.data(); n = t.inv_right.size(); break;
     case 4: src = t.fwd_tw.data(); n = t.fwd_tw.size() * 4; break;
-    default: src = t.inv_tw.data(); n = t.inv_tw.size() * 4; break;
+    case 5: src = t.inv_tw.data(); n = t.inv_tw.size() * 4; break;
+    case 7: src = t.fwd_left_plain.data(); n = t.fwd_left_plain.size(); break;
+    case 8: src = t.fwd_right_plain.data(); n = t.fwd_right_plain.size(); break;
+    case 9: src = t.inv_left_plain.data(); n = t.inv_left_plain.size(); break;
+    default: src = t.inv_right_plain.data(); n = t.inv_right_plain.size(); break;
   }
   if (!out) {
     *bytes = n;

@@ -20,6 +20,8 @@ struct Plan {
   int log_n = 0, log_r = 0;
   int log_c1 = 0;           // > 0: three factors, the row transform split as C1 x C2
   int8_t *fwd_left = nullptr, *fwd_right = nullptr, *inv_left = nullptr, *inv_right = nullptr;
+  int8_t *fwd_left_plain = nullptr, *fwd_right_plain = nullptr;      // without the Montgomery factor
+  int8_t *inv_left_plain = nullptr, *inv_right_plain = nullptr;
   uint32_t *fwd_tw = nullptr, *inv_tw = nullptr, *bf_fwd = nullptr, *bf_inv = nullptr;
   int8_t *row_fwd_b = nullptr, *row_fwd_c = nullptr, *row_inv_c = nullptr, *row_inv_b = nullptr;
   int8_t *row_fwd_b_plain = nullptr, *row_fwd_c_plain = nullptr;   // without the Montgomery factor

@@ -37,6 +37,7 @@ struct GemmJob {
   const uint32_t* tw;      // step-2 twiddles (Montgomery form) or nullptr
   uint64_t src_off, dst_off;
   uint32_t q, qinv;        // prime and q^-1 mod 2^32
+  uint32_t bar_m, bar_k;   // Barrett epilogue (plain table): floor(2^(2k) / q), k = bit length of q
 };
 
 // Step kinds of the layout-invariant 3-step NTT.
@@ -59,6 +60,7 @@ struct GemmLaunch {
   int tile;                // GemmTile; kTileAuto picks by shape and grid size
   bool in_rows;            // row side, packed input stored row-major (three-factor inverse)
   bool wide;               // wide primes (2^28 <= q < 2^31): byte operands, signed-digit tables
+  int red;                 // epilogue reduction: 0 Montgomery REDC, 1 Barrett (plain tables, q >= 2^21)
 };
 
 // Workgroup tile shapes of the BAT GEMM (rows x columns of the int8 product).

@@ -82,6 +82,7 @@ struct TileArgs {
   uint32_t q, qinv;
   int npoly, log_r, log_c;
   int m0, n0;
+  uint32_t bar_m, bar_k;   // Barrett epilogue constants (plain tables)
 };
 
 // MFMA v_mfma_i32_32x32x32_i8 (the int8 instruction that reaches the chip's
@@ -202,7 +203,7 @@ __device__ __forceinline__ uint32_t merge_redc_wide(int s0, int s1, int s2, int 
 // BN x (BM/4 + 4) words) as [column v][row u] and written back row by row, 16
 // bytes per lane.
 template <int NT, int BM, int BN, int MB, int NB, bool RIGHT, bool OUT_PACKED, bool TW, bool NARROW_ONLY = false,
-          bool WIDE = false>
+          bool WIDE = false, int RED = 0>
 __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const TileArgs& t, const StepShape& g,
                                               int wm, int wn, uint32_t* so) {
   const int tid = threadIdx.x, lane = tid & 63;
@@ -267,8 +268,20 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
             zlo = (uint32_t)z;
             zhi = (uint32_t)(z >> 32);
           }
-          // Montgomery REDC of z (the 2^32 factor was folded into the table): (0, 2q)
-          r = zhi + q - __umulhi(zlo * qinv, q);
+          if constexpr (RED == 1) {
+            // Barrett (Alg. barrett) for plain tables: with k = bit length of q, z below
+            // U * q * 4 * 127 < 2^21 q <= 2^(2k) (q >= 2^21), the quotient estimate
+            // ((z >> (k - 1)) * floor(2^(2k) / q)) >> (k + 1) is short by at most 2: [0, q)
+            const uint32_t kb = t.bar_k;
+            const uint32_t zh = (zhi << (33 - kb)) | (zlo >> (kb - 1));
+            const uint32_t tq = (uint32_t)(((uint64_t)zh * t.bar_m) >> (kb + 1));
+            r = zlo - tq * q;
+            r = r >= q ? r - q : r;
+            r = r >= q ? r - q : r;
+          } else {
+            // Montgomery REDC of z (the 2^32 factor was folded into the table): (0, 2q)
+            r = zhi + q - __umulhi(zlo * qinv, q);
+          }
           }
           if (TW) {
             // Shoup multiplication by the pre-known twiddle (w, floor(w 2^32 / q)): [0, 2q)
@@ -317,7 +330,7 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
 // residues are cut into 7-bit chunks on the way into LDS; packed data is
 // copied as is.
 template <int WM, int WN, int MB, int NB, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
-          bool PROWS = false, bool WIDE = false>
+          bool PROWS = false, bool WIDE = false, int RED = 0>
 __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8_t* lds_b) {
   constexpr int NW = WM * WN;
   constexpr int NT = NW * 64;
@@ -419,7 +432,7 @@ __device__ __forceinline__ void gemm_tile(const TileArgs& t, int8_t* lds_a, int8
     if (ks + 2 < nk) load(ks + 2);
     __syncthreads();
   }
-  gemm_epilogue<NT, BM, BN, MB, NB, RIGHT, OUT_PACKED, TW, false, WIDE>(acc, t, g, wm, wn,
+  gemm_epilogue<NT, BM, BN, MB, NB, RIGHT, OUT_PACKED, TW, false, WIDE, RED>(acc, t, g, wm, wn,
                                                                         reinterpret_cast<uint32_t*>(lds_a));
 }
 
@@ -570,11 +583,11 @@ __device__ __forceinline__ TileArgs uniform_tile(const GemmLaunch& g, int tiles_
   const int tm = rem - tn * tiles_m;
   const GemmJob job = g.jobs[job_id];
   return TileArgs{job.table, job.tw, g.src + job.src_off, g.dst + job.dst_off, g.src_stride, g.dst_stride,
-                  job.q, job.qinv, g.npoly, g.log_r, g.log_c, tm * BM, tn * BN};
+                  job.q, job.qinv, g.npoly, g.log_r, g.log_c, tm * BM, tn * BN, job.bar_m, job.bar_k};
 }
 
 template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
-          bool PROWS, bool WIDE>
+          bool PROWS, bool WIDE, int RED>
 __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   constexpr int BM = WM * MB * 32;
@@ -582,7 +595,7 @@ bat_gemm_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
   // two LDS stages of operand fragments (A stages then B stages), reused for output staging
   __shared__ __attribute__((aligned(1024))) int8_t lds[gemm_lds_bytes<WM, WN, MB, NB, KS, RIGHT, OUT_PACKED>()];
   const TileArgs t = uniform_tile<BM, BN>(g, tiles_m, tiles_n);
-  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW, PROWS, WIDE>(t, lds, lds + 2 * BM * 64 * KS);
+  gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW, PROWS, WIDE, RED>(t, lds, lds + 2 * BM * 64 * KS);
 }
 
 // LDS bytes of the direct-table form: two stages of data fragments, or the
@@ -646,12 +659,12 @@ bool uniform_grid(const GemmLaunch& g, int kdiv, int& tiles_m, int& tiles_n, int
 // LDS-staged tile: WM x WN waves of MB x NB blocks.
 template <int WM, int WN, int MB, int NB, int OCC, int KS = 1>
 struct StagedCfg {
-  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false, bool WIDE = false>
+  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false, bool WIDE = false, int RED = 0>
   static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
     constexpr int BM = WM * MB * 32, BN = WN * NB * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
-    launch_kernel((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW, PROWS, WIDE>), dim3(grid),
+    launch_kernel((bat_gemm_kernel<WM, WN, MB, NB, OCC, KS, RIGHT, INP, OUTP, TW, PROWS, WIDE, RED>), dim3(grid),
                        dim3(WM * WN * 64), 0, s, g, tm, tn);
     return hipGetLastError();
   }
@@ -660,9 +673,9 @@ struct StagedCfg {
 // Direct-table tile: WA x WN waves of MA x NBD blocks, stages of KS slabs, unrolled by two.
 template <int WA, int WN, int MA, int NBD, int OCC, int KS>
 struct DirectCfg {
-  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false, bool WIDE = false>
+  template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS = false, bool WIDE = false, int RED = 0>
   static hipError_t launch(const GemmLaunch& g, hipStream_t s) {
-    static_assert(!WIDE, "the direct tiles merge narrow chunk sums only");
+    static_assert(!WIDE && RED == 0, "the direct tiles: narrow chunk sums and Montgomery only");
     constexpr int BM = WA * MA * 32, BN = WN * NBD * 32;
     int tm, tn, grid;
     if (!uniform_grid<BM, BN, RIGHT>(g, 2 * BK * KS, tm, tn, grid)) return hipErrorInvalidValue;
@@ -672,21 +685,21 @@ struct DirectCfg {
   }
 };
 
-template <class Cfg, bool WIDE = false>
+template <class Cfg, bool WIDE = false, int RED = 0>
 hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
   // forward: LEFT(plain in, packed out, twiddle) then RIGHT(packed in, plain out)
   // inverse: RIGHT(plain in, packed out, twiddle) then LEFT(packed in, plain out)
   const bool right = g.kind == kRight;
   if (!right && !g.in_packed && g.out_packed && g.twiddle)
-    return Cfg::template launch<false, false, true, true, false, WIDE>(g, s);
+    return Cfg::template launch<false, false, true, true, false, WIDE, RED>(g, s);
   if (right && g.in_packed && !g.out_packed && !g.twiddle)
-    return Cfg::template launch<true, true, false, false, false, WIDE>(g, s);
+    return Cfg::template launch<true, true, false, false, false, WIDE, RED>(g, s);
   if (right && !g.in_packed && g.out_packed && g.twiddle)
-    return Cfg::template launch<true, false, true, true, false, WIDE>(g, s);
+    return Cfg::template launch<true, false, true, true, false, WIDE, RED>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle && g.in_rows)
-    return Cfg::template launch<false, true, false, false, true, WIDE>(g, s);
+    return Cfg::template launch<false, true, false, false, true, WIDE, RED>(g, s);
   if (!right && g.in_packed && !g.out_packed && !g.twiddle)
-    return Cfg::template launch<false, true, false, false, false, WIDE>(g, s);
+    return Cfg::template launch<false, true, false, false, false, WIDE, RED>(g, s);
   return hipErrorInvalidValue;
 }
 
@@ -722,8 +735,9 @@ int resolve_gemm_tile(const GemmLaunch& g) {
   const int M = 4 * U;
   const long ncols = (long)g.npoly * V;
   int t = g.tile;
-  // wide primes: the staged 256 x 128 (8 waves), 128 x 64 and 64 x 64 tiles only
-  if (g.wide && t != kTile256x128w8 && t != kTile128x64 && t != kTile64x64) t = kTileAuto;
+  // wide primes and the Barrett epilogue: the staged 256 x 128 (8 waves), 128 x 64 and
+  // 64 x 64 tiles only
+  if ((g.wide || g.red) && t != kTile256x128w8 && t != kTile128x64 && t != kTile64x64) t = kTileAuto;
   if ((t == kTile256x256 || t == kTile256x128w8 || t == kTile256x256w16 || t == kTile256x256w16k2) && M < 256)
     t = kTileAuto;
   if (t == kTile256x128 && M < 256) t = kTileAuto;
@@ -746,13 +760,23 @@ hipError_t launch_bat_gemm(const GemmLaunch& g, hipStream_t s) {
   if (4 * U < 64) return hipErrorInvalidValue;
   if (g.wide) {
     // wide primes: LDS-staged tiles only (the direct tiles merge in 32 bits)
-    if (U > 4096) return hipErrorInvalidValue;   // the 64-bit merge bound
+    if (U > 4096 || g.red != 0) return hipErrorInvalidValue;   // the 64-bit merge bound; Montgomery only
     switch (resolve_gemm_tile(g)) {
       case kTile256x128w8: return dispatch_flags<StagedCfg<4, 2, 2, 2, 4>, true>(g, s);
       case kTile128x64: return dispatch_flags<StagedCfg<2, 2, 2, 1, 4>, true>(g, s);
       default: return dispatch_flags<StagedCfg<2, 2, 1, 1, 4>, true>(g, s);
     }
   }
+  if (g.red == 1) {
+    // Barrett epilogue (plain tables): the same three staged tiles
+    if (U > 4096) return hipErrorInvalidValue;   // z < U q 508 <= 2^(2k) needs U <= 4096 at q >= 2^21
+    switch (resolve_gemm_tile(g)) {
+      case kTile256x128w8: return dispatch_flags<StagedCfg<4, 2, 2, 2, 4>, false, 1>(g, s);
+      case kTile128x64: return dispatch_flags<StagedCfg<2, 2, 2, 1, 4>, false, 1>(g, s);
+      default: return dispatch_flags<StagedCfg<2, 2, 1, 1, 4>, false, 1>(g, s);
+    }
+  }
+  if (g.red != 0) return hipErrorInvalidValue;
   switch (resolve_gemm_tile(g)) {
     case kTile256x256: return dispatch_flags<StagedCfg<2, 4, 4, 2, 2>>(g, s);     // 8 waves of 128x64
     case kTile256x128: return dispatch_flags<StagedCfg<2, 2, 4, 2, 2>>(g, s);     // 4 waves of 128x64

@@ -184,6 +184,10 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
   }
   bat_expand(m1, R, R, q, t.fwd_left);
   bat_expand(im1, R, R, q, t.inv_left);
+  if (!wide_prime(q)) {           // without the Montgomery factor, for the Barrett epilogue
+    bat_expand(m1, R, R, q, t.fwd_left_plain, false);
+    bat_expand(im1, R, R, q, t.inv_left_plain, false);
+  }
 
   auto shoup = [&](uint32_t w) { return (uint32_t)(((uint64_t)w << 32) / q); };
   if (log_c1 > 0) {
@@ -264,6 +268,10 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
   }
   bat_expand(m3, C, C, q, t.fwd_right);
   bat_expand(im3, C, C, q, t.inv_right);
+  if (!wide_prime(q)) {
+    bat_expand(m3, C, C, q, t.fwd_right_plain, false);
+    bat_expand(im3, C, C, q, t.inv_right_plain, false);
+  }
 
   // Step-2 twiddles T2[k][c] = psi^(c (2 brv_R(k)+1)), stored [k][c] (left kernel epilogue);
   // inverse twiddles IT2[k][c] = psi^(-c (2 brv_R(k)+1)), stored transposed [c][k]

@@ -54,6 +54,8 @@ void bat_expand(const std::vector<uint32_t>& T, int n_in, int n_out, uint32_t q,
 struct NttTables {
   // forward: step 1 (left-known, rows), step 2 twiddle, step 3 (right-known, cols)
   std::vector<int8_t> fwd_left, fwd_right, inv_left, inv_right;
+  // the same four without the Montgomery factor (Barrett epilogue; narrow primes only)
+  std::vector<int8_t> fwd_left_plain, fwd_right_plain, inv_left_plain, inv_right_plain;
   std::vector<uint32_t> fwd_tw, inv_tw;      // (w, floor(w 2^32 / q)) pairs for Shoup multiplication
   std::vector<uint32_t> bf_fwd, bf_inv;      // butterfly twiddles, Montgomery form
   uint32_t bf_ninv;                          // N^-1 * 2^32 mod q (butterfly inverse scale)

@@ -253,8 +253,8 @@ def test_three_factor_split_errors():
             B.set_ntt_split3(*bad)
 
 
-# Barrett epilogue in the row kernels (plain tables) for every row-kernel family:
-# LDS tables (16 x 16, 32 x 32, 64 x 32) and global-memory tables (64 x 64)
+# Barrett epilogue (plain tables) in the row-side step and the row kernels, for every
+# row-kernel family: one LDS table (16 x 16, 32 x 32, 64 x 64), two (64 x 32, 16 x 64)
 @pytest.mark.parametrize("log_n,log_r,log_c1,L,batch", [(13, 5, 4, 2, 1), (16, 6, 5, 3, 2), (16, 5, 6, 1, 1),
                                                         (16, 4, 6, 1, 1)])
 def test_three_factor_barrett_epilogue_matches_oracle(log_n, log_r, log_c1, L, batch):
@@ -273,6 +273,43 @@ def test_three_factor_barrett_epilogue_matches_oracle(log_n, log_r, log_c1, L, b
     finally:
         B.set_ntt_reduction("montgomery")
         B.set_ntt_split3(log_n, 0, 0)
+
+
+@pytest.mark.parametrize("log_n,log_r,tile", [(8, 4, 0), (10, 5, 0), (12, 6, 0), (12, 4, 3), (12, 8, 5), (12, 6, 1)])
+def test_two_factor_barrett_epilogue_matches_oracle(log_n, log_r, tile):
+    # both step GEMMs with plain tables and the Barrett epilogue (tile requests outside
+    # its staged tiles fall back to the automatic choice)
+    from paper_2501_07047_amd import binding as B
+    B.set_ntt_split(log_n, log_r)
+    B.set_gemm_tile(tile)
+    B.set_ntt_reduction("barrett")
+    try:
+        primes, x = synthetic.ntt_batch(320 + log_n + log_r, log_n, 3, 2)
+        x[0, :, 0] = [q - 1 for q in primes]
+        ref = _oracle_ntt(x, primes)
+        d = to_dev(x)
+        B.ntt_forward(d, primes)
+        assert np.array_equal(to_host(d), ref)
+        B.ntt_inverse(d, primes)
+        assert np.array_equal(to_host(d), x)
+    finally:
+        B.set_ntt_reduction("montgomery")
+        B.set_gemm_tile(0)
+        B.set_ntt_split(log_n, log_n // 2)
+
+
+def test_he_mult_with_barrett_ntt():
+    # every NTT inside HE-Mult (three-factor at N = 2^14) with the Barrett epilogue
+    from oracle import ckks as CK
+    from paper_2501_07047_amd import binding as B
+    B.set_ntt_reduction("barrett")
+    try:
+        qs, ps, a, bb, key = synthetic.ckks_pair(8, 14, 6, 3, 2, 1)
+        out = torch_empty(a.shape)
+        B.he_mult(to_dev(a), to_dev(bb), to_dev(key), out, qs, ps, 3)
+        assert np.array_equal(to_host(out)[0], CK.he_mult(a[0], bb[0], key, qs, ps, 3))
+    finally:
+        B.set_ntt_reduction("montgomery")
 
 
 def test_barrett_epilogue_rejects_small_primes():

@@ -77,42 +77,44 @@ def _merge_reduce(P, q, plain=False):
     return np.array((Z * rinv) % q, dtype=np.uint64).reshape(U, -1)
 
 
-def _emulate(X, q, log_n, log_r, inverse):
+def _emulate(X, q, log_n, log_r, inverse, plain=False):
+    # plain: the tables without the Montgomery factor (host tables 7-10, Barrett epilogue)
     from paper_2501_07047_amd import binding
     R, C = 1 << log_r, 1 << (log_n - log_r)
     rinv = pow(1 << 32, -1, q)
+    tab = lambda w: binding.host_tables(q, log_n, log_r, w + 7 if plain else w)
     if not inverse:
-        t1 = binding.host_tables(q, log_n, log_r, 0)
-        t3 = binding.host_tables(q, log_n, log_r, 1)
+        t1 = tab(0)
+        t3 = tab(1)
         pairs = binding.host_tables(q, log_n, log_r, 4).reshape(R, C, 2)
         assert np.array_equal(pairs[..., 1].astype(np.uint64), (pairs[..., 0].astype(np.uint64) << 32) // q)
         tw = (pairs[..., 0].astype(object) * (1 << 32)) % q          # Montgomery form for the emulation
         A = X.reshape(R, C)
-        Y = _merge_reduce(_gemm(t1, 4 * R, A, q), q)                # [k][c]
+        Y = _merge_reduce(_gemm(t1, 4 * R, A, q), q, plain)         # [k][c]
         Y = np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
-        out = _merge_reduce(_gemm(t3, 4 * C, Y.T, q), q)           # [c'][k]
+        out = _merge_reduce(_gemm(t3, 4 * C, Y.T, q), q, plain)    # [c'][k]
         return out.T.reshape(-1)
-    t3 = binding.host_tables(q, log_n, log_r, 3)
-    t1 = binding.host_tables(q, log_n, log_r, 2)
+    t3 = tab(3)
+    t1 = tab(2)
     tw = (binding.host_tables(q, log_n, log_r, 5).reshape(C, R, 2)[..., 0].astype(object) * (1 << 32)) % q
     A = X.reshape(R, C)
-    Y = _merge_reduce(_gemm(t3, 4 * C, A.T, q), q)                  # [c][k]
+    Y = _merge_reduce(_gemm(t3, 4 * C, A.T, q), q, plain)           # [c][k]
     Y = np.array((Y.astype(object) * tw * rinv) % q, dtype=np.uint64)
-    out = _merge_reduce(_gemm(t1, 4 * R, Y.T, q), q)               # [r][c]
+    out = _merge_reduce(_gemm(t1, 4 * R, Y.T, q), q, plain)        # [r][c]
     return out.reshape(-1)
 
 
 @pytest.mark.parametrize("log_n,log_r", [(8, 4), (10, 5), (10, 4), (10, 6), (12, 6)])
 def test_emulated_bat_ntt_matches_oracle(log_n, log_r):
     n = 1 << log_n
-    for q in prime_chain(2) + WIDE:
+    for q, plain in [(p, False) for p in prime_chain(2) + WIDE] + [(prime_chain(1)[0], True)]:
         psi = psi_of(q, n)
         g = np.random.Generator(np.random.PCG64(log_n * 7 + log_r))
         a = g.integers(0, q, n).astype(np.uint64)
         a[0] = q - 1
         ref = ntt_ct(a, q, psi)
-        assert np.array_equal(_emulate(a, q, log_n, log_r, False), ref)
-        assert np.array_equal(_emulate(ref, q, log_n, log_r, True), a)
+        assert np.array_equal(_emulate(a, q, log_n, log_r, False, plain), ref)
+        assert np.array_equal(_emulate(ref, q, log_n, log_r, True, plain), a)
         assert np.array_equal(intt_gs(ref, q, psi), a)
 
 
@@ -158,6 +160,9 @@ def test_wide_prime_limits():
     for which in (8, 9, 10, 11):        # no plain (Barrett) tables in the wide form
         with pytest.raises(binding.CrossError):
             binding.host_row_tables(q, 14, 5, 5, which)
+    for which in (7, 8, 9, 10):         # nor plain step tables
+        with pytest.raises(binding.CrossError):
+            binding.host_tables(q, 12, 6, which)
     with pytest.raises(binding.CrossError) as e:     # the BAT-lazy fragment is 28-bit only
         binding.host_tables(q, 12, 6, 6)
     assert e.value.code == -4
@@ -224,8 +229,8 @@ def _emulate3(X, q, log_n, log_r, log_c1, inverse, plain=False):
     rt = lambda w: binding.host_row_tables(q, log_n, log_r, log_c1, w + 8 if plain and w < 4 else w)
     mr = lambda P: _merge_reduce(P, q, plain)
     if not inverse:
-        t1 = binding.host_tables(q, log_n, log_r, 0)
-        Y = twist(_merge_reduce(_gemm(t1, 4 * R, X.reshape(R, C), q), q), mont(rt(7).reshape(R, C, 2)))
+        t1 = binding.host_tables(q, log_n, log_r, 7 if plain else 0)
+        Y = twist(mr(_gemm(t1, 4 * R, X.reshape(R, C), q)), mont(rt(7).reshape(R, C, 2)))
         tb, tc = rt(0), rt(1)
         t3 = mont(rt(4).reshape(C1, C2, 2))
         out = np.empty((R, C), dtype=np.uint64)
@@ -242,8 +247,8 @@ def _emulate3(X, q, log_n, log_r, log_c1, inverse, plain=False):
         Z = twist(mr(_gemm(itc, 4 * C2, X[k].T, q)), it3)                               # [c2][m]
         Yk = mr(_gemm(itb, 4 * C1, Z.T, q))                                             # [c1][c2]
         Y[k] = twist(Yk.reshape(-1), it2[k])
-    t1 = binding.host_tables(q, log_n, log_r, 2)
-    return _merge_reduce(_gemm(t1, 4 * R, Y, q), q).reshape(-1)
+    t1 = binding.host_tables(q, log_n, log_r, 9 if plain else 2)
+    return mr(_gemm(t1, 4 * R, Y, q)).reshape(-1)
 
 
 @pytest.mark.parametrize("plain,wide", [(False, False), (True, False), (False, True)])
