@@ -29,6 +29,31 @@ inline void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipSt
   }
 }
 
+// Wide primes (2^28 <= q < 2^31): merge of the four signed digit sums s_i
+// (weights 2^(8i)) and signed Montgomery reduction to [0, q), for contractions of
+// at most 64 inputs, where |s_i| <= 64 * 4 * 128 * 255 < 2^23.  Then A = s0 + 2^8 s1
+// and B = s2 + 2^8 s3 fit int32; z = A + 2^16 B has low word lo = A + (B << 16) mod
+// 2^32 and high word (B >> 16) + carry + (A >> 31) (the sign of A borrows one).
+// |z| < 64 * 1020 * 2^31.01 < 2^48, so |hi| <= 2^16 and w = (z - m q) / 2^32 + q =
+// (hi + q) - umulhi(m, q) lies in (-2^16, q + 2^16]: computed mod 2^32 a negative w
+// reads as at least 2^32 - 2^16, and one conditional addition or subtraction of q
+// brings it to [0, q).
+__device__ __forceinline__ uint32_t merge_redc_wide32(int32_t s0, int32_t s1, int32_t s2, int32_t s3, uint32_t q,
+                                                      uint32_t qinv) {
+  const int32_t A = s0 + (int32_t)((uint32_t)s1 << 8);
+  const int32_t B = s2 + (int32_t)((uint32_t)s3 << 8);
+  const uint32_t U = (uint32_t)B << 16;
+  const uint32_t lo = (uint32_t)A + U;
+  const int32_t hi = (B >> 16) + (lo < U ? 1 : 0) + (A >> 31);
+  const uint32_t m = lo * qinv;
+  uint32_t w = ((uint32_t)hi + q) - __umulhi(m, q);
+  if (w >= 0xffff0000u)
+    w += q;
+  else if (w >= q)
+    w -= q;
+  return w;
+}
+
 // One limb of one BAT NTT step: all `npoly` polynomials of the limb share the
 // prime and therefore the table.  Offsets are in uint32 elements from the
 // launch's base pointers, so a job list can be reused for any buffer.

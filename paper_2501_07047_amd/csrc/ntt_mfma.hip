@@ -254,7 +254,9 @@ __device__ __forceinline__ void gemm_epilogue(const v16i (&acc)[MB][NB], const T
           const uint32_t s2 = (uint32_t)sv[4 * j + 2], s3 = (uint32_t)sv[4 * j + 3];
           uint32_t r;
           if constexpr (WIDE) {
-            r = merge_redc_wide(sv[4 * j], sv[4 * j + 1], sv[4 * j + 2], sv[4 * j + 3], q, qinv);   // [0, q)
+            // [0, q); the 32-bit merge where the contraction is at most 64 inputs deep
+            r = g.U <= 64 ? merge_redc_wide32(sv[4 * j], sv[4 * j + 1], sv[4 * j + 2], sv[4 * j + 3], q, qinv)
+                          : merge_redc_wide(sv[4 * j], sv[4 * j + 1], sv[4 * j + 2], sv[4 * j + 3], q, qinv);
           } else {
           uint32_t zlo, zhi;
           if (!WIDE_MERGE) {

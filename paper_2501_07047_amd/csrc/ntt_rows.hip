@@ -97,18 +97,10 @@ __device__ __forceinline__ uint32_t merge_barrett(const v16i& a, int j, uint32_t
   return r >= q ? r - q : r;
 }
 
-// Wide primes: merge of the four signed digit sums (weights 2^(8i)) and signed
-// Montgomery reduction to [0, q).  |z| < 64 * 1020 * 2^31.01 < 2^48, so
-// (z - m q) / 2^32 = (z >> 32) - umulhi(m, q) lies in (-q - 2^16, 2^16], and two
-// conditional additions of q bring it to [0, q).
+// Wide primes: merge of the four signed digit sums and signed Montgomery
+// reduction (contractions here are at most 64 inputs deep).
 __device__ __forceinline__ uint32_t merge_redc_wide(const v16i& a, int j, uint32_t q, uint32_t qinv) {
-  const int64_t z = (int64_t)a[4 * j] + ((int64_t)a[4 * j + 1] << 8) + ((int64_t)a[4 * j + 2] << 16) +
-                    ((int64_t)a[4 * j + 3] << 24);
-  const uint32_t m = (uint32_t)z * qinv;
-  int64_t r = (z >> 32) - (int64_t)__umulhi(m, q);
-  if (r < 0) r += q;
-  if (r < 0) r += q;
-  return (uint32_t)r;
+  return merge_redc_wide32(a[4 * j], a[4 * j + 1], a[4 * j + 2], a[4 * j + 3], q, qinv);
 }
 
 // Epilogue reduction of register group j: RED = 0 Montgomery (0, 2q), 1 Barrett
