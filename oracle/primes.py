@@ -4,8 +4,9 @@ Test infrastructure: see ``oracle/__init__.py``.
 
 Paper: Sec. II-A (ring R_Q = Z_Q[x]/(x^N+1), RNS bases q_i of ~28 bits,
 Tab. Notation).  The paper does not fix the primes or the root; the readings
-used here (largest primes below 2^28 that are 1 mod 2^17; psi from the
-smallest generator) are listed as readings G1/G11 in the design notes.
+used here are the largest primes below 2^28 that are 1 mod 2^17 (below 2^31
+for the NTT's wide form: ``prime_chain(count, bits=31)``) and psi from the
+smallest generator.
 """
 
 
