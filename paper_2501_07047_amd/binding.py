@@ -163,7 +163,7 @@ NTT_REDUCTION = {"montgomery": 0, "barrett": 1}
 
 
 def set_ntt_reduction(method, device=None):
-    """Epilogue reduction of the three-factor row kernels ("montgomery" or "barrett")."""
+    """Epilogue reduction of every MFMA NTT step ("montgomery" or "barrett")."""
     ctx = context(device)
     _check(lib().cross_set_ntt_reduction(ctx, NTT_REDUCTION[method]), ctx)
 
