@@ -1,7 +1,8 @@
 """GPU parity of the NTT with wide primes (2^28 <= q < 2^31) against the oracle,
 bit-exact: byte operands biased to b - 128, balanced signed-digit tables with
-row corrections, signed 64-bit ChunkMerge and Montgomery step, in the two- and
-three-factor forms and the butterfly path."""
+row corrections, signed ChunkMerge (32-bit at contraction depths up to 64, else
+64-bit) and Montgomery step, in the two- and three-factor forms and the butterfly
+path."""
 import numpy as np
 import pytest
 
