@@ -122,6 +122,51 @@ def test_argument_errors():
         B.ntt_forward(torch.zeros((1, 1, 1000), dtype=torch.int32, device="cuda"), [268042241])
 
 
+def test_degenerate_arguments_are_rejected_before_any_launch():
+    # empty batch, no limbs, N outside 2^4..2^16, more limbs than the limit, misaligned
+    # and null data: every NTT entry point returns CROSS_EINVAL from its host checks and
+    # leaves the buffer as it was
+    import ctypes
+    import torch
+    from paper_2501_07047_amd import binding as B
+    primes, x = synthetic.ntt_batch(77, 12, 2, 1)
+    d = to_dev(x)
+    lib, ctx, s = B.lib(), B.context(d.device.index), B._stream(d)
+    arr = B._u32_array(primes * 33)                 # 66 entries: long enough for every L below
+    ptr = ctypes.c_void_p(d.data_ptr())
+    cases = [(12, 2, 0, ptr), (12, 0, 1, ptr), (3, 2, 1, ptr), (17, 2, 1, ptr), (12, 65, 1, ptr),
+             (12, 2, 1, ctypes.c_void_p(d.data_ptr() + 4)), (12, 2, 1, None)]
+    for fn in ("cross_ntt_forward", "cross_ntt_inverse", "cross_ntt_forward_butterfly",
+               "cross_ntt_inverse_butterfly"):
+        for log_n, L, batch, p in cases:
+            st = getattr(lib, fn)(ctx, log_n, arr, L, batch, p, s)
+            assert st == -1, (fn, log_n, L, batch)
+            assert lib.cross_last_error(ctx)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(d), x)
+
+
+def test_degenerate_ckks_batches_are_rejected():
+    # an empty batch is an argument error for BConv and HE-Mult as well
+    import ctypes
+    import torch
+    from paper_2501_07047_amd import binding as B
+    qs, ps = synthetic.primes(4)[:3], synthetic.primes(4)[3:]
+    z = torch.zeros((1, 2, 3, 1 << 10), dtype=torch.int32, device="cuda")
+    key = torch.zeros((3, 2, 4, 1 << 10), dtype=torch.int32, device="cuda")
+    out = torch.full_like(z, 7)
+    lib, ctx, s = B.lib(), B.context(0), B._stream(z)
+    prm = B._params(qs, ps, 3, 1 << 10)
+    st = lib.cross_he_mult(ctx, ctypes.byref(prm), ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                           ctypes.c_void_p(key.data_ptr()), ctypes.c_void_p(out.data_ptr()), 0, s)
+    assert st == -1
+    st = lib.cross_bconv(ctx, 10, B._u32_array(qs), 3, B._u32_array(ps), 1, ctypes.c_void_p(z.data_ptr()),
+                         ctypes.c_void_p(out.data_ptr()), 0, s)
+    assert st == -1
+    torch.cuda.synchronize()
+    assert bool((out == 7).all())
+
+
 @pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_every_tile_shape_is_bit_exact(tile):
     from paper_2501_07047_amd import binding as B
