@@ -132,7 +132,8 @@ cross_status cross_set_gemm_tile(cross_ctx ctx, int tile);
  * the runtime side is cut into its four bytes, fed to the signed int8 MFMA as
  * b - 128, the pre-known side into balanced signed 8-bit digits, and each
  * accumulator starts at a per-row correction 128 * (row sum); the partial sums
- * are merged in 64 bits and reduced with a signed Montgomery step.  Limbs of
+ * are merged (in 32 bits where a contraction is at most 64 inputs deep, else
+ * in 64) and reduced with a signed Montgomery step.  Limbs of
  * both kinds may be mixed in one call (they run as two groups).  With
  * CROSS_NTT_RED_BARRETT, wide primes fail with CROSS_EUNSUPPORTED.
  */
