@@ -25,6 +25,7 @@ INT8_PEAK_TOPS = 5000.0      # MI355X dense int8 MFMA, TOP/s
 HBM_PEAK_GBS = 8000.0
 
 LOG_N, L, POLYS = 16, 24, 16
+PROFILE_EVERY = 4      # one timed step in this many brackets the dominant kernel's launches with HIP events
 
 
 def gemm_ops_per_launch(log_n, log_r, nlimb_polys, kind):
@@ -429,12 +430,13 @@ def main():
     B.profile_enable(False)
     fam = max((k for k in pre if k in ("bat_gemm_left", "bat_gemm_right", "ntt_rows")),
               key=lambda k: pre[k][1])
-    # timed region: events on the dominant family's launches only (their stamps cost
-    # a little queue time per launch, so the other families run unbracketed)
+    # timed region: events bracket the dominant family's launches (one forward and one
+    # inverse per step) in one step of every PROFILE_EVERY; each bracketed launch costs a
+    # few microseconds of queue time, and the other families run unbracketed
     B.profile_only(fam)
-    B.profile_enable(True)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        B.profile_enable(i % PROFILE_EVERY == 0)
         step_mfma()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -488,6 +490,7 @@ def main():
                 "ops_per_launch": ops,
                 "frac_of_measured_mfma_peak": round(achieved / measured_peak["mfma_i8_tops"], 4)}
     roof.update({"avg_launch_us": round(avg_s * 1e6, 2), "launches_timed": launches,
+                 "timed_steps_with_events": f"1 of every {PROFILE_EVERY}",
                  "measured_peaks": measured_peak,
                  "event_ms_by_kernel_5_steps": {k: [v[0], round(v[1], 3)] for k, v in pre.items()}})
 
