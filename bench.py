@@ -80,8 +80,9 @@ def cpu_baseline(budget_s=12.0):
                       "oracle.ntt.ntt_ct/intt_gs, single process" % (done, POLYS, done // (2 * POLYS), dt)}
 
 
-def he_mult_bench(B, steps, warmup, batch):
-    """HE-Mult + relinearisation at N=2^16, L=24, dnum=3, K=8 (and Rotate at the same shape)."""
+def he_mult_bench(B, steps, warmup, batch, ops=("he_mult", "rotate", "rescale", "he_add")):
+    """HE-Mult + relinearisation at N=2^16, L=24, dnum=3, K=8 (and Rotate, Rescale, HE-Add at
+    the same shape); `ops` selects which."""
     import numpy as np
     import torch
     import synthetic
@@ -96,6 +97,8 @@ def he_mult_bench(B, steps, warmup, batch):
                      ("rotate", lambda: B.rotate(da, 1, dk, out, qs, ps, 3)),
                      ("rescale", lambda: B.rescale(da, out_rs, qs, 1)),
                      ("he_add", lambda: B.he_add(da, db, out, qs))):
+        if name not in ops:
+            continue
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -363,9 +366,10 @@ def main():
     ap.add_argument("--warmup-seconds", type=float, default=1.0,
                     help="keep warming up until this much wall time has passed (0 under a profiler)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["all", "ntt", "copy"], default="all",
+    ap.add_argument("--only", choices=["all", "ntt", "copy", "he_mult"], default="all",
                     help="ntt: time only the NTT step; copy: a plain 256 MiB device copy "
-                         "(calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes)")
+                         "(calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes); "
+                         "he_mult: only HE-Mult at batch 8 (for a kernel trace of its kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path shards by ciphertext with no "
@@ -386,6 +390,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "launches": args.steps}))
+        return
+    if args.only == "he_mult":
+        print(json.dumps({"he_mult_batch8": he_mult_bench(B, args.steps, args.warmup, 8, ("he_mult",))["he_mult"]}))
         return
     log_r, log_c1 = B.get_ntt_split(LOG_N)       # the library's default factoring of 2^16
     primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
