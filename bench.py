@@ -35,6 +35,17 @@ def gemm_ops_per_launch(log_n, log_r, nlimb_polys, kind):
     return 2.0 * (4 * U) * (4 * U) * V * nlimb_polys
 
 
+def rows_bytes_per_launch(log_n, log_r, log_c1, nlimbs, npolys):
+    """Algorithmic HBM bytes of one row-kernel launch, averaged over forward and inverse:
+    every residue read and written once, per prime the BAT-expanded C1 x C1 and C2 x C2
+    tables (one when C1 = C2) and the C inner twiddle pairs, and on inverse launches (half
+    of them) the N inverse step-2 twiddle pairs."""
+    n, c = 1 << log_n, 1 << (log_n - log_r)
+    c1, c2 = 1 << log_c1, c >> log_c1
+    tables = 16 * c1 * c1 if c1 == c2 else 16 * c1 * c1 + 16 * c2 * c2
+    return nlimbs * npolys * n * 8 + nlimbs * (tables + 8 * c) + nlimbs * n * 8 // 2
+
+
 def source_hash(*names):
     h = hashlib.sha256()
     for n in names:
@@ -478,8 +489,7 @@ def main():
         # step-2 twiddle pairs.
         c = 1 << (LOG_N - log_r)
         c1, c2 = 1 << log_c1, c // (1 << log_c1)
-        tables = 16 * c1 * c1 if c1 == c2 else 16 * c1 * c1 + 16 * c2 * c2
-        nbytes = npolys * n * 8 + L * (tables + 8 * c) + L * n * 8 // 2
+        nbytes = rows_bytes_per_launch(LOG_N, log_r, log_c1, L, POLYS)
         ops = 32.0 * n * (c1 + c2) * npolys
         achieved = nbytes / avg_s / 1e9
         khash = source_hash("ntt_rows.hip")

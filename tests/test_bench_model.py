@@ -1,0 +1,47 @@
+"""Host-side checks of the benchmark's byte and op models and of its traffic lookup (no GPU)."""
+import json
+import os
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_row_kernel_bytes_for_the_benchmarked_launch():
+    # N = 2^16 as 64 x 32 x 32, 24 limbs x 16 polynomials, counted term by term:
+    # data 24 * 16 * 65536 words read and written; per prime one 128 x 128-byte BAT
+    # table (C1 = C2 = 32, 4 x 4 bytes per entry) and 1024 inner twiddle pairs;
+    # inverse launches add 65536 step-2 twiddle pairs per prime
+    data = 2 * 4 * 24 * 16 * 65536
+    per_prime = 128 * 128 + 1024 * 8
+    inverse_twiddles = 24 * 65536 * 8
+    expect = data + 24 * per_prime + inverse_twiddles // 2
+    assert expect == 208207872
+    assert bench.rows_bytes_per_launch(16, 6, 5, 24, 16) == expect
+
+
+def test_row_kernel_bytes_with_unequal_factors():
+    # C1 != C2 stages both tables
+    got = bench.rows_bytes_per_launch(15, 6, 4, 2, 3)
+    n, c1, c2 = 1 << 15, 16, 32
+    assert got == 2 * 3 * n * 8 + 2 * (16 * c1 * c1 + 16 * c2 * c2 + 8 * 512) + 2 * n * 8 // 2
+
+
+def test_counted_traffic_is_close_to_the_model():
+    # the committed rocprofv3 counters of the row kernel: within 3% above the algorithmic bytes
+    with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+        rec = json.load(f)["ntt_rows"]
+    model = bench.rows_bytes_per_launch(16, 6, 5, 24, 16)
+    assert model <= rec["bytes_per_launch"] <= 1.03 * model
+    assert rec["fetch_bytes"] + rec["write_bytes"] == rec["bytes_per_launch"]
+
+
+def test_gemm_ops_model():
+    # one BAT GEMM step: 2 ops per int8 MAC, (4U)^2 MACs per output column block of V
+    assert bench.gemm_ops_per_launch(16, 6, 384, "left") == 2.0 * 256 * 256 * 1024 * 384
+    assert bench.gemm_ops_per_launch(12, 6, 1, "right") == 2.0 * 256 * 256 * 64
+
+
+def test_traffic_is_null_once_the_kernel_changed():
+    assert bench.traffic_for("ntt_rows", "0" * 16) is None
+    assert bench.traffic_for("no_such_kernel", bench.source_hash("ntt_rows.hip")) is None
