@@ -265,7 +265,8 @@ bconv_kernel(BconvLaunch g) {
   bconv_wave(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
-__global__ void __launch_bounds__(256)
+// the same per-wave work as bconv_kernel, so the same eight-wave launch
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
 bconv_list_kernel(const BconvLaunch* tasks) {
   const BconvLaunch g = tasks[blockIdx.y];
   bconv_wave(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
