@@ -13,6 +13,8 @@ The paper does not spell the position map out; this reading (G2) is the standard
 one produced by a Cooley-Tukey negacyclic butterfly network fed with bit-reversed
 powers of psi, so the butterfly baseline and the 3-step form agree bit for bit.
 """
+from functools import lru_cache
+
 import numpy as np
 
 U64 = np.uint64
@@ -26,9 +28,22 @@ def bitrev(i: int, bits: int) -> int:
     return r
 
 
+@lru_cache(maxsize=32)
 def bitrev_table(n: int) -> np.ndarray:
     bits = n.bit_length() - 1
-    return np.array([bitrev(i, bits) for i in range(n)], dtype=np.int64)
+    out = np.array([bitrev(i, bits) for i in range(n)], dtype=np.int64)
+    out.setflags(write=False)
+    return out
+
+
+@lru_cache(maxsize=256)
+def rev_powers(base: int, n: int, q: int) -> np.ndarray:
+    """[base^brv_N(k) mod q for k < N] -- the butterfly twiddles of ``ntt_ct`` /
+    ``intt_gs``.  Kept per (base, N, q) because every limb of a prime reuses it; the
+    array is read-only."""
+    out = _powers(base, n, q)[bitrev_table(n)]
+    out.setflags(write=False)
+    return out
 
 
 def _powers(base: int, count: int, q: int) -> np.ndarray:
@@ -98,8 +113,7 @@ def ntt_ct(a, q: int, psi: int) -> np.ndarray:
     x = np.array(a, dtype=U64, copy=True)
     n = x.shape[-1]
     lead = x.shape[:-1]
-    bits = n.bit_length() - 1
-    psi_rev = np.array([pow(psi, bitrev(k, bits), q) for k in range(n)], dtype=U64)
+    psi_rev = rev_powers(psi, n, q)
     qq = U64(q)
     m, t = 1, n
     while m < n:
@@ -119,9 +133,7 @@ def intt_gs(ahat, q: int, psi: int) -> np.ndarray:
     x = np.array(ahat, dtype=U64, copy=True)
     n = x.shape[-1]
     lead = x.shape[:-1]
-    bits = n.bit_length() - 1
-    ipsi = pow(psi, -1, q)
-    ipsi_rev = np.array([pow(ipsi, bitrev(k, bits), q) for k in range(n)], dtype=U64)
+    ipsi_rev = rev_powers(pow(psi, -1, q), n, q)
     qq = U64(q)
     m, t = n // 2, 1
     while m >= 1:
