@@ -1,12 +1,17 @@
 """Benchmark of the CROSS hot path on one MI355X.
 
 Workload (one "step"): forward + inverse NTT of a CKKS-shaped batch,
-N = 2^16 split 256 x 256, L = 24 limbs of 28-bit primes, 8 ciphertexts x 2
-polynomials = 384 limb-NTTs each way, through the BAT int8-MFMA path.  Inputs
-are resident in HBM before timing starts.  Reported beside it: the same step
-through the plain radix-2 butterfly kernels (bit-identical results, checked),
-the roofline of the dominant kernel from live HIP-event timings, and the CPU
-oracle timed on a bounded sample.
+N = 2^16, L = 24 limbs of 28-bit primes, 8 ciphertexts x 2 polynomials = 384
+limb-NTTs each way, through the BAT int8-MFMA path with the library's default
+factoring of 2^16 (three factors, 64 x 32 x 32; the 256 x 256 two-factor form
+is timed beside it).  Inputs are resident in HBM before timing starts.
+Reported beside it: the same step through the plain radix-2 butterfly kernels
+(bit-identical results, checked), the roofline of the dominant kernel from
+live HIP-event timings, HE-Mult / Rotate / Rescale / HE-Add at N = 2^16,
+L = 24, dnum = 3 (HE-Mult also with its NTTs on the butterfly kernels), the
+uneven batch, the request loop, and the CPU oracle timed on bounded samples
+(before the GPU is touched; its HE-Mult results also check the GPU's batch-8
+HE-Mult bit for bit).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -67,33 +72,149 @@ def traffic_for(kernel, kernel_hash):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(budget_s=12.0):
-    """The oracle's textbook NTT (numpy, one process) on a bounded sample of the workload."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def pool_size():
+    """Worker processes for the multi-process oracle leg: the CPUs this process may run
+    on, at most 16 (one GPU's share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n, os.cpu_count() or 1))
+
+
+_POOL_ARGS = None         # inputs handed to forked oracle workers
+
+
+def _ntt_limb_job(limb):
     import numpy as np
-    import synthetic
     from oracle.ntt import ntt_ct, intt_gs
     from oracle.primes import psi
+    primes, x = _POOL_ARGS
+    q = primes[limb]
+    p = psi(q, 1 << LOG_N)
+    y = ntt_ct(x[:, limb].astype(np.uint64), q, p)
+    intt_gs(y, q, p)
+    return 2 * x.shape[0]
+
+
+def _he_mult_job(k):
+    from oracle import ckks as CK
+    qs, ps, a, b, key = _POOL_ARGS
+    return k, CK.he_mult(a[k], b[k], key, qs, ps, 3).astype("uint32")
+
+
+def cpu_baseline(he_inputs, budget_s=6.0):
+    """The oracle on bounded samples of the workloads, on the host cores (run before the
+    GPU is touched, so the worker pool is a plain fork):
+      * the NTT step: oracle.ntt.ntt_ct / intt_gs, forward + inverse of the 16
+        polynomials of one limb per task, single process and over a process pool;
+      * HE-Mult at N=2^16, L=24, dnum=3, K=8 (oracle.ckks.he_mult) on ciphertexts of the
+        GPU benchmark's own batch-8 input: one in a single process, then every one of
+        the eight over the pool (those results are compared with the GPU's later);
+      * the N=4096 single-prime case by definition (O(N^2) ntt_def / intt_def, schoolbook
+        negacyclic product).
+    Returns (baseline dict, {ciphertext: oracle HE-Mult})."""
+    global _POOL_ARGS
+    import multiprocessing as mp
+    import numpy as np
+    import synthetic
+    from oracle.ntt import ntt_def, intt_def
+    from oracle.poly import negacyclic_mul
+    from oracle.primes import psi
+
     primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
-    n = 1 << LOG_N
-    done = 0
-    t0 = time.perf_counter()
+    _POOL_ARGS = (primes, x)
+    done, t0 = 0, time.perf_counter()
     for limb in range(len(primes)):
-        q = primes[limb]
-        p = psi(q, n)
-        y = ntt_ct(x[:, limb].astype(np.uint64), q, p)
-        intt_gs(y, q, p)
-        done += 2 * POLYS
+        done += _ntt_limb_job(limb)
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "limb-NTT/s", "cores": 1, "kind": "oracle",
-            "sample": "%d limb-NTTs (forward+inverse, N=2^16, %d polys x %d limbs) in %.1f s, "
-                      "oracle.ntt.ntt_ct/intt_gs, single process" % (done, POLYS, done // (2 * POLYS), dt)}
+    dt1 = time.perf_counter() - t0
+    single = {"value": round(done / dt1, 2), "unit": "limb-NTT/s", "cores": 1,
+              "sample": "%d limb-NTTs (forward+inverse of %d polys for each of %d limbs) in %.1f s"
+                        % (done, POLYS, done // (2 * POLYS), dt1)}
+    P = pool_size()
+    ctx = mp.get_context("fork")
+    per_limb = dt1 / max(1, done // (2 * POLYS))
+    nlimbs = int(P * max(1, budget_s // max(per_limb, 1e-3)))      # whole rounds of the pool
+    with ctx.Pool(P) as pool:
+        t0 = time.perf_counter()
+        done_p = sum(pool.map(_ntt_limb_job, [i % len(primes) for i in range(nlimbs)], chunksize=1))
+        dtp = time.perf_counter() - t0
+    # HE-Mult, single process (ciphertext 0), then the whole batch over the pool
+    qs, ps, a, b, key = he_inputs
+    _POOL_ARGS = he_inputs
+    t0 = time.perf_counter()
+    _, he0 = _he_mult_job(0)
+    dth = time.perf_counter() - t0
+    nct = a.shape[0]
+    with ctx.Pool(min(P, nct)) as pool:
+        t0 = time.perf_counter()
+        he_all = dict(pool.map(_he_mult_job, range(nct), chunksize=1))
+        dthp = time.perf_counter() - t0
+    _POOL_ARGS = None
+    # N = 4096, one prime, by definition
+    q = synthetic.primes(1)[0]
+    _, y = synthetic.ntt_batch(1, 12, 1, 2)
+    w = psi(q, 4096)
+    c1 = {}
+    t0 = time.perf_counter()
+    f = ntt_def(y[0, 0], q, w)
+    c1["ntt_us"] = round((time.perf_counter() - t0) * 1e6, 1)
+    t0 = time.perf_counter()
+    intt_def(f, q, w)
+    c1["intt_us"] = round((time.perf_counter() - t0) * 1e6, 1)
+    t0 = time.perf_counter()
+    negacyclic_mul(y[0, 0], y[1, 0], q)
+    c1["polymul_schoolbook_us"] = round((time.perf_counter() - t0) * 1e6, 1)
+    base = {"value": round(done_p / dtp, 2), "unit": "limb-NTT/s", "cores": P, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "sample": "%d limb-NTTs (forward+inverse, N=2^16, 16 polys per limb task) over a pool of %d "
+                      "processes in %.1f s, oracle.ntt.ntt_ct/intt_gs" % (done_p, P, dtp),
+            "single_process": single,
+            "he_mult": {"config": "N=2^16, L=24, dnum=3, K=8, oracle.ckks.he_mult",
+                        "single_process_per_s": round(1.0 / dth, 4), "single_process_s": round(dth, 2),
+                        "pool_per_s": round(nct / dthp, 4), "pool_processes": min(P, nct),
+                        "sample": "ciphertext 0, then all %d of the batch-8 input" % nct},
+            "config1_n4096": dict(c1, note="O(N^2) definitions, one prime, batch 1")}
+    return base, he_all
 
 
-def he_mult_bench(B, steps, warmup, batch, ops=("he_mult", "rotate", "rescale", "he_add")):
+def he_mult_model(log_n, L_, K, dnum, batch, log_r, log_c1):
+    """Algorithmic work of one HE-Mult (tensor + relinearisation) at (N, L, K, dnum), per
+    ciphertext pair in a call of `batch` pairs sharing one key:
+      int8 ops: every limb-(I)NTT at 32 N (R + C1 + C2) ops (three factors; 32 N (R + C)
+      for two), INTT(d2) L + ModUp dnum x (L + K - alpha) NTTs + ModDown 2 x (K INTT + L NTT),
+      and the BConv GEMMs 2 (4 l)(4 l') N per conversion (ModUp: alpha -> L + K - alpha per
+      digit; ModDown: K -> L, twice);
+      HBM bytes: both input ciphertexts read, the output written, the key read once per call."""
+    n = 1 << log_n
+    alpha = -(-L_ // dnum)
+    c = 1 << (log_n - log_r)
+    inner = (1 << log_c1) + (c >> log_c1) if log_c1 else c
+    per_ntt = 32.0 * n * ((1 << log_r) + inner)
+    n_ntt = L_ + dnum * (L_ + K - alpha) + 2 * (K + L_)
+    bconv = dnum * 2.0 * (4 * alpha) * (4 * (L_ + K - alpha)) * n + 2 * 2.0 * (4 * K) * (4 * L_) * n
+    ct = 2 * L_ * n * 4
+    key = dnum * 2 * (L_ + K) * n * 4
+    return {"int8_ops": per_ntt * n_ntt + bconv, "limb_ntts": n_ntt, "hbm_bytes": 3 * ct + key / batch}
+
+
+def he_mult_bench(B, steps, warmup, batch, ops=("he_mult", "rotate", "rescale", "he_add"), engine="mfma"):
     """HE-Mult + relinearisation at N=2^16, L=24, dnum=3, K=8 (and Rotate, Rescale, HE-Add at
-    the same shape); `ops` selects which."""
+    the same shape); `ops` selects which, `engine` the NTT kernels (MFMA or butterfly).
+    The HE-Mult output of the last call is returned under "_out" (host array)."""
     import numpy as np
     import torch
     import synthetic
@@ -104,31 +225,126 @@ def he_mult_bench(B, steps, warmup, batch, ops=("he_mult", "rotate", "rescale", 
     out = torch.empty_like(da)
     out_rs = torch.empty((batch, 2, 23, 1 << 16), dtype=torch.int32, device="cuda")
     res = {}
-    for name, fn in (("he_mult", lambda: B.he_mult(da, db, dk, out, qs, ps, 3)),
-                     ("rotate", lambda: B.rotate(da, 1, dk, out, qs, ps, 3)),
-                     ("rescale", lambda: B.rescale(da, out_rs, qs, 1)),
-                     ("he_add", lambda: B.he_add(da, db, out, qs))):
-        if name not in ops:
-            continue
-        for _ in range(warmup):
-            fn()
+    B.set_ntt_engine(engine)
+    try:
+        for name, fn in (("he_mult", lambda: B.he_mult(da, db, dk, out, qs, ps, 3)),
+                         ("rotate", lambda: B.rotate(da, 1, dk, out, qs, ps, 3)),
+                         ("rescale", lambda: B.rescale(da, out_rs, qs, 1)),
+                         ("he_add", lambda: B.he_add(da, db, out, qs))):
+            if name not in ops:
+                continue
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if name == "he_mult":
+                res["_out"] = out.cpu().numpy().view(np.uint32).copy()
+            # per-kernel breakdown from a second, event-timed pass (kept out of the timing)
+            B.profile_report()
+            B.profile_enable(True)
+            for _ in range(steps):
+                fn()
+            prof = B.profile_report()
+            B.profile_enable(False)
+            res[name] = {"per_s": round(batch * steps / dt, 1), "us_per_op": round(dt / steps / batch * 1e6, 1),
+                         "batch": batch, "calls_timed": steps,
+                         "event_us_per_op_by_kernel": {k: round(v[1] * 1e3 / steps / batch, 1)
+                                                       for k, v in prof.items()}}
+    finally:
+        B.set_ntt_engine("mfma")
+    return res
+
+
+def he_mult_roofline(B, us_per_op, batch):
+    """HE-Mult against both peaks: algorithmic int8 ops / time vs the dense int8 MFMA peak
+    and algorithmic HBM bytes / time vs the HBM peak; `bound` is the one whose time at
+    peak is longer."""
+    log_r, log_c1 = B.get_ntt_split(16)
+    m = he_mult_model(16, 24, 8, 3, batch, log_r, log_c1)
+    t = us_per_op * 1e-6
+    t_mfma, t_hbm = m["int8_ops"] / (INT8_PEAK_TOPS * 1e12), m["hbm_bytes"] / (HBM_PEAK_GBS * 1e9)
+    tops, gbs = m["int8_ops"] / t / 1e12, m["hbm_bytes"] / t / 1e9
+    if t_mfma >= t_hbm:
+        r = {"bound": "mfma", "achieved": round(tops, 1), "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+             "frac": round(tops / INT8_PEAK_TOPS, 4)}
+    else:
+        r = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    r.update({"int8_ops_per_op": m["int8_ops"], "limb_ntts_per_op": m["limb_ntts"],
+              "hbm_bytes_per_op": m["hbm_bytes"], "int8_tops": round(tops, 1), "hbm_gbs": round(gbs, 1),
+              "us_at_int8_peak": round(t_mfma * 1e6, 2), "us_at_hbm_peak": round(t_hbm * 1e6, 2),
+              "us_per_op": us_per_op})
+    return r
+
+
+def two_factor_bench(B, data, primes, reps):
+    """Config 2 as the paper writes it: N=2^16 as 256 x 256 (two factors, both steps BAT
+    int8 GEMMs), forward + inverse of the 384 limb-polynomials; the library default is
+    restored afterwards."""
+    import torch
+    B.set_ntt_split(LOG_N, 8)
+    try:
+        for _ in range(3):
+            B.ntt_forward(data, primes)
+            B.ntt_inverse(data, primes)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            fn()
+        for _ in range(reps):
+            B.ntt_forward(data, primes)
+            B.ntt_inverse(data, primes)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        # per-kernel breakdown from a second, event-timed pass (kept out of the timing)
+        dt = (time.perf_counter() - t0) / reps
         B.profile_report()
         B.profile_enable(True)
-        for _ in range(steps):
-            fn()
+        for _ in range(reps):
+            B.ntt_forward(data, primes)
+            B.ntt_inverse(data, primes)
         prof = B.profile_report()
         B.profile_enable(False)
-        res[name] = {"per_s": round(batch * steps / dt, 1), "us_per_op": round(dt / steps / batch * 1e6, 1),
-                     "batch": batch,
-                     "event_us_per_op_by_kernel": {k: round(v[1] * 1e3 / steps / batch, 1) for k, v in prof.items()}}
-    return res
+    finally:
+        B.set_ntt_split3(LOG_N, 0, 0)
+    npolys = L * POLYS
+    ops = gemm_ops_per_launch(LOG_N, 8, npolys, "left")      # 256 x 256: both steps alike
+    gemm = {k: v for k, v in prof.items() if k.startswith("bat_gemm")}
+    launches = sum(v[0] for v in gemm.values())
+    avg_s = sum(v[1] for v in gemm.values()) / 1e3 / max(1, launches)
+    return {"config": "N=2^16 as R x C = 256 x 256, L=24, 16 polys, forward + inverse",
+            "us_per_step": round(dt * 1e6, 1), "limb_ntt_per_s": round(2 * npolys / dt, 1),
+            "gemm_launch_us_avg": round(avg_s * 1e6, 2), "int8_ops_per_gemm_launch": ops,
+            "gemm_int8_tops": round(ops / avg_s / 1e12, 1),
+            "gemm_frac_of_int8_peak": round(ops / avg_s / 1e12 / INT8_PEAK_TOPS, 4)}
+
+
+def config1_bench(B, reps=200):
+    """Config 1: N=4096, one 28-bit prime, batch 1: NTT, INTT and the negacyclic product
+    (NTT a, NTT b, pointwise, INTT); median microseconds over individually event-timed calls."""
+    import numpy as np
+    import torch
+    import synthetic
+    primes, x = synthetic.ntt_batch(1, 12, 1, 2)
+    d = torch.from_numpy(np.ascontiguousarray(x[:1]).view(np.int32)).cuda()
+    e = torch.from_numpy(np.ascontiguousarray(x[1:]).view(np.int32)).cuda()
+    out = torch.empty_like(d)
+    calls = {"ntt_us": lambda: B.ntt_forward(d, primes), "intt_us": lambda: B.ntt_inverse(d, primes),
+             "polymul_us": lambda: B.poly_mul(d, e, out, primes)}
+    res = {}
+    for name, fn in calls.items():
+        for _ in range(20):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        res[name] = round(float(np.median(ts)), 2)
+    return dict(res, config="N=4096, one prime (268042241), batch 1; median of %d event-timed calls" % reps)
 
 
 def modred_bench(B, reps):
@@ -388,8 +604,14 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import synthetic
+
+    cpu, he_oracle = None, None
+    if not args.no_cpu and args.only == "all":
+        # the oracle first, before anything touches the GPU (its worker pool forks)
+        cpu, he_oracle = cpu_baseline(synthetic.ckks_pair(0, 16, 24, 3, 8, 8))
+
+    import torch
     from paper_2501_07047_amd import binding as B
 
     torch.cuda.set_device(0)
@@ -403,7 +625,8 @@ def main():
                           "launches": args.steps}))
         return
     if args.only == "he_mult":
-        print(json.dumps({"he_mult_batch8": he_mult_bench(B, args.steps, args.warmup, 8, ("he_mult",))["he_mult"]}))
+        r = he_mult_bench(B, args.steps, args.warmup, 8, ("he_mult",))
+        print(json.dumps({"he_mult_batch8": r["he_mult"]}))
         return
     log_r, log_c1 = B.get_ntt_split(LOG_N)       # the library's default factoring of 2^16
     primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
@@ -528,11 +751,24 @@ def main():
     if args.only == "ntt":
         print(json.dumps(line))
         return
-    he1 = he_mult_bench(B, max(4, args.steps // 2), 2, 1)
-    he8 = he_mult_bench(B, max(2, args.steps // 8), 1, 8)
+    line["config2_two_factor_256x256"] = two_factor_bench(B, data, primes, max(5, args.steps // 2))
+    line["config1"] = config1_bench(B)
+    he1 = he_mult_bench(B, max(10, args.steps), 2, 1)
+    he8 = he_mult_bench(B, max(20, args.steps), 3, 8)
+    he8_bf = he_mult_bench(B, 5, 1, 8, ("he_mult",), engine="butterfly")
+    out8 = he8.pop("_out")
+    he1.pop("_out", None)
+    he8_bf.pop("_out", None)
+    he8["he_mult"]["roofline"] = he_mult_roofline(B, he8["he_mult"]["us_per_op"], 8)
+    he1["he_mult"]["roofline"] = he_mult_roofline(B, he1["he_mult"]["us_per_op"], 1)
     line["he_mult_per_s"] = he8["he_mult"]["per_s"]
     line["he_mult"] = {"config": "N=2^16, L=24, dnum=3 (alpha=8), K=8 special primes, tensor + relinearisation",
-                       "batch1": he1["he_mult"], "batch8": he8["he_mult"]}
+                       "batch1": he1["he_mult"], "batch8": he8["he_mult"],
+                       "batch8_butterfly_ntt": he8_bf["he_mult"],
+                       "speedup_vs_butterfly_ntt": round(he8["he_mult"]["per_s"] / he8_bf["he_mult"]["per_s"], 3)}
+    if he_oracle is not None:
+        line["he_mult"]["bit_exact_vs_oracle"] = all(np.array_equal(out8[k], he_oracle[k]) for k in range(8))
+        line["he_mult"]["oracle_checked"] = "all 8 ciphertexts of the batch-8 call (oracle.ckks.he_mult)"
     line["rotate"] = {"config": "same parameters, 1 slot", "batch1": he1["rotate"], "batch8": he8["rotate"]}
     line["rescale"] = {"config": "N=2^16, L=24 -> 23 (divide by the last prime), per ciphertext",
                        "batch1": he1["rescale"], "batch8": he8["rescale"]}
@@ -557,9 +793,9 @@ def main():
                       "batch8": he8["he_add"], "bytes_per_op": add_bytes,
                       "hbm_gbs_batch8": round(add_bytes * he8["he_add"]["per_s"] / 1e9, 1)}
     line["uneven_batch"] = uneven_batch_bench(B, max(4, args.steps // 2))
-    line["serving"] = serving_bench(200)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
+    line["serving"] = serving_bench(2000)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line))
 
 

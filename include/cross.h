@@ -170,7 +170,8 @@ cross_status cross_poly_mul(cross_ctx ctx, uint32_t log_n, const uint32_t* prime
  * the approximate ("fast") conversion: the result may differ from the exact
  * CRT value by a multiple u*Q, 0 <= u < l.
  *   in : device [batch][l][N] coefficient form mod src_primes (1 <= l <= 32, distinct)
- *   out: device [batch][lp][N] mod dst_primes (1 <= lp <= 64); must not alias in
+ *   out: device [batch][lp][N] mod dst_primes (1 <= lp <= 64); must not overlap in
+ *        (CROSS_EINVAL otherwise)
  *   log_n: 5..16
  */
 cross_status cross_bconv(cross_ctx ctx, uint32_t log_n, const uint32_t* src_primes, uint32_t l,
@@ -210,8 +211,11 @@ cross_status cross_keyswitch_moddown(cross_ctx ctx, const cross_ckks_params* par
  * HE-Mult with relinearisation, no rescale (Tab. perf_cmp "HE-Mult"):
  * d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1 (NTT form, limb-wise), then
  * out = (d0 + ModDown(sum_j ModUp(d2)_j * key_j.b), d1 + ModDown(sum_j ModUp(d2)_j * key_j.a)).
- *   ct_a, ct_b, out: device [batch][2][L][N] NTT form; out aliases neither input
+ *   ct_a, ct_b, out: device [batch][2][L][N] NTT form; out must not overlap ct_a,
+ *                    ct_b or relin_key (ct_a and ct_b may be the same buffer)
  *   relin_key      : device [dnum][2][L+K][N] NTT form, index 0 = b, 1 = a
+ * Errors: CROSS_EINVAL for null / misaligned / overlapping buffers or bad
+ * parameters, prime checks as cross_ntt_forward (q < 2^28).
  */
 cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* params, const uint32_t* ct_a,
                            const uint32_t* ct_b, const uint32_t* relin_key, uint32_t* out,
@@ -222,7 +226,8 @@ cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* params, const
  * g = 5^steps mod 2N (steps taken mod N/2); automorphism first, in NTT form
  * (slot p <- slot brv(((2 brv(p)+1) g mod 2N - 1)/2)), then the key switch of
  * the second component with rot_key (the key for g, layout as relin_key):
- * out = (sigma(c0) + ModDown(acc_b), ModDown(acc_a)).  ct, out: [batch][2][L][N].
+ * out = (sigma(c0) + ModDown(acc_b), ModDown(acc_a)).  ct, out: [batch][2][L][N];
+ * out must not overlap ct or rot_key (CROSS_EINVAL otherwise).
  */
 cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* params, int32_t steps,
                           const uint32_t* ct, const uint32_t* rot_key, uint32_t* out, uint32_t batch,
@@ -476,6 +481,18 @@ cross_status cross_host_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint3
  */
 typedef enum { CROSS_NTT_RED_MONTGOMERY = 0, CROSS_NTT_RED_BARRETT = 1 } cross_ntt_reduction;
 cross_status cross_set_ntt_reduction(cross_ctx ctx, int method);
+
+/*
+ * Engine of every NTT the context runs (cross_ntt_forward/inverse and those
+ * inside HE-Mult, Rotate, ModUp, ModDown, Rescale and cross_poly_mul): the BAT
+ * int8-MFMA form (default) or the plain radix-2 butterfly kernels of
+ * cross_ntt_forward_butterfly (App. "Radix-2 Cooley-Tukey NTT"), for the
+ * comparison of whole HE operations on the two NTT paths.  Results are
+ * identical either way.  The batch runtime always uses the MFMA form.
+ * Returns CROSS_EINVAL for another value.
+ */
+typedef enum { CROSS_NTT_ENGINE_MFMA = 0, CROSS_NTT_ENGINE_BUTTERFLY = 1 } cross_ntt_engine;
+cross_status cross_set_ntt_engine(cross_ctx ctx, int engine);
 
 /*
  * Host-only introspection of the three-factor row tables (split as in

@@ -40,6 +40,7 @@ SIGNATURES = {
     "cross_set_gemm_tile": [c_vp, ctypes.c_int],
     "cross_set_ntt_split3": [c_vp, c_u32, c_u32, c_u32],
     "cross_set_ntt_reduction": [c_vp, ctypes.c_int],
+    "cross_set_ntt_engine": [c_vp, ctypes.c_int],
     "cross_get_ntt_split": [c_vp, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)],
     "cross_host_row_tables": [c_u32, c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
     "cross_autotune": [c_vp, c_u32, c_u32, c_u32, ctypes.c_char_p, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32),
@@ -166,6 +167,15 @@ def set_ntt_reduction(method, device=None):
     """Epilogue reduction of every MFMA NTT step ("montgomery" or "barrett")."""
     ctx = context(device)
     _check(lib().cross_set_ntt_reduction(ctx, NTT_REDUCTION[method]), ctx)
+
+
+NTT_ENGINE = {"mfma": 0, "butterfly": 1}
+
+
+def set_ntt_engine(engine, device=None):
+    """Engine of every NTT on the context ("mfma" or "butterfly"); the batch runtime keeps MFMA."""
+    ctx = context(device)
+    _check(lib().cross_set_ntt_engine(ctx, NTT_ENGINE[engine]), ctx)
 
 
 def get_ntt_split(log_n, device=None):

@@ -432,6 +432,12 @@ cross_status begin(cross_ctx ctx) {
 
 bool aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// Byte ranges [a, a + na) and [b, b + nb) share at least one byte.
+bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
 // Key switch of d (NTT form, [B][L][N], in workspace w.d): ModUp, inner product with key, ModDown
 // of both accumulators into out0/out1 of out [B][2][L][N] with optional base.
 cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* key, int B, KsWork& w,
@@ -489,17 +495,6 @@ cross_status cross_poly_mul(cross_ctx ctx, uint32_t log_n, const uint32_t* prime
   HIPCHK(hipMemcpyAsync(out, a, tot * 4, hipMemcpyDeviceToDevice, s), "copy a");
   const uint64_t stride = (uint64_t)L * N;
   auto ntt = [&](uint32_t* d, bool inv) -> cross_status {
-    if (log_n < 8) {
-      std::vector<ButterflyJob> jobs(L);
-      for (uint32_t i = 0; i < L; ++i)
-        jobs[i] = ButterflyJob{inv ? plans[i]->bf_inv : plans[i]->bf_fwd, offs[i], plans[i]->q,
-                               plans[i]->qinv, plans[i]->bf_ninv};
-      void* dj = nullptr;
-      cross_status s2 = cached_device_copy(ctx, jobs.data(), jobs.size() * sizeof(ButterflyJob), &dj);
-      if (s2 != CROSS_OK) return s2;
-      HIPCHK(launch_butterfly((const ButterflyJob*)dj, (int)L, d, stride, (int)batch, (int)log_n, inv, s), "butterfly");
-      return CROSS_OK;
-    }
     return ntt_limbs(ctx, plans, offs, d, stride, (int)batch, inv, tmp, s);
   };
   if ((st = ntt(out, false)) != CROSS_OK) return st;
@@ -527,6 +522,8 @@ cross_status cross_bconv(cross_ctx ctx, uint32_t log_n, const uint32_t* src_prim
     if (st != CROSS_OK) return st;
   }
   const uint64_t N = 1ull << log_n;
+  if (overlaps(in, (uint64_t)batch * l * N * 4, out, (uint64_t)batch * lp * N * 4))
+    return fail(ctx, CROSS_EINVAL, "out must not overlap in");
   std::vector<uint32_t> sp(src_primes, src_primes + l), dp(dst_primes, dst_primes + lp);
   std::vector<uint64_t> so(l), dof(lp);
   for (uint32_t i = 0; i < l; ++i) so[i] = i * N;
@@ -579,7 +576,13 @@ cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* prm, const ui
   if (!ct_a || !ct_b || !relin_key || !out || !aligned(ct_a) || !aligned(ct_b) || !aligned(relin_key) ||
       !aligned(out) || batch < 1)
     return fail(ctx, CROSS_EINVAL, "bad buffer or batch");
-  if (out == ct_a || out == ct_b) return fail(ctx, CROSS_EINVAL, "out must not alias the inputs");
+  {
+    const uint64_t N = 1ull << c->log_n, ct_bytes = (uint64_t)batch * 2 * c->L * N * 4,
+                   key_bytes = (uint64_t)c->dnum * 2 * (c->L + c->K) * N * 4;
+    if (overlaps(out, ct_bytes, ct_a, ct_bytes) || overlaps(out, ct_bytes, ct_b, ct_bytes) ||
+        overlaps(out, ct_bytes, relin_key, key_bytes))
+      return fail(ctx, CROSS_EINVAL, "out must not overlap ct_a, ct_b or relin_key");
+  }
   hipStream_t s = (hipStream_t)stream;
   KsWork w;
   if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
@@ -668,9 +671,14 @@ cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* prm, int32_t s
   if ((st = get_ckks_plan(ctx, prm, &c)) != CROSS_OK) return st;
   if (!ct || !rot_key || !out || !aligned(ct) || !aligned(rot_key) || !aligned(out) || batch < 1)
     return fail(ctx, CROSS_EINVAL, "bad buffer or batch");
-  if (out == ct) return fail(ctx, CROSS_EINVAL, "out must not alias ct");
   hipStream_t s = (hipStream_t)stream;
   const uint64_t N = 1ull << c->log_n;
+  {
+    const uint64_t ct_bytes = (uint64_t)batch * 2 * c->L * N * 4,
+                   key_bytes = (uint64_t)c->dnum * 2 * (c->L + c->K) * N * 4;
+    if (overlaps(out, ct_bytes, ct, ct_bytes) || overlaps(out, ct_bytes, rot_key, key_bytes))
+      return fail(ctx, CROSS_EINVAL, "out must not overlap ct or rot_key");
+  }
   const int64_t half = (int64_t)N / 2;
   const uint64_t r = (uint64_t)((((int64_t)steps % half) + half) % half);
   const uint32_t g = powmod(5, r, (uint32_t)(2 * N));
@@ -705,11 +713,6 @@ cross_status stream_mods(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, 
   cross_status st = cached_device_copy(ctx, m.data(), m.size() * sizeof(StreamMod), &d);
   *out = (const StreamMod*)d;
   return st;
-}
-
-bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
-  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
-  return x < y + nb && y < x + na;
 }
 
 }  // namespace

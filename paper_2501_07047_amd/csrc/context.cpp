@@ -334,8 +334,9 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
       return st != CROSS_OK ? st : ntt_limbs(ctx, pw, ow, data, stride, npoly, inverse, tmp, s);
     }
   }
-  if (log_n < 8) {
-    // below the MFMA minimum (4R >= 64): radix-2 kernels, in place
+  if (log_n < 8 || ctx->ntt_engine == CROSS_NTT_ENGINE_BUTTERFLY) {
+    // below the MFMA minimum (4R >= 64), or the butterfly engine selected: radix-2
+    // kernels, in place
     std::vector<ButterflyJob> jobs(plans.size());
     for (size_t i = 0; i < plans.size(); ++i)
       jobs[i] = ButterflyJob{inverse ? plans[i]->bf_inv : plans[i]->bf_fwd, offs[i], plans[i]->q,
@@ -542,6 +543,14 @@ cross_status cross_set_ntt_reduction(cross_ctx ctx, int method) {
   if (method != CROSS_NTT_RED_MONTGOMERY && method != CROSS_NTT_RED_BARRETT)
     return fail(ctx, CROSS_EINVAL, "unknown NTT reduction");
   ctx->ntt_reduction = method;
+  return CROSS_OK;
+}
+
+cross_status cross_set_ntt_engine(cross_ctx ctx, int engine) {
+  if (!ctx) return CROSS_EINVAL;
+  if (engine != CROSS_NTT_ENGINE_MFMA && engine != CROSS_NTT_ENGINE_BUTTERFLY)
+    return fail(ctx, CROSS_EINVAL, "unknown NTT engine");
+  ctx->ntt_engine = engine;
   return CROSS_OK;
 }
 

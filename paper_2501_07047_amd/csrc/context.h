@@ -72,6 +72,7 @@ struct cross_ctx_s {
                                               // (absent: the size's default)
   int gemm_tile = 0;                          // GemmTile override (0 = auto)
   int ntt_reduction = 0;                      // row-kernel epilogue: 0 Montgomery, 1 Barrett
+  int ntt_engine = 0;                         // NTTs inside other operations: 0 MFMA, 1 butterfly
   std::map<int, int> tile_by_logn;            // autotuned GemmTile per transform size
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)

@@ -45,3 +45,18 @@ def test_gemm_ops_model():
 def test_traffic_is_null_once_the_kernel_changed():
     assert bench.traffic_for("ntt_rows", "0" * 16) is None
     assert bench.traffic_for("no_such_kernel", bench.source_hash("ntt_rows.hip")) is None
+
+
+def test_he_mult_model_counts_config3():
+    # N = 2^16, L = 24, K = 8, dnum = 3 (alpha = 8): INTT(d2) 24 + ModUp 3 x 24 + ModDown 2 x (8 + 24)
+    m = bench.he_mult_model(16, 24, 8, 3, 1, 6, 5)
+    assert m["limb_ntts"] == 160
+    n = 1 << 16
+    per_ntt = 32.0 * n * (64 + 32 + 32)
+    bconv = 3 * 2.0 * 32 * 96 * n + 2 * 2.0 * 32 * 96 * n
+    assert m["int8_ops"] == 160 * per_ntt + bconv
+    ct = 2 * 24 * n * 4
+    assert m["hbm_bytes"] == 3 * ct + 3 * 2 * 32 * n * 4          # batch 1: the key once per op
+    assert bench.he_mult_model(16, 24, 8, 3, 8, 6, 5)["hbm_bytes"] == 3 * ct + 3 * 2 * 32 * n * 4 / 8
+    # two factors, 256 x 256: 32 N (R + C) per limb-NTT
+    assert bench.he_mult_model(16, 24, 8, 3, 1, 8, 0)["int8_ops"] == 160 * 32.0 * n * 512 + bconv

@@ -118,12 +118,21 @@ def test_config4_uneven_batch_64_ciphertexts():
         torch.cuda.synchronize()
         bad = [k for k, (j, ref) in enumerate(zip(jobs, refs)) if not np.array_equal(_result(j), ref)]
         assert not bad, "mismatching jobs %s in replay %d" % (bad, r)
+    got = {k: _result(jobs[k]) for k in range(len(jobs))}
     bt.close()
-    # one oracle check on the smallest HE-Mult job
+    # oracle checks of the batch's own results: the smallest and the largest HE-Mult
+    # job (N = 2^16, L = 36, K = 12 with this seed) and the largest N = 2^16 NTT job
     he = [k for k, s in enumerate(specs) if s[0] == "he_mult"]
-    k = min(he, key=lambda i: (specs[i][1], specs[i][2]))
+    for k in (min(he, key=lambda i: (specs[i][1], specs[i][2])), max(he, key=lambda i: (specs[i][1], specs[i][2]))):
+        h = host[k]
+        assert np.array_equal(got[k][0], CK.he_mult(h["a"][0], h["b"][0], h["key"], h["qs"], h["ps"], 3)), \
+            "HE-Mult job %d %s" % (k, specs[k])
+    nt = [k for k, s in enumerate(specs) if s[0] != "he_mult" and s[1] == 16]
+    k = max(nt, key=lambda i: specs[i][2])
     h = host[k]
-    assert np.array_equal(refs[k][0], CK.he_mult(h["a"][0], h["b"][0], h["key"], h["qs"], h["ps"], 3))
+    for i, q in enumerate(h["primes"]):
+        ref = ntt_ct(h["x"][:, i].astype(np.uint64), q, psi_of(q, 1 << 16))
+        assert np.array_equal(got[k][:, i], ref), "NTT job %d %s limb %d" % (k, specs[k], i)
 
 
 def test_batch_rejects_bad_jobs():

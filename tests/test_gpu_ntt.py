@@ -83,13 +83,23 @@ def test_other_splits(log_n, log_r):
         B.set_ntt_split(log_n, log_n // 2)
 
 
-def test_config2_full_size_spot_checks():
-    # N = 2^16 as 256 x 256, L = 24, 8 ciphertexts x 2 polys, in the launch shape the bench times
+@pytest.mark.parametrize("split", ["default", "256x256"])
+def test_config2_full_size_spot_checks(split):
+    # N = 2^16, L = 24, 8 ciphertexts x 2 polys: in the library's default split (64 x 32 x 32,
+    # the launch shape the bench's headline times) and as the two-factor 256 x 256 form
     from paper_2501_07047_amd import binding as B
     primes, x = synthetic.ntt_batch(2, 16, 24, 16)
     d = to_dev(x)
-    B.ntt_forward(d, primes)
-    got = to_host(d)
+    if split == "256x256":
+        B.set_ntt_split(16, 8)
+    try:
+        B.ntt_forward(d, primes)
+        got = to_host(d)
+        B.ntt_inverse(d, primes)
+        assert np.array_equal(to_host(d), x)
+    finally:
+        B.set_ntt_split3(16, 0, 0)
+    d = to_dev(got)
     bf = to_dev(x)
     B.ntt_forward_butterfly(bf, primes)
     assert np.array_equal(to_host(bf), got)            # two independent GPU paths agree
