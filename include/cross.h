@@ -483,6 +483,29 @@ typedef enum { CROSS_NTT_RED_MONTGOMERY = 0, CROSS_NTT_RED_BARRETT = 1 } cross_n
 cross_status cross_set_ntt_reduction(cross_ctx ctx, int method);
 
 /*
+ * Allocation-free NTT, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the transform of cross_ntt_forward (inverse = 0) or
+ * cross_ntt_inverse (inverse != 0) with the same arguments, results and
+ * kernels, but no device allocation and no free.  Its scratch (the NTT
+ * intermediate and the call's job lists) is a file-scope device array of the
+ * library, CROSS_NOALLOC_MAX_BYTES plus 64 KiB, of which each device the library
+ * runs on holds one copy until the process ends; every call on a device shares
+ * it, so calls that overlap on one device (on different streams, or from
+ * different host threads) race.  Calls in one stream are ordered and safe.
+ * The tables for the primes must already exist on ctx (built, and allocated, by
+ * an earlier cross_ntt_forward or cross_ntt_inverse call with the same primes and
+ * N on the same context and split).  Job lists are copied to the device with
+ * stream-ordered host-to-device copies.
+ * Errors: as cross_ntt_forward, plus CROSS_EINVAL when batch * L * N * 4 exceeds
+ * CROSS_NOALLOC_MAX_BYTES and CROSS_EUNSUPPORTED when a prime's tables are not
+ * on ctx yet; nothing is enqueued then.
+ */
+#define CROSS_NOALLOC_MAX_BYTES (128ull << 20)
+cross_status cross_ntt_noalloc(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L, uint32_t batch,
+                               uint32_t* data, int inverse, void* stream);
+
+/*
  * Engine of every NTT the context runs (cross_ntt_forward/inverse and those
  * inside HE-Mult, Rotate, ModUp, ModDown, Rescale and cross_poly_mul): the BAT
  * int8-MFMA form (default) or the plain radix-2 butterfly kernels of

@@ -41,6 +41,7 @@ SIGNATURES = {
     "cross_set_ntt_split3": [c_vp, c_u32, c_u32, c_u32],
     "cross_set_ntt_reduction": [c_vp, ctypes.c_int],
     "cross_set_ntt_engine": [c_vp, ctypes.c_int],
+    "cross_ntt_noalloc": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, ctypes.c_int, c_vp],
     "cross_get_ntt_split": [c_vp, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)],
     "cross_host_row_tables": [c_u32, c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
     "cross_autotune": [c_vp, c_u32, c_u32, c_u32, ctypes.c_char_p, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32),
@@ -236,6 +237,18 @@ def ntt_forward(data, primes):
 
 def ntt_inverse(data, primes):
     return _ntt("cross_ntt_inverse", data, primes)
+
+
+def ntt_noalloc(data, primes, inverse=False):
+    """cross_ntt_noalloc: the NTT (or INTT) of `data` with no device allocation (scratch in
+    the library's static device array; the tables must exist, e.g. from ntt_forward)."""
+    batch, L, n = data.shape
+    if L != len(primes):
+        raise ValueError("data has %d limbs, %d primes given" % (L, len(primes)))
+    ctx = context(data.device.index)
+    _check(lib().cross_ntt_noalloc(ctx, _log2(n), _u32_array(primes), L, batch, _dev_ptr(data, "data"),
+                                   int(bool(inverse)), _stream(data)), ctx)
+    return data
 
 
 def ntt_forward_butterfly(data, primes):

@@ -3,6 +3,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 
 #include "params.h"
@@ -195,6 +196,20 @@ cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool all
 }
 
 cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, void** out) {
+  if (ctx->arena.base) {
+    // no-alloc call: a stream-ordered copy into the arena (later calls on the same
+    // stream overwrite it only after this call's kernels have run)
+    cross_ctx_s::Arena& a = ctx->arena;
+    const size_t at = (a.used + 255) & ~(size_t)255;
+    if (at + bytes > a.cap) return fail(ctx, CROSS_EINVAL, "job lists exceed the no-alloc scratch head");
+    if (bytes && hipMemcpyAsync(a.base + at, host, bytes, hipMemcpyHostToDevice, a.stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, CROSS_EDEVICE, "job list copy failed");
+    }
+    a.used = at + bytes;
+    *out = a.base + at;
+    return CROSS_OK;
+  }
   std::string key(static_cast<const char*>(host), bytes);
   auto it = ctx->job_cache.find(key);
   if (it != ctx->job_cache.end()) {
@@ -414,6 +429,36 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   return CROSS_OK;
 }
 
+// ---- scratch of the allocation-free NTT entry point ------------------------
+// A file-scope device array: every device the library runs on holds its own copy
+// (loaded with the code object, kept until the process ends).  Host code never
+// uses its name as an address: the device address comes from hipGetSymbolAddress,
+// taken once per device with that device current, and is kept per device.
+constexpr size_t kNoAllocJobBytes = 64 << 10;      // head: the call's job lists
+static __device__ __align__(256) uint8_t scratch[kNoAllocJobBytes + CROSS_NOALLOC_MAX_BYTES];
+
+hipError_t noalloc_scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;                  // device -> address of its copy
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  int prev = 0;
+  hipError_t e = hipGetDevice(&prev);
+  if (e != hipSuccess) return e;
+  if ((e = hipSetDevice(device)) != hipSuccess) return e;
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  (void)hipSetDevice(prev);
+  if (e != hipSuccess) return e;
+  addr[device] = p;
+  *out = p;
+  return hipSuccess;
+}
+
 static cross_status ntt_common(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L,
                                uint32_t batch, uint32_t* data, void* stream, bool inverse,
                                bool butterfly) {
@@ -475,8 +520,14 @@ cross_status cross_ctx_create(int hip_device, cross_ctx* out) {
     (void)hipGetLastError();
     return CROSS_EDEVICE;
   }
+  void* scratch_ptr = nullptr;
+  if (noalloc_scratch_address(hip_device, &scratch_ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return CROSS_EDEVICE;
+  }
   cross_ctx c = new cross_ctx_s();
   c->device = hip_device;
+  c->noalloc_scratch = scratch_ptr;
   *out = c;
   return CROSS_OK;
 }
@@ -544,6 +595,46 @@ cross_status cross_set_ntt_reduction(cross_ctx ctx, int method) {
     return fail(ctx, CROSS_EINVAL, "unknown NTT reduction");
   ctx->ntt_reduction = method;
   return CROSS_OK;
+}
+
+cross_status cross_ntt_noalloc(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L, uint32_t batch,
+                               uint32_t* data, int inverse, void* stream) {
+  if (!ctx) return CROSS_EINVAL;
+  if (log_n < CROSS_MIN_LOG_N || log_n > CROSS_MAX_LOG_N)
+    return fail(ctx, CROSS_EINVAL, "log_n out of range [4, 16]");
+  if (!primes || !data) return fail(ctx, CROSS_EINVAL, "null pointer");
+  if (L < 1 || L > CROSS_MAX_LIMBS) return fail(ctx, CROSS_EINVAL, "L out of range");
+  if (batch < 1) return fail(ctx, CROSS_EINVAL, "batch must be >= 1");
+  if (reinterpret_cast<uintptr_t>(data) & 15) return fail(ctx, CROSS_EINVAL, "data not 16-byte aligned");
+  const uint64_t N = 1ull << log_n, bytes = (uint64_t)batch * L * N * 4;
+  if (bytes > CROSS_NOALLOC_MAX_BYTES)
+    return fail(ctx, CROSS_EINVAL, "batch * L * N * 4 = " + std::to_string(bytes) +
+                                       " bytes exceeds the no-alloc limit CROSS_NOALLOC_MAX_BYTES = " +
+                                       std::to_string((uint64_t)CROSS_NOALLOC_MAX_BYTES));
+  if (!ctx->noalloc_scratch) return fail(ctx, CROSS_EDEVICE, "no-alloc scratch address unknown");
+  std::vector<Plan*> plans(L);
+  std::vector<uint64_t> offs(L);
+  for (uint32_t i = 0; i < L; ++i) {
+    cross_status st = check_prime(ctx, primes[i], log_n, true);
+    if (st != CROSS_OK) return st;
+    int log_r = 0, log_c1 = 0;
+    effective_split(ctx, (int)log_n, true, &log_r, &log_c1);
+    auto it = ctx->plans.find(std::make_tuple(primes[i], (int)log_n, log_r, log_c1));
+    if (it == ctx->plans.end())
+      return fail(ctx, CROSS_EUNSUPPORTED, "no tables for modulus " + std::to_string(primes[i]) +
+                                               " at this size on this context: call cross_ntt_forward or "
+                                               "cross_ntt_inverse with these primes once first");
+    plans[i] = it->second;
+    offs[i] = i * N;
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ctx->noalloc_scratch);
+  ctx->arena = cross_ctx_s::Arena{base, kNoAllocJobBytes, 0, s};
+  const cross_status st = ntt_limbs(ctx, plans, offs, data, L * N, (int)batch, inverse != 0,
+                                    reinterpret_cast<uint32_t*>(base + kNoAllocJobBytes), s);
+  ctx->arena = cross_ctx_s::Arena{};
+  return st;
 }
 
 cross_status cross_set_ntt_engine(cross_ctx ctx, int engine) {

@@ -76,6 +76,14 @@ struct cross_ctx_s {
   std::map<int, int> tile_by_logn;            // autotuned GemmTile per transform size
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)
+  void* noalloc_scratch = nullptr;            // device address of this device's no-alloc scratch
+  // While set (cross_ntt_noalloc), job lists go into this arena with stream-ordered
+  // copies instead of the allocating cache.
+  struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    hipStream_t stream = nullptr;
+  } arena;
   bool prof = false;
   std::string prof_only;                      // time only this kernel family ("" = all)
   struct ProfRec {
@@ -101,6 +109,9 @@ int split_of(cross_ctx ctx, int log_n);
 void effective_split(cross_ctx ctx, int log_n, bool allow3, int* log_r, int* log_c1);
 // Device copy of a POD array, cached by content.
 cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, void** out);
+// Device address of `device`'s copy of the allocation-free NTT's scratch array
+// (looked up once per device).
+hipError_t noalloc_scratch_address(int device, void** out);
 // Per-stream scratch of at least `bytes`.
 cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out);
 
