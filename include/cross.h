@@ -98,7 +98,11 @@ cross_status cross_get_ntt_split(cross_ctx ctx, uint32_t log_n, uint32_t* log_r,
  * 16 <= C1, C2 <= 32 (the paper sweeps (R, C) and keeps the best); keep the
  * fastest on this context for that size (as cross_set_ntt_split3 plus a
  * per-size tile; the best two-factor split also becomes the batch runtime's).
- * *log_c1_out = 0 reports a two-factor choice.  If cache_path is non-NULL a
+ * *log_c1_out = 0 reports a two-factor choice.  For 12 <= log_n it also times
+ * the batch runtime's NTT of the same shape with every work-list tile that fits
+ * and keeps the fastest per direction (cross_batch_create uses it for that size;
+ * see cross_get_batch_tile; a cached line restores only the per-call choice).
+ * If cache_path is non-NULL a
  * matching line "<device> <log_n> <L> <batch> <log_r> <log_c1> <tile> <us>
  * <two-factor log_r>" is reused without timing, else the new choice is
  * appended.  Any out pointer may be NULL.  Allocates batch*L*N*4 bytes of
@@ -359,11 +363,15 @@ cross_status cross_tensor(cross_ctx ctx, uint32_t log_n, const uint32_t* primes,
 
 /*
  * Batch runtime (many jobs of uneven N and limb count in one pass).
- * Jobs are lowered onto a fixed sequence of 15 work-list launches (one per
- * step of the hot path, each covering that step for every job; the BAT GEMM
- * steps run as persistent grids over (task, tile) lists), optionally captured
- * once into a hipGraph so that a run is a single graph launch.  Results are
- * bit-identical to the per-call entry points.
+ * Jobs are lowered onto a fixed sequence of phases (one per step of the hot
+ * path, each covering that step for every job), each a few work-list launches:
+ * the BAT GEMM steps run as persistent grids over (task, tile) lists, one
+ * launch per list tile shape, and the three-factor row transform (R x 32 x 32,
+ * used from N = 2^14 up; 2^12 and 2^13 run in two factors) as one persistent
+ * launch over a task list -- at most 7 + 4 x 14 launches whatever the number of
+ * jobs -- optionally captured once into a hipGraph so that a run is a single
+ * graph launch.  The list tile per (N, direction) is the autotuner's choice
+ * where it has made one.  Results are bit-identical to the per-call entry points.
  *   op CROSS_OP_NTT_FORWARD / _INVERSE: params.log_n, params.L, params.primes (L
  *        primes); data = device [batch][L][N], transformed in place.
  *   op CROSS_OP_HE_MULT: params as cross_he_mult; ct_a, ct_b, key, out as there.
@@ -401,6 +409,13 @@ cross_status cross_batch_workspace_bytes(cross_ctx ctx, const cross_job* jobs, u
 cross_status cross_batch_create_in(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
                                    void* workspace, uint64_t workspace_bytes, void* stream,
                                    cross_batch* out);
+/* Work-list tile the batch runtime uses on ctx for the GEMM steps of a transform of
+ * size 2^log_n in one direction (inverse != 0): 0 = 256 x 128, 1 = 128 x 64,
+ * 2 = 64 x 64 (rows x columns of the int8 product per workgroup); *tuned = 1 if
+ * cross_autotune chose it, 0 for the default (the largest tile whose rows divide
+ * the step's 4U rows; here reported for the first step's U).
+ * Errors: CROSS_EINVAL for a null pointer or log_n outside 12..16. */
+cross_status cross_get_batch_tile(cross_ctx ctx, uint32_t log_n, int inverse, int* tile, int* tuned);
 /* Enqueue one pass over every job on `stream` (graph launch or eager launches). */
 cross_status cross_batch_run(cross_batch batch, void* stream);
 /* Launch count per run (eager), workspace bytes and total GEMM tiles per run. */

@@ -68,6 +68,7 @@ SIGNATURES = {
     "cross_batch_workspace_bytes": [c_vp, c_vp, c_u32, ctypes.POINTER(ctypes.c_uint64)],
     "cross_batch_create_in": [c_vp, c_vp, c_u32, ctypes.c_int, c_vp, ctypes.c_uint64, c_vp, ctypes.POINTER(c_vp)],
     "cross_batch_run": [c_vp, c_vp],
+    "cross_get_batch_tile": [c_vp, c_u32, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
     "cross_batch_info": [c_vp, ctypes.POINTER(c_u32), ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
     "cross_batch_destroy": [c_vp],
     "cross_measure_peak": [c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
@@ -540,6 +541,17 @@ def _marshal_jobs(jobs):
             raise ValueError("unknown op %r" % op)
         keep.append(prm)
     return arr, keep
+
+
+LIST_TILES = {0: "256x128", 1: "128x64", 2: "64x64"}
+
+
+def get_batch_tile(log_n, inverse=False, device=None):
+    """The batch runtime's work-list tile for size 2^log_n: (name, tuned)."""
+    ctx = context(device)
+    t, tuned = ctypes.c_int(), ctypes.c_int()
+    _check(lib().cross_get_batch_tile(ctx, log_n, int(bool(inverse)), ctypes.byref(t), ctypes.byref(tuned)), ctx)
+    return LIST_TILES[t.value], bool(tuned.value)
 
 
 def batch_workspace_bytes(jobs, device=None):

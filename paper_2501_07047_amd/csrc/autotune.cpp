@@ -188,6 +188,49 @@ cross_status cross_autotune(cross_ctx ctx, uint32_t log_n, uint32_t L, uint32_t 
   ctx->gemm_tile = saved_tile;
   if (saved3.first) ctx->split3[(int)log_n] = saved3.second;
   else ctx->split3.erase((int)log_n);
+  // batch runtime (log_n >= 12): the work-list tile of its GEMM steps, per direction,
+  // timed on one NTT job of the same shape through a batch (the runtime's own split:
+  // three factors R x 32 x 32 from 2^14 up, else the best two-factor split above)
+  if (st == CROSS_OK && log_n >= 12) {
+    ctx->split[(int)log_n] = (int)best.log_r2;
+    for (int inv = 0; inv < 2 && st == CROSS_OK; ++inv) {
+      const int key = 2 * (int)log_n + inv;
+      const auto saved_lt = ctx->list_tile.find(key);
+      const bool had = saved_lt != ctx->list_tile.end();
+      const int old_lt = had ? saved_lt->second : 0;
+      cross_job job{};
+      job.op = inv ? CROSS_OP_NTT_INVERSE : CROSS_OP_NTT_FORWARD;
+      job.params.log_n = log_n;
+      job.params.L = L;
+      job.params.primes = primes.data();
+      job.batch = batch;
+      job.data = (uint32_t*)data;
+      double best_us = 1e30;
+      int best_tile = -1;
+      for (int lt = 0; lt < kListTileCount && st == CROSS_OK; ++lt) {
+        ctx->list_tile[key] = lt;
+        cross_batch bt = nullptr;
+        if (cross_batch_create(ctx, &job, 1, 0, &bt) != CROSS_OK) continue;   // tile does not fit: skip
+        double us = 1e30;
+        for (int w = 0; w < 2; ++w) (void)cross_batch_run(bt, nullptr);
+        const int reps = 5;
+        (void)hipEventRecord(e0, nullptr);
+        for (int k = 0; k < reps; ++k) (void)cross_batch_run(bt, nullptr);
+        (void)hipEventRecord(e1, nullptr);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) us = ms * 1e3 / reps;
+        cross_batch_destroy(bt);
+        if (us < best_us) {
+          best_us = us;
+          best_tile = lt;
+        }
+      }
+      if (best_tile >= 0) ctx->list_tile[key] = best_tile;
+      else if (had) ctx->list_tile[key] = old_lt;
+      else ctx->list_tile.erase(key);
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(data);

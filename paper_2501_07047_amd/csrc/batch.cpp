@@ -1,15 +1,20 @@
 // Batch runtime: many jobs of uneven N, limb count and kind in a fixed
 // sequence of work-list launches, optionally captured once as a hipGraph.
 //
-// Every job is lowered onto the same 15 phases (automorphism, tensor product,
-// ModUp copies, INTT, BConv, NTT, inner product, ModDown INTT / BConv / NTT,
-// tail).  A phase is one launch whose task list holds the work of every job
-// that takes part in it: GEMM phases list (task, tile) pairs of the BAT NTT
-// steps, each task carrying its own N, R x C split, prime, tables and buffers,
-// and run as one persistent grid; vector phases list one task per polynomial.
-// Launch boundaries order the phases, so a batch of any size costs 15
+// Every job is lowered onto the same phases (automorphism, tensor product,
+// ModUp copies, INTT of d, BConv, NTT of the extension, inner product, ModDown
+// INTT / BConv / NTT, tail).  A phase holds the work of every job that takes
+// part in it: vector phases list one task per polynomial; an NTT phase has two
+// halves, each a few work-list launches -- BAT GEMM steps as persistent grids
+// over (task, tile) lists, one launch per list tile shape, and the row
+// transform of the three-factor form as one persistent launch over a task list
+// -- where each task carries its own N, split, prime, tables and buffers.
+// Sizes from 2^14 up run in three factors, R x 32 x 32 (a quarter of the
+// two-factor MAC work at 2^16); 2^12 and 2^13 in two (R, C >= 64).  Launch
+// boundaries order the phases, so a batch of any size costs a fixed number of
 // launches, and replaying the captured graph costs one.
 #include <algorithm>
+#include <map>
 #include <memory>
 #include <string>
 
@@ -21,16 +26,34 @@ namespace cross {
 
 namespace {
 
-enum PhaseId {
-  kAuto, kTensor, kCopy, kInv1, kInv2, kBconvUp, kFwd1, kFwd3, kInner, kInv1P, kInv2P, kBconvDown,
-  kFwd1Z, kFwd3Z, kTail, kNumPhases
-};
+// The NTT phases, in run order.
+enum NttPhaseId { kNttInvD, kNttFwdExt, kNttInvP, kNttFwdZ, kNumNtt };
 
+// One work-list GEMM launch.
 struct GemmPhase {
   std::vector<GemmTask> tasks;
   std::vector<GemmTileRef> tiles;
   const GemmTask* d_tasks = nullptr;
   const GemmTileRef* d_tiles = nullptr;
+};
+
+// One row-kernel launch over a task list.
+struct RowsPhase {
+  std::vector<RowsTask> tasks;
+  int64_t nblocks = 0;
+  const RowsTask* d_tasks = nullptr;
+};
+
+// Half of an NTT phase: GEMM launches keyed by (list tile, row-major packed input)
+// and one row-kernel launch.  The GEMM flags are fixed per half (first / second
+// step of the forward / inverse transform).
+struct NttHalf {
+  std::map<std::pair<int, bool>, GemmPhase> gemm;
+  RowsPhase rows;
+};
+
+struct NttPhase {
+  NttHalf half[2];
 };
 
 }  // namespace
@@ -39,8 +62,7 @@ struct GemmPhase {
 
 struct cross_batch_s {
   cross_ctx ctx = nullptr;
-  int grid = 512;
-  cross::GemmPhase gemm[cross::kNumPhases];
+  cross::NttPhase ntt[cross::kNumNtt];
   std::vector<cross::AutoTask> autos;
   std::vector<cross::TensorTask> tensors;
   std::vector<cross::CopyTask> copies;
@@ -102,89 +124,168 @@ cross_status upload(cross_batch b, const std::vector<T>& v, const T** out) {
 
 uint64_t task_list_bytes(cross_batch b) {
   uint64_t n = 0;
-  for (int ph = 0; ph < kNumPhases; ++ph) n += list_bytes(b->gemm[ph].tasks) + list_bytes(b->gemm[ph].tiles);
+  for (auto& ph : b->ntt)
+    for (auto& hf : ph.half) {
+      for (auto& kv : hf.gemm) n += list_bytes(kv.second.tasks) + list_bytes(kv.second.tiles);
+      n += list_bytes(hf.rows.tasks);
+    }
   n += list_bytes(b->autos) + list_bytes(b->tensors) + list_bytes(b->copies) + list_bytes(b->bconv_up) +
        list_bytes(b->bconv_down) + list_bytes(b->inners) + list_bytes(b->tails);
   return n;
 }
 
-// Add the tiles of one limb list of one NTT step to a GEMM phase.
-// Limb i of polynomial p lives at base + p * stride + offs[i]; `tmp` has the same layout.
-void add_ntt_step(GemmPhase& ph, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
-                  const uint32_t* src_base, uint32_t* dst_base, uint64_t stride, int npoly, bool inverse,
-                  bool first) {
+// List tile of a GEMM step with M = 4U output rows: the tuner's choice for the
+// transform size and direction where it fits, else the largest that tiles M.
+int list_tile_for(cross_ctx ctx, int log_n, bool inverse, int M) {
+  auto it = ctx->list_tile.find(2 * log_n + (inverse ? 1 : 0));
+  if (it != ctx->list_tile.end()) {
+    int rows = 0, cols = 0;
+    if (gemm_list_tile_dims(it->second, &rows, &cols) && M % rows == 0) return it->second;
+  }
+  return M >= 256 ? kListTile256x128 : M >= 128 ? kListTile128x64 : kListTile64x64;
+}
+
+// Add one limb's GEMM step to the half's launch for its tile.
+void add_gemm_task(cross_ctx ctx, NttHalf& hf, const GemmTask& t, int U, int V, int npoly, bool inverse,
+                   bool in_rows, int log_n) {
+  const int tile = list_tile_for(ctx, log_n, inverse, 4 * U);
+  int rows = 0, cols = 0;
+  gemm_list_tile_dims(tile, &rows, &cols);
+  GemmPhase& ph = hf.gemm[std::make_pair(tile, in_rows)];
+  const int tm_n = 4 * U / rows;
+  const long ncols = (long)npoly * V;
+  const int tn_n = (int)((ncols + cols - 1) / cols);
+  const uint32_t id = (uint32_t)ph.tasks.size();
+  ph.tasks.push_back(t);
+  for (int tn = 0; tn < tn_n; ++tn)
+    for (int tm = 0; tm < tm_n; ++tm) ph.tiles.push_back(GemmTileRef{id, (uint16_t)tm, (uint16_t)tn});
+}
+
+// A full NTT of a limb list through `tmp` (same layout as `data`): limb i of
+// polynomial p lives at data + p * stride + offs[i].  Two-factor limbs add both
+// GEMM steps; three-factor limbs (R x 32 x 32) add the row-side GEMM step and a
+// row-kernel task: forward = row-side step (data -> tmp, packed, step-2 twiddle)
+// then rows (tmp -> data); inverse = rows (data -> tmp, packed rows, inverse
+// step-2 twiddle) then the row-side step on row-major packed input (tmp -> data).
+void add_ntt(cross_batch b, NttPhase& ph, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+             uint32_t* data, uint32_t* tmp, uint64_t stride, int npoly, bool inverse) {
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];
     const int log_r = p->log_r, log_c = p->log_n - p->log_r;
-    // first step: forward = left-known TF1 (+T2), inverse = right-known ITF3 (+IT2)
-    const bool right = inverse ? first : !first;
+    const int R = 1 << log_r, C = 1 << log_c;
     GemmTask t{};
-    if (inverse)
-      t.table = first ? p->inv_right : p->inv_left;
-    else
-      t.table = first ? p->fwd_left : p->fwd_right;
-    t.tw = first ? (inverse ? p->inv_tw : p->fwd_tw) : nullptr;
-    t.src = src_base + offs[i];
-    t.dst = dst_base + offs[i];
     t.src_stride = t.dst_stride = stride;
     t.q = p->q;
     t.qinv = p->qinv;
     t.npoly = npoly;
     t.log_r = (int16_t)log_r;
     t.log_c = (int16_t)log_c;
-    const int U = right ? (1 << log_c) : (1 << log_r);
-    const int V = right ? (1 << log_r) : (1 << log_c);
-    const int tm_n = 4 * U / gemm_list_tile_rows();
-    const long ncols = (long)npoly * V;
-    const int tn_n = (int)((ncols + gemm_list_tile_cols() - 1) / gemm_list_tile_cols());
-    const uint32_t id = (uint32_t)ph.tasks.size();
-    ph.tasks.push_back(t);
-    for (int tn = 0; tn < tn_n; ++tn)
-      for (int tm = 0; tm < tm_n; ++tm) ph.tiles.push_back(GemmTileRef{id, (uint16_t)tm, (uint16_t)tn});
+    if (p->log_c1 > 0) {
+      RowsTask r{};
+      r.stride = stride;
+      r.q = p->q;
+      r.qinv = p->qinv;
+      r.npoly = npoly;
+      r.log_r = log_r;
+      t.tw = nullptr;
+      if (!inverse) {
+        t.table = p->fwd_left;
+        t.tw = p->fwd_tw;
+        t.src = data + offs[i];
+        t.dst = tmp + offs[i];
+        add_gemm_task(b->ctx, ph.half[0], t, R, C, npoly, false, false, p->log_n);
+        r.tab = p->row_fwd_b;
+        r.tw1 = p->row_fwd_t3;
+        r.in = tmp + offs[i];
+        r.out = data + offs[i];
+      } else {
+        r.tab = p->row_inv_c;
+        r.tw1 = p->row_inv_t3;
+        r.tw2 = p->inv_tw_rows;
+        r.in = data + offs[i];
+        r.out = tmp + offs[i];
+        t.table = p->inv_left;
+        t.src = tmp + offs[i];
+        t.dst = data + offs[i];
+        add_gemm_task(b->ctx, ph.half[1], t, R, C, npoly, true, true, p->log_n);
+      }
+      RowsPhase& rp = ph.half[inverse ? 0 : 1].rows;
+      r.first_block = (int32_t)rp.nblocks;
+      rp.nblocks += (int64_t)npoly * R / rows_list_rows_per_block();
+      rp.tasks.push_back(r);
+      continue;
+    }
+    // two factors: forward = left-known TF1 (+T2) then right-known TF3;
+    // inverse = right-known ITF3 (+IT2) then left-known ITF1
+    t.table = inverse ? p->inv_right : p->fwd_left;
+    t.tw = inverse ? p->inv_tw : p->fwd_tw;
+    t.src = data + offs[i];
+    t.dst = tmp + offs[i];
+    add_gemm_task(b->ctx, ph.half[0], t, inverse ? C : R, inverse ? R : C, npoly, inverse, false, p->log_n);
+    t.table = inverse ? p->inv_left : p->fwd_right;
+    t.tw = nullptr;
+    t.src = tmp + offs[i];
+    t.dst = data + offs[i];
+    add_gemm_task(b->ctx, ph.half[1], t, inverse ? R : C, inverse ? C : R, npoly, inverse, false, p->log_n);
   }
 }
 
-// A full NTT (both steps) of a limb list through `tmp`.
-void add_ntt(cross_batch b, int first_phase, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
-             uint32_t* data, uint32_t* tmp, uint64_t stride, int npoly, bool inverse) {
-  add_ntt_step(b->gemm[first_phase], plans, offs, data, tmp, stride, npoly, inverse, true);
-  add_ntt_step(b->gemm[first_phase + 1], plans, offs, tmp, data, stride, npoly, inverse, false);
+// The batch runtime's plan for prime q at size 2^log_n: three factors R x 32 x 32
+// from 2^14 up, else the context's two-factor split (R, C >= 64 for the list tiles).
+cross_status batch_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out) {
+  if (log_n >= 14) return get_plan_at(ctx, q, log_n, log_n - 10, 5, out);
+  cross_status st = get_plan(ctx, q, log_n, out, false);
+  if (st != CROSS_OK) return st;
+  if ((*out)->log_r < 6 || log_n - (*out)->log_r < 6)
+    return fail(ctx, CROSS_EUNSUPPORTED, "batch runtime needs R, C >= 64 below N = 2^14");
+  return CROSS_OK;
 }
 
-bool split_ok(const Plan* p) {
-  // the work-list GEMM uses 256-row tiles: both 4R and 4C must be multiples of 256
-  return p->log_r >= 6 && p->log_n - p->log_r >= 6;
+hipError_t run_ntt(cross_batch b, int phase, bool inverse, hipStream_t s, bool prof) {
+  cross_ctx ctx = b->ctx;
+  hipError_t e = hipSuccess;
+  for (int h = 0; h < 2 && e == hipSuccess; ++h) {
+    NttHalf& hf = b->ntt[phase].half[h];
+    // step flags: forward = LEFT(plain -> packed, twiddle) then RIGHT(packed -> plain);
+    // inverse = RIGHT(plain -> packed, twiddle) then LEFT(packed -> plain)
+    const bool first = h == 0;
+    const int kind = (inverse == first) ? kRight : kLeft;
+    for (auto& kv : hf.gemm) {
+      if (e != hipSuccess || kv.second.tiles.empty()) continue;
+      ProfScope ps(prof ? ctx : nullptr, kind == kLeft ? "bat_gemm_left" : "bat_gemm_right", s);
+      e = launch_bat_gemm_list(kv.second.d_tasks, kv.second.d_tiles, (int)kv.second.tiles.size(), kind,
+                               /*in_packed=*/!first, /*out_packed=*/first, /*twiddle=*/first,
+                               /*in_rows=*/kv.first.second, kv.first.first, s);
+    }
+    if (e == hipSuccess && !hf.rows.tasks.empty()) {
+      ProfScope ps(prof ? ctx : nullptr, "ntt_rows", s);
+      e = launch_ntt_rows_list(hf.rows.d_tasks, (int)hf.rows.tasks.size(), hf.rows.nblocks, inverse, s);
+    }
+  }
+  return e;
 }
 
 hipError_t run_phases(cross_batch b, hipStream_t s, bool prof) {
   cross_ctx ctx = b->ctx;
   hipError_t e = hipSuccess;
-  auto gemm = [&](int ph, int kind, bool inp, bool outp, bool tw, const char* name) {
-    if (e != hipSuccess || b->gemm[ph].tiles.empty()) return;
-    const int nt = (int)b->gemm[ph].tiles.size();
-    const int grid = std::min(b->grid, ((nt + 7) / 8) * 8);
-    ProfScope ps(prof ? ctx : nullptr, name, s);
-    e = launch_bat_gemm_list(b->gemm[ph].d_tasks, b->gemm[ph].d_tiles, nt, grid, kind, inp, outp, tw, s);
-  };
   auto vec = [&](const char* name, auto fn) {
     if (e != hipSuccess) return;
     ProfScope ps(prof ? ctx : nullptr, name, s);
     e = fn();
   };
+  auto ntt = [&](int phase, bool inverse) {
+    if (e == hipSuccess) e = run_ntt(b, phase, inverse, s, prof);
+  };
   vec("automorphism", [&] { return launch_auto_list(b->d_autos, (int)b->autos.size(), b->max_auto, s); });
   vec("tensor", [&] { return launch_tensor_list(b->d_tensors, (int)b->tensors.size(), b->max_tensor, s); });
   vec("limb_copy", [&] { return launch_copy_list(b->d_copies, (int)b->copies.size(), b->max_copy, s); });
-  gemm(kInv1, kRight, false, true, true, "bat_gemm_right");
-  gemm(kInv2, kLeft, true, false, false, "bat_gemm_left");
+  ntt(kNttInvD, true);
   vec("bconv", [&] { return launch_bconv_list(b->d_bconv_up, (int)b->bconv_up.size(), b->max_waves_up, s); });
-  gemm(kFwd1, kLeft, false, true, true, "bat_gemm_left");
-  gemm(kFwd3, kRight, true, false, false, "bat_gemm_right");
+  ntt(kNttFwdExt, false);
   vec("inner_product", [&] { return launch_inner_list(b->d_inners, (int)b->inners.size(), b->max_inner, s); });
-  gemm(kInv1P, kRight, false, true, true, "bat_gemm_right");
-  gemm(kInv2P, kLeft, true, false, false, "bat_gemm_left");
+  ntt(kNttInvP, true);
   vec("bconv", [&] { return launch_bconv_list(b->d_bconv_down, (int)b->bconv_down.size(), b->max_waves_down, s); });
-  gemm(kFwd1Z, kLeft, false, true, true, "bat_gemm_left");
-  gemm(kFwd3Z, kRight, true, false, false, "bat_gemm_right");
+  ntt(kNttFwdZ, false);
   vec("moddown_tail", [&] { return launch_tail_list(b->d_tails, (int)b->tails.size(), b->max_tail, s); });
   return e;
 }
@@ -224,14 +325,11 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
   std::unique_ptr<cross_batch_s, void (*)(cross_batch)> b(new cross_batch_s(), cross_batch_destroy);
   b->ctx = ctx;
-  int ncu = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && ncu > 0)
-    b->grid = ((2 * ncu + 7) / 8) * 8;   // two resident GEMM workgroups per CU
 
   // ---- pass 1: validate, plan, size the workspace --------------------------------
   struct JobPlan {
     CkksPlan* c = nullptr;
-    std::vector<Plan*> plans;   // NTT jobs
+    std::vector<Plan*> plans;   // NTT plans of the job's limbs (CKKS: all L + K, Q then P)
     uint64_t ws = 0;            // words
   };
   std::vector<JobPlan> jp(njobs);
@@ -250,16 +348,18 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
         cross_status st = check_prime(ctx, P.primes[i], P.log_n);
         if (st != CROSS_OK) return st;
         Plan* p = nullptr;
-        if ((st = get_plan(ctx, P.primes[i], (int)P.log_n, &p, false)) != CROSS_OK) return st;
-        if (!split_ok(p)) return fail(ctx, CROSS_EUNSUPPORTED, "batch runtime needs R, C >= 64");
+        if ((st = batch_plan(ctx, P.primes[i], (int)P.log_n, &p)) != CROSS_OK) return st;
         jp[j].plans.push_back(p);
       }
       jp[j].ws = (uint64_t)J.batch * P.L * N;
     } else if (J.op == CROSS_OP_HE_MULT || J.op == CROSS_OP_ROTATE) {
       cross_status st = get_ckks_plan(ctx, &P, &jp[j].c);
       if (st != CROSS_OK) return st;
-      for (Plan* p : jp[j].c->plans2)
-        if (!split_ok(p)) return fail(ctx, CROSS_EUNSUPPORTED, "batch runtime needs R, C >= 64");
+      for (uint32_t t : jp[j].c->primes) {
+        Plan* p = nullptr;
+        if ((st = batch_plan(ctx, t, (int)P.log_n, &p)) != CROSS_OK) return st;
+        jp[j].plans.push_back(p);
+      }
       const bool he = J.op == CROSS_OP_HE_MULT;
       if (!J.ct_a || !J.key || !J.out || (he && !J.ct_b) || !aligned16(J.ct_a) || !aligned16(J.key) ||
           !aligned16(J.out) || (he && !aligned16(J.ct_b)))
@@ -302,8 +402,8 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       const bool inv = J.op == CROSS_OP_NTT_INVERSE;
       std::vector<uint64_t> offs(J.params.L);
       for (uint32_t i = 0; i < J.params.L; ++i) offs[i] = i * N;
-      add_ntt(b.get(), inv ? kInv1 : kFwd1, jp[j].plans, offs, J.data, mine, (uint64_t)J.params.L * N,
-              (int)J.batch, inv);
+      add_ntt(b.get(), b->ntt[inv ? kNttInvD : kNttFwdExt], jp[j].plans, offs, J.data, mine,
+              (uint64_t)J.params.L * N, (int)J.batch, inv);
       continue;
     }
     const CkksPlan* c = jp[j].c;
@@ -360,10 +460,11 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       }
     }
     // INTT of d (all L limbs)
-    std::vector<Plan*> qp(c->plans2.begin(), c->plans2.begin() + L);
+    const std::vector<Plan*>& bp = jp[j].plans;
+    std::vector<Plan*> qp(bp.begin(), bp.begin() + L);
     std::vector<uint64_t> qo(L);
     for (int i = 0; i < L; ++i) qo[i] = i * N;
-    add_ntt(b.get(), kInv1, qp, qo, d, tmp, nd, B, true);
+    add_ntt(b.get(), b->ntt[kNttInvD], qp, qo, d, tmp, nd, B, true);
     // BConv of each digit, NTT of every converted limb
     std::vector<Plan*> ep;
     std::vector<uint64_t> eo;
@@ -373,23 +474,23 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       b->bconv_up.push_back(g);
       b->max_waves_up = std::max(b->max_waves_up, ((uint64_t)B << c->log_n) / 32);
       for (int t : c->targets[dj]) {
-        ep.push_back(c->plans2[t]);
+        ep.push_back(bp[t]);
         eo.push_back(((uint64_t)dj * LK + t) * N);
       }
     }
-    add_ntt(b.get(), kFwd1, ep, eo, ext, tmp, next, B, false);
+    add_ntt(b.get(), b->ntt[kNttFwdExt], ep, eo, ext, tmp, next, B, false);
     // ModDown of both accumulators: INTT of P limbs, BConv P -> Q, NTT of Q limbs
-    std::vector<Plan*> pp(c->plans2.begin() + L, c->plans2.end());
+    std::vector<Plan*> pp(bp.begin() + L, bp.end());
     std::vector<uint64_t> po(K);
     for (int k = 0; k < K; ++k) po[k] = (uint64_t)(L + k) * N;
-    add_ntt(b.get(), kInv1P, pp, po, acc, tmp, (uint64_t)LK * N, 2 * B, true);
+    add_ntt(b.get(), b->ntt[kNttInvP], pp, po, acc, tmp, (uint64_t)LK * N, 2 * B, true);
     {
       const BconvStatic& bs = c->moddown;
       BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, acc, z, (uint64_t)LK * N, nd, 2 * B, c->log_n};
       b->bconv_down.push_back(g);
       b->max_waves_down = std::max(b->max_waves_down, ((uint64_t)(2 * B) << c->log_n) / 32);
     }
-    add_ntt(b.get(), kFwd1Z, qp, qo, z, tmp, nd, 2 * B, false);
+    add_ntt(b.get(), b->ntt[kNttFwdZ], qp, qo, z, tmp, nd, 2 * B, false);
   }
 
   // ---- pass 3: device task lists ---------------------------------------------------
@@ -406,10 +507,14 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     b->upload_stream = upload_stream;
   }
   cross_status st = CROSS_OK;
-  for (int ph = 0; ph < kNumPhases && st == CROSS_OK; ++ph) {
-    st = upload(b.get(), b->gemm[ph].tasks, &b->gemm[ph].d_tasks);
-    if (st == CROSS_OK) st = upload(b.get(), b->gemm[ph].tiles, &b->gemm[ph].d_tiles);
-  }
+  for (auto& ph : b->ntt)
+    for (auto& hf : ph.half) {
+      for (auto& kv : hf.gemm) {
+        if (st == CROSS_OK) st = upload(b.get(), kv.second.tasks, &kv.second.d_tasks);
+        if (st == CROSS_OK) st = upload(b.get(), kv.second.tiles, &kv.second.d_tiles);
+      }
+      if (st == CROSS_OK) st = upload(b.get(), hf.rows.tasks, &hf.rows.d_tasks);
+    }
   if (st == CROSS_OK) st = upload(b.get(), b->autos, &b->d_autos);
   if (st == CROSS_OK) st = upload(b.get(), b->tensors, &b->d_tensors);
   if (st == CROSS_OK) st = upload(b.get(), b->copies, &b->d_copies);
@@ -459,6 +564,22 @@ cross_status cross_batch_create_in(cross_ctx ctx, const cross_job* jobs, uint32_
                      false, nullptr, out);
 }
 
+cross_status cross_get_batch_tile(cross_ctx ctx, uint32_t log_n, int inverse, int* tile, int* tuned) {
+  if (!ctx || !tile || !tuned) return CROSS_EINVAL;
+  if (log_n < 12 || log_n > CROSS_MAX_LOG_N) return fail(ctx, CROSS_EINVAL, "log_n outside 12..16");
+  const bool inv = inverse != 0;
+  auto it = ctx->list_tile.find(2 * (int)log_n + (inv ? 1 : 0));
+  *tuned = it != ctx->list_tile.end();
+  // the first step: the row-side step (U = R) in three factors, else U = R forward, C inverse
+  int log_u = (int)log_n - 10;
+  if (log_n < 14) {
+    const int lr = split_of(ctx, (int)log_n);
+    log_u = inv ? (int)log_n - lr : lr;
+  }
+  *tile = list_tile_for(ctx, (int)log_n, inv, 4 << log_u);
+  return CROSS_OK;
+}
+
 cross_status cross_batch_run(cross_batch b, void* stream) {
   if (!b) return CROSS_EINVAL;
   cross_ctx ctx = b->ctx;
@@ -479,10 +600,14 @@ cross_status cross_batch_info(cross_batch b, uint32_t* launches, uint64_t* works
   if (!b) return CROSS_EINVAL;
   uint32_t n = 0;
   uint64_t tiles = 0;
-  for (int ph = 0; ph < kNumPhases; ++ph) {
-    n += b->gemm[ph].tiles.empty() ? 0 : 1;
-    tiles += b->gemm[ph].tiles.size();
-  }
+  for (auto& ph : b->ntt)
+    for (auto& hf : ph.half) {
+      for (auto& kv : hf.gemm) {
+        n += kv.second.tiles.empty() ? 0 : 1;
+        tiles += kv.second.tiles.size();
+      }
+      n += hf.rows.tasks.empty() ? 0 : 1;
+    }
   n += !b->autos.empty() + !b->tensors.empty() + !b->copies.empty() + !b->bconv_up.empty() +
        !b->bconv_down.empty() + !b->inners.empty() + !b->tails.empty();
   if (launches) *launches = n;

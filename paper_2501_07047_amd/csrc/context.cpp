@@ -112,6 +112,10 @@ void effective_split(cross_ctx ctx, int log_n, bool allow3, int* log_r, int* log
 cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3) {
   int log_r = 0, log_c1 = 0;
   effective_split(ctx, log_n, allow3, &log_r, &log_c1);
+  return get_plan_at(ctx, q, log_n, log_r, log_c1, out);
+}
+
+cross_status get_plan_at(cross_ctx ctx, uint32_t q, int log_n, int log_r, int log_c1, Plan** out) {
   auto key = std::make_tuple(q, log_n, log_r, log_c1);
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end()) {

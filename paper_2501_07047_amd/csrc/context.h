@@ -74,6 +74,7 @@ struct cross_ctx_s {
   int ntt_reduction = 0;                      // row-kernel epilogue: 0 Montgomery, 1 Barrett
   int ntt_engine = 0;                         // NTTs inside other operations: 0 MFMA, 1 butterfly
   std::map<int, int> tile_by_logn;            // autotuned GemmTile per transform size
+  std::map<int, int> list_tile;               // batch runtime: GemmListTile per (2 log_n + inverse)
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)
   void* noalloc_scratch = nullptr;            // device address of this device's no-alloc scratch
@@ -104,6 +105,8 @@ cross_status check_prime(cross_ctx ctx, uint32_t q, uint32_t log_n, bool wide_ok
 // allow3 = false keeps the two-factor form even where a three-factor split is set
 // (the batch runtime's work lists implement two factors only).
 cross_status get_plan(cross_ctx ctx, uint32_t q, int log_n, Plan** out, bool allow3 = true);
+// The plan of an explicit split (log_c1 = 0: two factors); built on first use.
+cross_status get_plan_at(cross_ctx ctx, uint32_t q, int log_n, int log_r, int log_c1, Plan** out);
 int split_of(cross_ctx ctx, int log_n);
 // The (log_r, log_c1) get_plan uses for size 2^log_n (log_c1 = 0: two factors).
 void effective_split(cross_ctx ctx, int log_n, bool allow3, int* log_r, int* log_c1);

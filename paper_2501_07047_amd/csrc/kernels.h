@@ -117,13 +117,33 @@ struct RowsJob {
 hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
                            int npoly, int log_r, int log_c1, int log_c2, bool inverse, int red, bool wide,
                            hipStream_t s);
+// Work-list form of the row transform (batch runtime), split C1 = C2 = 32 only: each
+// task is one limb of one job (its prime's tables, its own buffers, npoly
+// polynomials `stride` apart, R = 2^log_r rows of 1024) and owns npoly * R / 8
+// blocks of eight rows, blocks [first_block, first_block of the next task); tasks are
+// in first_block order and nblocks is the total.  Forward: in = packed row-side
+// output, out = plain; inverse: in = plain, out = packed rows with the inverse step-2
+// twiddle applied (tw2 = its [R][C][2] pairs).
+struct RowsTask {
+  const int8_t* tab;        // 128 x 128 sub-step table (C1 = C2: one matrix for both sub-steps)
+  const uint32_t* tw1;      // first-epilogue twiddle pairs
+  const uint32_t* tw2;      // inverse only: step-2 twiddle pairs
+  const uint32_t* in;
+  uint32_t* out;
+  uint64_t stride;
+  uint32_t q, qinv;
+  int32_t npoly, log_r;
+  int32_t first_block, pad;
+};
+hipError_t launch_ntt_rows_list(const RowsTask* tasks, int ntasks, int64_t nblocks, bool inverse, hipStream_t s);
+int rows_list_rows_per_block();
 // Whether (log_r, log_c1, log_n - log_r - log_c1) is a split the row kernels implement.
 bool rows_split_supported(int log_n, int log_r, int log_c1);
 
 // Work-list GEMM step (batch runtime): each task is one limb list of one
 // transform with its own shape and buffers; each tile ref names (task, tm, tn)
-// of a 256 x 128 tile (gemm_list_tile_rows/cols).  All tasks of one launch share
-// the step kind and the packed/twiddle flags.  `grid` must be a multiple of 8.
+// of one list tile (gemm_list_tile_dims).  All tasks of one launch share the step
+// kind, the packed/twiddle/row-major flags and the tile.
 struct GemmTask {
   const int8_t* table;
   const uint32_t* tw;
@@ -138,10 +158,13 @@ struct GemmTileRef {
   uint32_t task;
   uint16_t tm, tn;
 };
-int gemm_list_tile_rows();
-int gemm_list_tile_cols();
-hipError_t launch_bat_gemm_list(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
-                                int kind, bool in_packed, bool out_packed, bool twiddle, hipStream_t s);
+// List tiles (rows x columns of the int8 product per workgroup tile).
+enum GemmListTile { kListTile256x128 = 0, kListTile128x64 = 1, kListTile64x64 = 2, kListTileCount = 3 };
+bool gemm_list_tile_dims(int tile, int* rows, int* cols);
+// in_rows: row side with packed input stored row-major (the three-factor inverse's
+// row-side step).  The grid is chosen here (resident workgroups of the tile).
+hipError_t launch_bat_gemm_list(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int kind, bool in_packed,
+                                bool out_packed, bool twiddle, bool in_rows, int tile, hipStream_t s);
 
 struct ButterflyJob {
   const uint32_t* tw;      // psi^brv(i) (or its inverse), Montgomery form, N entries

@@ -624,7 +624,8 @@ bat_gemm_direct_kernel(GemmLaunch g, int tiles_m, int tiles_n) {
 // Work-list form: tiles of many tasks (mixed N, R x C, primes, buffers) in one
 // persistent launch.  The grid is a multiple of 8; XCD x (= blockIdx % 8) walks
 // the x-th eighth of the tile list so each task's tiles share one L2.
-template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW>
+template <int WM, int WN, int MB, int NB, int OCC, int KS, bool RIGHT, bool IN_PACKED, bool OUT_PACKED, bool TW,
+          bool PROWS>
 __global__ void __launch_bounds__(WM * WN * 64, OCC)
 bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles) {
   constexpr int BM = WM * MB * 32;
@@ -637,7 +638,7 @@ bat_gemm_list_kernel(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles
     const GemmTask k = tasks[r.task];
     TileArgs t{k.table, k.tw, k.src, k.dst, k.src_stride, k.dst_stride, k.q, k.qinv, k.npoly,
                k.log_r, k.log_c, (int)r.tm * BM, (int)r.tn * BN};
-    gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW>(t, lds, lds + 2 * BM * 64 * KS);
+    gemm_tile<WM, WN, MB, NB, KS, RIGHT, IN_PACKED, OUT_PACKED, TW, PROWS>(t, lds, lds + 2 * BM * 64 * KS);
   }
 }
 
@@ -707,27 +708,64 @@ hipError_t dispatch_flags(const GemmLaunch& g, hipStream_t s) {
 
 }  // namespace
 
-template <bool RIGHT, bool INP, bool OUTP, bool TW>
-hipError_t launch_list_cfg(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
-                           hipStream_t s) {
-  // 256 x 128 tiles, 8 waves of 64 x 64, two workgroups per CU
-  launch_kernel((bat_gemm_list_kernel<4, 2, 2, 2, 4, 1, RIGHT, INP, OUTP, TW>), dim3(grid), dim3(512), 0, s,
-                     tasks, tiles, ntiles);
+namespace {
+
+// Work-list tiles: the staged 256 x 128 (8 waves of 64 x 64, two workgroups per CU),
+// 128 x 64 and 64 x 64 (4 waves each, four per CU).  The grid holds as many
+// workgroups as are resident, a multiple of 8 (one eighth of the list per XCD).
+template <int WM, int WN, int MB, int NB, bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS>
+hipError_t launch_list_tile(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, hipStream_t s) {
+  constexpr int NW = WM * WN, OCC = 4;
+  int ncu = 256;
+  {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      ncu = n;
+  }
+  const int resident = ((4 * OCC / NW) * ncu + 7) / 8 * 8;
+  const int grid = std::min(resident, (ntiles + 7) / 8 * 8);
+  launch_kernel((bat_gemm_list_kernel<WM, WN, MB, NB, OCC, 1, RIGHT, INP, OUTP, TW, PROWS>), dim3(grid),
+                dim3(NW * 64), 0, s, tasks, tiles, ntiles);
   return hipGetLastError();
 }
 
-int gemm_list_tile_rows() { return 256; }
-int gemm_list_tile_cols() { return 128; }
+template <bool RIGHT, bool INP, bool OUTP, bool TW, bool PROWS>
+hipError_t launch_list_cfg(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int tile, hipStream_t s) {
+  switch (tile) {
+    case kListTile256x128: return launch_list_tile<4, 2, 2, 2, RIGHT, INP, OUTP, TW, PROWS>(tasks, tiles, ntiles, s);
+    case kListTile128x64: return launch_list_tile<2, 2, 2, 1, RIGHT, INP, OUTP, TW, PROWS>(tasks, tiles, ntiles, s);
+    case kListTile64x64: return launch_list_tile<2, 2, 1, 1, RIGHT, INP, OUTP, TW, PROWS>(tasks, tiles, ntiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
-hipError_t launch_bat_gemm_list(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int grid,
-                                int kind, bool in_packed, bool out_packed, bool twiddle, hipStream_t s) {
+}  // namespace
+
+bool gemm_list_tile_dims(int tile, int* rows, int* cols) {
+  switch (tile) {
+    case kListTile256x128: *rows = 256; *cols = 128; return true;
+    case kListTile128x64: *rows = 128; *cols = 64; return true;
+    case kListTile64x64: *rows = 64; *cols = 64; return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_bat_gemm_list(const GemmTask* tasks, const GemmTileRef* tiles, int ntiles, int kind, bool in_packed,
+                                bool out_packed, bool twiddle, bool in_rows, int tile, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
-  if (grid <= 0 || (grid & 7)) return hipErrorInvalidValue;
   const bool right = kind == kRight;
-  if (!right && !in_packed && out_packed && twiddle) return launch_list_cfg<false, false, true, true>(tasks, tiles, ntiles, grid, s);
-  if (right && in_packed && !out_packed && !twiddle) return launch_list_cfg<true, true, false, false>(tasks, tiles, ntiles, grid, s);
-  if (right && !in_packed && out_packed && twiddle) return launch_list_cfg<true, false, true, true>(tasks, tiles, ntiles, grid, s);
-  if (!right && in_packed && !out_packed && !twiddle) return launch_list_cfg<false, true, false, false>(tasks, tiles, ntiles, grid, s);
+  if (in_rows && (right || !in_packed || out_packed || twiddle)) return hipErrorInvalidValue;
+  if (!right && !in_packed && out_packed && twiddle)
+    return launch_list_cfg<false, false, true, true, false>(tasks, tiles, ntiles, tile, s);
+  if (right && in_packed && !out_packed && !twiddle)
+    return launch_list_cfg<true, true, false, false, false>(tasks, tiles, ntiles, tile, s);
+  if (right && !in_packed && out_packed && twiddle)
+    return launch_list_cfg<true, false, true, true, false>(tasks, tiles, ntiles, tile, s);
+  if (!right && in_packed && !out_packed && !twiddle && in_rows)
+    return launch_list_cfg<false, true, false, false, true>(tasks, tiles, ntiles, tile, s);
+  if (!right && in_packed && !out_packed && !twiddle)
+    return launch_list_cfg<false, true, false, false, false>(tasks, tiles, ntiles, tile, s);
   return hipErrorInvalidValue;
 }
 

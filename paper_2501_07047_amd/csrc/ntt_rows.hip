@@ -31,6 +31,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace cross {
 
@@ -467,12 +468,17 @@ int cu_count() {
 // block in both sub-steps (its 32 columns are (row w, c2) in the first and (row w,
 // m) in the second), so the sub-steps exchange data only inside a wave: each wave
 // keeps its row's Z lines and output staging in a private LDS slice and needs no
-// workgroup barrier.  Each workgroup walks a contiguous range of blocks and, while
-// it computes a block, holds the next block's row (its first sub-step operands) in
-// flight in registers, so the memory latency of one block overlaps the work of the
-// previous one.  Tables and first twiddles are staged into LDS when the range
-// enters a new prime (the only workgroup barriers).  Narrow primes, Montgomery
-// epilogue; other splits and forms use the kernels above.
+// workgroup barrier.  Each workgroup walks a contiguous range of blocks; when the
+// range enters a new prime it stages that prime's 16 KB sub-step table (one matrix
+// for both sub-steps, C1 = C2) and first twiddles into LDS and copies the table
+// into 64 registers per lane, so the products read no LDS.  Each sub-step runs one
+// 32-row block at a time (16 live accumulators), which leaves room for the table in
+// registers at four waves per SIMD.  Narrow primes, Montgomery epilogue; other
+// splits and forms use the kernels above.  (Measured alternatives, all bit-exact
+// and slower or level: the table read from LDS per product, the next row's operands
+// loaded a block ahead, all four 32-row blocks of a sub-step at once, three waves
+// per SIMD with 4-wave workgroups, two waves per SIMD.)
+constexpr int kP32Waves = 8;                     // waves (= rows) per block
 constexpr int kP32Zp = 36;                       // Z line pitch (words): 16-byte aligned rows
 constexpr int kP32Xp = 33;                       // output staging pitch (words)
 constexpr int kP32SliceWords = 32 * kP32Zp;      // per-wave LDS slice
@@ -484,136 +490,152 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Block b (eight rows of one polynomial and prime) -> job index, element offset of
-// wave w's row.  rb_log = log2(R / 8) row blocks per polynomial.
-// Block b (NW rows of one polynomial and prime) -> job index, element offset of
-// wave w's row.  rb_log = log2(R / NW) row blocks per polynomial.
-template <int NW>
-__device__ __forceinline__ void p32_block(int b, int npoly, int rb_log, uint64_t stride, const RowsJob* jobs,
-                                          int wave, int* jb, uint64_t* row_off, int* row = nullptr) {
-  const int per_job = npoly << rb_log;
-  const int j = __builtin_amdgcn_readfirstlane(b / per_job);
-  const int rem = b - j * per_job;
-  const int poly = rem >> rb_log, rb = rem & ((1 << rb_log) - 1);
-  *jb = j;
-  *row_off = jobs[j].off + (uint64_t)poly * stride + (uint64_t)(rb * NW + wave) * 1024;
-  if (row) *row = rb * NW + wave;
-}
+// Where wave `wave`'s row of block b lives, and its prime's tables.
+struct RowLoc {
+  const int8_t* tab;        // 128 x 128 sub-step table (fragment order)
+  const uint32_t* tw1;      // first-epilogue twiddle pairs (T3 [m][c2] or IT3 [c2][m])
+  const uint32_t* tw2;      // inverse: step-2 twiddle pairs of this row, [C][2]
+  const uint32_t* in;       // the row (1024 residues)
+  uint32_t* out;
+  uint32_t q, qinv;
+};
 
-// The 16 fragments (K step ks, 32-row block mb; 1 KB each) of a 128 x 128 sub-step
-// table, read from LDS per product or held in registers for a workgroup's prime.
-template <bool REG>
-struct P32Tab {
-  v4i f[REG ? 16 : 1];
-  const int8_t* lds;
-  __device__ __forceinline__ void load(int lane) {
-    if constexpr (REG) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) f[i] = *reinterpret_cast<const v4i*>(lds + i * 1024 + lane * 16);
-    }
-  }
-  // fragment order of the table: ((ks / 2) * 4 + mb) * 2 + ks % 2
-  __device__ __forceinline__ v4i get(int ks, int mb, int lane) const {
-    const int i = ((ks >> 1) * 4 + mb) * 2 + (ks & 1);
-    if constexpr (REG)
-      return f[i];
-    else
-      return *reinterpret_cast<const v4i*>(lds + i * 1024 + lane * 16);
+// One launch of the uniform form: njobs limbs (one prime each) at offsets from
+// common bases, npoly polynomials `stride` apart, R / 8 blocks per polynomial.
+struct P32Uniform {
+  const RowsJob* jobs;
+  const uint32_t* in;
+  uint32_t* out;
+  uint64_t stride;
+  int npoly, rb_log;
+  __device__ __forceinline__ RowLoc locate(int b, int wave) {
+    const int per_job = npoly << rb_log;
+    const int j = __builtin_amdgcn_readfirstlane(b / per_job);
+    const int rem = b - j * per_job;
+    const int poly = rem >> rb_log, row = (rem & ((1 << rb_log) - 1)) * kP32Waves + wave;
+    const RowsJob& jb = jobs[j];
+    const uint64_t off = jb.off + (uint64_t)poly * stride + (uint64_t)row * 1024;
+    return RowLoc{jb.tab1, jb.tw1, jb.tw2 ? jb.tw2 + (uint64_t)row * 2048 : nullptr, in + off, out + off,
+                  jb.q, jb.qinv};
   }
 };
 
-// One 32-row block mb of a sub-step: 128 x 32 outputs-by-chunk rows times the four
-// K steps of the wave's 32 columns.
-template <bool REG>
-__device__ __forceinline__ v16i p32_block_mb(const P32Tab<REG>& tab, const v4i (&b)[4], int mb, int lane) {
+// The batch runtime's form: a task list (each task one limb with its own buffers,
+// polynomial count and R), block b in the task whose first_block is the last one
+// not above b.  Blocks of a workgroup are contiguous, so the task index only moves
+// forward.
+struct P32List {
+  const RowsTask* tasks;
+  int ntasks;
+  int t = 0;                // current task (wave-uniform)
+  __device__ __forceinline__ void seek(int b) {
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].first_block <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    t = __builtin_amdgcn_readfirstlane(lo);
+  }
+  __device__ __forceinline__ RowLoc locate(int b, int wave) {
+    while (t + 1 < ntasks && tasks[t + 1].first_block <= b) ++t;
+    const RowsTask& k = tasks[t];
+    const int rb_log = k.log_r - 3;
+    const int local = b - k.first_block;
+    const int poly = local >> rb_log, row = (local & ((1 << rb_log) - 1)) * kP32Waves + wave;
+    const uint64_t off = (uint64_t)poly * k.stride + (uint64_t)row * 1024;
+    return RowLoc{k.tab, k.tw1, k.tw2 ? k.tw2 + (uint64_t)row * 2048 : nullptr, k.in + off, k.out + off, k.q, k.qinv};
+  }
+};
+
+// The 16 fragments (K step ks, 32-row block mb; 1 KB each) of the sub-step table in
+// registers; fragment order ((ks / 2) * 4 + mb) * 2 + ks % 2.
+struct P32Tab {
+  v4i f[16];
+  __device__ __forceinline__ void load(const int8_t* lds, int lane) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = *reinterpret_cast<const v4i*>(lds + i * 1024 + lane * 16);
+  }
+  __device__ __forceinline__ v4i get(int ks, int mb) const { return f[((ks >> 1) * 4 + mb) * 2 + (ks & 1)]; }
+};
+
+// One 32-row block mb of a sub-step: the four K steps of the wave's 32 columns.
+__device__ __forceinline__ v16i p32_block_mb(const P32Tab& tab, const v4i (&b)[4], int mb) {
   v16i acc = v16i{};
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(tab.get(ks, mb, lane), b[ks], acc, 0, 0, 0);
+  for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(tab.get(ks, mb), b[ks], acc, 0, 0, 0);
   return acc;
 }
 
-// All four 32-row blocks of a sub-step, K step outer: four independent
-// accumulator chains, so back-to-back products do not wait on each other.
-template <bool REG>
-__device__ __forceinline__ void p32_all_mb(v16i (&acc)[4], const P32Tab<REG>& tab, const v4i (&b)[4], int lane) {
-#pragma unroll
-  for (int mb = 0; mb < 4; ++mb) acc[mb] = v16i{};
-#pragma unroll
-  for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-      acc[mb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(tab.get(ks, mb, lane), b[ks], acc[mb], 0, 0, 0);
+// Stage a prime's table and first twiddles when the block's prime changes
+// (workgroup-uniform: every wave of a block has the same prime).
+__device__ __forceinline__ void p32_stage(const RowLoc& L, const int8_t*& cur_tab, int8_t* tabs, uint32_t* tws,
+                                          P32Tab& tab, int lane) {
+  if (L.tab == cur_tab) return;
+  __syncthreads();
+  stage<64 * kP32Waves>(tabs, L.tab, 16 * 32 * 32);
+  stage<64 * kP32Waves>(tws, L.tw1, 8 * 1024);
+  __syncthreads();
+  tab.load(tabs, lane);
+  cur_tab = L.tab;
 }
 
-template <int NW, int OCC, bool REG, bool PREFETCH, bool KSOUT>
-__global__ void __launch_bounds__(64 * NW, OCC)
-ntt_rows32_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly,
-                      int rb_log, int nblocks) {
+// Write the staged output lines of a row (element e = line * 32 + c) with 16-byte stores.
+__device__ __forceinline__ void p32_write_row(const uint32_t* zw, uint32_t* out, int lane) {
+  const __amdgpu_buffer_rsrc_t ro = rows_rsrc(out, 1024 * 4);
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int e = (lane + it * 64) * 4;
+    const uint32_t* src = &zw[(e >> 5) * kP32Xp + (e & 31)];
+    __builtin_amdgcn_raw_buffer_store_b128(v4u{src[0], src[1], src[2], src[3]}, ro, e * 4, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void p32_range(int nblocks, int& b0, int& b1) {
+  b0 = (int)((int64_t)blockIdx.x * nblocks / gridDim.x);
+  b1 = (int)((int64_t)(blockIdx.x + 1) * nblocks / gridDim.x);
+}
+
+// Forward: sub-step 1 (TB over c1, columns (row, c2)) reads the chunk-packed row-side
+// output, applies T3 and packs Z lines [m][c2]; sub-step 2 (TC over c2, columns (row,
+// m)) finishes the row in natural residues.
+template <class SRC>
+__global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_fwd_kernel(SRC src, int nblocks) {
   __shared__ __attribute__((aligned(16))) int8_t tabs[16 * 32 * 32];
   __shared__ __attribute__((aligned(16))) uint32_t tws[2 * 1024];
-  __shared__ __attribute__((aligned(16))) uint32_t zs[NW * kP32SliceWords];
+  __shared__ __attribute__((aligned(16))) uint32_t zs[kP32Waves * kP32SliceWords];
   const int lane = threadIdx.x & 63, h = lane >> 5, c2 = lane & 31;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int G = gridDim.x, g = blockIdx.x;
-  const int b0 = (int)((int64_t)g * nblocks / G), b1 = (int)((int64_t)(g + 1) * nblocks / G);
+  int b0, b1;
+  p32_range(nblocks, b0, b1);
+  if constexpr (std::is_same<SRC, P32List>::value) src.seek(b0);
   uint32_t* zw = zs + wave * kP32SliceWords;
-  P32Tab<REG> tab;
-  tab.lds = tabs;
-  // sub-step 1 operands of a row: chunk-packed words of c1 = 8 ks + 4 h + i at column c2
-  auto load_row = [&](uint64_t row_off, v4i (&dst)[4]) {
-    const __amdgpu_buffer_rsrc_t r = rows_rsrc(in + row_off, 1024 * 4);
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const uint32_t o = (uint32_t)((8 * ks + 4 * h) * 32 + c2) * 4;
-      dst[ks] = v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0),
-                    (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 128, 0),
-                    (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 256, 0),
-                    (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 384, 0)};
-    }
-  };
-  v4i pre[4];
-  int cur_job = -1;
-  uint64_t off = 0;
-  if (PREFETCH && b0 < b1) {
-    int jn = 0;
-    uint64_t o = 0;
-    p32_block<NW>(b0, npoly, rb_log, stride, jobs, wave, &jn, &o);
-    load_row(o, pre);
-  }
+  P32Tab tab;
+  const int8_t* cur_tab = nullptr;
   for (int b = b0; b < b1; ++b) {
-    int j = 0;
-    p32_block<NW>(b, npoly, rb_log, stride, jobs, wave, &j, &off);
-    if (j != cur_job) {
-      __syncthreads();
-      stage<64 * NW>(tabs, jobs[j].tab1, 16 * 32 * 32);
-      stage<64 * NW>(tws, jobs[j].tw1, 8 * 1024);
-      __syncthreads();
-      tab.load(lane);
-      cur_job = j;
-    }
-    const uint32_t q = jobs[j].q, qinv = jobs[j].qinv;
+    const RowLoc L = src.locate(b, wave);
+    p32_stage(L, cur_tab, tabs, tws, tab, lane);
+    const uint32_t q = L.q, qinv = L.qinv;
+    // operands: chunk-packed words of c1 = 8 ks + 4 h + i at column c2
     v4i cur[4];
-    if constexpr (PREFETCH) {
+    {
+      const __amdgpu_buffer_rsrc_t r = rows_rsrc(L.in, 1024 * 4);
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) cur[ks] = pre[ks];
-      if (b + 1 < b1) {
-        int jn = 0;
-        uint64_t o = 0;
-        p32_block<NW>(b + 1, npoly, rb_log, stride, jobs, wave, &jn, &o);
-        load_row(o, pre);
+      for (int ks = 0; ks < 4; ++ks) {
+        const uint32_t o = (uint32_t)((8 * ks + 4 * h) * 32 + c2) * 4;
+        cur[ks] = v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0),
+                      (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 128, 0),
+                      (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 256, 0),
+                      (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 384, 0)};
       }
-    } else {
-      load_row(off, cur);
     }
-    // sub-step 1 over c1: out m = mb * 8 + 2 j + h at column c2, then T3 twiddle, packed into Z
+    // sub-step 1: out m = mb * 8 + 2 j + h at column c2, T3 twiddle, packed into Z
     {
       const uint32_t* twl = &tws[(h * 32 + c2) * 2];
       uint32_t* zl = &zw[h * kP32Zp + c2];
-      v16i acc4[KSOUT ? 4 : 1];
-      if constexpr (KSOUT) p32_all_mb<REG>(acc4, tab, cur, lane);
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
-        const v16i acc = KSOUT ? acc4[KSOUT ? mb : 0] : p32_block_mb<REG>(tab, cur, mb, lane);
+        const v16i acc = p32_block_mb(tab, cur, mb);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int m0 = mb * 8 + 2 * jj;
@@ -623,18 +645,16 @@ ntt_rows32_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, ui
       }
     }
     wave_lds_sync();
-    // sub-step 2 over c2: column m = lane % 32 reads its Z line (16 contiguous bytes per K step)
+    // sub-step 2: column m = lane % 32 reads its Z line (16 contiguous bytes per K step)
     v4i zb[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) zb[ks] = *reinterpret_cast<const v4i*>(&zw[c2 * kP32Zp + 8 * ks + 4 * h]);
     wave_lds_sync();
     {
       uint32_t* xl = &zw[c2 * kP32Xp + h];          // output c2' = mb * 8 + 2 j + h of line m = c2
-      v16i acc4[KSOUT ? 4 : 1];
-      if constexpr (KSOUT) p32_all_mb<REG>(acc4, tab, zb, lane);
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
-        const v16i acc = KSOUT ? acc4[KSOUT ? mb : 0] : p32_block_mb<REG>(tab, zb, mb, lane);
+        const v16i acc = p32_block_mb(tab, zb, mb);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const uint32_t r = merge_redc(acc, jj, q, qinv);
@@ -643,94 +663,50 @@ ntt_rows32_fwd_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, ui
       }
     }
     wave_lds_sync();
-    // the row: element e = line * 32 + c from staging line `line`, 16-byte stores
-    const __amdgpu_buffer_rsrc_t ro = rows_rsrc(out + off, 1024 * 4);
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int e = (lane + it * 64) * 4;
-      const uint32_t* src = &zw[(e >> 5) * kP32Xp + (e & 31)];
-      __builtin_amdgcn_raw_buffer_store_b128(v4u{src[0], src[1], src[2], src[3]}, ro, e * 4, 0, 0);
-    }
+    p32_write_row(zw, L.out, lane);
     wave_lds_sync();       // staging reads done before the next block's Z writes
   }
 }
 
-// Inverse: sub-step 1 (ITC over c2', columns (row, m)) reads plain residues, its
-// epilogue applies IT3 and packs Z lines [c2][m]; sub-step 2 (ITB over m, columns
-// (row, c2)) applies the inverse step-2 twiddle of the outer split, read from global
-// memory per 32-row block before its products, and stages packed output lines c1.
-template <int NW, int OCC, bool REG, bool PREFETCH, bool KSOUT>
-__global__ void __launch_bounds__(64 * NW, OCC)
-ntt_rows32_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, uint64_t stride, int npoly,
-                      int rb_log, int nblocks) {
+// Inverse: sub-step 1 (ITC over c2', columns (row, m)) reads plain residues, applies
+// IT3 and packs Z lines [c2][m]; sub-step 2 (ITB over m, columns (row, c2)) applies the
+// inverse step-2 twiddle of the outer split, read per 32-row block before its products,
+// and stages packed output lines c1.
+template <class SRC>
+__global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_inv_kernel(SRC src, int nblocks) {
   __shared__ __attribute__((aligned(16))) int8_t tabs[16 * 32 * 32];
   __shared__ __attribute__((aligned(16))) uint32_t tws[2 * 1024];
-  __shared__ __attribute__((aligned(16))) uint32_t zs[NW * kP32SliceWords];
+  __shared__ __attribute__((aligned(16))) uint32_t zs[kP32Waves * kP32SliceWords];
   const int lane = threadIdx.x & 63, h = lane >> 5, cl = lane & 31;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int G = gridDim.x, g = blockIdx.x;
-  const int b0 = (int)((int64_t)g * nblocks / G), b1 = (int)((int64_t)(g + 1) * nblocks / G);
+  int b0, b1;
+  p32_range(nblocks, b0, b1);
+  if constexpr (std::is_same<SRC, P32List>::value) src.seek(b0);
   uint32_t* zw = zs + wave * kP32SliceWords;
-  P32Tab<REG> tab;
-  tab.lds = tabs;
-  // sub-step 1 operands of a row: residues c2' = 8 ks + 4 h + i of line m = cl, packed
-  auto load_row = [&](uint64_t row_off, v4i (&dst)[4]) {
-    const __amdgpu_buffer_rsrc_t r = rows_rsrc(in + row_off, 1024 * 4);
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      const v4u x = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)(cl * 32 + 8 * ks + 4 * h) * 4, 0, 0);
-      dst[ks] = v4i{(int)x.x, (int)x.y, (int)x.z, (int)x.w};
-    }
-  };
-  v4i pre[4];
-  int cur_job = -1;
-  uint64_t off = 0;
-  if (PREFETCH && b0 < b1) {
-    int jn = 0;
-    uint64_t o = 0;
-    p32_block<NW>(b0, npoly, rb_log, stride, jobs, wave, &jn, &o);
-    load_row(o, pre);
-  }
+  P32Tab tab;
+  const int8_t* cur_tab = nullptr;
   for (int b = b0; b < b1; ++b) {
-    int j = 0, row = 0;
-    p32_block<NW>(b, npoly, rb_log, stride, jobs, wave, &j, &off, &row);
-    if (j != cur_job) {
-      __syncthreads();
-      stage<64 * NW>(tabs, jobs[j].tab1, 16 * 32 * 32);
-      stage<64 * NW>(tws, jobs[j].tw1, 8 * 1024);
-      __syncthreads();
-      tab.load(lane);
-      cur_job = j;
-    }
-    const uint32_t q = jobs[j].q, qinv = jobs[j].qinv;
-    // the inverse step-2 twiddle pairs of row `row` (index within the polynomial), [c][2]
-    const __amdgpu_buffer_rsrc_t tw2 = rows_rsrc(jobs[j].tw2 + (uint64_t)row * 2048, 8 * 1024);
+    const RowLoc L = src.locate(b, wave);
+    p32_stage(L, cur_tab, tabs, tws, tab, lane);
+    const uint32_t q = L.q, qinv = L.qinv;
+    const __amdgpu_buffer_rsrc_t tw2 = rows_rsrc(L.tw2, 8 * 1024);
+    // operands: residues c2' = 8 ks + 4 h + i of line m = cl, packed
     v4i cur[4];
-    if constexpr (PREFETCH) {
+    {
+      const __amdgpu_buffer_rsrc_t r = rows_rsrc(L.in, 1024 * 4);
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) cur[ks] = pre[ks];
-      if (b + 1 < b1) {
-        int jn = 0;
-        uint64_t o = 0;
-        p32_block<NW>(b + 1, npoly, rb_log, stride, jobs, wave, &jn, &o);
-        load_row(o, pre);
+      for (int ks = 0; ks < 4; ++ks) {
+        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(r, (uint32_t)(cl * 32 + 8 * ks + 4 * h) * 4, 0, 0);
+        cur[ks] = v4i{(int)pack7(x.x), (int)pack7(x.y), (int)pack7(x.z), (int)pack7(x.w)};
       }
-    } else {
-      load_row(off, cur);
     }
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
-      cur[ks] = v4i{(int)pack7((uint32_t)cur[ks].x), (int)pack7((uint32_t)cur[ks].y), (int)pack7((uint32_t)cur[ks].z),
-                    (int)pack7((uint32_t)cur[ks].w)};
-    // sub-step 1 over c2': out c2 = mb * 8 + 2 j + h at column m = cl, IT3 pairs [c2][m], Z lines [c2][m]
+    // sub-step 1: out c2 = mb * 8 + 2 j + h at column m = cl, IT3 pairs [c2][m], Z lines [c2][m]
     {
       const uint32_t* twl = &tws[(h * 32 + cl) * 2];
       uint32_t* zl = &zw[h * kP32Zp + cl];
-      v16i acc4[KSOUT ? 4 : 1];
-      if constexpr (KSOUT) p32_all_mb<REG>(acc4, tab, cur, lane);
 #pragma unroll
       for (int mb = 0; mb < 4; ++mb) {
-        const v16i acc = KSOUT ? acc4[KSOUT ? mb : 0] : p32_block_mb<REG>(tab, cur, mb, lane);
+        const v16i acc = p32_block_mb(tab, cur, mb);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int c0 = mb * 8 + 2 * jj;
@@ -740,7 +716,7 @@ ntt_rows32_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, ui
       }
     }
     wave_lds_sync();
-    // sub-step 2 over m: column c2 = cl reads its Z line
+    // sub-step 2: column c2 = cl reads its Z line
     v4i zb[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) zb[ks] = *reinterpret_cast<const v4i*>(&zw[cl * kP32Zp + 8 * ks + 4 * h]);
@@ -754,7 +730,7 @@ ntt_rows32_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, ui
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
           w2[jj] = __builtin_amdgcn_raw_buffer_load_b64(tw2, tw_lane, (mb * 8 + 2 * jj) * 32 * 8, 0);
-        const v16i acc = p32_block_mb<REG>(tab, zb, mb, lane);
+        const v16i acc = p32_block_mb(tab, zb, mb);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
           const int c0 = mb * 8 + 2 * jj;
@@ -763,42 +739,25 @@ ntt_rows32_inv_kernel(const RowsJob* jobs, const uint32_t* in, uint32_t* out, ui
       }
     }
     wave_lds_sync();
-    const __amdgpu_buffer_rsrc_t ro = rows_rsrc(out + off, 1024 * 4);
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int e = (lane + it * 64) * 4;
-      const uint32_t* src = &zw[(e >> 5) * kP32Xp + (e & 31)];
-      __builtin_amdgcn_raw_buffer_store_b128(v4u{src[0], src[1], src[2], src[3]}, ro, e * 4, 0, 0);
-    }
+    p32_write_row(zw, L.out, lane);
     wave_lds_sync();
   }
 }
 
-// Launch configuration of the persistent forward row kernel: waves per workgroup,
-// waves per SIMD, table in registers, next-row prefetch.
-#ifndef CROSS_P32_CFG
-#define CROSS_P32_CFG 8, 4, true, false, false
-#endif
-#ifndef CROSS_P32_INV_CFG
-#define CROSS_P32_INV_CFG 8, 4, true, false, false
-#endif
-template <int NW, int OCC, bool REG, bool PREFETCH, bool KSOUT>
-hipError_t p32_launch(const RowsJob* jobs, int njobs, const uint32_t* in, uint32_t* out, uint64_t stride,
-                      int npoly, int log_r, bool inverse, hipStream_t s) {
-  constexpr int kLogNw = NW == 8 ? 3 : NW == 4 ? 2 : 1;
-  static_assert(NW == 2 || NW == 4 || NW == 8, "waves per workgroup");
-  if (log_r < kLogNw) return hipErrorInvalidValue;
-  const int64_t nblocks = (int64_t)njobs * npoly << (log_r - kLogNw);
+// Workgroups that fit the device at four waves per SIMD (two per CU), at most one per block.
+int p32_grid(int64_t nblocks) {
+  return (int)std::min<int64_t>(nblocks, 2 * (int64_t)cu_count());
+}
+
+template <class SRC>
+hipError_t p32_launch(const SRC& src, int64_t nblocks, bool inverse, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-  // as many workgroups as fit on the device at this occupancy (4 SIMDs per CU)
-  const int64_t per_cu = 4 * OCC / NW;
-  const int grid = (int)std::min<int64_t>(nblocks, per_cu * (int64_t)cu_count());
+  const int grid = p32_grid(nblocks);
   if (inverse)
-    launch_kernel((ntt_rows32_inv_kernel<NW, OCC, REG, PREFETCH, KSOUT>), dim3(grid), dim3(64 * NW), 0, s, jobs, in,
-                  out, stride, npoly, log_r - kLogNw, (int)nblocks);
+    launch_kernel((ntt_rows32_inv_kernel<SRC>), dim3(grid), dim3(64 * kP32Waves), 0, s, src, (int)nblocks);
   else
-    launch_kernel((ntt_rows32_fwd_kernel<NW, OCC, REG, PREFETCH, KSOUT>), dim3(grid), dim3(64 * NW), 0, s, jobs, in,
-                  out, stride, npoly, log_r - kLogNw, (int)nblocks);
+    launch_kernel((ntt_rows32_fwd_kernel<SRC>), dim3(grid), dim3(64 * kP32Waves), 0, s, src, (int)nblocks);
   return hipGetLastError();
 }
 
@@ -813,9 +772,9 @@ hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, u
   // per-lane offsets are 32-bit within a workgroup's 32 KB of rows
   if (stride >= (1ull << 40)) return hipErrorInvalidValue;
   if (log_c1 == 5 && log_c2 == 5 && red == 0 && !wide && log_r >= 3) {
-    // persistent form: workgroups walk contiguous ranges of blocks of rows
-    if (inverse) return p32_launch<CROSS_P32_INV_CFG>(jobs, njobs, in, out, stride, npoly, log_r, true, s);
-    return p32_launch<CROSS_P32_CFG>(jobs, njobs, in, out, stride, npoly, log_r, false, s);
+    // persistent form: workgroups walk contiguous ranges of 8-row blocks
+    const P32Uniform src{jobs, in, out, stride, npoly, log_r - 3};
+    return p32_launch(src, (int64_t)njobs * npoly << (log_r - 3), inverse, s);
   }
 #define CROSS_ROWS(a, b)                                                                                    \
   if (log_c1 == a && log_c2 == b)                                                                         \
@@ -834,6 +793,14 @@ hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, u
 #undef CROSS_ROWS
   return hipErrorInvalidValue;
 }
+
+hipError_t launch_ntt_rows_list(const RowsTask* tasks, int ntasks, int64_t nblocks, bool inverse, hipStream_t s) {
+  if (ntasks <= 0 || nblocks <= 0) return hipSuccess;
+  const P32List src{tasks, ntasks, 0};
+  return p32_launch(src, nblocks, inverse, s);
+}
+
+int rows_list_rows_per_block() { return kP32Waves; }
 
 bool rows_split_supported(int log_n, int log_r, int log_c1) {
   const int log_c2 = log_n - log_r - log_c1;
