@@ -6,7 +6,11 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - Residues are uint32 values in [0, q).  Inputs outside that range give
- *    unspecified (but memory-safe) results.
+ *    unspecified (but memory-safe) results, unless the debug mode
+ *    (cross_set_debug_check, or CROSS_DEBUG_CHECK=1 in the environment when the
+ *    context is created) is on: then every entry point checks its residue
+ *    inputs on the device first and fails with CROSS_EDOMAIN, naming the first
+ *    offending polynomial, limb and coefficient, before enqueueing any work.
  *  - Polynomial data is device memory laid out [batch][L][N] (limb-major per
  *    polynomial, N contiguous coefficients per limb).  Pointers must be
  *    16-byte aligned.  The caller owns every data buffer.
@@ -46,7 +50,9 @@ typedef enum cross_status {
                               the NTT entry points q >= 2^31 */
   CROSS_ENOMEM = -5,       /* device allocation failed */
   CROSS_EDEVICE = -6,      /* HIP runtime error while enqueueing */
-  CROSS_EUNSUPPORTED = -7  /* valid but unsupported shape */
+  CROSS_EUNSUPPORTED = -7, /* valid but unsupported shape */
+  CROSS_EDOMAIN = -8       /* debug mode (cross_set_debug_check): an input residue is not below
+                              its limb's prime */
 } cross_status;
 
 #define CROSS_MAX_LIMBS 64   /* L + K limit per call */
@@ -519,6 +525,18 @@ cross_status cross_set_ntt_reduction(cross_ctx ctx, int method);
 #define CROSS_NOALLOC_MAX_BYTES (128ull << 20)
 cross_status cross_ntt_noalloc(cross_ctx ctx, uint32_t log_n, const uint32_t* primes, uint32_t L, uint32_t batch,
                                uint32_t* data, int inverse, void* stream);
+
+/*
+ * Debug mode (the preconditions check): while enabled, each entry point that
+ * takes residues checks every input residue against its limb's prime with a
+ * device kernel before its own work and returns CROSS_EDOMAIN (cross_last_error
+ * names the input, polynomial, limb and coefficient) if one is not below it.
+ * The check synchronises the stream (not for use under graph capture); the
+ * chunked evaluation key, the prepared VecModMul operand, the batch runtime and
+ * cross_ntt_noalloc are not checked.  Off by default; CROSS_DEBUG_CHECK=1 in the
+ * environment turns it on for contexts created afterwards.
+ */
+cross_status cross_set_debug_check(cross_ctx ctx, int enable);
 
 /*
  * Engine of every NTT the context runs (cross_ntt_forward/inverse and those

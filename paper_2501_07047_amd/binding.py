@@ -13,7 +13,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcross.so")
 
 STATUS = {0: "CROSS_OK", -1: "CROSS_EINVAL", -2: "CROSS_ENOTPRIME", -3: "CROSS_ENOROOT",
-          -4: "CROSS_ERANGE", -5: "CROSS_ENOMEM", -6: "CROSS_EDEVICE", -7: "CROSS_EUNSUPPORTED"}
+          -4: "CROSS_ERANGE", -5: "CROSS_ENOMEM", -6: "CROSS_EDEVICE", -7: "CROSS_EUNSUPPORTED",
+          -8: "CROSS_EDOMAIN"}
 
 
 class CrossError(RuntimeError):
@@ -41,6 +42,7 @@ SIGNATURES = {
     "cross_set_ntt_split3": [c_vp, c_u32, c_u32, c_u32],
     "cross_set_ntt_reduction": [c_vp, ctypes.c_int],
     "cross_set_ntt_engine": [c_vp, ctypes.c_int],
+    "cross_set_debug_check": [c_vp, ctypes.c_int],
     "cross_ntt_noalloc": [c_vp, c_u32, c_u32p, c_u32, c_u32, c_vp, ctypes.c_int, c_vp],
     "cross_get_ntt_split": [c_vp, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)],
     "cross_host_row_tables": [c_u32, c_u32, c_u32, c_u32, c_u32, c_vp, ctypes.POINTER(ctypes.c_uint64)],
@@ -169,6 +171,12 @@ def set_ntt_reduction(method, device=None):
     """Epilogue reduction of every MFMA NTT step ("montgomery" or "barrett")."""
     ctx = context(device)
     _check(lib().cross_set_ntt_reduction(ctx, NTT_REDUCTION[method]), ctx)
+
+
+def set_debug_check(enable=True, device=None):
+    """Residue-range check of every input (CROSS_EDOMAIN on a residue not below its prime)."""
+    ctx = context(device)
+    _check(lib().cross_set_debug_check(ctx, int(bool(enable))), ctx)
 
 
 NTT_ENGINE = {"mfma": 0, "butterfly": 1}

@@ -264,6 +264,13 @@ cross_status perm_table(cross_ctx ctx, int log_n, uint32_t g, const uint32_t** o
 
 namespace {
 
+// Debug mode: residue-range check of an input (no-op unless enabled on the context).
+#define CHECK_IN(...)                                                                   \
+  do {                                                                                  \
+    cross_status _c = check_residues(ctx, __VA_ARGS__);                                 \
+    if (_c != CROSS_OK) return _c;                                                      \
+  } while (0)
+
 #define HIPCHK(expr, what)                                                              \
   do {                                                                                  \
     hipError_t _e = (expr);                                                             \
@@ -491,6 +498,8 @@ cross_status cross_poly_mul(cross_ctx ctx, uint32_t log_n, const uint32_t* prime
   if (st != CROSS_OK) return st;
   uint32_t* wb = (uint32_t*)ws;
   uint32_t* tmp = wb + tot;
+  CHECK_IN("a", a, (uint64_t)L * N, (int)batch, primes, (int)L, (int)log_n, s);
+  CHECK_IN("b", b, (uint64_t)L * N, (int)batch, primes, (int)L, (int)log_n, s);
   HIPCHK(hipMemcpyAsync(wb, b, tot * 4, hipMemcpyDeviceToDevice, s), "copy b");   // b first: out may alias b
   HIPCHK(hipMemcpyAsync(out, a, tot * 4, hipMemcpyDeviceToDevice, s), "copy a");
   const uint64_t stride = (uint64_t)L * N;
@@ -531,6 +540,7 @@ cross_status cross_bconv(cross_ctx ctx, uint32_t log_n, const uint32_t* src_prim
   BconvStatic bs;
   st = make_bconv(ctx, sp, so, dp, dof, &bs);
   if (st != CROSS_OK) return st;
+  CHECK_IN("in", in, (uint64_t)l * N, (int)batch, src_primes, (int)l, (int)log_n, (hipStream_t)stream);
   HIPCHK(run_bconv(ctx, bs, in, (uint64_t)l * N, out, (uint64_t)lp * N, (int)batch, (int)log_n, (hipStream_t)stream),
          "bconv");
   return CROSS_OK;
@@ -547,6 +557,7 @@ cross_status cross_keyswitch_modup(cross_ctx ctx, const cross_ckks_params* prm, 
   KsWork w;
   if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
   const uint64_t N = 1ull << c->log_n;
+  CHECK_IN("in", in, (uint64_t)c->L * N, (int)batch, c->primes.data(), c->L, c->log_n, s);
   HIPCHK(hipMemcpyAsync(w.d, in, (uint64_t)batch * c->L * N * 4, hipMemcpyDeviceToDevice, s), "copy in");
   return modup_core(ctx, c, w.d, out, (int)batch, w.tmp, s);
 }
@@ -562,6 +573,7 @@ cross_status cross_keyswitch_moddown(cross_ctx ctx, const cross_ckks_params* prm
   KsWork w;
   if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
   const uint64_t N = 1ull << c->log_n, LK = c->L + c->K;
+  CHECK_IN("in", in, LK * N, (int)batch, c->primes.data(), (int)LK, c->log_n, s);
   HIPCHK(hipMemcpyAsync(w.acc, in, (uint64_t)batch * LK * N * 4, hipMemcpyDeviceToDevice, s), "copy in");
   return moddown_core(ctx, c, w.acc, (int)batch, w.z, nullptr, false, out, w.tmp, s);
 }
@@ -587,6 +599,13 @@ cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* prm, const ui
   KsWork w;
   if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
   {
+    const uint64_t N = 1ull << c->log_n;
+    CHECK_IN("ct_a", ct_a, (uint64_t)c->L * N, 2 * (int)batch, c->primes.data(), c->L, c->log_n, s);
+    CHECK_IN("ct_b", ct_b, (uint64_t)c->L * N, 2 * (int)batch, c->primes.data(), c->L, c->log_n, s);
+    CHECK_IN("relin_key", relin_key, (uint64_t)(c->L + c->K) * N, 2 * c->dnum, c->primes.data(), c->L + c->K,
+             c->log_n, s);
+  }
+  {
     ProfScope ps(ctx, "tensor", s);
     HIPCHK(launch_tensor(ct_a, ct_b, out, w.d, c->mods, c->L, c->log_n, (int)batch, s), "tensor");
   }
@@ -610,6 +629,8 @@ cross_status cross_he_add(cross_ctx ctx, uint32_t log_n, const uint32_t* primes,
   void* dm = nullptr;
   if ((st = cached_device_copy(ctx, mods.data(), mods.size() * sizeof(LimbMod), &dm)) != CROSS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  CHECK_IN("a", a, (uint64_t)L << log_n, (int)npoly, primes, (int)L, (int)log_n, s);
+  CHECK_IN("b", b, (uint64_t)L << log_n, (int)npoly, primes, (int)L, (int)log_n, s);
   ProfScope ps(ctx, "he_add", s);
   HIPCHK(launch_pointwise_add(a, b, out, (const LimbMod*)dm, (int)L, (int)log_n, (int)npoly, s), "he_add");
   return CROSS_OK;
@@ -631,6 +652,7 @@ cross_status cross_rescale(cross_ctx ctx, uint32_t log_n, const uint32_t* primes
     return fail(ctx, CROSS_EINVAL, "out must not overlap in");
   RescalePlan* r = nullptr;
   if ((st = get_rescale_plan(ctx, log_n, primes, L, drop, &r)) != CROSS_OK) return st;
+  CHECK_IN("in", in, (uint64_t)L * N, (int)npoly, primes, (int)L, (int)log_n, (hipStream_t)stream);
   const CkksPlan* c = r->c;
   hipStream_t s = (hipStream_t)stream;
   const uint64_t ny = (uint64_t)npoly * drop * N, nz = (uint64_t)npoly * Lk * N;
@@ -687,6 +709,8 @@ cross_status cross_rotate(cross_ctx ctx, const cross_ckks_params* prm, int32_t s
   KsWork w;
   if ((st = ks_workspace(ctx, c, (int)batch, s, &w)) != CROSS_OK) return st;
   const uint64_t L = c->L;
+  CHECK_IN("ct", ct, L * N, 2 * (int)batch, c->primes.data(), c->L, c->log_n, s);
+  CHECK_IN("rot_key", rot_key, (uint64_t)(c->L + c->K) * N, 2 * c->dnum, c->primes.data(), c->L + c->K, c->log_n, s);
   {
     ProfScope ps(ctx, "automorphism", s);
     // sigma(c0) -> out[b][0] (the ModDown base of the first component); sigma(c1) -> workspace
@@ -732,6 +756,7 @@ cross_status cross_evk_bat_prepare(cross_ctx ctx, uint32_t log_n, const uint32_t
   const StreamMod* m = nullptr;
   if ((st = stream_mods(ctx, log_n, primes, LK, &m)) != CROSS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  CHECK_IN("key", key, (uint64_t)LK << log_n, 2 * (int)dnum, primes, (int)LK, (int)log_n, s);
   ProfScope ps(ctx, "evk_bat_prepare", s);
   HIPCHK(launch_evk_bat_prepare(key, key_bat, m, (int)LK, (int)dnum, (int)log_n, s), "evk_bat_prepare");
   return CROSS_OK;
@@ -754,6 +779,8 @@ cross_status cross_keyswitch_inner_product(cross_ctx ctx, uint32_t log_n, const 
   if (overlaps(out, n_out * 4, ext, n_ext * 4) || overlaps(out, n_out * 4, key, n_key * 4))
     return fail(ctx, CROSS_EINVAL, "out must not overlap ext or key");
   hipStream_t s = (hipStream_t)stream;
+  CHECK_IN("ext", ext, LK * N, (int)(batch * dnum), primes, (int)LK, (int)log_n, s);
+  if (form == CROSS_STREAM_VALU) CHECK_IN("key", key, LK * N, 2 * (int)dnum, primes, (int)LK, (int)log_n, s);
   if (form == CROSS_STREAM_CHUNKED) {
     const StreamMod* m = nullptr;
     if ((st = stream_mods(ctx, log_n, primes, LK, &m)) != CROSS_OK) return st;
@@ -793,6 +820,8 @@ cross_status cross_tensor(cross_ctx ctx, uint32_t log_n, const uint32_t* primes,
       overlaps(d2, n_d2 * 4, out, n_ct * 4))
     return fail(ctx, CROSS_EINVAL, "out and d2 must not overlap each other or the inputs");
   hipStream_t s = (hipStream_t)stream;
+  CHECK_IN("a", a, (uint64_t)L * N, 2 * (int)batch, primes, (int)L, (int)log_n, s);
+  CHECK_IN("b", b, (uint64_t)L * N, 2 * (int)batch, primes, (int)L, (int)log_n, s);
   if (form == CROSS_STREAM_CHUNKED) {
     const StreamMod* m = nullptr;
     if ((st = stream_mods(ctx, log_n, primes, L, &m)) != CROSS_OK) return st;

@@ -2,6 +2,7 @@
 #include "context.h"
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <stdexcept>
@@ -433,6 +434,36 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   return CROSS_OK;
 }
 
+cross_status check_residues(cross_ctx ctx, const char* what, const uint32_t* base, uint64_t stride, int npoly,
+                            const uint32_t* qs, int nl, int log_n, hipStream_t s) {
+  if (!ctx->debug_check || npoly <= 0 || nl <= 0) return CROSS_OK;
+  if (!ctx->debug_flag) {
+    void* f = nullptr;
+    cross_status st = dev_alloc(ctx, sizeof(unsigned long long), &f);
+    if (st != CROSS_OK) return st;
+    ctx->debug_flag = static_cast<unsigned long long*>(f);
+  }
+  const uint64_t N = 1ull << log_n;
+  std::vector<CheckLimb> limbs(nl);
+  for (int i = 0; i < nl; ++i) limbs[i] = CheckLimb{(uint64_t)i * N, qs[i], 0};
+  void* dl = nullptr;
+  cross_status st = cached_device_copy(ctx, limbs.data(), limbs.size() * sizeof(CheckLimb), &dl);
+  if (st != CROSS_OK) return st;
+  unsigned long long first = ~0ull;
+  hipError_t e = hipMemcpyAsync(ctx->debug_flag, &first, sizeof(first), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_residue_check(base, stride, npoly, (const CheckLimb*)dl, nl, log_n, ctx->debug_flag, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&first, ctx->debug_flag, sizeof(first), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("debug check: ") + hipGetErrorString(e));
+  if (first == ~0ull) return CROSS_OK;
+  const uint64_t n = first % N, pl = first / N;
+  const uint64_t l = pl % (uint64_t)nl, p = pl / (uint64_t)nl;
+  return fail(ctx, CROSS_EDOMAIN, std::string(what) + ": polynomial " + std::to_string(p) + ", limb " +
+                                      std::to_string(l) + ", coefficient " + std::to_string(n) +
+                                      " is not below its modulus " + std::to_string(qs[l]));
+}
+
 // ---- scratch of the allocation-free NTT entry point ------------------------
 // A file-scope device array: every device the library runs on holds its own copy
 // (loaded with the code object, kept until the process ends).  Host code never
@@ -480,6 +511,10 @@ static cross_status ntt_common(cross_ctx ctx, uint32_t log_n, const uint32_t* pr
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CROSS_EDEVICE, "hipSetDevice failed");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint64_t N = 1ull << log_n;
+  {
+    cross_status st = check_residues(ctx, "data", data, (uint64_t)L * N, (int)batch, primes, (int)L, (int)log_n, s);
+    if (st != CROSS_OK) return st;
+  }
   std::vector<Plan*> plans(L);
   std::vector<uint64_t> offs(L);
   for (uint32_t i = 0; i < L; ++i) {
@@ -532,6 +567,7 @@ cross_status cross_ctx_create(int hip_device, cross_ctx* out) {
   cross_ctx c = new cross_ctx_s();
   c->device = hip_device;
   c->noalloc_scratch = scratch_ptr;
+  if (const char* v = std::getenv("CROSS_DEBUG_CHECK")) c->debug_check = v[0] == '1';
   *out = c;
   return CROSS_OK;
 }
@@ -547,6 +583,7 @@ void cross_ctx_destroy(cross_ctx ctx) {
   for (auto& kv : ctx->job_cache) (void)hipFree(kv.second);
   for (auto& kv : ctx->const_cache) (void)hipFree(kv.second);
   for (auto& kv : ctx->workspace) (void)hipFree(kv.second.ptr);
+  if (ctx->debug_flag) (void)hipFree(ctx->debug_flag);
   for (auto& r : ctx->prof_recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -639,6 +676,12 @@ cross_status cross_ntt_noalloc(cross_ctx ctx, uint32_t log_n, const uint32_t* pr
                                     reinterpret_cast<uint32_t*>(base + kNoAllocJobBytes), s);
   ctx->arena = cross_ctx_s::Arena{};
   return st;
+}
+
+cross_status cross_set_debug_check(cross_ctx ctx, int enable) {
+  if (!ctx) return CROSS_EINVAL;
+  ctx->debug_check = enable != 0;
+  return CROSS_OK;
 }
 
 cross_status cross_set_ntt_engine(cross_ctx ctx, int engine) {

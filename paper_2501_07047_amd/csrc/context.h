@@ -78,6 +78,8 @@ struct cross_ctx_s {
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)
   void* noalloc_scratch = nullptr;            // device address of this device's no-alloc scratch
+  bool debug_check = false;                   // residue-range check of every input (CROSS_DEBUG_CHECK)
+  unsigned long long* debug_flag = nullptr;   // device word of the check
   // While set (cross_ntt_noalloc), job lists go into this arena with stream-ordered
   // copies instead of the allocating cache.
   struct Arena {
@@ -112,6 +114,11 @@ int split_of(cross_ctx ctx, int log_n);
 void effective_split(cross_ctx ctx, int log_n, bool allow3, int* log_r, int* log_c1);
 // Device copy of a POD array, cached by content.
 cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, void** out);
+// Debug mode (ctx->debug_check): every coefficient of npoly polynomials `stride`
+// apart, limb i at offset i * N with prime qs[i], must be below its prime; checked
+// on the device and synchronously on `s`.  CROSS_EDOMAIN names the first offender.
+cross_status check_residues(cross_ctx ctx, const char* what, const uint32_t* base, uint64_t stride, int npoly,
+                            const uint32_t* qs, int nl, int log_n, hipStream_t s);
 // Device address of `device`'s copy of the allocation-free NTT's scratch array
 // (looked up once per device).
 hipError_t noalloc_scratch_address(int device, void** out);

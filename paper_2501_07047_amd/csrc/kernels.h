@@ -336,6 +336,15 @@ hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_waves, hi
 }  // namespace cross
 
 namespace cross {
+// Debug mode: record in *first the lowest position (p * nl + l) * N + n with
+// base[p * stride + limbs[l].off + n] >= limbs[l].q (*first untouched if none).
+struct CheckLimb {
+  uint64_t off;
+  uint32_t q, pad;
+};
+hipError_t launch_residue_check(const uint32_t* base, uint64_t stride, int npoly, const CheckLimb* limbs, int nl,
+                                int log_n, unsigned long long* first, hipStream_t s);
+
 struct AutoTask {              // out[l][x] = in[l][perm[x]] for L limbs of one polynomial
   const uint32_t* in;
   uint32_t* out;

@@ -99,6 +99,7 @@ cross_status cross_vec_modmul_prepare(cross_ctx ctx, uint32_t log_n, const uint3
   const uintptr_t a0 = reinterpret_cast<uintptr_t>(w), b0 = reinterpret_cast<uintptr_t>(w_prep);
   if (a0 < b0 + 2 * n * 4 && b0 < a0 + n * 4) return fail(ctx, CROSS_EINVAL, "w_prep must not overlap w");
   hipStream_t s = (hipStream_t)stream;
+  if (aligned16(w) && (st = check_residues(ctx, "w", w, n, 1, primes, (int)L, (int)log_n, s)) != CROSS_OK) return st;
   ProfScope ps(ctx, "modmul_prepare", s);
   const hipError_t e = launch_modmul_prepare(w, w_prep, w_prep + n, limbs, (int)L, (int)log_n, method, s);
   if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("prepare launch: ") + hipGetErrorString(e));
@@ -117,6 +118,7 @@ cross_status cross_vec_modmul(cross_ctx ctx, uint32_t log_n, const uint32_t* pri
   if (st != CROSS_OK) return st;
   const uint64_t n = (uint64_t)L << log_n;
   hipStream_t s = (hipStream_t)stream;
+  if ((st = check_residues(ctx, "a", a, n, (int)npoly, primes, (int)L, (int)log_n, s)) != CROSS_OK) return st;
   ProfScope ps(ctx, "vec_modmul", s);
   const hipError_t e = launch_vec_modmul(a, w_prep, w_prep + n, out, limbs, lazy, (int)L, (int)log_n, (int)npoly,
                                          method, s);
