@@ -13,6 +13,7 @@
 // two-factor MAC work at 2^16); 2^12 and 2^13 in two (R, C >= 64).  Launch
 // boundaries order the phases, so a batch of any size costs a fixed number of
 // launches, and replaying the captured graph costs one.
+#include <cstring>
 #include <algorithm>
 #include <map>
 #include <memory>
@@ -82,6 +83,10 @@ struct cross_batch_s {
   bool external = false;        // scratch and task lists live in the caller's workspace
   char* ext_cursor = nullptr;   // next free byte of the caller's workspace (task lists)
   char* ext_end = nullptr;
+  char* ext_lists = nullptr;    // first byte of the task lists in the caller's workspace
+  std::vector<char> stage;      // task lists as laid out there (host copy)
+  void* pinned = nullptr;       // pinned source of their one upload
+  hipEvent_t uploaded = nullptr;
   hipStream_t upload_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -106,9 +111,10 @@ cross_status upload(cross_batch b, const std::vector<T>& v, const T** out) {
     if (b->ext_cursor + n > b->ext_end) return fail(b->ctx, CROSS_EINVAL, "workspace too small for the task lists");
     d = b->ext_cursor;
     b->ext_cursor += n;
-    // stream-ordered before any run enqueued on the same stream; the host vector lives in the batch
-    if (hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, b->upload_stream) != hipSuccess)
-      return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
+    // gathered into the host stage; finish_upload copies every list at once
+    const size_t at = b->stage.size();
+    b->stage.resize(at + n, 0);
+    std::memcpy(b->stage.data() + at, v.data(), v.size() * sizeof(T));
   } else {
     if (hipMalloc(&d, v.size() * sizeof(T)) != hipSuccess) {
       (void)hipGetLastError();
@@ -119,6 +125,28 @@ cross_status upload(cross_batch b, const std::vector<T>& v, const T** out) {
       return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
   }
   *out = static_cast<const T*>(d);
+  return CROSS_OK;
+}
+
+// Caller's workspace: one stream-ordered copy of all task lists from pinned host
+// memory (kept, with an event marking the copy's end, until the batch is destroyed).
+cross_status finish_upload(cross_batch b) {
+  if (b->stage.empty()) return CROSS_OK;
+  if (hipHostMalloc(&b->pinned, b->stage.size(), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    b->pinned = nullptr;
+    return fail(b->ctx, CROSS_ENOMEM, "pinned staging of the task lists failed");
+  }
+  std::memcpy(b->pinned, b->stage.data(), b->stage.size());
+  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    b->uploaded = nullptr;
+    return fail(b->ctx, CROSS_EDEVICE, "event creation failed");
+  }
+  if (hipMemcpyAsync(b->ext_lists, b->pinned, b->stage.size(), hipMemcpyHostToDevice, b->upload_stream) !=
+          hipSuccess ||
+      hipEventRecord(b->uploaded, b->upload_stream) != hipSuccess)
+    return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
   return CROSS_OK;
 }
 
@@ -304,6 +332,12 @@ void cross_batch_destroy(cross_batch b) {
   if (!b) return;
   (void)hipSetDevice(b->ctx->device);
   if (!b->external) (void)hipDeviceSynchronize();
+  if (b->uploaded) {
+    // the pinned source must outlive its copy (long finished once any run has completed)
+    (void)hipEventSynchronize(b->uploaded);
+    (void)hipEventDestroy(b->uploaded);
+  }
+  if (b->pinned) (void)hipHostFree(b->pinned);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (void* p : b->allocs) (void)hipFree(p);
@@ -503,6 +537,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     if ((reinterpret_cast<uintptr_t>(ext_ws) & 255) != 0 || ext_bytes < scratch + task_list_bytes(b.get()))
       return fail(ctx, CROSS_EINVAL, "workspace must be 256-byte aligned and at least cross_batch_workspace_bytes");
     b->ext_cursor = static_cast<char*>(ext_ws) + scratch;
+    b->ext_lists = b->ext_cursor;
     b->ext_end = static_cast<char*>(ext_ws) + ext_bytes;
     b->upload_stream = upload_stream;
   }
@@ -522,6 +557,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
   if (st == CROSS_OK) st = upload(b.get(), b->bconv_down, &b->d_bconv_down);
   if (st == CROSS_OK) st = upload(b.get(), b->inners, &b->d_inners);
   if (st == CROSS_OK) st = upload(b.get(), b->tails, &b->d_tails);
+  if (st == CROSS_OK && b->external) st = finish_upload(b.get());
   if (st != CROSS_OK) return st;
 
   if (use_graph) {

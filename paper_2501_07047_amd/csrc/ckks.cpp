@@ -350,9 +350,16 @@ cross_status moddown_core(cross_ctx ctx, const CkksPlan* c, uint32_t* acc, int n
   HIPCHK(run_bconv(ctx, c->moddown, acc, (uint64_t)LK * N, z, (uint64_t)L * N, npoly, c->log_n, s), "moddown bconv");
   std::vector<int> ql(L);
   std::vector<uint64_t> qo(L);
+  std::vector<Plan*> qp(L);
   for (int i = 0; i < L; ++i) {
     ql[i] = i;
     qo[i] = (uint64_t)i * N;
+    qp[i] = c->plans[i];
+  }
+  if (ntt_tail_fusable(ctx, qp)) {
+    // the NTT's row kernel writes out = base + (acc - NTT(z)) * P^-1 directly
+    const RowsTail t{acc, (uint64_t)LK * N, base, out, (uint64_t)L * N, c->tail, base_only_even ? 1 : 0};
+    return ntt_limbs_tail(ctx, qp, qo, z, (uint64_t)L * N, npoly, tmp, t, s);
   }
   st = ntt_list(ctx, c, ql, qo, z, (uint64_t)L * N, npoly, false, tmp, s);
   if (st != CROSS_OK) return st;
@@ -678,6 +685,15 @@ cross_status cross_rescale(cross_ctx ctx, uint32_t log_n, const uint32_t* primes
   }
   if ((st = ntt_list(ctx, c, pl, po, y, (uint64_t)drop * N, (int)npoly, true, tmp, s)) != CROSS_OK) return st;
   HIPCHK(run_bconv(ctx, r->bconv, y, (uint64_t)drop * N, z, Lk * N, (int)npoly, (int)log_n, s), "rescale bconv");
+  {
+    std::vector<Plan*> qp(Lk);
+    for (uint32_t i = 0; i < Lk; ++i) qp[i] = c->plans[i];
+    if (ntt_tail_fusable(ctx, qp)) {
+      // the NTT's row kernel writes out = (in - NTT(z)) * P^-1 directly
+      const RowsTail t{in, (uint64_t)L * N, nullptr, out, Lk * N, c->tail, 0};
+      return ntt_limbs_tail(ctx, qp, qo, z, Lk * N, (int)npoly, tmp, t, s);
+    }
+  }
   if ((st = ntt_list(ctx, c, ql, qo, z, Lk * N, (int)npoly, false, tmp, s)) != CROSS_OK) return st;
   ProfScope ps(ctx, "rescale_tail", s);
   HIPCHK(launch_moddown_tail(in, (uint64_t)L * N, z, nullptr, out, Lk * N, c->tail, (int)Lk, (int)log_n,

@@ -258,7 +258,7 @@ cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out) {
 // row-major input (N^-1 folded in).
 static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
                               uint32_t* data, uint64_t stride, int npoly, bool inverse, uint32_t* tmp,
-                              hipStream_t s) {
+                              hipStream_t s, const RowsTail* tail = nullptr) {
   const int log_n = plans[0]->log_n, log_r = plans[0]->log_r, log_c1 = plans[0]->log_c1;
   const int log_c2 = log_n - log_r - log_c1;
   const int red = ctx->ntt_reduction;
@@ -324,13 +324,36 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
     g.dst = tmp;
     g.out_packed = g.twiddle = true;
     if ((st = left()) != CROSS_OK) return st;
-    return rows(tmp, data);
+    if (!tail) return rows(tmp, data);
+    hipError_t e;
+    {
+      ProfScope ps(ctx, "ntt_rows", s);
+      e = launch_ntt_rows_tail((const RowsJob*)dr, (int)plans.size(), tmp, stride, npoly, log_r, *tail, s);
+    }
+    if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("row transform launch: ") + hipGetErrorString(e));
+    return CROSS_OK;
   }
   if ((st = rows(data, tmp)) != CROSS_OK) return st;
   g.src = tmp;
   g.dst = data;
   g.in_packed = g.in_rows = true;
   return left();
+}
+
+bool ntt_tail_fusable(cross_ctx ctx, const std::vector<Plan*>& plans) {
+  if (plans.empty() || ctx->ntt_engine != CROSS_NTT_ENGINE_MFMA || ctx->ntt_reduction != 0) return false;
+  const Plan* p0 = plans[0];
+  if (p0->log_n < 8 || p0->log_c1 == 0 || !rows_tail_supported(p0->log_n, p0->log_r, p0->log_c1)) return false;
+  for (const Plan* p : plans)
+    if (p->wide || p->log_r != p0->log_r || p->log_c1 != p0->log_c1) return false;
+  return true;
+}
+
+cross_status ntt_limbs_tail(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+                            uint32_t* data, uint64_t stride, int npoly, uint32_t* tmp, const RowsTail& tail,
+                            hipStream_t s) {
+  if (!ntt_tail_fusable(ctx, plans)) return fail(ctx, CROSS_EUNSUPPORTED, "no fused tail for this NTT form");
+  return ntt_three(ctx, plans, offs, data, stride, npoly, false, tmp, s, &tail);
 }
 
 cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,

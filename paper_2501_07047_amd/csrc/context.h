@@ -131,5 +131,15 @@ cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out);
 cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
                        const std::vector<uint64_t>& offs, uint32_t* data, uint64_t stride,
                        int npoly, bool inverse, uint32_t* tmp, hipStream_t s);
+// Whether the forward NTT of these limbs can end in the fused ModDown tail: the
+// MFMA engine with the Montgomery epilogue, narrow primes, and a three-factor split
+// whose row kernel has the fused form.
+bool ntt_tail_fusable(cross_ctx ctx, const std::vector<Plan*>& plans);
+// Forward NTT of the listed limbs of `data` (as ntt_limbs) whose row kernel applies
+// `tail` instead of writing the transform back (data is left in its input state
+// except where tail.out overlaps it); CROSS_EUNSUPPORTED when !ntt_tail_fusable.
+cross_status ntt_limbs_tail(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+                            uint32_t* data, uint64_t stride, int npoly, uint32_t* tmp, const RowsTail& tail,
+                            hipStream_t s);
 
 }  // namespace cross

@@ -231,6 +231,27 @@ hipError_t launch_moddown_tail(const uint32_t* acc, uint64_t acc_stride, const u
                                const TailConst* tc, int L, int log_n, int npoly,
                                bool base_only_even, hipStream_t s);
 
+// The same tail fused into the forward row kernel of the NTT of z (three factors
+// with the 32 x 32 row split): the kernel's output row y of job j (limb offset
+// jobs[j].off), polynomial p, row r is not stored; instead, at o = jobs[j].off + r * 1024,
+// out[p * out_stride + o ..] = base[p * out_stride + o ..] + (acc[p * acc_stride + o ..] - y) * Pinv_j
+// mod q_j (tc[j] per job).  base may be null (treated as 0), alias out, or, with
+// base_only_even, be added for even p only.
+struct RowsTail {
+  const uint32_t* acc;
+  uint64_t acc_stride;
+  const uint32_t* base;
+  uint32_t* out;
+  uint64_t out_stride;
+  const TailConst* tc;
+  int base_only_even;
+};
+// in: the packed row-side output (layout of z: job offset + p * stride + r * 1024).
+hipError_t launch_ntt_rows_tail(const RowsJob* jobs, int njobs, const uint32_t* in, uint64_t stride, int npoly,
+                                int log_r, const RowsTail& tail, hipStream_t s);
+// Whether the fused form exists for this split (the persistent 32 x 32 row kernel).
+bool rows_tail_supported(int log_n, int log_r, int log_c1);
+
 // NTT-domain automorphism: out[p][l][x] = in[p][l][perm[x]] for L limbs of npoly polynomials.
 hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t* out,
                                uint64_t out_stride, const uint32_t* perm, int log_n, int L,

@@ -503,6 +503,7 @@ struct RowLoc {
 // One launch of the uniform form: njobs limbs (one prime each) at offsets from
 // common bases, npoly polynomials `stride` apart, R / 8 blocks per polynomial.
 struct P32Uniform {
+  static constexpr bool kTail = false;
   const RowsJob* jobs;
   const uint32_t* in;
   uint32_t* out;
@@ -525,6 +526,7 @@ struct P32Uniform {
 // not above b.  Blocks of a workgroup are contiguous, so the task index only moves
 // forward.
 struct P32List {
+  static constexpr bool kTail = false;
   const RowsTask* tasks;
   int ntasks;
   int t = 0;                // current task (wave-uniform)
@@ -590,6 +592,48 @@ __device__ __forceinline__ void p32_write_row(const uint32_t* zw, uint32_t* out,
     __builtin_amdgcn_raw_buffer_store_b128(v4u{src[0], src[1], src[2], src[3]}, ro, e * 4, 0, 0);
   }
 }
+
+// The uniform form with the ModDown / rescale tail fused into the forward kernel's
+// write: out = base + (acc - y) * Pinv for the staged output row y.
+struct P32UniformTail : P32Uniform {
+  static constexpr bool kTail = true;
+  RowsTail t;
+  __device__ __forceinline__ void write_tail(int b, int wave, const uint32_t* zw, uint32_t q, int lane) const {
+    const int per_job = npoly << rb_log;
+    const int j = __builtin_amdgcn_readfirstlane(b / per_job);
+    const int rem = b - j * per_job;
+    const int poly = rem >> rb_log, row = (rem & ((1 << rb_log) - 1)) * kP32Waves + wave;
+    const uint64_t o = jobs[j].off + (uint64_t)row * 1024;
+    const TailConst c = t.tc[j];
+    const bool use_base = t.base != nullptr && (!t.base_only_even || (poly & 1) == 0);
+    const __amdgpu_buffer_rsrc_t ra = rows_rsrc(t.acc + poly * t.acc_stride + o, 1024 * 4);
+    const __amdgpu_buffer_rsrc_t ro = rows_rsrc(t.out + poly * t.out_stride + o, 1024 * 4);
+    // without a base the descriptor holds no records: its loads read zero
+    const __amdgpu_buffer_rsrc_t rb =
+        rows_rsrc(use_base ? t.base + poly * t.out_stride + o : t.out, use_base ? 1024 * 4 : 0);
+    v4u a[4], bs[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const uint32_t e = (uint32_t)(lane + it * 64) * 16;
+      a[it] = __builtin_amdgcn_raw_buffer_load_b128(ra, e, 0, 0);
+      bs[it] = __builtin_amdgcn_raw_buffer_load_b128(rb, e, 0, 0);
+    }
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int e = (lane + it * 64) * 4;
+      const uint32_t* y = &zw[(e >> 5) * kP32Xp + (e & 31)];
+      v4u r;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t d = a[it][k] + c.q - y[k];                       // (0, 2q)
+        const uint32_t m = d * c.pinv - __umulhi(d, c.pinv_shoup) * c.q; // [0, 2q)
+        const uint32_t v = (m >= c.q ? m - c.q : m) + bs[it][k];
+        r[k] = v >= c.q ? v - c.q : v;
+      }
+      __builtin_amdgcn_raw_buffer_store_b128(r, ro, (uint32_t)e * 4, 0, 0);
+    }
+  }
+};
 
 __device__ __forceinline__ void p32_range(int nblocks, int& b0, int& b1) {
   b0 = (int)((int64_t)blockIdx.x * nblocks / gridDim.x);
@@ -663,7 +707,10 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_fwd_kernel(SRC s
       }
     }
     wave_lds_sync();
-    p32_write_row(zw, L.out, lane);
+    if constexpr (SRC::kTail)
+      src.write_tail(b, wave, zw, q, lane);
+    else
+      p32_write_row(zw, L.out, lane);
     wave_lds_sync();       // staging reads done before the next block's Z writes
   }
 }
@@ -792,6 +839,29 @@ hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, u
   CROSS_ROWS(6, 4)
 #undef CROSS_ROWS
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_ntt_rows_tail(const RowsJob* jobs, int njobs, const uint32_t* in, uint64_t stride, int npoly,
+                                int log_r, const RowsTail& tail, hipStream_t s) {
+  if (njobs <= 0 || npoly <= 0) return hipSuccess;
+  if (log_r < 3 || stride >= (1ull << 40) || !tail.acc || !tail.out || !tail.tc) return hipErrorInvalidValue;
+  P32UniformTail src;
+  src.jobs = jobs;
+  src.in = in;
+  src.out = tail.out;       // unused: the tail writes every row
+  src.stride = stride;
+  src.npoly = npoly;
+  src.rb_log = log_r - 3;
+  src.t = tail;
+  const int64_t nblocks = (int64_t)njobs * npoly << (log_r - 3);
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  launch_kernel((ntt_rows32_fwd_kernel<P32UniformTail>), dim3(p32_grid(nblocks)), dim3(64 * kP32Waves), 0, s, src,
+                (int)nblocks);
+  return hipGetLastError();
+}
+
+bool rows_tail_supported(int log_n, int log_r, int log_c1) {
+  return log_c1 == 5 && log_n - log_r - log_c1 == 5 && log_r >= 3;
 }
 
 hipError_t launch_ntt_rows_list(const RowsTask* tasks, int ntasks, int64_t nblocks, bool inverse, hipStream_t s) {
