@@ -411,9 +411,10 @@ cross_status cross_batch_workspace_bytes(cross_ctx ctx, const cross_job* jobs, u
  * cross_batch_workspace_bytes): the batch allocates and frees no device memory
  * and destroying it does not synchronise the device, so the caller must know
  * that its last run has finished.  Task lists are copied on `stream`, in one copy
- * from pinned host memory that the batch holds until it is destroyed; run the
- * batch on the same stream (or order it after that copy).  CROSS_ENOMEM if that
- * pinned buffer cannot be allocated. */
+ * from a pinned host buffer of the context (held by the batch until it is
+ * destroyed, then reused by later batches once that copy has finished); run the
+ * batch on the same stream (or order it after that copy).  CROSS_ENOMEM if no
+ * pinned buffer can be allocated. */
 cross_status cross_batch_create_in(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
                                    void* workspace, uint64_t workspace_bytes, void* stream,
                                    cross_batch* out);

@@ -85,8 +85,7 @@ struct cross_batch_s {
   char* ext_end = nullptr;
   char* ext_lists = nullptr;    // first byte of the task lists in the caller's workspace
   std::vector<char> stage;      // task lists as laid out there (host copy)
-  void* pinned = nullptr;       // pinned source of their one upload
-  hipEvent_t uploaded = nullptr;
+  int pinned = -1;              // the context's pinned buffer holding their upload's source
   hipStream_t upload_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -128,25 +127,20 @@ cross_status upload(cross_batch b, const std::vector<T>& v, const T** out) {
   return CROSS_OK;
 }
 
-// Caller's workspace: one stream-ordered copy of all task lists from pinned host
-// memory (kept, with an event marking the copy's end, until the batch is destroyed).
+// Caller's workspace: one stream-ordered copy of all task lists from a pinned
+// buffer of the context's pool (released when the batch is destroyed; the copy's
+// end is recorded on the buffer's event, so the buffer is reused only after it).
 cross_status finish_upload(cross_batch b) {
   if (b->stage.empty()) return CROSS_OK;
-  if (hipHostMalloc(&b->pinned, b->stage.size(), hipHostMallocDefault) != hipSuccess) {
+  cross_status st = pinned_acquire(b->ctx, b->stage.size(), &b->pinned);
+  if (st != CROSS_OK) return st;
+  cross_ctx_s::Pinned& pb = b->ctx->pinned[b->pinned];
+  std::memcpy(pb.p, b->stage.data(), b->stage.size());
+  if (hipMemcpyAsync(b->ext_lists, pb.p, b->stage.size(), hipMemcpyHostToDevice, b->upload_stream) != hipSuccess ||
+      hipEventRecord(pb.ev, b->upload_stream) != hipSuccess) {
     (void)hipGetLastError();
-    b->pinned = nullptr;
-    return fail(b->ctx, CROSS_ENOMEM, "pinned staging of the task lists failed");
-  }
-  std::memcpy(b->pinned, b->stage.data(), b->stage.size());
-  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    b->uploaded = nullptr;
-    return fail(b->ctx, CROSS_EDEVICE, "event creation failed");
-  }
-  if (hipMemcpyAsync(b->ext_lists, b->pinned, b->stage.size(), hipMemcpyHostToDevice, b->upload_stream) !=
-          hipSuccess ||
-      hipEventRecord(b->uploaded, b->upload_stream) != hipSuccess)
     return fail(b->ctx, CROSS_EDEVICE, "batch task list upload failed");
+  }
   return CROSS_OK;
 }
 
@@ -332,12 +326,7 @@ void cross_batch_destroy(cross_batch b) {
   if (!b) return;
   (void)hipSetDevice(b->ctx->device);
   if (!b->external) (void)hipDeviceSynchronize();
-  if (b->uploaded) {
-    // the pinned source must outlive its copy (long finished once any run has completed)
-    (void)hipEventSynchronize(b->uploaded);
-    (void)hipEventDestroy(b->uploaded);
-  }
-  if (b->pinned) (void)hipHostFree(b->pinned);
+  pinned_release(b->ctx, b->pinned);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (void* p : b->allocs) (void)hipFree(p);

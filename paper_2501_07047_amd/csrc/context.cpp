@@ -233,6 +233,40 @@ cross_status cached_device_copy(cross_ctx ctx, const void* host, size_t bytes, v
   return CROSS_OK;
 }
 
+cross_status pinned_acquire(cross_ctx ctx, size_t bytes, int* idx) {
+  int best = -1;
+  for (size_t i = 0; i < ctx->pinned.size(); ++i) {
+    const auto& b = ctx->pinned[i];
+    if (!b.busy && b.size >= bytes && (best < 0 || b.size < ctx->pinned[best].size)) best = (int)i;
+  }
+  if (best < 0) {
+    cross_ctx_s::Pinned b;
+    b.size = std::max<size_t>(bytes, 64 << 10);
+    if (hipHostMalloc(&b.p, b.size, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, CROSS_ENOMEM, "pinned host allocation failed");
+    }
+    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(b.p);
+      return fail(ctx, CROSS_EDEVICE, "event creation failed");
+    }
+    ctx->pinned.push_back(b);
+    best = (int)ctx->pinned.size() - 1;
+  } else if (hipEventSynchronize(ctx->pinned[best].ev) != hipSuccess) {
+    // its previous copy must have left the buffer (normally long done)
+    (void)hipGetLastError();
+    return fail(ctx, CROSS_EDEVICE, "waiting for a pinned buffer's copy failed");
+  }
+  ctx->pinned[best].busy = true;
+  *idx = best;
+  return CROSS_OK;
+}
+
+void pinned_release(cross_ctx ctx, int idx) {
+  if (idx >= 0 && idx < (int)ctx->pinned.size()) ctx->pinned[idx].busy = false;
+}
+
 cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out) {
   DevBuf& b = ctx->workspace[s];
   if (b.size < bytes) {
@@ -606,6 +640,10 @@ void cross_ctx_destroy(cross_ctx ctx) {
   for (auto& kv : ctx->job_cache) (void)hipFree(kv.second);
   for (auto& kv : ctx->const_cache) (void)hipFree(kv.second);
   for (auto& kv : ctx->workspace) (void)hipFree(kv.second.ptr);
+  for (auto& b : ctx->pinned) {
+    (void)hipEventDestroy(b.ev);
+    (void)hipHostFree(b.p);
+  }
   if (ctx->debug_flag) (void)hipFree(ctx->debug_flag);
   for (auto& r : ctx->prof_recs) {
     (void)hipEventDestroy(r.a);

@@ -77,6 +77,16 @@ struct cross_ctx_s {
   std::map<int, int> list_tile;               // batch runtime: GemmListTile per (2 log_n + inverse)
   std::map<std::string, void*> const_cache;   // other device-resident constants
   std::map<std::string, std::shared_ptr<void>> ext_plans;   // CKKS plans (host structs)
+  // Pinned host buffers for stream-ordered task-list uploads, reused across batches:
+  // `ev` is recorded after the last copy out of the buffer, and a buffer is handed
+  // out again only once that copy has finished.
+  struct Pinned {
+    void* p = nullptr;
+    size_t size = 0;
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+  };
+  std::vector<Pinned> pinned;
   void* noalloc_scratch = nullptr;            // device address of this device's no-alloc scratch
   bool debug_check = false;                   // residue-range check of every input (CROSS_DEBUG_CHECK)
   unsigned long long* debug_flag = nullptr;   // device word of the check
@@ -124,6 +134,11 @@ cross_status check_residues(cross_ctx ctx, const char* what, const uint32_t* bas
 hipError_t noalloc_scratch_address(int device, void** out);
 // Per-stream scratch of at least `bytes`.
 cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out);
+// A pinned host buffer of at least `bytes` from the context's pool (index in *idx),
+// free to overwrite; pinned_release returns it, after its last copy was recorded
+// on its event.
+cross_status pinned_acquire(cross_ctx ctx, size_t bytes, int* idx);
+void pinned_release(cross_ctx ctx, int idx);
 
 // Run forward / inverse NTTs for a list of limbs, each given by (plan, element
 // offset) inside `data` with `npoly` polynomials at `stride` elements apart.
