@@ -120,7 +120,8 @@ hipError_t launch_ntt_rows(const RowsJob* jobs, int njobs, const uint32_t* in, u
 // Work-list form of the row transform (batch runtime), split C1 = C2 = 32 only: each
 // task is one limb of one job (its prime's tables, its own buffers, npoly
 // polynomials `stride` apart, R = 2^log_r rows of 1024) and owns npoly * R / 8
-// blocks of eight rows, blocks [first_block, first_block of the next task); tasks are
+// blocks of eight rows (row block major, polynomial minor), blocks [first_block,
+// first_block of the next task); tasks are
 // in first_block order and nblocks is the total.  Forward: in = packed row-side
 // output, out = plain; inverse: in = plain, out = packed rows with the inverse step-2
 // twiddle applied (tw2 = its [R][C][2] pairs).

@@ -501,7 +501,8 @@ struct RowLoc {
 };
 
 // One launch of the uniform form: njobs limbs (one prime each) at offsets from
-// common bases, npoly polynomials `stride` apart, R / 8 blocks per polynomial.
+// common bases, npoly polynomials `stride` apart, R / 8 blocks per polynomial;
+// block b is (job, row block, polynomial) with the polynomial fastest.
 struct P32Uniform {
   static constexpr bool kTail = false;
   const RowsJob* jobs;
@@ -513,7 +514,8 @@ struct P32Uniform {
     const int per_job = npoly << rb_log;
     const int j = __builtin_amdgcn_readfirstlane(b / per_job);
     const int rem = b - j * per_job;
-    const int poly = rem >> rb_log, row = (rem & ((1 << rb_log) - 1)) * kP32Waves + wave;
+    const int rb = __builtin_amdgcn_readfirstlane(rem / npoly);
+    const int poly = rem - rb * npoly, row = rb * kP32Waves + wave;
     const RowsJob& jb = jobs[j];
     const uint64_t off = jb.off + (uint64_t)poly * stride + (uint64_t)row * 1024;
     return RowLoc{jb.tab1, jb.tw1, jb.tw2 ? jb.tw2 + (uint64_t)row * 2048 : nullptr, in + off, out + off,
@@ -523,8 +525,8 @@ struct P32Uniform {
 
 // The batch runtime's form: a task list (each task one limb with its own buffers,
 // polynomial count and R), block b in the task whose first_block is the last one
-// not above b.  Blocks of a workgroup are contiguous, so the task index only moves
-// forward.
+// not above b (within a task: row block, then polynomial, the polynomial fastest).
+// Blocks of a workgroup are contiguous, so the task index only moves forward.
 struct P32List {
   static constexpr bool kTail = false;
   const RowsTask* tasks;
@@ -542,9 +544,9 @@ struct P32List {
   __device__ __forceinline__ RowLoc locate(int b, int wave) {
     while (t + 1 < ntasks && tasks[t + 1].first_block <= b) ++t;
     const RowsTask& k = tasks[t];
-    const int rb_log = k.log_r - 3;
     const int local = b - k.first_block;
-    const int poly = local >> rb_log, row = (local & ((1 << rb_log) - 1)) * kP32Waves + wave;
+    const int rb = __builtin_amdgcn_readfirstlane(local / k.npoly);
+    const int poly = local - rb * k.npoly, row = rb * kP32Waves + wave;
     const uint64_t off = (uint64_t)poly * k.stride + (uint64_t)row * 1024;
     return RowLoc{k.tab, k.tw1, k.tw2 ? k.tw2 + (uint64_t)row * 2048 : nullptr, k.in + off, k.out + off, k.q, k.qinv};
   }
@@ -602,21 +604,22 @@ struct P32UniformTail : P32Uniform {
     const int per_job = npoly << rb_log;
     const int j = __builtin_amdgcn_readfirstlane(b / per_job);
     const int rem = b - j * per_job;
-    const int poly = rem >> rb_log, row = (rem & ((1 << rb_log) - 1)) * kP32Waves + wave;
+    const int rb = __builtin_amdgcn_readfirstlane(rem / npoly);
+    const int poly = rem - rb * npoly, row = rb * kP32Waves + wave;
     const uint64_t o = jobs[j].off + (uint64_t)row * 1024;
     const TailConst c = t.tc[j];
     const bool use_base = t.base != nullptr && (!t.base_only_even || (poly & 1) == 0);
     const __amdgpu_buffer_rsrc_t ra = rows_rsrc(t.acc + poly * t.acc_stride + o, 1024 * 4);
     const __amdgpu_buffer_rsrc_t ro = rows_rsrc(t.out + poly * t.out_stride + o, 1024 * 4);
     // without a base the descriptor holds no records: its loads read zero
-    const __amdgpu_buffer_rsrc_t rb =
+    const __amdgpu_buffer_rsrc_t rbase =
         rows_rsrc(use_base ? t.base + poly * t.out_stride + o : t.out, use_base ? 1024 * 4 : 0);
     v4u a[4], bs[4];
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
       const uint32_t e = (uint32_t)(lane + it * 64) * 16;
       a[it] = __builtin_amdgcn_raw_buffer_load_b128(ra, e, 0, 0);
-      bs[it] = __builtin_amdgcn_raw_buffer_load_b128(rb, e, 0, 0);
+      bs[it] = __builtin_amdgcn_raw_buffer_load_b128(rbase, e, 0, 0);
     }
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
@@ -635,9 +638,16 @@ struct P32UniformTail : P32Uniform {
   }
 };
 
+// Block range of this workgroup.  Workgroups are dispatched to the eight XCDs in
+// turn (workgroup w on XCD w % 8), so XCD x takes the x-th eighth of the blocks and
+// its workgroups split that slice: with blocks ordered (job, row block, polynomial),
+// every polynomial of a (prime, row block) -- which share its tables and the inverse
+// step-2 twiddles -- is handled within one XCD's L2.  The grid is a multiple of 8.
 __device__ __forceinline__ void p32_range(int nblocks, int& b0, int& b1) {
-  b0 = (int)((int64_t)blockIdx.x * nblocks / gridDim.x);
-  b1 = (int)((int64_t)(blockIdx.x + 1) * nblocks / gridDim.x);
+  const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
+  const int lo = (int)((int64_t)nblocks * xcd / 8), hi = (int)((int64_t)nblocks * (xcd + 1) / 8);
+  b0 = lo + (int)((int64_t)(hi - lo) * local / per_xcd);
+  b1 = lo + (int)((int64_t)(hi - lo) * (local + 1) / per_xcd);
 }
 
 // Forward: sub-step 1 (TB over c1, columns (row, c2)) reads the chunk-packed row-side
@@ -791,9 +801,11 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_inv_kernel(SRC s
   }
 }
 
-// Workgroups that fit the device at four waves per SIMD (two per CU), at most one per block.
+// Workgroups that fit the device at four waves per SIMD (two per CU), at most one
+// per block, rounded to a multiple of 8 (p32_range; surplus workgroups get no block).
 int p32_grid(int64_t nblocks) {
-  return (int)std::min<int64_t>(nblocks, 2 * (int64_t)cu_count());
+  const int64_t fit = std::max<int64_t>(8, 2 * (int64_t)cu_count() / 8 * 8);
+  return (int)std::min<int64_t>((nblocks + 7) / 8 * 8, fit);
 }
 
 template <class SRC>
