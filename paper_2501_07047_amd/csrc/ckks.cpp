@@ -286,21 +286,25 @@ cross_status ntt_list(cross_ctx ctx, const CkksPlan* c, const std::vector<int>& 
   return ntt_limbs(ctx, pl, offs, data, stride, npoly, inverse, tmp, s);
 }
 
-// ModUp of d (NTT form, [B][L][N], may be overwritten: used as the INTT scratch)
-// into ext [B][dnum][L+K][N].  `tmp` holds B*dnum*(L+K)*N words.
+// ModUp of d (NTT form, [B][L][N]) into ext [B][dnum][L+K][N].  `tmp` holds
+// B*dnum*(L+K)*N words.  Without x, d is overwritten (its INTT runs in place) and ext
+// receives every limb of every digit (a digit's own limbs copied from d, inactive
+// digits zero).  With x ([B][L][N] scratch), d is kept, its INTT goes to x, and ext
+// receives only the converted limbs (t outside digit j): the key-switch inner
+// product then reads a digit's own limbs from d.
 cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t* ext, int B,
-                        uint32_t* tmp, hipStream_t s) {
+                        uint32_t* tmp, hipStream_t s, uint32_t* x = nullptr) {
   const int L = c->L, K = c->K, LK = L + K;
   const uint64_t N = 1ull << c->log_n;
   const uint64_t ext_stride = (uint64_t)c->dnum * LK * N;
   // 1. digit limbs are copied unchanged (NTT form)
-  {
+  if (!x) {
     ProfScope ps(ctx, "limb_copy", s);
     HIPCHK(launch_limb_copy(d, (uint64_t)L * N, c->copy_src, ext, ext_stride, c->copy_dst, L, c->log_n, B, s),
            "modup copy");
   }
   // inactive digits are zero
-  if (c->ndig < c->dnum) {
+  if (!x && c->ndig < c->dnum) {
     std::vector<uint64_t> zo;
     for (int j = c->ndig; j < c->dnum; ++j)
       for (int t = 0; t < LK; ++t) zo.push_back(((uint64_t)j * LK + t) * N);
@@ -311,19 +315,18 @@ cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t*
                             (int)zo.size(), c->log_n, B, s), "modup zero");
   }
   // 2. coefficient form of d
-  std::vector<int> li(L);
   std::vector<uint64_t> lo(L);
-  for (int i = 0; i < L; ++i) {
-    li[i] = i;
-    lo[i] = (uint64_t)i * N;
-  }
-  cross_status st = ntt_list(ctx, c, li, lo, d, (uint64_t)L * N, B, true, tmp, s);
+  for (int i = 0; i < L; ++i) lo[i] = (uint64_t)i * N;
+  std::vector<Plan*> pl(L);
+  for (int i = 0; i < L; ++i) pl[i] = c->plans[i];
+  cross_status st = ntt_limbs(ctx, pl, lo, d, (uint64_t)L * N, B, true, tmp, s, x);
   if (st != CROSS_OK) return st;
+  const uint32_t* coef = x ? x : d;
   // 3. BConv of each digit to the other limbs, then 4. NTT of all converted limbs in one launch
   std::vector<int> nl;
   std::vector<uint64_t> no;
   for (int j = 0; j < c->ndig; ++j) {
-    HIPCHK(run_bconv(ctx, c->modup[j], d, (uint64_t)L * N, ext, ext_stride, B, c->log_n, s), "modup bconv");
+    HIPCHK(run_bconv(ctx, c->modup[j], coef, (uint64_t)L * N, ext, ext_stride, B, c->log_n, s), "modup bconv");
     for (int t : c->targets[j]) {
       nl.push_back(t);
       no.push_back(((uint64_t)j * LK + t) * N);
@@ -456,11 +459,13 @@ bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
 // of both accumulators into out0/out1 of out [B][2][L][N] with optional base.
 cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* key, int B, KsWork& w,
                             uint32_t* out, const uint32_t* base, bool base_only_even, hipStream_t s) {
-  cross_status st = modup_core(ctx, c, w.d, w.ext, B, w.tmp, s);
+  // the coefficient form of d goes to w.z, free until the ModDown
+  cross_status st = modup_core(ctx, c, w.d, w.ext, B, w.tmp, s, w.z);
   if (st != CROSS_OK) return st;
   {
     ProfScope ps(ctx, "inner_product", s);
-    HIPCHK(launch_inner_product(w.ext, key, w.acc, c->mods, c->L + c->K, c->dnum, c->ndig, c->log_n, B, s),
+    HIPCHK(launch_inner_product(w.ext, key, w.acc, c->mods, c->L + c->K, c->dnum, c->ndig, c->log_n, B, s, w.d,
+                                c->L, c->alpha),
            "inner product");
   }
   return moddown_core(ctx, c, w.acc, 2 * B, w.z, base, base_only_even, out, w.tmp, s);

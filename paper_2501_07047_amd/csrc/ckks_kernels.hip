@@ -75,9 +75,11 @@ tensor_kernel(const v4u* a, const v4u* b, v4u* out, v4u* d2, const LimbMod* mods
 // vector is read once per kIpCts ciphertexts rather than once per ciphertext.
 constexpr int kIpCts = 4;
 
+// With d (NTT-form ModUp input [B][L][N]), digit j's own limbs t in [j alpha,
+// (j + 1) alpha) are read from d instead of ext (where they are not stored).
 __global__ void __launch_bounds__(256)
 inner_product_kernel(const v4u* ext, const v4u* key, v4u* acc, const LimbMod* mods, int LK,
-                     int dnum, int ndig, int log_n4, int B, uint64_t total4) {
+                     int dnum, int ndig, int log_n4, int B, uint64_t total4, const v4u* d, int L, int alpha) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total4) return;
   const uint64_t per_limb = 1ull << log_n4;
@@ -93,10 +95,12 @@ inner_product_kernel(const v4u* ext, const v4u* key, v4u* acc, const LimbMod* mo
   for (int j = 0; j < ndig; ++j) {
     const v4u k0 = key[((uint64_t)(j * 2 + 0) * LK + t) * per_limb + w];
     const v4u k1 = key[((uint64_t)(j * 2 + 1) * LK + t) * per_limb + w];
+    const bool own = d && t < L && t >= j * alpha && t < (j + 1) * alpha;
 #pragma unroll
     for (int c = 0; c < kIpCts; ++c) {
       if (c < nb) {
-        const v4u e = ext[(((uint64_t)(b0 + c) * dnum + j) * LK + t) * per_limb + w];
+        const v4u e = own ? d[((uint64_t)(b0 + c) * L + t) * per_limb + w]
+                          : ext[(((uint64_t)(b0 + c) * dnum + j) * LK + t) * per_limb + w];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           s0[c][k] = addmod(s0[c][k], mulmod(e[k], k0[k], md), md.q);
@@ -377,12 +381,12 @@ hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, ui
 
 hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32_t* acc,
                                 const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
-                                hipStream_t s) {
+                                hipStream_t s, const uint32_t* d, int L, int alpha) {
   const uint64_t groups = (uint64_t)(B + kIpCts - 1) / kIpCts;
   const uint64_t total4 = (groups * LK) << (log_n - 2);
   launch_kernel(inner_product_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
                      (const v4u*)ext, (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2, B,
-                     total4);
+                     total4, (const v4u*)d, L, alpha);
   return hipGetLastError();
 }
 

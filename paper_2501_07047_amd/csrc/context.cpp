@@ -292,7 +292,8 @@ cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out) {
 // row-major input (N^-1 folded in).
 static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
                               uint32_t* data, uint64_t stride, int npoly, bool inverse, uint32_t* tmp,
-                              hipStream_t s, const RowsTail* tail = nullptr) {
+                              hipStream_t s, const RowsTail* tail = nullptr, uint32_t* dst = nullptr) {
+  if (!dst) dst = data;
   const int log_n = plans[0]->log_n, log_r = plans[0]->log_r, log_c1 = plans[0]->log_c1;
   const int log_c2 = log_n - log_r - log_c1;
   const int red = ctx->ntt_reduction;
@@ -358,7 +359,7 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
     g.dst = tmp;
     g.out_packed = g.twiddle = true;
     if ((st = left()) != CROSS_OK) return st;
-    if (!tail) return rows(tmp, data);
+    if (!tail) return rows(tmp, dst);
     hipError_t e;
     {
       ProfScope ps(ctx, "ntt_rows", s);
@@ -369,7 +370,7 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
   }
   if ((st = rows(data, tmp)) != CROSS_OK) return st;
   g.src = tmp;
-  g.dst = data;
+  g.dst = dst;
   g.in_packed = g.in_rows = true;
   return left();
 }
@@ -392,8 +393,9 @@ cross_status ntt_limbs_tail(cross_ctx ctx, const std::vector<Plan*>& plans, cons
 
 cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
                        const std::vector<uint64_t>& offs, uint32_t* data, uint64_t stride,
-                       int npoly, bool inverse, uint32_t* tmp, hipStream_t s) {
+                       int npoly, bool inverse, uint32_t* tmp, hipStream_t s, uint32_t* dst) {
   if (plans.empty()) return CROSS_OK;
+  if (dst == data) dst = nullptr;
   const int log_n = plans[0]->log_n;
   const int log_r = plans[0]->log_r;
   if (log_n >= 8) {
@@ -407,13 +409,23 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
         (plans[i]->wide ? pw : pn).push_back(plans[i]);
         (plans[i]->wide ? ow : on).push_back(offs[i]);
       }
-      cross_status st = ntt_limbs(ctx, pn, on, data, stride, npoly, inverse, tmp, s);
-      return st != CROSS_OK ? st : ntt_limbs(ctx, pw, ow, data, stride, npoly, inverse, tmp, s);
+      cross_status st = ntt_limbs(ctx, pn, on, data, stride, npoly, inverse, tmp, s, dst);
+      return st != CROSS_OK ? st : ntt_limbs(ctx, pw, ow, data, stride, npoly, inverse, tmp, s, dst);
     }
   }
   if (log_n < 8 || ctx->ntt_engine == CROSS_NTT_ENGINE_BUTTERFLY) {
     // below the MFMA minimum (4R >= 64), or the butterfly engine selected: radix-2
-    // kernels, in place
+    // kernels, in place (out of place: the limbs are copied to dst first)
+    if (dst) {
+      void* doff = nullptr;
+      cross_status st = cached_device_copy(ctx, offs.data(), offs.size() * 8, &doff);
+      if (st != CROSS_OK) return st;
+      const hipError_t e = launch_limb_copy(data, stride, (const uint64_t*)doff, dst, stride, (const uint64_t*)doff,
+                                            (int)offs.size(), log_n, npoly, s);
+      if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("limb copy: ") + hipGetErrorString(e));
+      data = dst;
+      dst = nullptr;
+    }
     std::vector<ButterflyJob> jobs(plans.size());
     for (size_t i = 0; i < plans.size(); ++i)
       jobs[i] = ButterflyJob{inverse ? plans[i]->bf_inv : plans[i]->bf_fwd, offs[i], plans[i]->q,
@@ -429,7 +441,7 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
     if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("butterfly launch: ") + hipGetErrorString(e));
     return CROSS_OK;
   }
-  if (plans[0]->log_c1 > 0) return ntt_three(ctx, plans, offs, data, stride, npoly, inverse, tmp, s);
+  if (plans[0]->log_c1 > 0) return ntt_three(ctx, plans, offs, data, stride, npoly, inverse, tmp, s, nullptr, dst);
   const int red = ctx->ntt_reduction;
   if (red == 1)
     for (const Plan* p : plans) {
@@ -478,7 +490,7 @@ cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
   if (e != hipSuccess) return fail(ctx, CROSS_EDEVICE, std::string("step-1 launch: ") + hipGetErrorString(e));
   g.jobs = (const GemmJob*)d2;
   g.src = tmp;
-  g.dst = data;
+  g.dst = dst ? dst : data;
   g.kind = inverse ? kLeft : kRight;
   g.in_packed = true;
   g.out_packed = false;

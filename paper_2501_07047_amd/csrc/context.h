@@ -142,10 +142,12 @@ void pinned_release(cross_ctx ctx, int idx);
 
 // Run forward / inverse NTTs for a list of limbs, each given by (plan, element
 // offset) inside `data` with `npoly` polynomials at `stride` elements apart.
-// `tmp` must hold (max offset + npoly*stride) elements laid out like data.
+// `tmp` must hold (max offset + npoly*stride) elements laid out like data.  With
+// dst (laid out like data, overlapping neither data nor tmp) the result goes there
+// and data keeps its input (the butterfly path copies the limbs to dst first).
 cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,
                        const std::vector<uint64_t>& offs, uint32_t* data, uint64_t stride,
-                       int npoly, bool inverse, uint32_t* tmp, hipStream_t s);
+                       int npoly, bool inverse, uint32_t* tmp, hipStream_t s, uint32_t* dst = nullptr);
 // Whether the forward NTT of these limbs can end in the fused ModDown tail: the
 // MFMA engine with the Montgomery epilogue, narrow primes, and a three-factor split
 // whose row kernel has the fused form.

@@ -195,10 +195,11 @@ hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, ui
 
 // Key-switch inner product: acc[b][s][t] = sum_j ext[b][j][t] * key[j][s][t] mod p_t,
 // j < ndig (active digits), s in {0, 1}.  ext: [B][dnum][LK][N], key: [dnum][2][LK][N],
-// acc: [B][2][LK][N].
+// acc: [B][2][LK][N].  With d ([B][L][N]), digit j's own limbs t in [j alpha,
+// min((j + 1) alpha, L)) are read from d[b][t] instead of ext[b][j][t].
 hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32_t* acc,
                                 const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
-                                hipStream_t s);
+                                hipStream_t s, const uint32_t* d = nullptr, int L = 0, int alpha = 0);
 
 // Per-limb constants of the chunked stream forms (streams.hip).
 struct StreamMod {
