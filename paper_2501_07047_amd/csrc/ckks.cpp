@@ -292,8 +292,15 @@ cross_status ntt_list(cross_ctx ctx, const CkksPlan* c, const std::vector<int>& 
 // digits zero).  With x ([B][L][N] scratch), d is kept, its INTT goes to x, and ext
 // receives only the converted limbs (t outside digit j): the key-switch inner
 // product then reads a digit's own limbs from d.
+// With conv (x given), the converted limbs are left in coefficient form and their
+// (limb, offset) lists returned for a fused NTT + inner product.
+struct ConvLimbs {
+  std::vector<int> limb;
+  std::vector<uint64_t> off;
+};
+
 cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t* ext, int B,
-                        uint32_t* tmp, hipStream_t s, uint32_t* x = nullptr) {
+                        uint32_t* tmp, hipStream_t s, uint32_t* x = nullptr, ConvLimbs* conv = nullptr) {
   const int L = c->L, K = c->K, LK = L + K;
   const uint64_t N = 1ull << c->log_n;
   const uint64_t ext_stride = (uint64_t)c->dnum * LK * N;
@@ -331,6 +338,11 @@ cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t*
       nl.push_back(t);
       no.push_back(((uint64_t)j * LK + t) * N);
     }
+  }
+  if (conv) {
+    conv->limb = nl;
+    conv->off = no;
+    return CROSS_OK;
   }
   return ntt_list(ctx, c, nl, no, ext, ext_stride, B, false, tmp, s);
 }
@@ -460,6 +472,34 @@ bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
 cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* key, int B, KsWork& w,
                             uint32_t* out, const uint32_t* base, bool base_only_even, hipStream_t s) {
   // the coefficient form of d goes to w.z, free until the ModDown
+  const int LK = c->L + c->K;
+  const uint64_t N = 1ull << c->log_n, ext_stride = (uint64_t)c->dnum * LK * N;
+  std::vector<Plan*> all(c->plans.begin(), c->plans.begin() + LK);
+  if (ntt_tail_fusable(ctx, all)) {
+    // ModUp NTT and inner product fused: the row-side step of the converted limbs,
+    // then one row kernel that finishes each transform and accumulates its key products
+    ConvLimbs cv;
+    cross_status st = modup_core(ctx, c, w.d, w.ext, B, w.tmp, s, w.z, &cv);
+    if (st != CROSS_OK) return st;
+    std::vector<Plan*> cp(cv.limb.size());
+    for (size_t i = 0; i < cv.limb.size(); ++i) cp[i] = c->plans[cv.limb[i]];
+    if ((st = ntt_rowside_forward(ctx, cp, cv.off, w.ext, ext_stride, B, w.tmp, s)) != CROSS_OK) return st;
+    std::vector<IpLimb> lm(LK);
+    for (int t = 0; t < LK; ++t) {
+      const Plan* p = c->plans[t];
+      const LimbMod m = limb_mod(p->q);
+      lm[t] = IpLimb{p->row_fwd_b, p->row_fwd_t3, p->q, p->qinv, m.bar_m, m.bar_k, t < c->L ? t / c->alpha : -1, 0};
+    }
+    void* dl = nullptr;
+    if ((st = cached_device_copy(ctx, lm.data(), lm.size() * sizeof(IpLimb), &dl)) != CROSS_OK) return st;
+    const RowsIp rp{(const IpLimb*)dl, w.tmp, w.d, key, w.acc, ext_stride, LK, c->L, B, c->ndig,
+                    all[0]->log_r - 3};
+    {
+      ProfScope ps(ctx, "ntt_rows_ip", s);
+      HIPCHK(launch_ntt_rows_ip(rp, s), "fused ModUp NTT and inner product");
+    }
+    return moddown_core(ctx, c, w.acc, 2 * B, w.z, base, base_only_even, out, w.tmp, s);
+  }
   cross_status st = modup_core(ctx, c, w.d, w.ext, B, w.tmp, s, w.z);
   if (st != CROSS_OK) return st;
   {

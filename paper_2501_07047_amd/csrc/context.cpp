@@ -292,7 +292,8 @@ cross_status workspace(cross_ctx ctx, hipStream_t s, size_t bytes, void** out) {
 // row-major input (N^-1 folded in).
 static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
                               uint32_t* data, uint64_t stride, int npoly, bool inverse, uint32_t* tmp,
-                              hipStream_t s, const RowsTail* tail = nullptr, uint32_t* dst = nullptr) {
+                              hipStream_t s, const RowsTail* tail = nullptr, uint32_t* dst = nullptr,
+                              bool left_only = false) {
   if (!dst) dst = data;
   const int log_n = plans[0]->log_n, log_r = plans[0]->log_r, log_c1 = plans[0]->log_c1;
   const int log_c2 = log_n - log_r - log_c1;
@@ -359,6 +360,7 @@ static cross_status ntt_three(cross_ctx ctx, const std::vector<Plan*>& plans, co
     g.dst = tmp;
     g.out_packed = g.twiddle = true;
     if ((st = left()) != CROSS_OK) return st;
+    if (left_only) return CROSS_OK;
     if (!tail) return rows(tmp, dst);
     hipError_t e;
     {
@@ -389,6 +391,12 @@ cross_status ntt_limbs_tail(cross_ctx ctx, const std::vector<Plan*>& plans, cons
                             hipStream_t s) {
   if (!ntt_tail_fusable(ctx, plans)) return fail(ctx, CROSS_EUNSUPPORTED, "no fused tail for this NTT form");
   return ntt_three(ctx, plans, offs, data, stride, npoly, false, tmp, s, &tail);
+}
+
+cross_status ntt_rowside_forward(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+                                 uint32_t* data, uint64_t stride, int npoly, uint32_t* tmp, hipStream_t s) {
+  if (!ntt_tail_fusable(ctx, plans)) return fail(ctx, CROSS_EUNSUPPORTED, "no fused row kernel for this NTT form");
+  return ntt_three(ctx, plans, offs, data, stride, npoly, false, tmp, s, nullptr, nullptr, true);
 }
 
 cross_status ntt_limbs(cross_ctx ctx, const std::vector<Plan*>& plans,

@@ -158,5 +158,10 @@ bool ntt_tail_fusable(cross_ctx ctx, const std::vector<Plan*>& plans);
 cross_status ntt_limbs_tail(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
                             uint32_t* data, uint64_t stride, int npoly, uint32_t* tmp, const RowsTail& tail,
                             hipStream_t s);
+// Only the first launch of the forward three-factor NTT of these limbs: the row-side
+// step data -> tmp (packed, step-2 twiddle applied), for a fused row kernel to finish;
+// CROSS_EUNSUPPORTED when !ntt_tail_fusable.
+cross_status ntt_rowside_forward(cross_ctx ctx, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
+                                 uint32_t* data, uint64_t stride, int npoly, uint32_t* tmp, hipStream_t s);
 
 }  // namespace cross

@@ -254,6 +254,31 @@ hipError_t launch_ntt_rows_tail(const RowsJob* jobs, int njobs, const uint32_t* 
 // Whether the fused form exists for this split (the persistent 32 x 32 row kernel).
 bool rows_tail_supported(int log_n, int log_r, int log_c1);
 
+// ModUp NTT fused with the key-switch inner product (three factors R x 32 x 32): for
+// every ciphertext b < B and limb t < LK,
+//   acc[b][s][t] = sum_{j < ndig} E_j[b][t] * key[j][s][t] mod p_t,
+// where E_j[b][t] = d[b][t] for t in digit j (limbs[t].own == j) and otherwise the
+// forward row transform of tmp + b * ext_stride + (j * LK + t) * N (the packed row-side
+// step output of the converted limb, ext layout).  d: [B][L][N]; key: [dnum][2][LK][N];
+// acc: [B][2][LK][N]; N = 2^(rb_log + 13).
+struct IpLimb {
+  const int8_t* tab;        // forward 32-point sub-step table of t's prime (fragment order)
+  const uint32_t* tw1;      // its first-epilogue twiddle pairs
+  uint32_t q, qinv;         // prime, q^-1 mod 2^32
+  uint32_t bar_m, bar_k;    // Barrett constants of the key products
+  int32_t own, pad;         // digit holding t (-1 for special primes)
+};
+struct RowsIp {
+  const IpLimb* limbs;
+  const uint32_t* tmp;
+  const uint32_t* d;
+  const uint32_t* key;
+  uint32_t* acc;
+  uint64_t ext_stride;
+  int LK, L, B, ndig, rb_log;
+};
+hipError_t launch_ntt_rows_ip(const RowsIp& p, hipStream_t s);
+
 // NTT-domain automorphism: out[p][l][x] = in[p][l][perm[x]] for L limbs of npoly polynomials.
 hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t* out,
                                uint64_t out_stride, const uint32_t* perm, int log_n, int L,

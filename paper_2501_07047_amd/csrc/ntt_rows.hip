@@ -563,8 +563,18 @@ struct P32Tab {
   __device__ __forceinline__ v4i get(int ks, int mb) const { return f[((ks >> 1) * 4 + mb) * 2 + (ks & 1)]; }
 };
 
+// The same fragments read from the LDS copy at each product (frees the 64 registers).
+struct P32LdsTab {
+  const int8_t* lds;
+  int lane;
+  __device__ __forceinline__ v4i get(int ks, int mb) const {
+    return *reinterpret_cast<const v4i*>(lds + (((ks >> 1) * 4 + mb) * 2 + (ks & 1)) * 1024 + lane * 16);
+  }
+};
+
 // One 32-row block mb of a sub-step: the four K steps of the wave's 32 columns.
-__device__ __forceinline__ v16i p32_block_mb(const P32Tab& tab, const v4i (&b)[4], int mb) {
+template <class TAB>
+__device__ __forceinline__ v16i p32_block_mb(const TAB& tab, const v4i (&b)[4], int mb) {
   v16i acc = v16i{};
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(tab.get(ks, mb), b[ks], acc, 0, 0, 0);
@@ -650,15 +660,69 @@ __device__ __forceinline__ void p32_range(int nblocks, int& b0, int& b1) {
   b1 = lo + (int)((int64_t)(hi - lo) * (local + 1) / per_xcd);
 }
 
-// Forward: sub-step 1 (TB over c1, columns (row, c2)) reads the chunk-packed row-side
-// output, applies T3 and packs Z lines [m][c2]; sub-step 2 (TC over c2, columns (row,
-// m)) finishes the row in natural residues.
+// Forward transform of one row (the wave's): sub-step 1 (TB over c1, columns (row, c2))
+// reads the chunk-packed row-side output at `in`, applies T3 and packs Z lines [m][c2];
+// sub-step 2 (TC over c2, columns (row, m)) finishes the row in natural residues, staged
+// in the wave's LDS slice (element e at zw[(e >> 5) * kP32Xp + (e & 31)]).
+template <class TAB>
+__device__ __forceinline__ void p32_fwd_row(const uint32_t* in, const TAB& tab, const uint32_t* tws, uint32_t* zw,
+                                            uint32_t q, uint32_t qinv, int lane) {
+  const int h = lane >> 5, c2 = lane & 31;
+  // operands: chunk-packed words of c1 = 8 ks + 4 h + i at column c2
+  v4i cur[4];
+  {
+    const __amdgpu_buffer_rsrc_t r = rows_rsrc(in, 1024 * 4);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const uint32_t o = (uint32_t)((8 * ks + 4 * h) * 32 + c2) * 4;
+      cur[ks] = v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0),
+                    (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 128, 0),
+                    (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 256, 0),
+                    (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 384, 0)};
+    }
+  }
+  // sub-step 1: out m = mb * 8 + 2 j + h at column c2, T3 twiddle, packed into Z
+  {
+    const uint32_t* twl = &tws[(h * 32 + c2) * 2];
+    uint32_t* zl = &zw[h * kP32Zp + c2];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const v16i acc = p32_block_mb(tab, cur, mb);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int m0 = mb * 8 + 2 * jj;
+        const v2u w = *reinterpret_cast<const v2u*>(&twl[m0 * 64]);
+        zl[m0 * kP32Zp] = pack7(shoup_tw(merge_redc(acc, jj, q, qinv), w, q));
+      }
+    }
+  }
+  wave_lds_sync();
+  // sub-step 2: column m = lane % 32 reads its Z line (16 contiguous bytes per K step)
+  v4i zb[4];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) zb[ks] = *reinterpret_cast<const v4i*>(&zw[c2 * kP32Zp + 8 * ks + 4 * h]);
+  wave_lds_sync();
+  {
+    uint32_t* xl = &zw[c2 * kP32Xp + h];          // output c2' = mb * 8 + 2 j + h of line m = c2
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+      const v16i acc = p32_block_mb(tab, zb, mb);
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const uint32_t r = merge_redc(acc, jj, q, qinv);
+        xl[mb * 8 + 2 * jj] = r >= q ? r - q : r;
+      }
+    }
+  }
+  wave_lds_sync();
+}
+
 template <class SRC>
 __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_fwd_kernel(SRC src, int nblocks) {
   __shared__ __attribute__((aligned(16))) int8_t tabs[16 * 32 * 32];
   __shared__ __attribute__((aligned(16))) uint32_t tws[2 * 1024];
   __shared__ __attribute__((aligned(16))) uint32_t zs[kP32Waves * kP32SliceWords];
-  const int lane = threadIdx.x & 63, h = lane >> 5, c2 = lane & 31;
+  const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int b0, b1;
   p32_range(nblocks, b0, b1);
@@ -669,59 +733,109 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_fwd_kernel(SRC s
   for (int b = b0; b < b1; ++b) {
     const RowLoc L = src.locate(b, wave);
     p32_stage(L, cur_tab, tabs, tws, tab, lane);
-    const uint32_t q = L.q, qinv = L.qinv;
-    // operands: chunk-packed words of c1 = 8 ks + 4 h + i at column c2
-    v4i cur[4];
-    {
-      const __amdgpu_buffer_rsrc_t r = rows_rsrc(L.in, 1024 * 4);
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const uint32_t o = (uint32_t)((8 * ks + 4 * h) * 32 + c2) * 4;
-        cur[ks] = v4i{(int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0),
-                      (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 128, 0),
-                      (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 256, 0),
-                      (int)__builtin_amdgcn_raw_buffer_load_b32(r, o, 384, 0)};
-      }
-    }
-    // sub-step 1: out m = mb * 8 + 2 j + h at column c2, T3 twiddle, packed into Z
-    {
-      const uint32_t* twl = &tws[(h * 32 + c2) * 2];
-      uint32_t* zl = &zw[h * kP32Zp + c2];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const v16i acc = p32_block_mb(tab, cur, mb);
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const int m0 = mb * 8 + 2 * jj;
-          const v2u w = *reinterpret_cast<const v2u*>(&twl[m0 * 64]);
-          zl[m0 * kP32Zp] = pack7(shoup_tw(merge_redc(acc, jj, q, qinv), w, q));
-        }
-      }
-    }
-    wave_lds_sync();
-    // sub-step 2: column m = lane % 32 reads its Z line (16 contiguous bytes per K step)
-    v4i zb[4];
-#pragma unroll
-    for (int ks = 0; ks < 4; ++ks) zb[ks] = *reinterpret_cast<const v4i*>(&zw[c2 * kP32Zp + 8 * ks + 4 * h]);
-    wave_lds_sync();
-    {
-      uint32_t* xl = &zw[c2 * kP32Xp + h];          // output c2' = mb * 8 + 2 j + h of line m = c2
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        const v16i acc = p32_block_mb(tab, zb, mb);
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const uint32_t r = merge_redc(acc, jj, q, qinv);
-          xl[mb * 8 + 2 * jj] = r >= q ? r - q : r;
-        }
-      }
-    }
-    wave_lds_sync();
+    p32_fwd_row(L.in, tab, tws, zw, L.q, L.qinv, lane);
     if constexpr (SRC::kTail)
-      src.write_tail(b, wave, zw, q, lane);
+      src.write_tail(b, wave, zw, L.q, lane);
     else
       p32_write_row(zw, L.out, lane);
     wave_lds_sync();       // staging reads done before the next block's Z writes
+  }
+}
+
+// Barrett product of two runtime residues (Alg. barrett): k = bit length of q,
+// m = floor(2^(2k) / q); the quotient estimate ((z >> (k - 1)) m) >> (k + 1) is short
+// by at most 2, so two conditional subtractions finish.
+__device__ __forceinline__ uint32_t ip_mulmod(uint32_t a, uint32_t b, const IpLimb& md) {
+  const uint64_t z = (uint64_t)a * b;
+  const uint32_t zh = (uint32_t)(z >> (md.bar_k - 1));
+  const uint32_t t = (uint32_t)(((uint64_t)zh * md.bar_m) >> (md.bar_k + 1));
+  uint32_t r = (uint32_t)z - t * md.q;
+  if (r >= md.q) r -= md.q;
+  if (r >= md.q) r -= md.q;
+  return r;
+}
+
+// ModUp NTT fused with the key-switch inner product: block b is (target limb t, row
+// block, ciphertext), the ciphertext fastest, so the eight rows of key a row block reads
+// are shared by every ciphertext within one XCD.  Per block, each wave takes one row
+// and, for every active digit j, either transforms row (j, t) of the packed row-side
+// output (t outside digit j) or reads row t of the NTT-form input (t in digit j), and
+// accumulates its products with the two key rows of (j, t) in registers; the two
+// accumulator rows are written once.  Every transform of a block uses t's prime, so
+// the row tables are staged once per run of blocks with the same t.
+__global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(RowsIp p, int nblocks) {
+  __shared__ __attribute__((aligned(16))) int8_t tabs[16 * 32 * 32];
+  __shared__ __attribute__((aligned(16))) uint32_t tws[2 * 1024];
+  __shared__ __attribute__((aligned(16))) uint32_t zs[kP32Waves * kP32SliceWords];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int b0, b1;
+  p32_range(nblocks, b0, b1);
+  uint32_t* zw = zs + wave * kP32SliceWords;
+  const P32LdsTab tab{tabs, lane};
+  const int8_t* cur_tab = nullptr;
+  const uint64_t N = 1024ull << p.rb_log << 3;
+  const int per_t = p.B << p.rb_log;
+  for (int b = b0; b < b1; ++b) {
+    const int t = __builtin_amdgcn_readfirstlane(b / per_t);
+    const int rem = b - t * per_t;
+    const int rb = __builtin_amdgcn_readfirstlane(rem / p.B);
+    const int ct = rem - rb * p.B, row = rb * kP32Waves + wave;
+    const IpLimb md = p.limbs[t];
+    if (md.tab != cur_tab) {
+      // t's table and first twiddles into LDS (workgroup-uniform: a block has one t)
+      __syncthreads();
+      stage<64 * kP32Waves>(tabs, md.tab, 16 * 32 * 32);
+      stage<64 * kP32Waves>(tws, md.tw1, 8 * 1024);
+      __syncthreads();
+      cur_tab = md.tab;
+    }
+    const uint64_t roff = (uint64_t)t * N + (uint64_t)row * 1024;
+    v4u s0[4], s1[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) s0[it] = s1[it] = v4u{0, 0, 0, 0};
+    for (int j = 0; j < p.ndig; ++j) {
+      v4u v[4];
+      if (j == md.own) {
+        const __amdgpu_buffer_rsrc_t rd = rows_rsrc(p.d + (uint64_t)ct * p.L * N + roff, 1024 * 4);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) v[it] = __builtin_amdgcn_raw_buffer_load_b128(rd, (lane + it * 64) * 16, 0, 0);
+      } else {
+        p32_fwd_row(p.tmp + (uint64_t)ct * p.ext_stride + (uint64_t)j * p.LK * N + roff, tab, tws, zw, md.q, md.qinv,
+                    lane);
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+          const int e = (lane + it * 64) * 4;
+          const uint32_t* y = &zw[(e >> 5) * kP32Xp + (e & 31)];
+          v[it] = v4u{y[0], y[1], y[2], y[3]};
+        }
+        wave_lds_sync();   // staging reads done before the next transform's Z writes
+      }
+      const uint32_t* k0 = p.key + (uint64_t)(j * 2) * p.LK * N + roff;
+      const __amdgpu_buffer_rsrc_t rk0 = rows_rsrc(k0, 1024 * 4);
+      const __amdgpu_buffer_rsrc_t rk1 = rows_rsrc(k0 + (uint64_t)p.LK * N, 1024 * 4);
+#pragma unroll
+      for (int it = 0; it < 4; ++it) {
+        const uint32_t e = (uint32_t)(lane + it * 64) * 16;
+        const v4u a0 = __builtin_amdgcn_raw_buffer_load_b128(rk0, e, 0, 0);
+        const v4u a1 = __builtin_amdgcn_raw_buffer_load_b128(rk1, e, 0, 0);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          uint32_t x = s0[it][k] + ip_mulmod(v[it][k], a0[k], md);
+          s0[it][k] = x >= md.q ? x - md.q : x;
+          x = s1[it][k] + ip_mulmod(v[it][k], a1[k], md);
+          s1[it][k] = x >= md.q ? x - md.q : x;
+        }
+      }
+    }
+    uint32_t* o0 = p.acc + (uint64_t)ct * 2 * p.LK * N + roff;
+    const __amdgpu_buffer_rsrc_t ro0 = rows_rsrc(o0, 1024 * 4);
+    const __amdgpu_buffer_rsrc_t ro1 = rows_rsrc(o0 + (uint64_t)p.LK * N, 1024 * 4);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      __builtin_amdgcn_raw_buffer_store_b128(s0[it], ro0, (lane + it * 64) * 16, 0, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(s1[it], ro1, (lane + it * 64) * 16, 0, 0);
+    }
   }
 }
 
@@ -869,6 +983,15 @@ hipError_t launch_ntt_rows_tail(const RowsJob* jobs, int njobs, const uint32_t* 
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
   launch_kernel((ntt_rows32_fwd_kernel<P32UniformTail>), dim3(p32_grid(nblocks)), dim3(64 * kP32Waves), 0, s, src,
                 (int)nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_rows_ip(const RowsIp& p, hipStream_t s) {
+  if (p.B <= 0 || p.LK <= 0 || p.ndig <= 0) return hipSuccess;
+  if (p.rb_log < 0 || !p.limbs || !p.tmp || !p.d || !p.key || !p.acc) return hipErrorInvalidValue;
+  const int64_t nblocks = (int64_t)p.LK * p.B << p.rb_log;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  launch_kernel(ntt_rows32_ip_kernel, dim3(p32_grid(nblocks)), dim3(64 * kP32Waves), 0, s, p, (int)nblocks);
   return hipGetLastError();
 }
 

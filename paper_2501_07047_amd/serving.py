@@ -138,7 +138,13 @@ def summarize(reqs, makespan, peak, iterations):
 
 
 class GpuExecutor:
-    """Runs each admitted group as one libcross batch on the slot's stream."""
+    """Runs each admitted group as one libcross batch on the slot's stream.
+
+    A group's batch is planned, uploaded and enqueued while earlier groups run, but its
+    kernels start only after the previous group's have finished (its stream waits on
+    that group's completion event): groups whose batches executed at the same time on
+    two streams gave wrong results for some requests (seen in the full-scale
+    request-loop test), so execution on the device is kept in admission order."""
 
     def __init__(self, slots, use_graph=False):
         import torch
@@ -149,6 +155,7 @@ class GpuExecutor:
         self.use_graph = use_graph
         self.groups = 0
         self.host_s = 0.0
+        self.last_ev = None
 
     def prepare(self, requests):
         """Build the tables of every request shape (NTT plans of each prime and size, CKKS
@@ -210,9 +217,12 @@ class GpuExecutor:
             off = (-ws.data_ptr()) % 256 // 4
             ws = ws[off:]
             batch = self.B.Batch(jobs, use_graph=self.use_graph, workspace=ws, stream=s.cuda_stream)
+            if self.last_ev is not None:
+                s.wait_event(self.last_ev)
             batch.run(s.cuda_stream)
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
+            self.last_ev = ev
         self.groups += 1
         self.host_s += time.perf_counter() - t_host
         return (ev, batch, ws)

@@ -156,3 +156,24 @@ def test_he_mult_on_butterfly_engine(log_n, L, K, batch):
         B.set_ntt_engine("mfma")
     for k in range(batch):
         assert np.array_equal(got[k], CK.he_mult(a[k], b[k], key, qs, ps, 3)), "ciphertext %d" % k
+
+
+def test_modup_moddown_n2_16_L24():
+    """The public ModUp and ModDown entry points at N = 2^16, L = 24, dnum = 3, K = 8, two
+    polynomials (ModDown takes the fused-tail row kernel at this size)."""
+    from paper_2501_07047_amd import binding as B
+    qs, ps, a, _, _ = synthetic.ckks_pair(21, 16, 24, 3, 8, 1)
+    d = a[0]                                     # two polynomials [2][L][N]
+    d = _with_edges(d[None], qs)[0]
+    ext = _empty((2, 3, 32, 1 << 16))
+    B.keyswitch_modup(to_dev(d), ext, qs, ps, 3)
+    got = to_host(ext)
+    refs = [CK.modup(d[p], qs, ps, 3) for p in range(2)]
+    for p in range(2):
+        assert np.array_equal(got[p], refs[p]), "ModUp of polynomial %d" % p
+    src = np.stack([refs[p][1] for p in range(2)])          # digit 1 extensions [2][L+K][N]
+    out = _empty((2, 24, 1 << 16))
+    B.keyswitch_moddown(to_dev(src), out, qs, ps, 3)
+    got = to_host(out)
+    for p in range(2):
+        assert np.array_equal(got[p], CK.moddown(src[p], qs, ps)), "ModDown of polynomial %d" % p
