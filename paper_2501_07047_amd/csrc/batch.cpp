@@ -70,6 +70,12 @@ struct cross_batch_s {
   std::vector<cross::BconvLaunch> bconv_up, bconv_down;
   std::vector<cross::InnerTask> inners;
   std::vector<cross::TailTask> tails;
+  // N >= 2^14 (R x 32 x 32): ModUp NTT + inner product and ModDown NTT + tail fused
+  std::vector<cross::IpTask> ips;
+  std::vector<cross::RowsTailTask> rtails;
+  int64_t ip_blocks = 0, rtail_blocks = 0;
+  const cross::IpTask* d_ips = nullptr;
+  const cross::RowsTailTask* d_rtails = nullptr;
   const cross::AutoTask* d_autos = nullptr;
   const cross::TensorTask* d_tensors = nullptr;
   const cross::CopyTask* d_copies = nullptr;
@@ -152,7 +158,8 @@ uint64_t task_list_bytes(cross_batch b) {
       n += list_bytes(hf.rows.tasks);
     }
   n += list_bytes(b->autos) + list_bytes(b->tensors) + list_bytes(b->copies) + list_bytes(b->bconv_up) +
-       list_bytes(b->bconv_down) + list_bytes(b->inners) + list_bytes(b->tails);
+       list_bytes(b->bconv_down) + list_bytes(b->inners) + list_bytes(b->tails) + list_bytes(b->ips) +
+       list_bytes(b->rtails);
   return n;
 }
 
@@ -189,8 +196,12 @@ void add_gemm_task(cross_ctx ctx, NttHalf& hf, const GemmTask& t, int U, int V, 
 // row-kernel task: forward = row-side step (data -> tmp, packed, step-2 twiddle)
 // then rows (tmp -> data); inverse = rows (data -> tmp, packed rows, inverse
 // step-2 twiddle) then the row-side step on row-major packed input (tmp -> data).
+// dst (three factors, inverse): the result goes there instead of back into data.
+// first_half_only (three factors, forward): only the row-side step (data -> tmp), for
+// a fused row kernel to finish.
 void add_ntt(cross_batch b, NttPhase& ph, const std::vector<Plan*>& plans, const std::vector<uint64_t>& offs,
-             uint32_t* data, uint32_t* tmp, uint64_t stride, int npoly, bool inverse) {
+             uint32_t* data, uint32_t* tmp, uint64_t stride, int npoly, bool inverse, uint32_t* dst = nullptr,
+             bool first_half_only = false) {
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];
     const int log_r = p->log_r, log_c = p->log_n - p->log_r;
@@ -216,6 +227,7 @@ void add_ntt(cross_batch b, NttPhase& ph, const std::vector<Plan*>& plans, const
         t.src = data + offs[i];
         t.dst = tmp + offs[i];
         add_gemm_task(b->ctx, ph.half[0], t, R, C, npoly, false, false, p->log_n);
+        if (first_half_only) continue;
         r.tab = p->row_fwd_b;
         r.tw1 = p->row_fwd_t3;
         r.in = tmp + offs[i];
@@ -228,7 +240,7 @@ void add_ntt(cross_batch b, NttPhase& ph, const std::vector<Plan*>& plans, const
         r.out = tmp + offs[i];
         t.table = p->inv_left;
         t.src = tmp + offs[i];
-        t.dst = data + offs[i];
+        t.dst = (dst ? dst : data) + offs[i];
         add_gemm_task(b->ctx, ph.half[1], t, R, C, npoly, true, true, p->log_n);
       }
       RowsPhase& rp = ph.half[inverse ? 0 : 1].rows;
@@ -304,10 +316,14 @@ hipError_t run_phases(cross_batch b, hipStream_t s, bool prof) {
   ntt(kNttInvD, true);
   vec("bconv", [&] { return launch_bconv_list(b->d_bconv_up, (int)b->bconv_up.size(), b->max_waves_up, s); });
   ntt(kNttFwdExt, false);
+  vec("ntt_rows_ip", [&] { return launch_ntt_rows_ip_list(b->d_ips, (int)b->ips.size(), b->ip_blocks, s); });
   vec("inner_product", [&] { return launch_inner_list(b->d_inners, (int)b->inners.size(), b->max_inner, s); });
   ntt(kNttInvP, true);
   vec("bconv", [&] { return launch_bconv_list(b->d_bconv_down, (int)b->bconv_down.size(), b->max_waves_down, s); });
   ntt(kNttFwdZ, false);
+  vec("ntt_rows", [&] {
+    return launch_ntt_rows_tail_list(b->d_rtails, (int)b->rtails.size(), b->rtail_blocks, s);
+  });
   vec("moddown_tail", [&] { return launch_tail_list(b->d_tails, (int)b->tails.size(), b->max_tail, s); });
   return e;
 }
@@ -447,6 +463,9 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       cross_status st = perm_table(ctx, c->log_n, powmod(5, r, (uint32_t)(2 * N)), &perm);
       if (st != CROSS_OK) return st;
     }
+    // from 2^14 up (R x 32 x 32) the inner product runs in the ModUp NTT's row kernel and
+    // the tail in the ModDown NTT's: no digit copies, no extension limbs stored
+    const bool fuse = c->log_n >= 14;
     for (int bb = 0; bb < B; ++bb) {
       const uint32_t* a = J.ct_a + bb * ct;
       uint32_t* o = J.out + bb * ct;
@@ -459,6 +478,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
         b->autos.push_back(AutoTask{a + nd, db, perm, c->log_n, nd});      // sigma(c1) -> d
         b->max_auto = std::max(b->max_auto, nd);
       }
+      if (fuse) continue;
       // ModUp: digit limbs copied unchanged, inactive digits zeroed
       uint32_t* eb = ext + bb * next;
       for (int dj = 0; dj < c->dnum; ++dj) {
@@ -487,13 +507,14 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     std::vector<Plan*> qp(bp.begin(), bp.begin() + L);
     std::vector<uint64_t> qo(L);
     for (int i = 0; i < L; ++i) qo[i] = i * N;
-    add_ntt(b.get(), b->ntt[kNttInvD], qp, qo, d, tmp, nd, B, true);
+    // (fused: out of place into z, free until the ModDown, so d keeps its NTT form)
+    add_ntt(b.get(), b->ntt[kNttInvD], qp, qo, d, tmp, nd, B, true, fuse ? z : nullptr);
     // BConv of each digit, NTT of every converted limb
     std::vector<Plan*> ep;
     std::vector<uint64_t> eo;
     for (int dj = 0; dj < c->ndig; ++dj) {
       const BconvStatic& bs = c->modup[dj];
-      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, d, ext, nd, next, B, c->log_n};
+      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, fuse ? z : d, ext, nd, next, B, c->log_n};
       b->bconv_up.push_back(g);
       b->max_waves_up = std::max(b->max_waves_up, ((uint64_t)B << c->log_n) / 32);
       for (int t : c->targets[dj]) {
@@ -501,7 +522,27 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
         eo.push_back(((uint64_t)dj * LK + t) * N);
       }
     }
-    add_ntt(b.get(), b->ntt[kNttFwdExt], ep, eo, ext, tmp, next, B, false);
+    add_ntt(b.get(), b->ntt[kNttFwdExt], ep, eo, ext, tmp, next, B, false, nullptr, fuse);
+    const int log_r = bp[0]->log_r;
+    if (fuse) {
+      std::vector<IpLimb> lm(LK);
+      for (int t = 0; t < LK; ++t) {
+        // Barrett constants of the key products: k = bit length of q, m = floor(2^(2k) / q)
+        const uint32_t q = bp[t]->q;
+        uint32_t k = 0;
+        while ((1ull << k) <= q) ++k;
+        const uint32_t m = (uint32_t)(((unsigned __int128)1 << (2 * k)) / q);
+        lm[t] = IpLimb{bp[t]->row_fwd_b, bp[t]->row_fwd_t3, q, bp[t]->qinv, m, k, t < L ? t / c->alpha : -1, 0};
+      }
+      void* dl = nullptr;
+      cross_status st = cached_device_copy(ctx, lm.data(), lm.size() * sizeof(IpLimb), &dl);
+      if (st != CROSS_OK) return st;
+      IpTask it{};
+      it.p = RowsIp{(const IpLimb*)dl, tmp, d, J.key, acc, next, LK, L, B, c->ndig, log_r - 3};
+      it.first_block = (int32_t)b->ip_blocks;
+      b->ip_blocks += (int64_t)LK * B << (log_r - 3);
+      b->ips.push_back(it);
+    }
     // ModDown of both accumulators: INTT of P limbs, BConv P -> Q, NTT of Q limbs
     std::vector<Plan*> pp(bp.begin() + L, bp.end());
     std::vector<uint64_t> po(K);
@@ -513,7 +554,41 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       b->bconv_down.push_back(g);
       b->max_waves_down = std::max(b->max_waves_down, ((uint64_t)(2 * B) << c->log_n) / 32);
     }
-    add_ntt(b.get(), b->ntt[kNttFwdZ], qp, qo, z, tmp, nd, 2 * B, false);
+    add_ntt(b.get(), b->ntt[kNttFwdZ], qp, qo, z, tmp, nd, 2 * B, false, nullptr, fuse);
+    if (fuse) {
+      uint64_t pmod[64];
+      for (int i = 0; i < L; ++i) {
+        const uint32_t q = c->primes[i];
+        uint64_t pm = 1;
+        for (int k = 0; k < K; ++k) pm = pm * (c->primes[L + k] % q) % q;
+        pmod[i] = pm;
+      }
+      for (int i = 0; i < L; ++i) {
+        const Plan* p = bp[i];
+        const uint32_t q = p->q;
+        const uint32_t pinv = powmod(pmod[i], q - 2, q);
+        RowsTailTask rt{};
+        rt.r.tab = p->row_fwd_b;
+        rt.r.tw1 = p->row_fwd_t3;
+        rt.r.in = tmp + qo[i];
+        rt.r.stride = nd;
+        rt.r.q = q;
+        rt.r.qinv = p->qinv;
+        rt.r.npoly = 2 * B;
+        rt.r.log_r = log_r;
+        rt.r.first_block = (int32_t)b->rtail_blocks;
+        rt.acc = acc + qo[i];
+        rt.acc_stride = (uint64_t)LK * N;
+        rt.base = J.out + qo[i];
+        rt.out = J.out + qo[i];
+        rt.out_stride = nd;
+        rt.pinv = pinv;
+        rt.pinv_shoup = (uint32_t)(((uint64_t)pinv << 32) / q);
+        rt.base_only_even = he ? 0 : 1;
+        b->rtail_blocks += (int64_t)(2 * B) << (log_r - 3);
+        b->rtails.push_back(rt);
+      }
+    }
   }
 
   // ---- pass 3: device task lists ---------------------------------------------------
@@ -546,6 +621,8 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
   if (st == CROSS_OK) st = upload(b.get(), b->bconv_down, &b->d_bconv_down);
   if (st == CROSS_OK) st = upload(b.get(), b->inners, &b->d_inners);
   if (st == CROSS_OK) st = upload(b.get(), b->tails, &b->d_tails);
+  if (st == CROSS_OK) st = upload(b.get(), b->ips, &b->d_ips);
+  if (st == CROSS_OK) st = upload(b.get(), b->rtails, &b->d_rtails);
   if (st == CROSS_OK && b->external) st = finish_upload(b.get());
   if (st != CROSS_OK) return st;
 
@@ -634,7 +711,7 @@ cross_status cross_batch_info(cross_batch b, uint32_t* launches, uint64_t* works
       n += hf.rows.tasks.empty() ? 0 : 1;
     }
   n += !b->autos.empty() + !b->tensors.empty() + !b->copies.empty() + !b->bconv_up.empty() +
-       !b->bconv_down.empty() + !b->inners.empty() + !b->tails.empty();
+       !b->bconv_down.empty() + !b->inners.empty() + !b->tails.empty() + !b->ips.empty() + !b->rtails.empty();
   if (launches) *launches = n;
   if (workspace_bytes) *workspace_bytes = b->ws_bytes;
   if (gemm_tiles) *gemm_tiles = tiles;

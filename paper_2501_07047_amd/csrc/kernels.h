@@ -278,6 +278,28 @@ struct RowsIp {
   int LK, L, B, ndig, rb_log;
 };
 hipError_t launch_ntt_rows_ip(const RowsIp& p, hipStream_t s);
+// Task-list form (batch runtime): task k covers blocks [first_block, next task's
+// first_block), LK * B * R / 8 of them, in first_block order; nblocks is the total.
+struct IpTask {
+  RowsIp p;
+  int32_t first_block, pad;
+};
+hipError_t launch_ntt_rows_ip_list(const IpTask* tasks, int ntasks, int64_t nblocks, hipStream_t s);
+// Task-list form of the forward row kernel with the fused tail (batch runtime): each
+// task one limb (r, in = its packed row-side output, npoly polynomials) and its tail:
+// out[p * out_stride + r * 1024 ..] = base[same] + (acc[p * acc_stride + r * 1024 ..] - y) * Pinv,
+// base null (0) or, with base_only_even, added for even p only.
+struct RowsTailTask {
+  RowsTask r;
+  const uint32_t* acc;
+  uint64_t acc_stride;
+  const uint32_t* base;
+  uint32_t* out;
+  uint64_t out_stride;
+  uint32_t pinv, pinv_shoup;
+  int32_t base_only_even, pad;
+};
+hipError_t launch_ntt_rows_tail_list(const RowsTailTask* tasks, int ntasks, int64_t nblocks, hipStream_t s);
 
 // NTT-domain automorphism: out[p][l][x] = in[p][l][perm[x]] for L limbs of npoly polynomials.
 hipError_t launch_automorphism(const uint32_t* in, uint64_t in_stride, uint32_t* out,

@@ -504,7 +504,7 @@ struct RowLoc {
 // common bases, npoly polynomials `stride` apart, R / 8 blocks per polynomial;
 // block b is (job, row block, polynomial) with the polynomial fastest.
 struct P32Uniform {
-  static constexpr bool kTail = false;
+  static constexpr bool kTail = false, kList = false;
   const RowsJob* jobs;
   const uint32_t* in;
   uint32_t* out;
@@ -528,7 +528,7 @@ struct P32Uniform {
 // not above b (within a task: row block, then polynomial, the polynomial fastest).
 // Blocks of a workgroup are contiguous, so the task index only moves forward.
 struct P32List {
-  static constexpr bool kTail = false;
+  static constexpr bool kTail = false, kList = true;
   const RowsTask* tasks;
   int ntasks;
   int t = 0;                // current task (wave-uniform)
@@ -605,6 +605,37 @@ __device__ __forceinline__ void p32_write_row(const uint32_t* zw, uint32_t* out,
   }
 }
 
+// Tail write of one staged output row y: out = base + (acc - y) * Pinv (base may be
+// null), 16-byte loads and stores of the row.
+__device__ __forceinline__ void p32_tail_row(const uint32_t* zw, const uint32_t* acc, const uint32_t* base,
+                                             uint32_t* out, const TailConst c, int lane) {
+  const __amdgpu_buffer_rsrc_t ra = rows_rsrc(acc, 1024 * 4);
+  const __amdgpu_buffer_rsrc_t ro = rows_rsrc(out, 1024 * 4);
+  // without a base the descriptor holds no records: its loads read zero
+  const __amdgpu_buffer_rsrc_t rbase = rows_rsrc(base ? base : out, base ? 1024 * 4 : 0);
+  v4u a[4], bs[4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const uint32_t e = (uint32_t)(lane + it * 64) * 16;
+    a[it] = __builtin_amdgcn_raw_buffer_load_b128(ra, e, 0, 0);
+    bs[it] = __builtin_amdgcn_raw_buffer_load_b128(rbase, e, 0, 0);
+  }
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int e = (lane + it * 64) * 4;
+    const uint32_t* y = &zw[(e >> 5) * kP32Xp + (e & 31)];
+    v4u r;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t d = a[it][k] + c.q - y[k];                       // (0, 2q)
+      const uint32_t m = d * c.pinv - __umulhi(d, c.pinv_shoup) * c.q; // [0, 2q)
+      const uint32_t v = (m >= c.q ? m - c.q : m) + bs[it][k];
+      r[k] = v >= c.q ? v - c.q : v;
+    }
+    __builtin_amdgcn_raw_buffer_store_b128(r, ro, (uint32_t)e * 4, 0, 0);
+  }
+}
+
 // The uniform form with the ModDown / rescale tail fused into the forward kernel's
 // write: out = base + (acc - y) * Pinv for the staged output row y.
 struct P32UniformTail : P32Uniform {
@@ -617,42 +648,49 @@ struct P32UniformTail : P32Uniform {
     const int rb = __builtin_amdgcn_readfirstlane(rem / npoly);
     const int poly = rem - rb * npoly, row = rb * kP32Waves + wave;
     const uint64_t o = jobs[j].off + (uint64_t)row * 1024;
-    const TailConst c = t.tc[j];
     const bool use_base = t.base != nullptr && (!t.base_only_even || (poly & 1) == 0);
-    const __amdgpu_buffer_rsrc_t ra = rows_rsrc(t.acc + poly * t.acc_stride + o, 1024 * 4);
-    const __amdgpu_buffer_rsrc_t ro = rows_rsrc(t.out + poly * t.out_stride + o, 1024 * 4);
-    // without a base the descriptor holds no records: its loads read zero
-    const __amdgpu_buffer_rsrc_t rbase =
-        rows_rsrc(use_base ? t.base + poly * t.out_stride + o : t.out, use_base ? 1024 * 4 : 0);
-    v4u a[4], bs[4];
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const uint32_t e = (uint32_t)(lane + it * 64) * 16;
-      a[it] = __builtin_amdgcn_raw_buffer_load_b128(ra, e, 0, 0);
-      bs[it] = __builtin_amdgcn_raw_buffer_load_b128(rbase, e, 0, 0);
-    }
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int e = (lane + it * 64) * 4;
-      const uint32_t* y = &zw[(e >> 5) * kP32Xp + (e & 31)];
-      v4u r;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t d = a[it][k] + c.q - y[k];                       // (0, 2q)
-        const uint32_t m = d * c.pinv - __umulhi(d, c.pinv_shoup) * c.q; // [0, 2q)
-        const uint32_t v = (m >= c.q ? m - c.q : m) + bs[it][k];
-        r[k] = v >= c.q ? v - c.q : v;
-      }
-      __builtin_amdgcn_raw_buffer_store_b128(r, ro, (uint32_t)e * 4, 0, 0);
-    }
+    p32_tail_row(zw, t.acc + poly * t.acc_stride + o, use_base ? t.base + poly * t.out_stride + o : nullptr,
+                 t.out + poly * t.out_stride + o, t.tc[j], lane);
   }
 };
 
-// Block range of this workgroup.  Workgroups are dispatched to the eight XCDs in
-// turn (workgroup w on XCD w % 8), so XCD x takes the x-th eighth of the blocks and
-// its workgroups split that slice: with blocks ordered (job, row block, polynomial),
-// every polynomial of a (prime, row block) -- which share its tables and the inverse
-// step-2 twiddles -- is handled within one XCD's L2.  The grid is a multiple of 8.
+// The task-list form of the fused tail (batch runtime): each task is one limb of
+// the NTT of z with its own tail buffers.
+struct P32ListTail {
+  static constexpr bool kTail = true, kList = true;
+  const RowsTailTask* tasks;
+  int ntasks;
+  int t = 0;
+  __device__ __forceinline__ void seek(int b) {
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].r.first_block <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    t = __builtin_amdgcn_readfirstlane(lo);
+  }
+  __device__ __forceinline__ RowLoc locate(int b, int wave) {
+    while (t + 1 < ntasks && tasks[t + 1].r.first_block <= b) ++t;
+    const RowsTask& k = tasks[t].r;
+    const int local = b - k.first_block;
+    const int rb = __builtin_amdgcn_readfirstlane(local / k.npoly);
+    const int poly = local - rb * k.npoly, row = rb * kP32Waves + wave;
+    const uint64_t off = (uint64_t)poly * k.stride + (uint64_t)row * 1024;
+    return RowLoc{k.tab, k.tw1, nullptr, k.in + off, nullptr, k.q, k.qinv};
+  }
+  __device__ __forceinline__ void write_tail(int b, int wave, const uint32_t* zw, uint32_t q, int lane) const {
+    const RowsTailTask& k = tasks[t];
+    const int local = b - k.r.first_block;
+    const int rb = __builtin_amdgcn_readfirstlane(local / k.r.npoly);
+    const int poly = local - rb * k.r.npoly, row = rb * kP32Waves + wave;
+    const uint64_t o = (uint64_t)row * 1024;
+    const bool use_base = k.base != nullptr && (!k.base_only_even || (poly & 1) == 0);
+    p32_tail_row(zw, k.acc + poly * k.acc_stride + o, use_base ? k.base + poly * k.out_stride + o : nullptr,
+                 k.out + poly * k.out_stride + o, TailConst{k.r.q, k.pinv, k.pinv_shoup, 0}, lane);
+  }
+};
+
 __device__ __forceinline__ void p32_range(int nblocks, int& b0, int& b1) {
   const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
   const int lo = (int)((int64_t)nblocks * xcd / 8), hi = (int)((int64_t)nblocks * (xcd + 1) / 8);
@@ -726,7 +764,7 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_fwd_kernel(SRC s
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int b0, b1;
   p32_range(nblocks, b0, b1);
-  if constexpr (std::is_same<SRC, P32List>::value) src.seek(b0);
+  if constexpr (SRC::kList) src.seek(b0);
   uint32_t* zw = zs + wave * kP32SliceWords;
   P32Tab tab;
   const int8_t* cur_tab = nullptr;
@@ -763,7 +801,38 @@ __device__ __forceinline__ uint32_t ip_mulmod(uint32_t a, uint32_t b, const IpLi
 // accumulates its products with the two key rows of (j, t) in registers; the two
 // accumulator rows are written once.  Every transform of a block uses t's prime, so
 // the row tables are staged once per run of blocks with the same t.
-__global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(RowsIp p, int nblocks) {
+// Block sources of the fused kernel: one RowsIp, or a task list of them (batch
+// runtime; blocks of a task contiguous, tasks in first_block order).
+struct IpUniform {
+  RowsIp p;
+  __device__ __forceinline__ void seek(int) {}
+  __device__ __forceinline__ const RowsIp& at(int b, int& local) {
+    local = b;
+    return p;
+  }
+};
+struct IpList {
+  const IpTask* tasks;
+  int ntasks;
+  int t = 0;
+  __device__ __forceinline__ void seek(int b) {
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].first_block <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    t = __builtin_amdgcn_readfirstlane(lo);
+  }
+  __device__ __forceinline__ const RowsIp& at(int b, int& local) {
+    while (t + 1 < ntasks && tasks[t + 1].first_block <= b) ++t;
+    local = b - tasks[t].first_block;
+    return tasks[t].p;
+  }
+};
+
+template <class SRC>
+__global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC src, int nblocks) {
   __shared__ __attribute__((aligned(16))) int8_t tabs[16 * 32 * 32];
   __shared__ __attribute__((aligned(16))) uint32_t tws[2 * 1024];
   __shared__ __attribute__((aligned(16))) uint32_t zs[kP32Waves * kP32SliceWords];
@@ -771,14 +840,17 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(RowsIp
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int b0, b1;
   p32_range(nblocks, b0, b1);
+  if (b0 < b1) src.seek(b0);
   uint32_t* zw = zs + wave * kP32SliceWords;
   const P32LdsTab tab{tabs, lane};
   const int8_t* cur_tab = nullptr;
-  const uint64_t N = 1024ull << p.rb_log << 3;
-  const int per_t = p.B << p.rb_log;
   for (int b = b0; b < b1; ++b) {
-    const int t = __builtin_amdgcn_readfirstlane(b / per_t);
-    const int rem = b - t * per_t;
+    int local;
+    const RowsIp& p = src.at(b, local);
+    const uint64_t N = 1024ull << p.rb_log << 3;
+    const int per_t = p.B << p.rb_log;
+    const int t = __builtin_amdgcn_readfirstlane(local / per_t);
+    const int rem = local - t * per_t;
     const int rb = __builtin_amdgcn_readfirstlane(rem / p.B);
     const int ct = rem - rb * p.B, row = rb * kP32Waves + wave;
     const IpLimb md = p.limbs[t];
@@ -852,7 +924,7 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_inv_kernel(SRC s
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   int b0, b1;
   p32_range(nblocks, b0, b1);
-  if constexpr (std::is_same<SRC, P32List>::value) src.seek(b0);
+  if constexpr (SRC::kList) src.seek(b0);
   uint32_t* zw = zs + wave * kP32SliceWords;
   P32Tab tab;
   const int8_t* cur_tab = nullptr;
@@ -991,7 +1063,27 @@ hipError_t launch_ntt_rows_ip(const RowsIp& p, hipStream_t s) {
   if (p.rb_log < 0 || !p.limbs || !p.tmp || !p.d || !p.key || !p.acc) return hipErrorInvalidValue;
   const int64_t nblocks = (int64_t)p.LK * p.B << p.rb_log;
   if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
-  launch_kernel(ntt_rows32_ip_kernel, dim3(p32_grid(nblocks)), dim3(64 * kP32Waves), 0, s, p, (int)nblocks);
+  const IpUniform src{p};
+  launch_kernel((ntt_rows32_ip_kernel<IpUniform>), dim3(p32_grid(nblocks)), dim3(64 * kP32Waves), 0, s, src,
+                (int)nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_rows_ip_list(const IpTask* tasks, int ntasks, int64_t nblocks, hipStream_t s) {
+  if (ntasks <= 0 || nblocks <= 0) return hipSuccess;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  const IpList src{tasks, ntasks, 0};
+  launch_kernel((ntt_rows32_ip_kernel<IpList>), dim3(p32_grid(nblocks)), dim3(64 * kP32Waves), 0, s, src,
+                (int)nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_rows_tail_list(const RowsTailTask* tasks, int ntasks, int64_t nblocks, hipStream_t s) {
+  if (ntasks <= 0 || nblocks <= 0) return hipSuccess;
+  if (nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  const P32ListTail src{tasks, ntasks, 0};
+  launch_kernel((ntt_rows32_fwd_kernel<P32ListTail>), dim3(p32_grid(nblocks)), dim3(64 * kP32Waves), 0, s, src,
+                (int)nblocks);
   return hipGetLastError();
 }
 
