@@ -83,7 +83,8 @@ struct cross_batch_s {
   const cross::InnerTask* d_inners = nullptr;
   const cross::TailTask* d_tails = nullptr;
   uint64_t max_auto = 0, max_tensor = 0, max_copy = 0, max_inner = 0, max_tail = 0;
-  uint64_t max_waves_up = 0, max_waves_down = 0;
+  uint64_t max_cols_up = 0, max_cols_down = 0;   // largest npoly << log_n of the BConv tasks
+  int max_nsrc_up = 0, max_nsrc_down = 0;
   std::vector<void*> allocs;
   uint64_t ws_bytes = 0;
   bool external = false;        // scratch and task lists live in the caller's workspace
@@ -314,12 +315,16 @@ hipError_t run_phases(cross_batch b, hipStream_t s, bool prof) {
   vec("tensor", [&] { return launch_tensor_list(b->d_tensors, (int)b->tensors.size(), b->max_tensor, s); });
   vec("limb_copy", [&] { return launch_copy_list(b->d_copies, (int)b->copies.size(), b->max_copy, s); });
   ntt(kNttInvD, true);
-  vec("bconv", [&] { return launch_bconv_list(b->d_bconv_up, (int)b->bconv_up.size(), b->max_waves_up, s); });
+  vec("bconv", [&] {
+    return launch_bconv_list(b->d_bconv_up, (int)b->bconv_up.size(), b->max_cols_up, b->max_nsrc_up, s);
+  });
   ntt(kNttFwdExt, false);
   vec("ntt_rows_ip", [&] { return launch_ntt_rows_ip_list(b->d_ips, (int)b->ips.size(), b->ip_blocks, s); });
   vec("inner_product", [&] { return launch_inner_list(b->d_inners, (int)b->inners.size(), b->max_inner, s); });
   ntt(kNttInvP, true);
-  vec("bconv", [&] { return launch_bconv_list(b->d_bconv_down, (int)b->bconv_down.size(), b->max_waves_down, s); });
+  vec("bconv", [&] {
+    return launch_bconv_list(b->d_bconv_down, (int)b->bconv_down.size(), b->max_cols_down, b->max_nsrc_down, s);
+  });
   ntt(kNttFwdZ, false);
   vec("ntt_rows", [&] {
     return launch_ntt_rows_tail_list(b->d_rtails, (int)b->rtails.size(), b->rtail_blocks, s);
@@ -516,7 +521,8 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       const BconvStatic& bs = c->modup[dj];
       BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, fuse ? z : d, ext, nd, next, B, c->log_n};
       b->bconv_up.push_back(g);
-      b->max_waves_up = std::max(b->max_waves_up, ((uint64_t)B << c->log_n) / 32);
+      b->max_cols_up = std::max(b->max_cols_up, (uint64_t)B << c->log_n);
+      b->max_nsrc_up = std::max(b->max_nsrc_up, bs.nsrc);
       for (int t : c->targets[dj]) {
         ep.push_back(bp[t]);
         eo.push_back(((uint64_t)dj * LK + t) * N);
@@ -552,7 +558,8 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       const BconvStatic& bs = c->moddown;
       BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, acc, z, (uint64_t)LK * N, nd, 2 * B, c->log_n};
       b->bconv_down.push_back(g);
-      b->max_waves_down = std::max(b->max_waves_down, ((uint64_t)(2 * B) << c->log_n) / 32);
+      b->max_cols_down = std::max(b->max_cols_down, (uint64_t)(2 * B) << c->log_n);
+      b->max_nsrc_down = std::max(b->max_nsrc_down, bs.nsrc);
     }
     add_ntt(b.get(), b->ntt[kNttFwdZ], qp, qo, z, tmp, nd, 2 * B, false, nullptr, fuse);
     if (fuse) {

@@ -204,76 +204,104 @@ limb_copy_kernel(const v4u* src, uint64_t src_stride4, const uint64_t* src_off, 
 // v_mfma_i32_32x32x32_i8: 8 targets x 8 sources x 32 coefficients per instruction.
 // Lane l of a 32x32 output block holds rows 8(v/4) + 4(l/32) + v%4 (v < 16) of
 // column l%32, so the four chunk rows of each target sit in four consecutive
-// registers and the merge stays in-register.  Each wave owns 32 coefficients.
+// registers and the merge stays in-register.
+//
+// Each wave converts 128 consecutive coefficients of the flattened (polynomial,
+// coefficient) range.  Lane l loads the four coefficients 4 (l % 32) .. +3 of each of
+// its sources with one 16-byte load, and product k (k < 4) takes coefficient k of
+// them as column l % 32: after the four products of a 32-target block each lane
+// holds four consecutive outputs of each of its targets, stored as one 16-byte word.
+// Source and target descriptors are wave-uniform loads (one per pair of lane halves).
 constexpr int BCONV_MAX_KB = 4;   // up to 32 source limbs
+constexpr int BCONV_COLS = 128;   // coefficients per wave
 
+template <int KB>
 __device__ __forceinline__ void bconv_wave(const BconvLaunch& g, uint64_t wave_global) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t n_per_poly = 1ull << g.log_n;
-  if (wave_global * 32 >= ((uint64_t)g.npoly << g.log_n)) return;
-  const uint64_t col0 = (uint64_t)wave_global * 32;
-  const uint64_t poly = col0 >> g.log_n;
-  if (poly >= (uint64_t)g.npoly) return;
-  const uint64_t n = (col0 & (n_per_poly - 1)) + (lane & 31);
+  const int lane = threadIdx.x & 63, half = lane >> 5;
+  const uint64_t total = (uint64_t)g.npoly << g.log_n;
+  if (wave_global * BCONV_COLS >= total) return;
+  const uint64_t f = wave_global * BCONV_COLS + (uint64_t)(lane & 31) * 4;
+  const bool live = f < total;             // total is a multiple of 32: groups of four are whole
+  const uint64_t poly = f >> g.log_n, n = f & ((1ull << g.log_n) - 1);
+  const uint32_t* in = g.in + poly * g.in_stride + n;
+  uint32_t* out = g.out + poly * g.out_stride + n;
   const int kblocks = (g.nsrc + 7) >> 3;
   const int mblocks = (g.ndst + 7) >> 3;
-  const uint32_t* in = g.in + poly * g.in_stride;
-  uint32_t* out = g.out + poly * g.out_stride;
 
-  // B fragments: step 1 (x * qhat^-1 mod q) and chunking, one v4i per K block
-  v4i bf[BCONV_MAX_KB];
+  // B operands: step 1 (x * qhat^-1 mod q) and chunking; bf[kb][k] holds the packed
+  // sources kb * 8 + 4 half + e (e < 4) at coefficient 4 (l % 32) + k
+  v4i bf[KB][4];
 #pragma unroll
-  for (int kb = 0; kb < BCONV_MAX_KB; ++kb) {
-    v4i f = {0, 0, 0, 0};
-    if (kb < kblocks) {
+  for (int kb = 0; kb < KB; ++kb) {
+    v4u x[4];
+    BconvSrc sd[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = kb * 8 + (lane >> 5) * 4 + e;
-        uint32_t v = 0;
-        if (i < g.nsrc) {
-          const BconvSrc sd = g.src[i];
-          v = pack_chunks(mulmod_shoup(in[sd.off + n], sd.w, sd.w_shoup, sd.q));
-        }
-        f[e] = (int)v;
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int i0 = kb * 8 + e, i1 = i0 + 4;
+      const BconvSrc s0 = g.src[i0 < g.nsrc ? i0 : 0], s1 = g.src[i1 < g.nsrc ? i1 : 0];
+      sd[e] = half ? s1 : s0;
+      const bool ok = live && (half ? i1 : i0) < g.nsrc;
+      x[e] = ok ? *reinterpret_cast<const v4u*>(in + sd[e].off) : v4u{0, 0, 0, 0};
     }
-    bf[kb] = f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) bf[kb][k][e] = (int)pack_chunks(mulmod_shoup(x[e][k], sd[e].w, sd[e].w_shoup, sd[e].q));
   }
 
   for (int mb = 0; mb < mblocks; ++mb) {
-    v16i acc = {};
-    for (int kb = 0; kb < kblocks; ++kb) {
-      const v4i a = *reinterpret_cast<const v4i*>(g.table + ((size_t)(mb * kblocks + kb) * 1024) + lane * 16);
-      acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bf[kb], acc, 0, 0, 0);
-    }
+    v4i a[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb)
+      a[kb] = kb < kblocks ? *reinterpret_cast<const v4i*>(g.table + ((size_t)(mb * kblocks + kb) * 1024) + lane * 16)
+                           : v4i{0, 0, 0, 0};
+    BconvDst d[4];
 #pragma unroll
     for (int g4 = 0; g4 < 4; ++g4) {
-      const int t = mb * 8 + 2 * g4 + (lane >> 5);
-      if (t >= g.ndst) continue;
-      const BconvDst d = g.dst[t];
-      uint64_t z = (uint64_t)(uint32_t)acc[4 * g4] + ((uint64_t)(uint32_t)acc[4 * g4 + 1] << 7) +
-                   ((uint64_t)(uint32_t)acc[4 * g4 + 2] << 14) + ((uint64_t)(uint32_t)acc[4 * g4 + 3] << 21);
-      uint32_t tq = (uint32_t)z * d.qinv;
-      uint32_t r = (uint32_t)(z >> 32) + d.q - __umulhi(tq, d.q);
-      if (r >= d.q) r -= d.q;
-      out[d.off + n] = r;
+      const int t0 = mb * 8 + 2 * g4, t1 = t0 + 1;
+      const BconvDst d0 = g.dst[t0 < g.ndst ? t0 : 0], d1 = g.dst[t1 < g.ndst ? t1 : 0];
+      d[g4] = half ? d1 : d0;
     }
+    // product k, merged and reduced at once: r[g4][k] is target mb * 8 + 2 g4 + half
+    // at coefficient 4 (l % 32) + k
+    uint32_t r[4][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v16i acc = v16i{};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb)
+        if (kb < kblocks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[kb], bf[kb][k], acc, 0, 0, 0);
+#pragma unroll
+      for (int g4 = 0; g4 < 4; ++g4) {
+        const uint64_t z = (uint64_t)(uint32_t)acc[4 * g4] + ((uint64_t)(uint32_t)acc[4 * g4 + 1] << 7) +
+                           ((uint64_t)(uint32_t)acc[4 * g4 + 2] << 14) + ((uint64_t)(uint32_t)acc[4 * g4 + 3] << 21);
+        const uint32_t tq = (uint32_t)z * d[g4].qinv;
+        const uint32_t v = (uint32_t)(z >> 32) + d[g4].q - __umulhi(tq, d[g4].q);
+        r[g4][k] = v >= d[g4].q ? v - d[g4].q : v;
+      }
+    }
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4)
+      if (live && mb * 8 + 2 * g4 + half < g.ndst)
+        *reinterpret_cast<v4u*>(out + d[g4].off) = v4u{r[g4][0], r[g4][1], r[g4][2], r[g4][3]};
   }
 }
 
-// Eight waves per SIMD (at most 64 registers; the compiler moves 16 to AGPRs, no
-// spills): BConv moves no extra bytes but waits on its loads, and the two extra
-// waves hide that (15.3 -> 13.4 us of BConv per HE-Mult at N = 2^16, L = 24, batch 8).
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+// Occupancy: four waves per SIMD for one K block (120 registers, no spills), fewer
+// for deeper conversions (more live B operands).
+template <int KB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB == 1 ? 4 : KB == 2 ? 3 : 2)))
 bconv_kernel(BconvLaunch g) {
-  bconv_wave(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  bconv_wave<KB>(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
-// the same per-wave work as bconv_kernel, so the same eight-wave launch
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+// Work-list form (batch runtime): one task per blockIdx.y, KB the largest K-block
+// count of the list (tasks with fewer K blocks skip the rest).
+template <int KB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB == 1 ? 4 : KB == 2 ? 3 : 2)))
 bconv_list_kernel(const BconvLaunch* tasks) {
   const BconvLaunch g = tasks[blockIdx.y];
-  bconv_wave(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  bconv_wave<KB>(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 __global__ void __launch_bounds__(256)
@@ -461,16 +489,30 @@ hipError_t launch_tail_list(const TailTask* t, int n, uint64_t max4, hipStream_t
   launch_kernel(tail_list_kernel, dim3(blocks_for(max4), n), dim3(256), 0, s, t);
   return hipGetLastError();
 }
-hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_waves, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  launch_kernel(bconv_list_kernel, dim3(blocks_for(max_waves * 64), n), dim3(256), 0, s, t);
+hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_cols, int max_nsrc, hipStream_t s) {
+  if (n <= 0 || max_cols == 0) return hipSuccess;
+  if (max_nsrc < 1 || max_nsrc > 8 * BCONV_MAX_KB) return hipErrorInvalidValue;
+  const dim3 grid(blocks_for((max_cols + BCONV_COLS - 1) / BCONV_COLS * 64), n);
+  switch ((max_nsrc + 7) >> 3) {
+    case 1: launch_kernel(bconv_list_kernel<1>, grid, dim3(256), 0, s, t); break;
+    case 2: launch_kernel(bconv_list_kernel<2>, grid, dim3(256), 0, s, t); break;
+    case 3: launch_kernel(bconv_list_kernel<3>, grid, dim3(256), 0, s, t); break;
+    default: launch_kernel(bconv_list_kernel<4>, grid, dim3(256), 0, s, t); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s) {
   if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5) return hipErrorInvalidValue;
-  const uint64_t waves = ((uint64_t)b.npoly << b.log_n) / 32;
-  launch_kernel(bconv_kernel, dim3(blocks_for(waves * 64)), dim3(256), 0, s, b);
+  if (b.npoly <= 0) return hipSuccess;
+  const uint64_t waves = (((uint64_t)b.npoly << b.log_n) + BCONV_COLS - 1) / BCONV_COLS;
+  const dim3 grid(blocks_for(waves * 64));
+  switch ((b.nsrc + 7) >> 3) {
+    case 1: launch_kernel(bconv_kernel<1>, grid, dim3(256), 0, s, b); break;
+    case 2: launch_kernel(bconv_kernel<2>, grid, dim3(256), 0, s, b); break;
+    case 3: launch_kernel(bconv_kernel<3>, grid, dim3(256), 0, s, b); break;
+    default: launch_kernel(bconv_kernel<4>, grid, dim3(256), 0, s, b); break;
+  }
   return hipGetLastError();
 }
 

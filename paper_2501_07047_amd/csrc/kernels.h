@@ -400,8 +400,9 @@ hipError_t launch_tensor_list(const TensorTask* t, int n, uint64_t max4, hipStre
 hipError_t launch_copy_list(const CopyTask* t, int n, uint64_t max4, hipStream_t s);
 hipError_t launch_inner_list(const InnerTask* t, int n, uint64_t max4, hipStream_t s);
 hipError_t launch_tail_list(const TailTask* t, int n, uint64_t max4, hipStream_t s);
-// BConv over many independent conversions (one BconvLaunch per task, pointers absolute).
-hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_waves, hipStream_t s);
+// BConv over many independent conversions (one BconvLaunch per task, pointers absolute):
+// max_cols the largest npoly << log_n and max_nsrc the largest nsrc of the tasks.
+hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_cols, int max_nsrc, hipStream_t s);
 
 }  // namespace cross
 
