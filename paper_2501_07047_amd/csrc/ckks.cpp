@@ -330,14 +330,22 @@ cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t*
   if (st != CROSS_OK) return st;
   const uint32_t* coef = x ? x : d;
   // 3. BConv of each digit to the other limbs, then 4. NTT of all converted limbs in one launch
+  // (all digits in one launch)
   std::vector<int> nl;
   std::vector<uint64_t> no;
+  std::vector<BconvLaunch> gs;
   for (int j = 0; j < c->ndig; ++j) {
-    HIPCHK(run_bconv(ctx, c->modup[j], coef, (uint64_t)L * N, ext, ext_stride, B, c->log_n, s), "modup bconv");
+    const BconvStatic& bs = c->modup[j];
+    gs.push_back(BconvLaunch{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, coef, ext, (uint64_t)L * N, ext_stride, B,
+                             c->log_n});
     for (int t : c->targets[j]) {
       nl.push_back(t);
       no.push_back(((uint64_t)j * LK + t) * N);
     }
+  }
+  {
+    ProfScope ps(ctx, "bconv", s);
+    HIPCHK(launch_bconv_multi(gs.data(), (int)gs.size(), s), "modup bconv");
   }
   if (conv) {
     conv->limb = nl;

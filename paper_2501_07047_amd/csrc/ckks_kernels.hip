@@ -8,6 +8,8 @@
 // with 128-bit (4 x uint32) coalesced accesses per lane.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace cross {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -304,6 +306,14 @@ bconv_list_kernel(const BconvLaunch* tasks) {
   bconv_wave<KB>(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
+// Up to kBconvMulti conversions in one launch, passed by value (one per blockIdx.y):
+// the ModUp digits of one call, which alone fill the device only once each.
+template <int KB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB == 1 ? 4 : KB == 2 ? 3 : 2)))
+bconv_multi_kernel(BconvMulti m) {
+  bconv_wave<KB>(m.g[blockIdx.y], ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+}
+
 __global__ void __launch_bounds__(256)
 tensor_list_kernel(const TensorTask* tasks) {
   const TensorTask t = tasks[blockIdx.y];
@@ -500,6 +510,34 @@ hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_cols, int
     default: launch_kernel(bconv_list_kernel<4>, grid, dim3(256), 0, s, t); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_bconv_multi(const BconvLaunch* gs, int n, hipStream_t s) {
+  for (int base = 0; base < n; base += kBconvMulti) {
+    BconvMulti m{};
+    const int cnt = n - base < kBconvMulti ? n - base : kBconvMulti;
+    uint64_t cols = 0;
+    int nsrc = 1;
+    for (int i = 0; i < cnt; ++i) {
+      const BconvLaunch& b = gs[base + i];
+      if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5 || b.npoly < 0)
+        return hipErrorInvalidValue;
+      m.g[i] = b;
+      cols = std::max(cols, (uint64_t)b.npoly << b.log_n);
+      nsrc = std::max(nsrc, b.nsrc);
+    }
+    if (cols == 0) continue;
+    const dim3 grid(blocks_for((cols + BCONV_COLS - 1) / BCONV_COLS * 64), cnt);
+    switch ((nsrc + 7) >> 3) {
+      case 1: launch_kernel(bconv_multi_kernel<1>, grid, dim3(256), 0, s, m); break;
+      case 2: launch_kernel(bconv_multi_kernel<2>, grid, dim3(256), 0, s, m); break;
+      case 3: launch_kernel(bconv_multi_kernel<3>, grid, dim3(256), 0, s, m); break;
+      default: launch_kernel(bconv_multi_kernel<4>, grid, dim3(256), 0, s, m); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s) {

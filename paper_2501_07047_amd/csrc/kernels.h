@@ -358,6 +358,13 @@ struct BconvLaunch {
   int npoly, log_n;
 };
 hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s);
+// Several conversions in one launch (by value, kBconvMulti per launch; more are
+// split over launches), e.g. the digits of one ModUp.
+constexpr int kBconvMulti = 8;
+struct BconvMulti {
+  BconvLaunch g[kBconvMulti];
+};
+hipError_t launch_bconv_multi(const BconvLaunch* gs, int n, hipStream_t s);
 
 }  // namespace cross
 
