@@ -564,6 +564,9 @@ cross_status cross_set_ntt_engine(cross_ctx ctx, int engine);
  *   which 6/7 : uint32 pairs of the inverse / forward step-2 twiddles, row-major [R][C][2]
  *   which 8-11: the tables of which 0-3 without the Montgomery factor 2^32
  *               (CROSS_NTT_RED_BARRETT; CROSS_EINVAL for wide primes, which have none)
+ *   which 12  : uint32 pairs of T3 * 2^32 mod q, [C1][C2][2]: with them the forward
+ *               row transform yields its outputs times 2^32 (Montgomery form), as the
+ *               fused ModUp NTT + key-switch inner product uses them
  */
 cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,
                                    void* out, uint64_t* bytes);

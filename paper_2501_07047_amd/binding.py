@@ -207,7 +207,7 @@ def host_row_tables(q, log_n, log_r, log_c1, which):
     st = lib().cross_host_row_tables(q, log_n, log_r, log_c1, which, c_vp(buf.ctypes.data), ctypes.byref(nbytes))
     if st != 0:
         raise CrossError(st, "cross_host_row_tables")
-    return buf.view(np.int8) if which < 4 or which >= 8 else buf.view(np.uint32)
+    return buf.view(np.int8) if which < 4 or 8 <= which <= 11 else buf.view(np.uint32)
 
 
 def set_gemm_tile(tile, device=None):

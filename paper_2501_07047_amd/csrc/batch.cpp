@@ -538,7 +538,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
         uint32_t k = 0;
         while ((1ull << k) <= q) ++k;
         const uint32_t m = (uint32_t)(((unsigned __int128)1 << (2 * k)) / q);
-        lm[t] = IpLimb{bp[t]->row_fwd_b, bp[t]->row_fwd_t3, q, bp[t]->qinv, m, k, t < L ? t / c->alpha : -1, 0};
+        lm[t] = IpLimb{bp[t]->row_fwd_b, bp[t]->row_fwd_t3_mont, q, bp[t]->qinv, m, k, t < L ? t / c->alpha : -1, 0};
       }
       void* dl = nullptr;
       cross_status st = cached_device_copy(ctx, lm.data(), lm.size() * sizeof(IpLimb), &dl);

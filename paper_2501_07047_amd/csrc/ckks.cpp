@@ -496,7 +496,7 @@ cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* ke
     for (int t = 0; t < LK; ++t) {
       const Plan* p = c->plans[t];
       const LimbMod m = limb_mod(p->q);
-      lm[t] = IpLimb{p->row_fwd_b, p->row_fwd_t3, p->q, p->qinv, m.bar_m, m.bar_k, t < c->L ? t / c->alpha : -1, 0};
+      lm[t] = IpLimb{p->row_fwd_b, p->row_fwd_t3_mont, p->q, p->qinv, m.bar_m, m.bar_k, t < c->L ? t / c->alpha : -1, 0};
     }
     void* dl = nullptr;
     if ((st = cached_device_copy(ctx, lm.data(), lm.size() * sizeof(IpLimb), &dl)) != CROSS_OK) return st;

@@ -136,6 +136,7 @@ cross_status get_plan_at(cross_ctx ctx, uint32_t q, int log_n, int log_r, int lo
               al(t.bf_fwd.size() * 4) + al(t.bf_inv.size() * 4) + al(t.row_fwd_b.size()) +
               al(t.row_fwd_c.size()) + al(t.row_inv_c.size()) + al(t.row_inv_b.size()) +
               al(t.row_fwd_t3.size() * 4) + al(t.row_inv_t3.size() * 4) + al(t.inv_tw_rows.size() * 4) +
+              al(t.row_fwd_t3_mont.size() * 4) +
               al(t.row_fwd_b_plain.size()) + al(t.row_fwd_c_plain.size()) + al(t.row_inv_c_plain.size()) +
               al(t.row_inv_b_plain.size()) + al(t.fwd_left_plain.size()) + al(t.fwd_right_plain.size()) +
               al(t.inv_left_plain.size()) + al(t.inv_right_plain.size());
@@ -170,6 +171,7 @@ cross_status get_plan_at(cross_ctx ctx, uint32_t q, int log_n, int log_r, int lo
   p->row_inv_c = (int8_t*)put(t.row_inv_c.data(), t.row_inv_c.size());
   p->row_inv_b = (int8_t*)put(t.row_inv_b.data(), t.row_inv_b.size());
   p->row_fwd_t3 = (uint32_t*)put(t.row_fwd_t3.data(), t.row_fwd_t3.size() * 4);
+  p->row_fwd_t3_mont = (uint32_t*)put(t.row_fwd_t3_mont.data(), t.row_fwd_t3_mont.size() * 4);
   p->row_inv_t3 = (uint32_t*)put(t.row_inv_t3.data(), t.row_inv_t3.size() * 4);
   p->inv_tw_rows = (uint32_t*)put(t.inv_tw_rows.data(), t.inv_tw_rows.size() * 4);
   p->row_fwd_b_plain = (int8_t*)put(t.row_fwd_b_plain.data(), t.row_fwd_b_plain.size());
@@ -847,12 +849,12 @@ cross_status cross_profile_report(cross_ctx ctx, char* buf, uint64_t len) {
 
 cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, uint32_t log_c1, uint32_t which,
                                    void* out, uint64_t* bytes) {
-  if (!bytes || which > 11 || log_n > CROSS_MAX_LOG_N || log_r > log_n ||
+  if (!bytes || which > 12 || log_n > CROSS_MAX_LOG_N || log_r > log_n ||
       !rows_split_supported((int)log_n, (int)log_r, (int)log_c1))
     return CROSS_EINVAL;
   cross_status st = check_prime(nullptr, q, log_n, true);
   if (st != CROSS_OK) return st;
-  if (which >= 8 && wide_prime(q)) return CROSS_EINVAL;     // no plain tables in the wide form
+  if (which >= 8 && which <= 11 && wide_prime(q)) return CROSS_EINVAL;   // no plain tables in the wide form
   NttTables t;
   try {
     build_ntt_tables(q, log_n, log_r, t, true, log_c1);
@@ -873,7 +875,8 @@ cross_status cross_host_row_tables(uint32_t q, uint32_t log_n, uint32_t log_r, u
     case 8: src = t.row_fwd_b_plain.data(); n = t.row_fwd_b_plain.size(); break;
     case 9: src = t.row_fwd_c_plain.data(); n = t.row_fwd_c_plain.size(); break;
     case 10: src = t.row_inv_c_plain.data(); n = t.row_inv_c_plain.size(); break;
-    default: src = t.row_inv_b_plain.data(); n = t.row_inv_b_plain.size(); break;
+    case 11: src = t.row_inv_b_plain.data(); n = t.row_inv_b_plain.size(); break;
+    default: src = t.row_fwd_t3_mont.data(); n = t.row_fwd_t3_mont.size() * 4; break;
   }
   if (!out) {
     *bytes = n;

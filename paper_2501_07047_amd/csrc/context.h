@@ -28,6 +28,7 @@ struct Plan {
   int8_t *row_inv_c_plain = nullptr, *row_inv_b_plain = nullptr;
   uint32_t bar_m = 0, bar_k = 0;              // Barrett constants: floor(2^(2k) / q), k = bit length
   uint32_t *row_fwd_t3 = nullptr, *row_inv_t3 = nullptr, *inv_tw_rows = nullptr;
+  uint32_t* row_fwd_t3_mont = nullptr;        // T3 x 2^32 (fused ModUp NTT + inner product)
   uint32_t bf_ninv = 0;
   bool wide = false;        // 2^28 <= q < 2^31: signed-digit tables, byte operands
   void* block = nullptr;

@@ -263,9 +263,10 @@ bool rows_tail_supported(int log_n, int log_r, int log_c1);
 // acc: [B][2][LK][N]; N = 2^(rb_log + 13).
 struct IpLimb {
   const int8_t* tab;        // forward 32-point sub-step table of t's prime (fragment order)
-  const uint32_t* tw1;      // its first-epilogue twiddle pairs
+  const uint32_t* tw1;      // its first-epilogue twiddle pairs times 2^32 (T3 * 2^32 mod q): the
+                            // transforms come out times 2^32, ready for a Montgomery product
   uint32_t q, qinv;         // prime, q^-1 mod 2^32
-  uint32_t bar_m, bar_k;    // Barrett constants of the key products
+  uint32_t bar_m, bar_k;    // Barrett constants of the key products with t's own digit
   int32_t own, pad;         // digit holding t (-1 for special primes)
 };
 struct RowsIp {

@@ -780,6 +780,13 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_fwd_kernel(SRC s
   }
 }
 
+// Montgomery product x' k 2^-32 mod q of a Montgomery-form residue x' = x 2^32 mod q and a
+// plain one: x k in (0, 2q) (x' k < q 2^32, so one REDC step).
+__device__ __forceinline__ uint32_t ip_mont(uint32_t xm, uint32_t k, const IpLimb& md) {
+  const uint32_t lo = xm * k, hi = __umulhi(xm, k);
+  return hi + md.q - __umulhi(lo * md.qinv, md.q);
+}
+
 // Barrett product of two runtime residues (Alg. barrett): k = bit length of q,
 // m = floor(2^(2k) / q); the quotient estimate ((z >> (k - 1)) m) >> (k + 1) is short
 // by at most 2, so two conditional subtractions finish.
@@ -793,14 +800,19 @@ __device__ __forceinline__ uint32_t ip_mulmod(uint32_t a, uint32_t b, const IpLi
   return r;
 }
 
-// ModUp NTT fused with the key-switch inner product: block b is (target limb t, row
-// block, ciphertext), the ciphertext fastest, so the eight rows of key a row block reads
-// are shared by every ciphertext within one XCD.  Per block, each wave takes one row
-// and, for every active digit j, either transforms row (j, t) of the packed row-side
-// output (t outside digit j) or reads row t of the NTT-form input (t in digit j), and
+// ModUp NTT fused with the key-switch inner product: the (row, ciphertext) pairs of a
+// target limb t, the ciphertext fastest, are dealt eight to a block, one per wave, so
+// with eight or more ciphertexts the waves of a block read the same key rows together
+// (one fetch from HBM; a block per ciphertext re-fetched them about four times, once
+// the other workgroups' streams had pushed them out of L2).  Each wave, for every active
+// digit j, either transforms its row of limb (j, t) of the packed row-side output (t
+// outside digit j) or reads that row of the NTT-form input (t in digit j), and
 // accumulates its products with the two key rows of (j, t) in registers; the two
-// accumulator rows are written once.  Every transform of a block uses t's prime, so
-// the row tables are staged once per run of blocks with the same t.
+// accumulator rows are written once.  The transforms run with T3 * 2^32 as their first
+// twiddle, so their outputs come out times 2^32 and each key product is one REDC step
+// (four multiplies) instead of a Barrett product (five, and two 64-bit shifts); the key
+// products are most of this kernel's vector work.  Every transform of a block uses t's
+// prime, so the row tables are staged once per run of blocks with the same t.
 // Block sources of the fused kernel: one RowsIp, or a task list of them (batch
 // runtime; blocks of a task contiguous, tasks in first_block order).
 struct IpUniform {
@@ -850,9 +862,10 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC sr
     const uint64_t N = 1024ull << p.rb_log << 3;
     const int per_t = p.B << p.rb_log;
     const int t = __builtin_amdgcn_readfirstlane(local / per_t);
-    const int rem = local - t * per_t;
-    const int rb = __builtin_amdgcn_readfirstlane(rem / p.B);
-    const int ct = rem - rb * p.B, row = rb * kP32Waves + wave;
+    // the wave's (row, ciphertext) pair, the ciphertext fastest
+    const int pair = (local - t * per_t) * kP32Waves + wave;
+    const int row = __builtin_amdgcn_readfirstlane(pair / p.B);
+    const int ct = pair - row * p.B;
     const IpLimb md = p.limbs[t];
     if (md.tab != cur_tab) {
       // t's table and first twiddles into LDS (workgroup-uniform: a block has one t)
@@ -891,12 +904,24 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC sr
         const uint32_t e = (uint32_t)(lane + it * 64) * 16;
         const v4u a0 = __builtin_amdgcn_raw_buffer_load_b128(rk0, e, 0, 0);
         const v4u a1 = __builtin_amdgcn_raw_buffer_load_b128(rk1, e, 0, 0);
+        // accumulators in [0, 2q): the own digit's plain residues take a Barrett product
+        // ([0, q)), the transforms' Montgomery-form ones a REDC step ((0, 2q))
+        if (j == md.own) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uint32_t x = s0[it][k] + ip_mulmod(v[it][k], a0[k], md);
-          s0[it][k] = x >= md.q ? x - md.q : x;
-          x = s1[it][k] + ip_mulmod(v[it][k], a1[k], md);
-          s1[it][k] = x >= md.q ? x - md.q : x;
+          for (int k = 0; k < 4; ++k) {
+            uint32_t x = s0[it][k] + ip_mulmod(v[it][k], a0[k], md);
+            s0[it][k] = x >= 2 * md.q ? x - 2 * md.q : x;
+            x = s1[it][k] + ip_mulmod(v[it][k], a1[k], md);
+            s1[it][k] = x >= 2 * md.q ? x - 2 * md.q : x;
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            uint32_t x = s0[it][k] + ip_mont(v[it][k], a0[k], md);
+            s0[it][k] = x >= 2 * md.q ? x - 2 * md.q : x;
+            x = s1[it][k] + ip_mont(v[it][k], a1[k], md);
+            s1[it][k] = x >= 2 * md.q ? x - 2 * md.q : x;
+          }
         }
       }
     }
@@ -905,6 +930,11 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC sr
     const __amdgpu_buffer_rsrc_t ro1 = rows_rsrc(o0 + (uint64_t)p.LK * N, 1024 * 4);
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s0[it][k] = s0[it][k] >= md.q ? s0[it][k] - md.q : s0[it][k];
+        s1[it][k] = s1[it][k] >= md.q ? s1[it][k] - md.q : s1[it][k];
+      }
       __builtin_amdgcn_raw_buffer_store_b128(s0[it], ro0, (lane + it * 64) * 16, 0, 0);
       __builtin_amdgcn_raw_buffer_store_b128(s1[it], ro1, (lane + it * 64) * 16, 0, 0);
     }

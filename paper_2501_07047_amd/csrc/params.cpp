@@ -225,6 +225,7 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
       bat_expand(itb, C1, C1, q, t.row_inv_b_plain, false);
     }
     t.row_fwd_t3.resize((size_t)2 * C);
+    t.row_fwd_t3_mont.resize((size_t)2 * C);
     t.row_inv_t3.resize((size_t)2 * C);
     for (uint32_t m = 0; m < C1; ++m)
       for (uint32_t c2 = 0; c2 < C2; ++c2) {
@@ -235,6 +236,9 @@ void build_ntt_tables(uint32_t q, uint32_t log_n, uint32_t log_r, NttTables& t, 
         const size_t f = 2 * ((size_t)m * C2 + c2), g = 2 * ((size_t)c2 * C1 + m);
         t.row_fwd_t3[f] = wf;
         t.row_fwd_t3[f + 1] = shoup(wf);
+        const uint32_t wm = (uint32_t)(((uint64_t)wf << 32) % q);
+        t.row_fwd_t3_mont[f] = wm;
+        t.row_fwd_t3_mont[f + 1] = shoup(wm);
         t.row_inv_t3[g] = wi;
         t.row_inv_t3[g + 1] = shoup(wi);
       }

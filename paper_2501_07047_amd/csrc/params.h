@@ -65,6 +65,9 @@ struct NttTables {
   // the same four without the Montgomery factor (Barrett epilogue)
   std::vector<int8_t> row_fwd_b_plain, row_fwd_c_plain, row_inv_c_plain, row_inv_b_plain;
   std::vector<uint32_t> row_fwd_t3, row_inv_t3, inv_tw_rows;
+  // T3 times 2^32 mod q, as pairs: a forward row transform with these twiddles yields
+  // its outputs times 2^32 (Montgomery form), for the fused key-switch inner product
+  std::vector<uint32_t> row_fwd_t3_mont;
 };
 // with_bat = false builds only the butterfly twiddles (sizes below the MFMA minimum).
 // log_c1 > 0 selects the three-factor form: the C-point row transform is split as

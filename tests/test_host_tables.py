@@ -208,7 +208,7 @@ def test_bat_lazy_fragment_returns_each_lanes_chunk_products_in_lane():
                 assert lazy == bat_lazy_reduce(int(p[l, t]), q) and lazy % q == int(p[l, t]) % q
 
 
-def _emulate3(X, q, log_n, log_r, log_c1, inverse, plain=False):
+def _emulate3(X, q, log_n, log_r, log_c1, inverse, plain=False, t3_which=4):
     # three factors: the row-side step with the library's step-1 tables, then the
     # row transform with its row tables (cross_host_row_tables), in the kernels'
     # operand roles; Montgomery factors as in _emulate
@@ -232,7 +232,7 @@ def _emulate3(X, q, log_n, log_r, log_c1, inverse, plain=False):
         t1 = binding.host_tables(q, log_n, log_r, 7 if plain else 0)
         Y = twist(mr(_gemm(t1, 4 * R, X.reshape(R, C), q)), mont(rt(7).reshape(R, C, 2)))
         tb, tc = rt(0), rt(1)
-        t3 = mont(rt(4).reshape(C1, C2, 2))
+        t3 = mont(rt(t3_which).reshape(C1, C2, 2))
         out = np.empty((R, C), dtype=np.uint64)
         for k in range(R):
             Z = twist(mr(_gemm(tb, 4 * C1, Y[k].reshape(C1, C2), q)), t3)               # [m][c2]
@@ -263,6 +263,25 @@ def test_emulated_three_factor_ntt_matches_oracle(log_n, log_r, log_c1, plain, w
     ref = ntt_ct(a, q, psi)
     assert np.array_equal(_emulate3(a, q, log_n, log_r, log_c1, False, plain), ref)
     assert np.array_equal(_emulate3(ref, q, log_n, log_r, log_c1, True, plain), a)
+
+
+@pytest.mark.parametrize("log_n,log_r,log_c1", [(13, 5, 4), (16, 6, 5)])
+def test_montgomery_form_t3_scales_the_forward_transform(log_n, log_r, log_c1):
+    # the fused ModUp NTT + inner product runs the forward row transform with T3 * 2^32
+    # (row table 12): its outputs are the NTT times 2^32 mod q, and the pairs keep the
+    # Shoup quotient floor(w 2^32 / q) of the scaled twiddle
+    from paper_2501_07047_amd import binding
+    n = 1 << log_n
+    q = prime_chain(1)[0]
+    t3 = binding.host_row_tables(q, log_n, log_r, log_c1, 4).reshape(-1, 2).astype(object)
+    t3m = binding.host_row_tables(q, log_n, log_r, log_c1, 12).reshape(-1, 2).astype(object)
+    assert all(wm == (w << 32) % q for w, wm in zip(t3[:, 0], t3m[:, 0]))
+    assert all(s == (wm << 32) // q for wm, s in zip(t3m[:, 0], t3m[:, 1]))
+    g = np.random.Generator(np.random.PCG64(log_n))
+    a = g.integers(0, q, n).astype(np.uint64)
+    ref = ntt_ct(a, q, psi_of(q, n))
+    got = _emulate3(a, q, log_n, log_r, log_c1, False, t3_which=12)
+    assert np.array_equal(got, np.array([(int(v) << 32) % q for v in ref], dtype=np.uint64))
 
 
 @pytest.mark.parametrize("wide", [False, True])
