@@ -64,12 +64,9 @@ tensor_kernel(const v4u* a, const v4u* b, v4u* out, v4u* d2, const LimbMod* mods
   v4u r0, r1, r2;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    // three products: a0 b1 + a1 b0 = (a0 + a1)(b0 + b1) - a0 b0 - a1 b1
     r0[k] = mulmod(a0[k], b0[k], md);
+    r1[k] = addmod(mulmod(a0[k], b1[k], md), mulmod(a1[k], b0[k], md), md.q);
     r2[k] = mulmod(a1[k], b1[k], md);
-    const uint32_t m = mulmod(addmod(a0[k], a1[k], md.q), addmod(b0[k], b1[k], md.q), md);
-    const uint32_t s = addmod(r0[k], r2[k], md.q);
-    r1[k] = m >= s ? m - s : m + md.q - s;
   }
   out[o0] = r0;
   out[o1] = r1;
@@ -334,12 +331,9 @@ tensor_list_kernel(const TensorTask* tasks) {
   v4u r0, r1, r2;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    // three products: a0 b1 + a1 b0 = (a0 + a1)(b0 + b1) - a0 b0 - a1 b1
     r0[k] = mulmod(a0[k], b0[k], md);
+    r1[k] = addmod(mulmod(a0[k], b1[k], md), mulmod(a1[k], b0[k], md), md.q);
     r2[k] = mulmod(a1[k], b1[k], md);
-    const uint32_t m = mulmod(addmod(a0[k], a1[k], md.q), addmod(b0[k], b1[k], md.q), md);
-    const uint32_t s = addmod(r0[k], r2[k], md.q);
-    r1[k] = m >= s ? m - s : m + md.q - s;
   }
   ((v4u*)t.out)[o0] = r0;
   ((v4u*)t.out)[o1] = r1;
