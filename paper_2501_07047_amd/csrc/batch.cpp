@@ -523,11 +523,15 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
       b->bconv_up.push_back(g);
       b->max_cols_up = std::max(b->max_cols_up, (uint64_t)B << c->log_n);
       b->max_nsrc_up = std::max(b->max_nsrc_up, bs.nsrc);
-      for (int t : c->targets[dj]) {
-        ep.push_back(bp[t]);
-        eo.push_back(((uint64_t)dj * LK + t) * N);
-      }
     }
+    // the converted limbs target-major (one prime's transforms adjacent: its step-2
+    // twiddles are fetched into one L2)
+    for (int t = 0; t < LK; ++t)
+      for (int dj = 0; dj < c->ndig; ++dj)
+        if (std::find(c->targets[dj].begin(), c->targets[dj].end(), t) != c->targets[dj].end()) {
+          ep.push_back(bp[t]);
+          eo.push_back(((uint64_t)dj * LK + t) * N);
+        }
     add_ntt(b.get(), b->ntt[kNttFwdExt], ep, eo, ext, tmp, next, B, false, nullptr, fuse);
     const int log_r = bp[0]->log_r;
     if (fuse) {

@@ -17,6 +17,8 @@
 #include "params.h"
 #include "ckks_plan.h"
 
+#include <algorithm>
+
 namespace cross {
 
 namespace {
@@ -346,6 +348,21 @@ cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t*
   {
     ProfScope ps(ctx, "bconv", s);
     HIPCHK(launch_bconv_multi(gs.data(), (int)gs.size(), s), "modup bconv");
+  }
+  // the converted limbs target-major: the digits' transforms of one prime are
+  // neighbours in the launch, so its step-2 twiddles are fetched into one L2
+  {
+    std::vector<size_t> ord(nl.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return nl[x] < nl[y]; });
+    std::vector<int> nl2(nl.size());
+    std::vector<uint64_t> no2(no.size());
+    for (size_t i = 0; i < ord.size(); ++i) {
+      nl2[i] = nl[ord[i]];
+      no2[i] = no[ord[i]];
+    }
+    nl.swap(nl2);
+    no.swap(no2);
   }
   if (conv) {
     conv->limb = nl;
