@@ -183,6 +183,10 @@ cross_status cross_poly_mul(cross_ctx ctx, uint32_t log_n, const uint32_t* prime
  *   out: device [batch][lp][N] mod dst_primes (1 <= lp <= 64); must not overlap in
  *        (CROSS_EINVAL otherwise)
  *   log_n: 5..16
+ * Primes are odd primes below 2^31 (CROSS_ERANGE at or above): with any of them at
+ * or above 2^28 the whole conversion takes the byte form (residue bytes as
+ * b - 128 against balanced signed 8-bit digits with per-row corrections, the
+ * paper's full-byte BAT), otherwise 7-bit chunks.
  */
 cross_status cross_bconv(cross_ctx ctx, uint32_t log_n, const uint32_t* src_primes, uint32_t l,
                          const uint32_t* dst_primes, uint32_t lp, const uint32_t* in, uint32_t* out,

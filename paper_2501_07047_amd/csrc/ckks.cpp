@@ -46,12 +46,28 @@ StreamMod stream_mod(uint32_t q) {
   return m;
 }
 
+// Balanced base-256 digits of v: v = sum_i d_i 256^i, d_i in [-128, 127] (v within
+// [-128 * 0x1010101, 127 * 0x1010101]).
+void balanced_digits4(int64_t v, int8_t (&d)[4]) {
+  for (int i = 0; i < 4; ++i) {
+    int64_t r = ((v % 256) + 256) % 256;
+    if (r >= 128) r -= 256;
+    d[i] = (int8_t)r;
+    v = (v - r) / 256;
+  }
+}
+
 // Fragment-ordered BAT table of the BConv matrix [qhat_i]_t (see bconv_kernel).
-std::vector<int8_t> bconv_table(const std::vector<uint32_t>& src, const std::vector<uint32_t>& dst) {
+// Narrow primes: 7-bit chunks ii of ([qhat_i]_t 2^32 2^(7j)) mod t.  With a wide
+// prime among sources or targets: balanced signed 8-bit digits ii of the
+// representative of ([qhat_i]_t 2^32 2^(8j)) mod t in [-128 * 0x1010101, 127 * 0x1010101],
+// followed by the int32 correction 128 * (sum of the row's digits) of every output
+// row (mblocks x 32), which undoes the operand bias b - 128.
+std::vector<int8_t> bconv_table(const std::vector<uint32_t>& src, const std::vector<uint32_t>& dst, bool wide) {
   const int ns = (int)src.size(), nd = (int)dst.size();
   const int kb = (ns + 7) / 8, mb = (nd + 7) / 8;
-  std::vector<int8_t> out((size_t)mb * kb * 1024, 0);
-  // Montgomery-form [qhat_i]_t * 2^(7j) mod t, chunked
+  std::vector<int8_t> out((size_t)mb * kb * 1024 + (wide ? (size_t)mb * 32 * 4 : 0), 0);
+  // Montgomery-form [qhat_i]_t
   std::vector<uint32_t> qh((size_t)nd * ns);
   for (int t = 0; t < nd; ++t) {
     const uint32_t p = dst[t];
@@ -62,6 +78,8 @@ std::vector<int8_t> bconv_table(const std::vector<uint32_t>& src, const std::vec
       qh[(size_t)t * ns + i] = (uint32_t)(h * (((uint64_t)1 << 32) % p) % p);
     }
   }
+  std::vector<int64_t> rowsum((size_t)mb * 32, 0);
+  const int64_t hi = 127 * (int64_t)0x1010101;
   for (int m = 0; m < mb; ++m)
     for (int k = 0; k < kb; ++k)
       for (int lane = 0; lane < 64; ++lane)
@@ -72,11 +90,24 @@ std::vector<int8_t> bconv_table(const std::vector<uint32_t>& src, const std::vec
           int8_t v = 0;
           if (t < nd && i < ns) {
             const uint32_t p = dst[t];
-            uint64_t x = ((uint64_t)qh[(size_t)t * ns + i] << (kChunkBits * j)) % p;
-            v = (int8_t)((x >> (kChunkBits * ii)) & 0x7f);
+            if (wide) {
+              const uint64_t x = ((uint64_t)qh[(size_t)t * ns + i] << (8 * j)) % p;
+              int8_t dg[4];
+              balanced_digits4((int64_t)x > hi ? (int64_t)x - (int64_t)p : (int64_t)x, dg);
+              v = dg[ii];
+            } else {
+              const uint64_t x = ((uint64_t)qh[(size_t)t * ns + i] << (kChunkBits * j)) % p;
+              v = (int8_t)((x >> (kChunkBits * ii)) & 0x7f);
+            }
           }
           out[((size_t)(m * kb + k) * 1024) + lane * 16 + e] = v;
+          rowsum[row] += v;
         }
+  if (wide)
+    for (int r = 0; r < mb * 32; ++r) {
+      const int32_t c = (int32_t)(128 * rowsum[r]);
+      std::memcpy(&out[(size_t)mb * kb * 1024 + 4 * (size_t)r], &c, 4);
+    }
   return out;
 }
 
@@ -93,7 +124,10 @@ cross_status make_bconv(cross_ctx ctx, const std::vector<uint32_t>& sp, const st
   }
   std::vector<BconvDst> d(dp.size());
   for (size_t t = 0; t < dp.size(); ++t) d[t] = BconvDst{doff[t], dp[t], inv_mod_2_32(dp[t])};
-  std::vector<int8_t> tab = bconv_table(sp, dp);
+  bool wide = false;
+  for (uint32_t q : sp) wide = wide || wide_prime(q);
+  for (uint32_t q : dp) wide = wide || wide_prime(q);
+  std::vector<int8_t> tab = bconv_table(sp, dp, wide);
   void *a = nullptr, *b = nullptr, *c = nullptr;
   cross_status st = cached_device_copy(ctx, s.data(), s.size() * sizeof(BconvSrc), &a);
   if (st == CROSS_OK) st = cached_device_copy(ctx, d.data(), d.size() * sizeof(BconvDst), &b);
@@ -104,12 +138,13 @@ cross_status make_bconv(cross_ctx ctx, const std::vector<uint32_t>& sp, const st
   out->table = (const int8_t*)c;
   out->nsrc = (int)sp.size();
   out->ndst = (int)dp.size();
+  out->wide = wide ? 1 : 0;
   return CROSS_OK;
 }
 
 hipError_t run_bconv(cross_ctx ctx, const BconvStatic& bs, const uint32_t* in, uint64_t in_stride,
                      uint32_t* out, uint64_t out_stride, int npoly, int log_n, hipStream_t s) {
-  BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, in, out, in_stride, out_stride, npoly, log_n};
+  BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, in, out, in_stride, out_stride, npoly, log_n, bs.wide};
   ProfScope ps(ctx, "bconv", s);
   return launch_bconv(g, s);
 }
@@ -117,9 +152,9 @@ hipError_t run_bconv(cross_ctx ctx, const BconvStatic& bs, const uint32_t* in, u
 
 
 
-cross_status validate_primes(cross_ctx ctx, const uint32_t* p, uint32_t n, uint32_t log_n) {
+cross_status validate_primes(cross_ctx ctx, const uint32_t* p, uint32_t n, uint32_t log_n, bool wide_ok = false) {
   for (uint32_t i = 0; i < n; ++i) {
-    cross_status st = check_prime(ctx, p[i], log_n);
+    cross_status st = check_prime(ctx, p[i], log_n, wide_ok);
     if (st != CROSS_OK) return st;
     for (uint32_t j = 0; j < i; ++j)
       if (p[j] == p[i]) return fail(ctx, CROSS_EINVAL, "primes must be pairwise distinct");
@@ -601,10 +636,10 @@ cross_status cross_bconv(cross_ctx ctx, uint32_t log_n, const uint32_t* src_prim
     return fail(ctx, CROSS_EINVAL, "null or misaligned pointer");
   if (log_n < 5 || log_n > CROSS_MAX_LOG_N || l < 1 || l > 32 || lp < 1 || lp > CROSS_MAX_LIMBS || batch < 1)
     return fail(ctx, CROSS_EINVAL, "bad shape (1 <= l <= 32, 1 <= lp <= 64, 5 <= log_n <= 16)");
-  st = validate_primes(ctx, src_primes, l, 0);
+  st = validate_primes(ctx, src_primes, l, 0, true);
   if (st != CROSS_OK) return st;
   for (uint32_t j = 0; j < lp; ++j) {
-    st = check_prime(ctx, dst_primes[j], 0);
+    st = check_prime(ctx, dst_primes[j], 0, true);
     if (st != CROSS_OK) return st;
   }
   const uint64_t N = 1ull << log_n;

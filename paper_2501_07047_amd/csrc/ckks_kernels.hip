@@ -214,10 +214,15 @@ limb_copy_kernel(const v4u* src, uint64_t src_stride4, const uint64_t* src_off, 
 // them as column l % 32: after the four products of a 32-target block each lane
 // holds four consecutive outputs of each of its targets, stored as one 16-byte word.
 // Source and target descriptors are wave-uniform loads (one per pair of lane halves).
+//
+// Wide primes (template flag WIDE): the B operand is the four bytes of each step-1
+// residue, each as b - 128 (one XOR); the accumulators start at the table's int32 row
+// corrections, so they hold the plain digit sums, which merge_redc_wide32 merges
+// with weights 2^(8i) and reduces (contractions of at most 32 sources).
 constexpr int BCONV_MAX_KB = 4;   // up to 32 source limbs
 constexpr int BCONV_COLS = 128;   // coefficients per wave
 
-template <int KB>
+template <int KB, bool WIDE = false>
 __device__ __forceinline__ void bconv_wave(const BconvLaunch& g, uint64_t wave_global) {
   const int lane = threadIdx.x & 63, half = lane >> 5;
   const uint64_t total = (uint64_t)g.npoly << g.log_n;
@@ -248,7 +253,10 @@ __device__ __forceinline__ void bconv_wave(const BconvLaunch& g, uint64_t wave_g
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int k = 0; k < 4; ++k) bf[kb][k][e] = (int)pack_chunks(mulmod_shoup(x[e][k], sd[e].w, sd[e].w_shoup, sd[e].q));
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t y = mulmod_shoup(x[e][k], sd[e].w, sd[e].w_shoup, sd[e].q);
+        bf[kb][k][e] = WIDE ? (int)(y ^ 0x80808080u) : (int)pack_chunks(y);
+      }
   }
 
   for (int mb = 0; mb < mblocks; ++mb) {
@@ -267,19 +275,36 @@ __device__ __forceinline__ void bconv_wave(const BconvLaunch& g, uint64_t wave_g
     // product k, merged and reduced at once: r[g4][k] is target mb * 8 + 2 g4 + half
     // at coefficient 4 (l % 32) + k
     uint32_t r[4][4];
+    // wide: lane l's register v of a 32-row block holds row 8 (v / 4) + 4 half + v % 4
+    v16i acc0 = v16i{};
+    if constexpr (WIDE) {
+      const int* corr = reinterpret_cast<const int*>(g.table + (size_t)mblocks * kblocks * 1024) + mb * 32;
+#pragma unroll
+      for (int g4 = 0; g4 < 4; ++g4) {
+        const v4i c = *reinterpret_cast<const v4i*>(corr + 8 * g4 + 4 * half);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc0[4 * g4 + i] = c[i];
+      }
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      v16i acc = v16i{};
+      v16i acc = acc0;
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb)
         if (kb < kblocks) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[kb], bf[kb][k], acc, 0, 0, 0);
 #pragma unroll
       for (int g4 = 0; g4 < 4; ++g4) {
-        const uint64_t z = (uint64_t)(uint32_t)acc[4 * g4] + ((uint64_t)(uint32_t)acc[4 * g4 + 1] << 7) +
-                           ((uint64_t)(uint32_t)acc[4 * g4 + 2] << 14) + ((uint64_t)(uint32_t)acc[4 * g4 + 3] << 21);
-        const uint32_t tq = (uint32_t)z * d[g4].qinv;
-        const uint32_t v = (uint32_t)(z >> 32) + d[g4].q - __umulhi(tq, d[g4].q);
-        r[g4][k] = v >= d[g4].q ? v - d[g4].q : v;
+        if constexpr (WIDE) {
+          r[g4][k] = merge_redc_wide32(acc[4 * g4], acc[4 * g4 + 1], acc[4 * g4 + 2], acc[4 * g4 + 3], d[g4].q,
+                                       d[g4].qinv);
+        } else {
+          const uint64_t z = (uint64_t)(uint32_t)acc[4 * g4] + ((uint64_t)(uint32_t)acc[4 * g4 + 1] << 7) +
+                             ((uint64_t)(uint32_t)acc[4 * g4 + 2] << 14) +
+                             ((uint64_t)(uint32_t)acc[4 * g4 + 3] << 21);
+          const uint32_t tq = (uint32_t)z * d[g4].qinv;
+          const uint32_t v = (uint32_t)(z >> 32) + d[g4].q - __umulhi(tq, d[g4].q);
+          r[g4][k] = v >= d[g4].q ? v - d[g4].q : v;
+        }
       }
     }
 #pragma unroll
@@ -291,10 +316,10 @@ __device__ __forceinline__ void bconv_wave(const BconvLaunch& g, uint64_t wave_g
 
 // Occupancy: four waves per SIMD for one K block (120 registers, no spills), fewer
 // for deeper conversions (more live B operands).
-template <int KB>
+template <int KB, bool WIDE = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB == 1 ? 4 : KB == 2 ? 3 : 2)))
 bconv_kernel(BconvLaunch g) {
-  bconv_wave<KB>(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  bconv_wave<KB, WIDE>(g, ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 // Work-list form (batch runtime): one task per blockIdx.y, KB the largest K-block
@@ -501,7 +526,7 @@ hipError_t launch_tail_list(const TailTask* t, int n, uint64_t max4, hipStream_t
 }
 hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_cols, int max_nsrc, hipStream_t s) {
   if (n <= 0 || max_cols == 0) return hipSuccess;
-  if (max_nsrc < 1 || max_nsrc > 8 * BCONV_MAX_KB) return hipErrorInvalidValue;
+  if (max_nsrc < 1 || max_nsrc > 8 * BCONV_MAX_KB) return hipErrorInvalidValue;   // (narrow primes only)
   const dim3 grid(blocks_for((max_cols + BCONV_COLS - 1) / BCONV_COLS * 64), n);
   switch ((max_nsrc + 7) >> 3) {
     case 1: launch_kernel(bconv_list_kernel<1>, grid, dim3(256), 0, s, t); break;
@@ -520,8 +545,8 @@ hipError_t launch_bconv_multi(const BconvLaunch* gs, int n, hipStream_t s) {
     int nsrc = 1;
     for (int i = 0; i < cnt; ++i) {
       const BconvLaunch& b = gs[base + i];
-      if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5 || b.npoly < 0)
-        return hipErrorInvalidValue;
+      if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5 || b.npoly < 0 || b.wide)
+        return hipErrorInvalidValue;      // narrow primes only (the CKKS key-switch limbs)
       m.g[i] = b;
       cols = std::max(cols, (uint64_t)b.npoly << b.log_n);
       nsrc = std::max(nsrc, b.nsrc);
@@ -545,6 +570,15 @@ hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s) {
   if (b.npoly <= 0) return hipSuccess;
   const uint64_t waves = (((uint64_t)b.npoly << b.log_n) + BCONV_COLS - 1) / BCONV_COLS;
   const dim3 grid(blocks_for(waves * 64));
+  if (b.wide) {
+    switch ((b.nsrc + 7) >> 3) {
+      case 1: launch_kernel(bconv_kernel<1, true>, grid, dim3(256), 0, s, b); break;
+      case 2: launch_kernel(bconv_kernel<2, true>, grid, dim3(256), 0, s, b); break;
+      case 3: launch_kernel(bconv_kernel<3, true>, grid, dim3(256), 0, s, b); break;
+      default: launch_kernel(bconv_kernel<4, true>, grid, dim3(256), 0, s, b); break;
+    }
+    return hipGetLastError();
+  }
   switch ((b.nsrc + 7) >> 3) {
     case 1: launch_kernel(bconv_kernel<1>, grid, dim3(256), 0, s, b); break;
     case 2: launch_kernel(bconv_kernel<2>, grid, dim3(256), 0, s, b); break;

@@ -12,6 +12,7 @@ struct BconvStatic {
   const BconvDst* dst = nullptr;
   const int8_t* table = nullptr;
   int nsrc = 0, ndst = 0;
+  int wide = 0;             // a prime >= 2^28: byte operands, signed digits, row corrections
 };
 
 

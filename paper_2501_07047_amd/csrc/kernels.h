@@ -357,10 +357,16 @@ struct BconvLaunch {
   uint32_t* out;
   uint64_t in_stride, out_stride;   // elements per polynomial
   int npoly, log_n;
+  // 1 when a source or target prime is wide (2^28 <= q < 2^31): the operand is
+  // the four bytes of each step-1 residue fed as b - 128, the table holds balanced
+  // signed 8-bit digits followed by one int32 row correction 128 * (row sum) per
+  // output row (mblocks x 32), and the epilogue merges with weights 2^(8i)
+  int wide;
 };
 hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s);
 // Several conversions in one launch (by value, kBconvMulti per launch; more are
-// split over launches), e.g. the digits of one ModUp.
+// split over launches), e.g. the digits of one ModUp.  Narrow primes only, as in
+// the work-list form.
 constexpr int kBconvMulti = 8;
 struct BconvMulti {
   BconvLaunch g[kBconvMulti];

@@ -58,6 +58,38 @@ def test_bconv_shapes(log_n, l, lp, batch):
         assert np.array_equal(got[bi], bconv_u64(x[bi], src, dst))
 
 
+@pytest.mark.parametrize("log_n,l,lp,batch,mix", [(8, 3, 5, 2, "wide"), (12, 8, 24, 1, "wide"),
+                                                  (16, 12, 36, 1, "narrow_src"), (10, 20, 40, 2, "wide"),
+                                                  (10, 32, 8, 1, "wide_src"), (5, 1, 1, 1, "wide")])
+def test_bconv_wide_primes(log_n, l, lp, batch, mix):
+    # primes in [2^30, 2^31) take the byte form (b - 128 against balanced signed digits
+    # with per-row corrections): one to four K blocks, wide / narrow sources and targets
+    from paper_2501_07047_amd import binding as B
+    wp = synthetic.wide_primes(l + lp)
+    npr = synthetic.primes(l + lp)
+    src = npr[:l] if mix == "narrow_src" else wp[:l]
+    dst = npr[l:] if mix == "wide_src" else wp[l:]
+    g = synthetic.rng(l * 100 + lp + 7)
+    x = synthetic.residues(g, (batch,), src, 1 << log_n)
+    x[0, :, 0] = [q - 1 for q in src]
+    x[0, :, 1] = 0
+    out = _empty((batch, lp, 1 << log_n))
+    B.bconv(to_dev(x), src, dst, out)
+    got = to_host(out)
+    for bi in range(batch):
+        assert np.array_equal(got[bi], bconv_u64(x[bi], src, dst)), "batch %d" % bi
+
+
+def test_bconv_rejects_primes_from_2_31():
+    from paper_2501_07047_amd import binding as B
+    src = synthetic.wide_primes(2)
+    x = synthetic.residues(synthetic.rng(1), (1,), src, 64)
+    out = _empty((1, 1, 64))
+    with pytest.raises(B.CrossError) as e:
+        B.bconv(to_dev(x), src, [2147483659], out)     # a prime above 2^31
+    assert e.value.code == -4                            # CROSS_ERANGE
+
+
 def _ckks(log_n, L, dnum, K=None, seed=0, batch=1):
     return synthetic.ckks_pair(seed, log_n, L, dnum, K, batch)
 

@@ -35,6 +35,24 @@ def test_bconv_u64_equals_bigint():
     assert np.array_equal(BC.bconv_u64(a, src, dst), BC.bconv_bigint(a, src, dst))
 
 
+def test_bconv_u64_equals_bigint_wide_primes():
+    # primes in [2^30, 2^31): products of two residues stay below 2^62, so the uint64
+    # form is still exact; the lift y is still a CRT lift plus a small multiple of Q
+    import synthetic
+    wp = synthetic.wide_primes(7)
+    src, dst = wp[:3], wp[3:] + prime_chain(2)
+    g = np.random.Generator(np.random.PCG64(3))
+    a = np.stack([g.integers(0, q, 32) for q in src])
+    a[:, 0] = [q - 1 for q in src]
+    a[:, 1] = 0
+    assert np.array_equal(BC.bconv_u64(a, src, dst), BC.bconv_bigint(a, src, dst))
+    Q = prod(src)
+    for n in range(a.shape[1]):
+        col = [int(v) for v in a[:, n]]
+        y = BC.bconv_y(col, src)
+        assert all(y % q == c for q, c in zip(src, col)) and 0 <= y < len(src) * Q
+
+
 def test_bconv_single_source_is_reduction():
     # |S| = 1: qhat = 1, so the conversion is plain reduction of a into each target
     src = [prime_chain(1)[0]]
