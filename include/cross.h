@@ -20,9 +20,12 @@
  *    canonical primitive 2N-th root g^((q-1)/2N), g the smallest generator of
  *    Z_q^* (see cross_root).
  *  - Primes: 2 < q < 2^28, prime, q = 1 (mod 2N).  The NTT entry points
- *    (cross_ntt_forward/inverse and their butterfly forms) also take wide
- *    primes 2^28 <= q < 2^31 (see cross_ntt_forward).  Arrays of primes are host
- *    memory.
+ *    (cross_ntt_forward/inverse and their butterfly forms), cross_bconv and the
+ *    CKKS operators (cross_keyswitch_modup/moddown, cross_he_mult, cross_rotate,
+ *    cross_rescale) also take wide primes 2^28 <= q < 2^31 (see
+ *    cross_ntt_forward and cross_bconv; with a wide prime the CKKS operators run
+ *    their separate, unfused kernels); the batch runtime does not.  Arrays of
+ *    primes are host memory.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls return
  *    after enqueueing; argument errors are reported synchronously and nothing
  *    is enqueued; device faults surface at the caller's next synchronisation.
@@ -47,7 +50,7 @@ typedef enum cross_status {
   CROSS_ENOTPRIME = -2,    /* a modulus is not prime */
   CROSS_ENOROOT = -3,      /* q != 1 (mod 2N): no primitive 2N-th root of unity */
   CROSS_ERANGE = -4,       /* q >= 2^28 (residues must split into four 7-bit chunks); for
-                              the NTT entry points q >= 2^31 */
+                              the entry points that take wide primes q >= 2^31 */
   CROSS_ENOMEM = -5,       /* device allocation failed */
   CROSS_EDEVICE = -6,      /* HIP runtime error while enqueueing */
   CROSS_EUNSUPPORTED = -7, /* valid but unsupported shape */
@@ -229,7 +232,7 @@ cross_status cross_keyswitch_moddown(cross_ctx ctx, const cross_ckks_params* par
  *                    ct_b or relin_key (ct_a and ct_b may be the same buffer)
  *   relin_key      : device [dnum][2][L+K][N] NTT form, index 0 = b, 1 = a
  * Errors: CROSS_EINVAL for null / misaligned / overlapping buffers or bad
- * parameters, prime checks as cross_ntt_forward (q < 2^28).
+ * parameters, prime checks as cross_ntt_forward (q < 2^31).
  */
 cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* params, const uint32_t* ct_a,
                            const uint32_t* ct_b, const uint32_t* relin_key, uint32_t* out,
@@ -404,7 +407,8 @@ typedef struct cross_job {
 } cross_job;
 typedef struct cross_batch_s* cross_batch;
 /* Plan the jobs (tables, task lists, workspace) and, if use_graph, capture the
- * launch sequence into a hipGraph.  No device work runs until cross_batch_run. */
+ * launch sequence into a hipGraph.  No device work runs until cross_batch_run.
+ * Primes below 2^28 only (CROSS_ERANGE for a wide prime in any job). */
 cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
                                 cross_batch* out);
 /* Bytes of device workspace a batch of these jobs needs when the caller provides it. */

@@ -399,6 +399,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     } else if (J.op == CROSS_OP_HE_MULT || J.op == CROSS_OP_ROTATE) {
       cross_status st = get_ckks_plan(ctx, &P, &jp[j].c);
       if (st != CROSS_OK) return st;
+      if (jp[j].c->wide) return fail(ctx, CROSS_ERANGE, "the batch runtime takes primes below 2^28 only");
       for (uint32_t t : jp[j].c->primes) {
         Plan* p = nullptr;
         if ((st = batch_plan(ctx, t, (int)P.log_n, &p)) != CROSS_OK) return st;
@@ -519,7 +520,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     std::vector<uint64_t> eo;
     for (int dj = 0; dj < c->ndig; ++dj) {
       const BconvStatic& bs = c->modup[dj];
-      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, fuse ? z : d, ext, nd, next, B, c->log_n};
+      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, fuse ? z : d, ext, nd, next, B, c->log_n, bs.wide};
       b->bconv_up.push_back(g);
       b->max_cols_up = std::max(b->max_cols_up, (uint64_t)B << c->log_n);
       b->max_nsrc_up = std::max(b->max_nsrc_up, bs.nsrc);
@@ -560,7 +561,7 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     add_ntt(b.get(), b->ntt[kNttInvP], pp, po, acc, tmp, (uint64_t)LK * N, 2 * B, true);
     {
       const BconvStatic& bs = c->moddown;
-      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, acc, z, (uint64_t)LK * N, nd, 2 * B, c->log_n};
+      BconvLaunch g{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, acc, z, (uint64_t)LK * N, nd, 2 * B, c->log_n, bs.wide};
       b->bconv_down.push_back(g);
       b->max_cols_down = std::max(b->max_cols_down, (uint64_t)(2 * B) << c->log_n);
       b->max_nsrc_down = std::max(b->max_nsrc_down, bs.nsrc);

@@ -185,10 +185,11 @@ cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan
     *out = static_cast<CkksPlan*>(it->second.get());
     return CROSS_OK;
   }
-  cross_status st = validate_primes(ctx, prm->primes, L + K, prm->log_n);
+  cross_status st = validate_primes(ctx, prm->primes, L + K, prm->log_n, true);
   if (st != CROSS_OK) return st;
   std::shared_ptr<CkksPlan> holder = std::make_shared<CkksPlan>();
   CkksPlan* c = holder.get();
+  for (int i = 0; i < L + K; ++i) c->wide = c->wide || wide_prime(prm->primes[i]);
   c->log_n = (int)prm->log_n;
   c->L = L;
   c->K = K;
@@ -374,7 +375,7 @@ cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t*
   for (int j = 0; j < c->ndig; ++j) {
     const BconvStatic& bs = c->modup[j];
     gs.push_back(BconvLaunch{bs.src, bs.dst, bs.table, bs.nsrc, bs.ndst, coef, ext, (uint64_t)L * N, ext_stride, B,
-                             c->log_n});
+                             c->log_n, bs.wide});
     for (int t : c->targets[j]) {
       nl.push_back(t);
       no.push_back(((uint64_t)j * LK + t) * N);
@@ -565,7 +566,7 @@ cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* ke
   {
     ProfScope ps(ctx, "inner_product", s);
     HIPCHK(launch_inner_product(w.ext, key, w.acc, c->mods, c->L + c->K, c->dnum, c->ndig, c->log_n, B, s, w.d,
-                                c->L, c->alpha),
+                                c->L, c->alpha, c->wide),
            "inner product");
   }
   return moddown_core(ctx, c, w.acc, 2 * B, w.z, base, base_only_even, out, w.tmp, s);
@@ -719,7 +720,7 @@ cross_status cross_he_mult(cross_ctx ctx, const cross_ckks_params* prm, const ui
   }
   {
     ProfScope ps(ctx, "tensor", s);
-    HIPCHK(launch_tensor(ct_a, ct_b, out, w.d, c->mods, c->L, c->log_n, (int)batch, s), "tensor");
+    HIPCHK(launch_tensor(ct_a, ct_b, out, w.d, c->mods, c->L, c->log_n, (int)batch, s, c->wide), "tensor");
   }
   return keyswitch_into(ctx, c, relin_key, (int)batch, w, out, out, false, s);
 }

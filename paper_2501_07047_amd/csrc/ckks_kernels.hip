@@ -31,6 +31,26 @@ __device__ __forceinline__ uint32_t mulmod(uint32_t a, uint32_t b, const LimbMod
   return r;
 }
 
+// The same product for wide primes (2^28 <= q < 2^31): the remainder before the two
+// subtractions is below 3q, which needs 33 bits, so it is kept in 64.
+__device__ __forceinline__ uint32_t mulmod_wide(uint32_t a, uint32_t b, const LimbMod& md) {
+  const uint64_t z = (uint64_t)a * b;
+  const uint32_t zh = (uint32_t)(z >> (md.bar_k - 1));
+  const uint32_t t = (uint32_t)(((uint64_t)zh * md.bar_m) >> (md.bar_k + 1));
+  uint64_t r = z - (uint64_t)t * md.q;
+  if (r >= md.q) r -= md.q;
+  if (r >= md.q) r -= md.q;
+  return (uint32_t)r;
+}
+
+template <bool WIDE>
+__device__ __forceinline__ uint32_t mulmod_t(uint32_t a, uint32_t b, const LimbMod& md) {
+  if constexpr (WIDE)
+    return mulmod_wide(a, b, md);
+  else
+    return mulmod(a, b, md);
+}
+
 __device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t q) {
   uint32_t r = a + b;
   return r >= q ? r - q : r;
@@ -47,6 +67,7 @@ __device__ __forceinline__ uint32_t pack_chunks(uint32_t x) {
   return (x & 0x7fu) | ((x << 1) & 0x7f00u) | ((x << 2) & 0x7f0000u) | ((x << 3) & 0x7f000000u);
 }
 
+template <bool WIDE>
 __global__ void __launch_bounds__(256)
 tensor_kernel(const v4u* a, const v4u* b, v4u* out, v4u* d2, const LimbMod* mods, int L,
               int log_n4, uint64_t total4) {
@@ -64,9 +85,9 @@ tensor_kernel(const v4u* a, const v4u* b, v4u* out, v4u* d2, const LimbMod* mods
   v4u r0, r1, r2;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    r0[k] = mulmod(a0[k], b0[k], md);
-    r1[k] = addmod(mulmod(a0[k], b1[k], md), mulmod(a1[k], b0[k], md), md.q);
-    r2[k] = mulmod(a1[k], b1[k], md);
+    r0[k] = mulmod_t<WIDE>(a0[k], b0[k], md);
+    r1[k] = addmod(mulmod_t<WIDE>(a0[k], b1[k], md), mulmod_t<WIDE>(a1[k], b0[k], md), md.q);
+    r2[k] = mulmod_t<WIDE>(a1[k], b1[k], md);
   }
   out[o0] = r0;
   out[o1] = r1;
@@ -79,6 +100,7 @@ constexpr int kIpCts = 4;
 
 // With d (NTT-form ModUp input [B][L][N]), digit j's own limbs t in [j alpha,
 // (j + 1) alpha) are read from d instead of ext (where they are not stored).
+template <bool WIDE>
 __global__ void __launch_bounds__(256)
 inner_product_kernel(const v4u* ext, const v4u* key, v4u* acc, const LimbMod* mods, int LK,
                      int dnum, int ndig, int log_n4, int B, uint64_t total4, const v4u* d, int L, int alpha) {
@@ -105,8 +127,8 @@ inner_product_kernel(const v4u* ext, const v4u* key, v4u* acc, const LimbMod* mo
                           : ext[(((uint64_t)(b0 + c) * dnum + j) * LK + t) * per_limb + w];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          s0[c][k] = addmod(s0[c][k], mulmod(e[k], k0[k], md), md.q);
-          s1[c][k] = addmod(s1[c][k], mulmod(e[k], k1[k], md), md.q);
+          s0[c][k] = addmod(s0[c][k], mulmod_t<WIDE>(e[k], k0[k], md), md.q);
+          s1[c][k] = addmod(s1[c][k], mulmod_t<WIDE>(e[k], k1[k], md), md.q);
         }
       }
     }
@@ -435,21 +457,28 @@ inline unsigned blocks_for(uint64_t total, int per = 256) { return (unsigned)((t
 }  // namespace
 
 hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
-                         const LimbMod* mods, int L, int log_n, int B, hipStream_t s) {
+                         const LimbMod* mods, int L, int log_n, int B, hipStream_t s, bool wide) {
   const uint64_t total4 = ((uint64_t)B * L) << (log_n - 2);
-  launch_kernel(tensor_kernel, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a,
-                     (const v4u*)b, (v4u*)out, (v4u*)d2, mods, L, log_n - 2, total4);
+  if (wide)
+    launch_kernel(tensor_kernel<true>, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a, (const v4u*)b,
+                  (v4u*)out, (v4u*)d2, mods, L, log_n - 2, total4);
+  else
+    launch_kernel(tensor_kernel<false>, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)a, (const v4u*)b,
+                  (v4u*)out, (v4u*)d2, mods, L, log_n - 2, total4);
   return hipGetLastError();
 }
 
 hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32_t* acc,
                                 const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
-                                hipStream_t s, const uint32_t* d, int L, int alpha) {
+                                hipStream_t s, const uint32_t* d, int L, int alpha, bool wide) {
   const uint64_t groups = (uint64_t)(B + kIpCts - 1) / kIpCts;
   const uint64_t total4 = (groups * LK) << (log_n - 2);
-  launch_kernel(inner_product_kernel, dim3(blocks_for(total4)), dim3(256), 0, s,
-                     (const v4u*)ext, (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2, B,
-                     total4, (const v4u*)d, L, alpha);
+  if (wide)
+    launch_kernel(inner_product_kernel<true>, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)ext,
+                  (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2, B, total4, (const v4u*)d, L, alpha);
+  else
+    launch_kernel(inner_product_kernel<false>, dim3(blocks_for(total4)), dim3(256), 0, s, (const v4u*)ext,
+                  (const v4u*)key, (v4u*)acc, mods, LK, dnum, ndig, log_n - 2, B, total4, (const v4u*)d, L, alpha);
   return hipGetLastError();
 }
 
@@ -538,6 +567,16 @@ hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_cols, int
 }
 
 hipError_t launch_bconv_multi(const BconvLaunch* gs, int n, hipStream_t s) {
+  bool wide = false;
+  for (int i = 0; i < n; ++i) wide = wide || gs[i].wide;
+  if (wide) {
+    // the byte form: one launch per conversion
+    for (int i = 0; i < n; ++i) {
+      const hipError_t e = launch_bconv(gs[i], s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   for (int base = 0; base < n; base += kBconvMulti) {
     BconvMulti m{};
     const int cnt = n - base < kBconvMulti ? n - base : kBconvMulti;
@@ -545,8 +584,8 @@ hipError_t launch_bconv_multi(const BconvLaunch* gs, int n, hipStream_t s) {
     int nsrc = 1;
     for (int i = 0; i < cnt; ++i) {
       const BconvLaunch& b = gs[base + i];
-      if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5 || b.npoly < 0 || b.wide)
-        return hipErrorInvalidValue;      // narrow primes only (the CKKS key-switch limbs)
+      if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5 || b.npoly < 0)
+        return hipErrorInvalidValue;
       m.g[i] = b;
       cols = std::max(cols, (uint64_t)b.npoly << b.log_n);
       nsrc = std::max(nsrc, b.nsrc);

@@ -18,6 +18,7 @@ struct BconvStatic {
 
 struct CkksPlan {
   int log_n = 0, L = 0, K = 0, dnum = 0, alpha = 0, ndig = 0;
+  bool wide = false;                      // a prime >= 2^28: 64-bit remainders in the VALU products
   std::vector<uint32_t> primes;
   std::vector<Plan*> plans;               // L + K
   std::vector<Plan*> plans2;              // the same primes in the two-factor form (batch runtime)

@@ -191,7 +191,7 @@ struct LimbMod {
 // out0 = a0 b0, out1 = a0 b1 + a1 b0, d2 = a1 b1, limb-wise mod q_i.
 // a, b, out: [B][2][L][N]; d2: [B][L][N].
 hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, uint32_t* d2,
-                         const LimbMod* mods, int L, int log_n, int B, hipStream_t s);
+                         const LimbMod* mods, int L, int log_n, int B, hipStream_t s, bool wide = false);
 
 // Key-switch inner product: acc[b][s][t] = sum_j ext[b][j][t] * key[j][s][t] mod p_t,
 // j < ndig (active digits), s in {0, 1}.  ext: [B][dnum][LK][N], key: [dnum][2][LK][N],
@@ -199,7 +199,8 @@ hipError_t launch_tensor(const uint32_t* a, const uint32_t* b, uint32_t* out, ui
 // min((j + 1) alpha, L)) are read from d[b][t] instead of ext[b][j][t].
 hipError_t launch_inner_product(const uint32_t* ext, const uint32_t* key, uint32_t* acc,
                                 const LimbMod* mods, int LK, int dnum, int ndig, int log_n, int B,
-                                hipStream_t s, const uint32_t* d = nullptr, int L = 0, int alpha = 0);
+                                hipStream_t s, const uint32_t* d = nullptr, int L = 0, int alpha = 0,
+                                bool wide = false);
 
 // Per-limb constants of the chunked stream forms (streams.hip).
 struct StreamMod {

@@ -146,6 +146,22 @@ def test_batch_rejects_bad_jobs():
     assert e.value.code == -7
 
 
+def test_batch_rejects_wide_primes():
+    # the work-list kernels are narrow-only: a wide prime (2^28 <= q < 2^31) in a
+    # CKKS job is refused with CROSS_ERANGE before anything is planned
+    from paper_2501_07047_amd import binding as B
+    wp = synthetic.wide_primes(6)
+    qs, ps = wp[:4], wp[4:]
+    n = 1 << 14
+    a = synthetic.residues(synthetic.rng(5), (1, 2), qs, n)
+    key = synthetic.residues(synthetic.rng(6), (2, 2), qs + ps, n)
+    out = to_dev(np.zeros_like(a))
+    with pytest.raises(B.CrossError) as e:
+        B.Batch([{"op": "he_mult", "a": to_dev(a), "b": to_dev(a), "key": to_dev(key), "out": out,
+                  "qs": qs, "ps": ps, "dnum": 2}])
+    assert e.value.code == -4
+
+
 def test_tuned_list_tiles_keep_batch_results():
     """After the autotuner has chosen the batch runtime's work-list tiles for N = 2^13
     and 2^14 (two- and three-factor forms), a mixed batch still equals the per-call

@@ -192,10 +192,14 @@ def test_keyswitch_semantics_with_real_keys(L, dnum):
     assert _centered_max(diff, qs) < 1 << 24          # versus Q ~ 2^(28 L)
 
 
-def test_he_mult_and_rotate_decrypt_correctly():
+@pytest.mark.parametrize("wide", [False, True])
+def test_he_mult_and_rotate_decrypt_correctly(wide):
+    # wide: primes in [2^30, 2^31) (the byte forms of the library); the oracle's
+    # products of two residues stay below 2^62, so it is exact there too
+    import synthetic
     n, L, dnum = 64, 6, 3
     _, alpha = CK.digits(L, dnum)
-    chain = prime_chain(L + alpha)
+    chain = synthetic.wide_primes(L + alpha) if wide else prime_chain(L + alpha)
     qs, ps = chain[:L], chain[L:]
     allp = qs + ps
     g = np.random.Generator(np.random.PCG64(77))
