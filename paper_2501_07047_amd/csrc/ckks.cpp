@@ -367,8 +367,8 @@ cross_status modup_core(cross_ctx ctx, const CkksPlan* c, uint32_t* d, uint32_t*
   cross_status st = ntt_limbs(ctx, pl, lo, d, (uint64_t)L * N, B, true, tmp, s, x);
   if (st != CROSS_OK) return st;
   const uint32_t* coef = x ? x : d;
-  // 3. BConv of each digit to the other limbs, then 4. NTT of all converted limbs in one launch
-  // (all digits in one launch)
+  // 3. BConv of each digit to the other limbs (all digits in one launch), then 4. NTT of
+  // all converted limbs in one launch
   std::vector<int> nl;
   std::vector<uint64_t> no;
   std::vector<BconvLaunch> gs;
@@ -549,7 +549,8 @@ cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* ke
     for (int t = 0; t < LK; ++t) {
       const Plan* p = c->plans[t];
       const LimbMod m = limb_mod(p->q);
-      lm[t] = IpLimb{p->row_fwd_b, p->row_fwd_t3_mont, p->q, p->qinv, m.bar_m, m.bar_k, t < c->L ? t / c->alpha : -1, 0};
+      lm[t] = IpLimb{p->row_fwd_b, p->row_fwd_t3_mont, p->q, p->qinv, m.bar_m, m.bar_k,
+                     t < c->L ? t / c->alpha : -1, 0};
     }
     void* dl = nullptr;
     if ((st = cached_device_copy(ctx, lm.data(), lm.size() * sizeof(IpLimb), &dl)) != CROSS_OK) return st;
