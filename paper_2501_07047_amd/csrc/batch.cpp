@@ -537,13 +537,16 @@ cross_status build_batch(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, i
     const int log_r = bp[0]->log_r;
     if (fuse) {
       std::vector<IpLimb> lm(LK);
-      for (int t = 0; t < LK; ++t) {
+      const std::vector<int> order = ip_limb_order(L, K);
+      for (int pos = 0; pos < LK; ++pos) {
+        const int t = order[pos];
         // Barrett constants of the key products: k = bit length of q, m = floor(2^(2k) / q)
         const uint32_t q = bp[t]->q;
         uint32_t k = 0;
         while ((1ull << k) <= q) ++k;
         const uint32_t m = (uint32_t)(((unsigned __int128)1 << (2 * k)) / q);
-        lm[t] = IpLimb{bp[t]->row_fwd_b, bp[t]->row_fwd_t3_mont, q, bp[t]->qinv, m, k, t < L ? t / c->alpha : -1, 0};
+        lm[pos] = IpLimb{bp[t]->row_fwd_b, bp[t]->row_fwd_t3_mont, q, bp[t]->qinv, m, k,
+                         t < L ? t / c->alpha : -1, t};
       }
       void* dl = nullptr;
       cross_status st = cached_device_copy(ctx, lm.data(), lm.size() * sizeof(IpLimb), &dl);

@@ -546,11 +546,13 @@ cross_status keyswitch_into(cross_ctx ctx, const CkksPlan* c, const uint32_t* ke
     for (size_t i = 0; i < cv.limb.size(); ++i) cp[i] = c->plans[cv.limb[i]];
     if ((st = ntt_rowside_forward(ctx, cp, cv.off, w.ext, ext_stride, B, w.tmp, s)) != CROSS_OK) return st;
     std::vector<IpLimb> lm(LK);
-    for (int t = 0; t < LK; ++t) {
+    const std::vector<int> order = ip_limb_order(c->L, c->K);
+    for (int pos = 0; pos < LK; ++pos) {
+      const int t = order[pos];
       const Plan* p = c->plans[t];
       const LimbMod m = limb_mod(p->q);
-      lm[t] = IpLimb{p->row_fwd_b, p->row_fwd_t3_mont, p->q, p->qinv, m.bar_m, m.bar_k,
-                     t < c->L ? t / c->alpha : -1, 0};
+      lm[pos] = IpLimb{p->row_fwd_b, p->row_fwd_t3_mont, p->q, p->qinv, m.bar_m, m.bar_k,
+                       t < c->L ? t / c->alpha : -1, t};
     }
     void* dl = nullptr;
     if ((st = cached_device_copy(ctx, lm.data(), lm.size() * sizeof(IpLimb), &dl)) != CROSS_OK) return st;

@@ -31,6 +31,23 @@ struct CkksPlan {
   const uint64_t* copy_dst = nullptr;
 };
 
+// Order in which the fused ModUp NTT + inner product takes the L + K target limbs:
+// the K special limbs (three transforms each, against two and a load for a Q limb)
+// spread evenly among the Q limbs, so that each XCD's contiguous share of the blocks
+// gets the same mix.  Q limb i sits at (2i + 1) / 2L, special limb k at (2k + 1) / 2K,
+// Q limbs first on ties.
+inline std::vector<int> ip_limb_order(int L, int K) {
+  std::vector<int> ord;
+  int i = 0, k = 0;
+  while (i < L || k < K) {
+    if (k >= K || (i < L && (int64_t)(2 * i + 1) * K <= (int64_t)(2 * k + 1) * L))
+      ord.push_back(i++);
+    else
+      ord.push_back(L + k++);
+  }
+  return ord;
+}
+
 // Validated, cached plan for a parameter set (tables uploaded on first use).
 cross_status get_ckks_plan(cross_ctx ctx, const cross_ckks_params* prm, CkksPlan** out);
 

@@ -268,7 +268,9 @@ struct IpLimb {
                             // transforms come out times 2^32, ready for a Montgomery product
   uint32_t q, qinv;         // prime, q^-1 mod 2^32
   uint32_t bar_m, bar_k;    // Barrett constants of the key products with t's own digit
-  int32_t own, pad;         // digit holding t (-1 for special primes)
+  int32_t own;              // digit holding t (-1 for special primes)
+  int32_t limb;             // t itself: the list runs in the order the blocks take the
+                            // limbs, which need not be 0 .. LK - 1
 };
 struct RowsIp {
   const IpLimb* limbs;

@@ -808,7 +808,10 @@ __device__ __forceinline__ uint32_t ip_mulmod(uint32_t a, uint32_t b, const IpLi
 // digit j, either transforms its row of limb (j, t) of the packed row-side output (t
 // outside digit j) or reads that row of the NTT-form input (t in digit j), and
 // accumulates its products with the two key rows of (j, t) in registers; the two
-// accumulator rows are written once.  The transforms run with T3 * 2^32 as their first
+// accumulator rows are written once.  The blocks take the target limbs in the order of
+// the limb list, which spreads the special limbs (three transforms each, against two and
+// a load for a Q limb) evenly, so that each XCD's contiguous eighth of the blocks holds
+// the same mix of work.  The transforms run with T3 * 2^32 as their first
 // twiddle, so their outputs come out times 2^32 and each key product is one REDC step
 // (four multiplies) instead of a Barrett product (five, and two 64-bit shifts); the key
 // products are most of this kernel's vector work.  Every transform of a block uses t's
@@ -861,12 +864,14 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC sr
     const RowsIp& p = src.at(b, local);
     const uint64_t N = 1024ull << p.rb_log << 3;
     const int per_t = p.B << p.rb_log;
-    const int t = __builtin_amdgcn_readfirstlane(local / per_t);
+    const int tp = __builtin_amdgcn_readfirstlane(local / per_t);    // position in the limb list
     // the wave's (row, ciphertext) pair, the ciphertext fastest
-    const int pair = (local - t * per_t) * kP32Waves + wave;
+    const int pair = (local - tp * per_t) * kP32Waves + wave;
     const int row = __builtin_amdgcn_readfirstlane(pair / p.B);
     const int ct = pair - row * p.B;
-    const IpLimb md = p.limbs[t];
+    const IpLimb md = p.limbs[tp];
+    // the limb index and its digit drive the row addresses and branches: wave-uniform
+    const int t = __builtin_amdgcn_readfirstlane(md.limb), own = __builtin_amdgcn_readfirstlane(md.own);
     if (md.tab != cur_tab) {
       // t's table and first twiddles into LDS (workgroup-uniform: a block has one t)
       __syncthreads();
@@ -881,7 +886,7 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC sr
     for (int it = 0; it < 4; ++it) s0[it] = s1[it] = v4u{0, 0, 0, 0};
     for (int j = 0; j < p.ndig; ++j) {
       v4u v[4];
-      if (j == md.own) {
+      if (j == own) {
         const __amdgpu_buffer_rsrc_t rd = rows_rsrc(p.d + (uint64_t)ct * p.L * N + roff, 1024 * 4);
 #pragma unroll
         for (int it = 0; it < 4; ++it) v[it] = __builtin_amdgcn_raw_buffer_load_b128(rd, (lane + it * 64) * 16, 0, 0);
@@ -906,7 +911,7 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC sr
         const v4u a1 = __builtin_amdgcn_raw_buffer_load_b128(rk1, e, 0, 0);
         // accumulators in [0, 2q): the own digit's plain residues take a Barrett product
         // ([0, q)), the transforms' Montgomery-form ones a REDC step ((0, 2q))
-        if (j == md.own) {
+        if (j == own) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             uint32_t x = s0[it][k] + ip_mulmod(v[it][k], a0[k], md);
