@@ -258,10 +258,11 @@ bool rows_tail_supported(int log_n, int log_r, int log_c1);
 // ModUp NTT fused with the key-switch inner product (three factors R x 32 x 32): for
 // every ciphertext b < B and limb t < LK,
 //   acc[b][s][t] = sum_{j < ndig} E_j[b][t] * key[j][s][t] mod p_t,
-// where E_j[b][t] = d[b][t] for t in digit j (limbs[t].own == j) and otherwise the
-// forward row transform of tmp + b * ext_stride + (j * LK + t) * N (the packed row-side
-// step output of the converted limb, ext layout).  d: [B][L][N]; key: [dnum][2][LK][N];
-// acc: [B][2][LK][N]; N = 2^(rb_log + 13).
+// where E_j[b][t] = d[b][t] for t in digit j (own == j in t's limb entry) and otherwise
+// the forward row transform of tmp + b * ext_stride + (j * LK + t) * N (the packed
+// row-side step output of the converted limb, ext layout).  limbs: LK entries, one per
+// limb, in the order the blocks take them (each carries its limb index).
+// d: [B][L][N]; key: [dnum][2][LK][N]; acc: [B][2][LK][N]; N = 2^(rb_log + 13).
 struct IpLimb {
   const int8_t* tab;        // forward 32-point sub-step table of t's prime (fragment order)
   const uint32_t* tw1;      // its first-epilogue twiddle pairs times 2^32 (T3 * 2^32 mod q): the
