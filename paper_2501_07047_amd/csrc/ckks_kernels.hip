@@ -355,10 +355,10 @@ bconv_list_kernel(const BconvLaunch* tasks) {
 
 // Up to kBconvMulti conversions in one launch, passed by value (one per blockIdx.y):
 // the ModUp digits of one call, which alone fill the device only once each.
-template <int KB>
+template <int KB, bool WIDE = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KB == 1 ? 4 : KB == 2 ? 3 : 2)))
 bconv_multi_kernel(BconvMulti m) {
-  bconv_wave<KB>(m.g[blockIdx.y], ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  bconv_wave<KB, WIDE>(m.g[blockIdx.y], ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
 }
 
 __global__ void __launch_bounds__(256)
@@ -567,16 +567,6 @@ hipError_t launch_bconv_list(const BconvLaunch* t, int n, uint64_t max_cols, int
 }
 
 hipError_t launch_bconv_multi(const BconvLaunch* gs, int n, hipStream_t s) {
-  bool wide = false;
-  for (int i = 0; i < n; ++i) wide = wide || gs[i].wide;
-  if (wide) {
-    // the byte form: one launch per conversion
-    for (int i = 0; i < n; ++i) {
-      const hipError_t e = launch_bconv(gs[i], s);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  }
   for (int base = 0; base < n; base += kBconvMulti) {
     BconvMulti m{};
     const int cnt = n - base < kBconvMulti ? n - base : kBconvMulti;
@@ -584,19 +574,30 @@ hipError_t launch_bconv_multi(const BconvLaunch* gs, int n, hipStream_t s) {
     int nsrc = 1;
     for (int i = 0; i < cnt; ++i) {
       const BconvLaunch& b = gs[base + i];
-      if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5 || b.npoly < 0)
-        return hipErrorInvalidValue;
+      if (b.nsrc < 1 || b.nsrc > 8 * BCONV_MAX_KB || b.ndst < 1 || b.log_n < 5 || b.npoly < 0 ||
+          b.wide != gs[base].wide)
+        return hipErrorInvalidValue;      // one launch takes one form
       m.g[i] = b;
       cols = std::max(cols, (uint64_t)b.npoly << b.log_n);
       nsrc = std::max(nsrc, b.nsrc);
     }
     if (cols == 0) continue;
     const dim3 grid(blocks_for((cols + BCONV_COLS - 1) / BCONV_COLS * 64), cnt);
-    switch ((nsrc + 7) >> 3) {
-      case 1: launch_kernel(bconv_multi_kernel<1>, grid, dim3(256), 0, s, m); break;
-      case 2: launch_kernel(bconv_multi_kernel<2>, grid, dim3(256), 0, s, m); break;
-      case 3: launch_kernel(bconv_multi_kernel<3>, grid, dim3(256), 0, s, m); break;
-      default: launch_kernel(bconv_multi_kernel<4>, grid, dim3(256), 0, s, m); break;
+    const int kb = (nsrc + 7) >> 3;
+    if (gs[base].wide) {
+      switch (kb) {
+        case 1: launch_kernel(bconv_multi_kernel<1, true>, grid, dim3(256), 0, s, m); break;
+        case 2: launch_kernel(bconv_multi_kernel<2, true>, grid, dim3(256), 0, s, m); break;
+        case 3: launch_kernel(bconv_multi_kernel<3, true>, grid, dim3(256), 0, s, m); break;
+        default: launch_kernel(bconv_multi_kernel<4, true>, grid, dim3(256), 0, s, m); break;
+      }
+    } else {
+      switch (kb) {
+        case 1: launch_kernel(bconv_multi_kernel<1>, grid, dim3(256), 0, s, m); break;
+        case 2: launch_kernel(bconv_multi_kernel<2>, grid, dim3(256), 0, s, m); break;
+        case 3: launch_kernel(bconv_multi_kernel<3>, grid, dim3(256), 0, s, m); break;
+        default: launch_kernel(bconv_multi_kernel<4>, grid, dim3(256), 0, s, m); break;
+      }
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

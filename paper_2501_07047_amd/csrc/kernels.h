@@ -369,8 +369,7 @@ struct BconvLaunch {
 };
 hipError_t launch_bconv(const BconvLaunch& b, hipStream_t s);
 // Several conversions in one launch (by value, kBconvMulti per launch; more are
-// split over launches), e.g. the digits of one ModUp.  Narrow primes only, as in
-// the work-list form.
+// split over launches), e.g. the digits of one ModUp; all of one form (narrow or wide).
 constexpr int kBconvMulti = 8;
 struct BconvMulti {
   BconvLaunch g[kBconvMulti];
