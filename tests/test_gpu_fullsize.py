@@ -53,6 +53,20 @@ def test_he_mult_batch8_n2_16_L24():
         assert np.array_equal(calls[0][k], CK.he_mult(a[k], b[k], key, qs, ps, 3)), "ciphertext %d" % k
 
 
+@pytest.mark.parametrize("batch", [3, 5])
+def test_he_mult_odd_batch_n2_16_L24(batch):
+    # batches that do not fill whole workgroups of the fused ModUp kernel: its blocks of
+    # eight (row, ciphertext) pairs then straddle rows, and workgroups cross from one
+    # target limb to the next (restaging the tables) in the middle of their range
+    from paper_2501_07047_amd import binding as B
+    qs, ps, a, b, key = synthetic.ckks_pair(23 + batch, 16, 24, 3, 8, batch)
+    out = _empty(a.shape)
+    B.he_mult(to_dev(a), to_dev(b), to_dev(key), out, qs, ps, 3)
+    got = to_host(out)
+    for k in (0, batch - 1):
+        assert np.array_equal(got[k], CK.he_mult(a[k], b[k], key, qs, ps, 3)), "ciphertext %d" % k
+
+
 def test_rotate_batch8_n2_16_L24():
     from paper_2501_07047_amd import binding as B
     qs, ps, a, _, key = synthetic.ckks_pair(22, 16, 24, 3, 8, 8)
