@@ -543,10 +543,11 @@ struct P32List {
   }
   __device__ __forceinline__ RowLoc locate(int b, int wave) {
     while (t + 1 < ntasks && tasks[t + 1].first_block <= b) ++t;
+    t = __builtin_amdgcn_readfirstlane(t);
     const RowsTask& k = tasks[t];
     const int local = b - k.first_block;
     const int rb = __builtin_amdgcn_readfirstlane(local / k.npoly);
-    const int poly = local - rb * k.npoly, row = rb * kP32Waves + wave;
+    const int poly = __builtin_amdgcn_readfirstlane(local - rb * k.npoly), row = rb * kP32Waves + wave;
     const uint64_t off = (uint64_t)poly * k.stride + (uint64_t)row * 1024;
     return RowLoc{k.tab, k.tw1, k.tw2 ? k.tw2 + (uint64_t)row * 2048 : nullptr, k.in + off, k.out + off, k.q, k.qinv};
   }
@@ -672,10 +673,11 @@ struct P32ListTail {
   }
   __device__ __forceinline__ RowLoc locate(int b, int wave) {
     while (t + 1 < ntasks && tasks[t + 1].r.first_block <= b) ++t;
+    t = __builtin_amdgcn_readfirstlane(t);
     const RowsTask& k = tasks[t].r;
     const int local = b - k.first_block;
     const int rb = __builtin_amdgcn_readfirstlane(local / k.npoly);
-    const int poly = local - rb * k.npoly, row = rb * kP32Waves + wave;
+    const int poly = __builtin_amdgcn_readfirstlane(local - rb * k.npoly), row = rb * kP32Waves + wave;
     const uint64_t off = (uint64_t)poly * k.stride + (uint64_t)row * 1024;
     return RowLoc{k.tab, k.tw1, nullptr, k.in + off, nullptr, k.q, k.qinv};
   }
@@ -683,7 +685,7 @@ struct P32ListTail {
     const RowsTailTask& k = tasks[t];
     const int local = b - k.r.first_block;
     const int rb = __builtin_amdgcn_readfirstlane(local / k.r.npoly);
-    const int poly = local - rb * k.r.npoly, row = rb * kP32Waves + wave;
+    const int poly = __builtin_amdgcn_readfirstlane(local - rb * k.r.npoly), row = rb * kP32Waves + wave;
     const uint64_t o = (uint64_t)row * 1024;
     const bool use_base = k.base != nullptr && (!k.base_only_even || (poly & 1) == 0);
     p32_tail_row(zw, k.acc + poly * k.acc_stride + o, use_base ? k.base + poly * k.out_stride + o : nullptr,
@@ -841,6 +843,7 @@ struct IpList {
   }
   __device__ __forceinline__ const RowsIp& at(int b, int& local) {
     while (t + 1 < ntasks && tasks[t + 1].first_block <= b) ++t;
+    t = __builtin_amdgcn_readfirstlane(t);
     local = b - tasks[t].first_block;
     return tasks[t].p;
   }
@@ -868,7 +871,7 @@ __global__ void __launch_bounds__(64 * kP32Waves, 4) ntt_rows32_ip_kernel(SRC sr
     // the wave's (row, ciphertext) pair, the ciphertext fastest
     const int pair = (local - tp * per_t) * kP32Waves + wave;
     const int row = __builtin_amdgcn_readfirstlane(pair / p.B);
-    const int ct = pair - row * p.B;
+    const int ct = __builtin_amdgcn_readfirstlane(pair - row * p.B);
     const IpLimb md = p.limbs[tp];
     // the limb index and its digit drive the row addresses and branches: wave-uniform
     const int t = __builtin_amdgcn_readfirstlane(md.limb), own = __builtin_amdgcn_readfirstlane(md.own);
