@@ -610,10 +610,11 @@ def main():
     ap.add_argument("--warmup-seconds", type=float, default=1.0,
                     help="keep warming up until this much wall time has passed (0 under a profiler)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=["all", "ntt", "copy", "he_mult"], default="all",
+    ap.add_argument("--only", choices=["all", "ntt", "copy", "he_mult", "uneven"], default="all",
                     help="ntt: time only the NTT step; copy: a plain 256 MiB device copy "
                          "(calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE against known bytes); "
-                         "he_mult: only HE-Mult at batch 8 (for a kernel trace of its kernels)")
+                         "he_mult: only HE-Mult at batch 8 (for a kernel trace of its kernels); "
+                         "uneven: only the 64-ciphertext uneven batch (for a trace of the batch runtime)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path shards by ciphertext with no "
@@ -644,6 +645,9 @@ def main():
     if args.only == "he_mult":
         r = he_mult_bench(B, args.steps, args.warmup, 8, ("he_mult",))
         print(json.dumps({"he_mult_batch8": r["he_mult"]}))
+        return
+    if args.only == "uneven":
+        print(json.dumps({"uneven_batch": uneven_batch_bench(B, max(4, args.steps // 2))}))
         return
     log_r, log_c1 = B.get_ntt_split(LOG_N)       # the library's default factoring of 2^16
     primes, x = synthetic.ntt_batch(0, LOG_N, L, POLYS)
