@@ -63,3 +63,16 @@ def test_he_mult_model_counts_config3():
     assert bench.he_mult_model(16, 24, 8, 3, 8, 6, 5)["hbm_bytes"] == 3 * ct + 3 * 2 * 32 * n * 4 / 8
     # two factors, 256 x 256: 32 N (R + C) per limb-NTT
     assert bench.he_mult_model(16, 24, 8, 3, 1, 8, 0)["int8_ops"] == 160 * 32.0 * n * 512 + bconv
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    # the bench measures one GPU: --gpus above 1 (or a multi-rank launch) exits before
+    # anything touches the device, with a message that says why
+    import subprocess
+    import sys
+    for argv, env in ((["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + argv, cwd=ROOT,
+                           env=dict(os.environ, **env), capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2
+        assert "one GPU only" in r.stderr
+        assert r.stdout == ""
