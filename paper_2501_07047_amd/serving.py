@@ -156,12 +156,17 @@ class GpuExecutor:
         self.groups = 0
         self.host_s = 0.0
         self.last_ev = None
+        # workspace bytes of a batch of one request, by request shape: a group's batch
+        # needs at most the sum over its requests (its scratch is the sum of theirs and
+        # its merged task lists take no more than their lists apart; creating a batch
+        # checks the size it is given), so a group is not lowered once more to size it
+        self.ws_bytes = {}
 
     def prepare(self, requests):
         """Build the tables of every request shape (NTT plans of each prime and size, CKKS
-        plans, automorphism tables) once, before serving: a batch of one request per
-        (op, N, L, rotation) is lowered for its workspace size only, which creates them and
-        allocates nothing else."""
+        plans, automorphism tables) once, before serving: one request per (op, N, L,
+        rotation) is lowered alone for its workspace size only, which creates them and
+        allocates nothing else, and the sizes are kept by request shape."""
         seen = {}
         for r in requests:
             seen.setdefault((r.op, r.log_n, r.L, r.steps if r.op == "rotate" else 0), r)
@@ -175,11 +180,27 @@ class GpuExecutor:
         for r in group:
             r.out = scratch.view(-1)[:r.inputs["a"].numel()].view(r.inputs["a"].shape)
         try:
-            self.B.batch_workspace_bytes(self._jobs(group, alloc=False))
+            for r, j in zip(group, self._jobs(group, alloc=False)):
+                n = self.B.batch_workspace_bytes([j])          # also builds the request's tables
+                k = self._shape(r)
+                self.ws_bytes[k] = max(n, self.ws_bytes.get(k, 0))
         finally:
             for r, o in zip(group, saved):
                 r.out = o
         self.torch.cuda.synchronize()
+
+    @staticmethod
+    def _shape(r):
+        return (r.op, r.log_n, r.L, len(r.ps), r.dnum)
+
+    def _workspace_bytes(self, group, jobs):
+        total = 0
+        for r, j in zip(group, jobs):
+            k = self._shape(r)
+            if k not in self.ws_bytes:
+                self.ws_bytes[k] = self.B.batch_workspace_bytes([j])
+            total += self.ws_bytes[k]
+        return total
 
     def host_stats(self):
         return {"groups": self.groups,
@@ -212,7 +233,7 @@ class GpuExecutor:
         t_host = time.perf_counter()
         with torch.cuda.stream(s):
             jobs = self._jobs(group)
-            nbytes = self.B.batch_workspace_bytes(jobs)
+            nbytes = self._workspace_bytes(group, jobs)
             ws = torch.empty((nbytes + 255) // 256 * 64 + 64, dtype=torch.int32, device="cuda")
             off = (-ws.data_ptr()) % 256 // 4
             ws = ws[off:]
