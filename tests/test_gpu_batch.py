@@ -137,6 +137,19 @@ def test_config4_uneven_batch_64_ciphertexts():
         assert np.array_equal(got[k][:, i], ref), "NTT job %d %s limb %d" % (k, specs[k], i)
 
 
+def test_group_workspace_within_the_sum_of_its_jobs_alone():
+    # the request loop sizes a group's workspace as the sum of its requests' sizes alone:
+    # a batch's scratch is the sum of its jobs' and its merged task lists take no more
+    # room than theirs apart.  Sizing only, nothing runs.
+    from paper_2501_07047_amd import binding as B
+    jobs, _ = _mixed_jobs(5, SPECS)
+    alone = [B.batch_workspace_bytes([j]) for j in jobs]
+    for k in range(1, len(jobs) + 1):
+        assert B.batch_workspace_bytes(jobs[:k]) <= sum(alone[:k])
+    # in reverse order too (the phases' lists are filled in job order)
+    assert B.batch_workspace_bytes(jobs[::-1]) <= sum(alone)
+
+
 def test_batch_rejects_bad_jobs():
     import torch
     from paper_2501_07047_amd import binding as B
