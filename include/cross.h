@@ -411,7 +411,10 @@ typedef struct cross_batch_s* cross_batch;
  * Primes below 2^28 only (CROSS_ERANGE for a wide prime in any job). */
 cross_status cross_batch_create(cross_ctx ctx, const cross_job* jobs, uint32_t njobs, int use_graph,
                                 cross_batch* out);
-/* Bytes of device workspace a batch of these jobs needs when the caller provides it. */
+/* Bytes of device workspace a batch of these jobs needs when the caller provides it.
+ * Never more than the sum of the bytes of each job alone (a batch's scratch is the
+ * sum of its jobs', its merged task lists no larger than theirs apart), so a caller
+ * may size a group of jobs from sizes it keeps per job shape. */
 cross_status cross_batch_workspace_bytes(cross_ctx ctx, const cross_job* jobs, uint32_t njobs,
                                          uint64_t* bytes);
 /* As cross_batch_create, but all of the batch's device memory (scratch and task
