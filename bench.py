@@ -618,7 +618,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the hot path shards by ciphertext with no "
-              "exchange, and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+              "exchange between GPUs, so one MI355X's throughput is the figure (use --gpus 1).",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
