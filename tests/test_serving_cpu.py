@@ -85,3 +85,38 @@ def test_poisson_workload_is_seeded():
 def test_footprint_grows_with_size():
     assert footprint_bytes(16, 24, 8, 3, "he_mult") > footprint_bytes(14, 24, 8, 3, "he_mult")
     assert footprint_bytes(16, 24, 8, 3, "he_mult") > footprint_bytes(16, 24, 8, 3, "rotate")
+
+
+def test_automatic_collection_is_off_while_serving_and_restored():
+    # a full collection of the interpreter's objects would stall the loop: it runs once
+    # before the clock starts, automatic collection stays off during the loop, and the
+    # caller's setting comes back afterwards, also when the executor raises
+    import gc
+
+    class Recording(FakeExecutor):
+        def launch(self, group, slot):
+            self.gc_states = getattr(self, "gc_states", []) + [gc.isenabled()]
+            return super().launch(group, slot)
+
+    class Failing(FakeExecutor):
+        def launch(self, group, slot):
+            raise RuntimeError("launch failed")
+
+    was = gc.isenabled()
+    try:
+        for caller_setting in (True, False):
+            (gc.enable if caller_setting else gc.disable)()
+            clk = Clock()
+            ex = Recording(clk)
+            Server(ex, hbm_budget=1000, slots=2, max_group=4).run(_reqs(12, 300, 0.001), clock=clk)
+            assert ex.gc_states and not any(ex.gc_states)
+            assert gc.isenabled() == caller_setting
+            try:
+                Server(Failing(Clock()), hbm_budget=1000, slots=2, max_group=4).run(_reqs(3, 300, 0.0),
+                                                                                    clock=Clock())
+                assert False, "the executor's error must propagate"
+            except RuntimeError:
+                pass
+            assert gc.isenabled() == caller_setting
+    finally:
+        (gc.enable if was else gc.disable)()
