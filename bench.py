@@ -16,6 +16,7 @@ HE-Mult bit for bit).
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -629,6 +630,12 @@ def main():
     if not args.no_cpu and args.only == "all":
         # the oracle first, before anything touches the GPU (its worker pool forks)
         cpu, he_oracle = cpu_baseline(synthetic.ckks_pair(0, 16, 24, 3, 8, 8))
+
+    # a full collection of the interpreter's objects takes tens of milliseconds, longer
+    # than most timed regions here: collect once now and time with automatic collection
+    # off (as timeit does)
+    gc.collect()
+    gc.disable()
 
     import torch
     from paper_2501_07047_amd import binding as B
